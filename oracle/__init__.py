@@ -1,0 +1,323 @@
+"""FP64 CPU oracle of the BYSDF (arXiv 2401.12724) -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never calls it.
+
+The arithmetic lives in ``bysdf_oracle.c`` (plain C, double precision,
+OpenMP over queries); this module only marshals numpy arrays through ctypes.
+Queries are the same FP32 arrays the GPU consumes, promoted to double inside.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bysdf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# flag bits (same numbering as the library's public flags)
+PASS_THROUGH = 1 << 0
+ILLCOND = 1 << 1
+NEARTIE = 1 << 2
+NEARTANGENT = 1 << 3
+AXIAL = 1 << 4
+BACKFACING = 1 << 5
+SAMPLE_FAIL = 1 << 6
+NEAR_LOBE_BOUNDARY = 1 << 7
+NEAR_TIR = 1 << 8
+BAD_INPUT = 1 << 9
+MARGIN_MASK = ILLCOND | NEARTIE | NEARTANGENT | NEAR_LOBE_BOUNDARY | NEAR_TIR
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("n_plies", C.c_int32), ("fibers_per_ply", C.c_int32), ("K", C.c_int32),
+        ("n_iter", C.c_int32), ("tex_size", C.c_int32),
+        ("ply_radius", C.c_double), ("ply_center_radius", C.c_double),
+        ("fiber_radius", C.c_double), ("ply_twist", C.c_double),
+        ("fiber_twist", C.c_double), ("eta", C.c_double), ("albedo", C.c_double * 3),
+        ("beta", C.c_double), ("aniso", C.c_double), ("k_spec", C.c_double),
+        ("B", C.c_double), ("r", C.c_double), ("sigma_t", C.c_double),
+        ("ply_density", C.c_double), ("fiber_density", C.c_double),
+        ("shadow_halfwidth", C.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain C99, -O2, OpenMP, IEEE math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "bysdf_oracle.h"))):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        dp = C.POINTER(C.c_double)
+        fp = C.POINTER(C.c_float)
+        ip = C.POINTER(C.c_int32)
+        up = C.POINTER(C.c_uint32)
+        pp = C.POINTER(OrcParams)
+        tp = C.POINTER(dp)
+        L.orc_table.argtypes = [pp, dp]
+        L.orc_eval.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp, up,
+                               C.c_int]
+        L.orc_sample.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp,
+                                 up, C.c_int]
+        L.orc_furnace.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp, fp,
+                                  fp, fp, dp, dp, C.c_int]
+        L.orc_eval_far.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, C.c_double, ip, fp,
+                                   fp, fp, fp, dp, C.c_int]
+        L.orc_grad_fd.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp,
+                                  C.c_double, dp, dp, C.c_int]
+        L.orc_philox4x32_10.argtypes = [up, up, up]
+        L.orc_fresnel.argtypes = [C.c_double, C.c_double]
+        L.orc_fresnel.restype = C.c_double
+        L.orc_ggx_D.argtypes = [dp, C.c_double, C.c_double]
+        L.orc_ggx_D.restype = C.c_double
+        L.orc_smith_G1.argtypes = [dp, dp, C.c_double, C.c_double]
+        L.orc_smith_G1.restype = C.c_double
+        L.orc_vndf.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_ls_albedo.argtypes = [C.c_double]
+        L.orc_ls_albedo.restype = C.c_double
+        L.orc_ply_shadow_raw.argtypes = [pp, C.c_double, C.c_double]
+        L.orc_ply_shadow_raw.restype = C.c_double
+        L.orc_ply_hit.argtypes = [pp, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_ply_hit.restype = C.c_uint32
+        L.orc_set_margins.argtypes = [C.c_double] * 5
+        L.orc_nodes.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_nodes.restype = C.c_uint32
+        L.orc_frame_x.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_frame_x.restype = C.c_uint32
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- helpers
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+def params_struct(d: dict) -> OrcParams:
+    p = OrcParams()
+    for name, _ in OrcParams._fields_:
+        if name == "albedo":
+            for c in range(3):
+                p.albedo[c] = float(d["albedo"][c])
+        else:
+            setattr(p, name, d[name])
+    return p
+
+
+class TypeSet:
+    """Parameter records and their fiber tables, built by the oracle."""
+
+    def __init__(self, param_dicts):
+        self.dicts = [dict(d) for d in param_dicts]
+        n = len(self.dicts)
+        self.structs = (OrcParams * n)()
+        for i, d in enumerate(self.dicts):
+            self.structs[i] = params_struct(d)
+        self.tables = []
+        cache = {}
+        for i, d in enumerate(self.dicts):
+            key = (d["fibers_per_ply"], float(d["fiber_radius"]), d["tex_size"])
+            if key not in cache:
+                cache[key] = table(d)
+            self.tables.append(cache[key])
+        self._tp = (C.POINTER(C.c_double) * n)(*[_ptr(t, C.c_double) for t in self.tables])
+
+    def __len__(self):
+        return len(self.dicts)
+
+
+def table(d: dict) -> np.ndarray:
+    """Fiber table (N_u x 3: dn, rho_hat, G_f) of one parameter record."""
+    tab = np.zeros((d["tex_size"], 3), dtype=np.float64)
+    p = params_struct(d)
+    rc = lib().orc_table(C.byref(p), _ptr(tab, C.c_double))
+    if rc != 0:
+        raise ValueError("invalid fiber-table parameters")
+    return tab
+
+
+def _types(ts):
+    return ts if isinstance(ts, TypeSet) else TypeSet(ts)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def eval(ts, q: dict, nthreads: int = 0):
+    """BYSDF value and pdf.  Returns (out[n,13] float64, flags[n] uint32)."""
+    ts = _types(ts)
+    n = len(q["h"])
+    out = np.zeros((n, 13), dtype=np.float64)
+    flags = np.zeros(n, dtype=np.uint32)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    h, u, v = _f32(q["h"]), _f32(q["u"]), _f32(q["v"])
+    wi, wo = _f32(q["wi"]), _f32(q["wo"])
+    sh = _f32(q["shift"]) if q.get("shift") is not None else None
+    lib().orc_eval(ts.structs, ts._tp, len(ts), n, _ptr(tpe, C.c_int32), _ptr(h, C.c_float),
+                   _ptr(u, C.c_float), _ptr(v, C.c_float), _ptr(wi, C.c_float),
+                   _ptr(wo, C.c_float), _ptr(sh, C.c_float), _ptr(out, C.c_double),
+                   _ptr(flags, C.c_uint32), nthreads)
+    return out, flags
+
+
+def sample(ts, q: dict, nthreads: int = 0):
+    """Importance sampling.  Returns (out[n,12] float64, flags[n] uint32):
+    wo(3) weight(3) pdf exit(3) lobe node."""
+    ts = _types(ts)
+    n = len(q["h"])
+    out = np.zeros((n, 12), dtype=np.float64)
+    flags = np.zeros(n, dtype=np.uint32)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    h, u, v = _f32(q["h"]), _f32(q["u"]), _f32(q["v"])
+    wi, xi = _f32(q["wi"]), _f32(q["xi"])
+    sh = _f32(q["shift"]) if q.get("shift") is not None else None
+    lib().orc_sample(ts.structs, ts._tp, len(ts), n, _ptr(tpe, C.c_int32), _ptr(h, C.c_float),
+                     _ptr(u, C.c_float), _ptr(v, C.c_float), _ptr(wi, C.c_float),
+                     _ptr(xi, C.c_float), _ptr(sh, C.c_float), _ptr(out, C.c_double),
+                     _ptr(flags, C.c_uint32), nthreads)
+    return out, flags
+
+
+def furnace(ts, q: dict, block: int, nthreads: int = 0):
+    ts = _types(ts)
+    n = len(q["h"])
+    nb = n // block
+    mean = np.zeros((nb, 3), dtype=np.float64)
+    var = np.zeros((nb, 3), dtype=np.float64)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    h, u, v = _f32(q["h"]), _f32(q["u"]), _f32(q["v"])
+    wi, xi = _f32(q["wi"]), _f32(q["xi"])
+    sh = _f32(q["shift"]) if q.get("shift") is not None else None
+    rc = lib().orc_furnace(ts.structs, ts._tp, len(ts), n, block, _ptr(tpe, C.c_int32),
+                           _ptr(h, C.c_float), _ptr(u, C.c_float), _ptr(v, C.c_float),
+                           _ptr(wi, C.c_float), _ptr(xi, C.c_float), _ptr(sh, C.c_float),
+                           _ptr(mean, C.c_double), _ptr(var, C.c_double), nthreads)
+    if rc != 0:
+        raise ValueError("block must be >= 2")
+    return mean, var
+
+
+def eval_far(ts, q: dict, n_h: int = 4, zeta: float = 0.5, nthreads: int = 0):
+    ts = _types(ts)
+    n = len(q["u"])
+    out = np.zeros((n, 3), dtype=np.float64)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    u, v = _f32(q["u"]), _f32(q["v"])
+    wi, wo = _f32(q["wi"]), _f32(q["wo"])
+    lib().orc_eval_far(ts.structs, ts._tp, len(ts), n, n_h, zeta, _ptr(tpe, C.c_int32),
+                       _ptr(u, C.c_float), _ptr(v, C.c_float), _ptr(wi, C.c_float),
+                       _ptr(wo, C.c_float), _ptr(out, C.c_double), nthreads)
+    return out
+
+
+def grad_fd(ts, q: dict, gE, rel_step: float = 1e-6, nthreads: int = 0):
+    """Central FD of sum gE*E wrt theta.  Returns (grad[n_types,8], per_query[n,8])."""
+    ts = _types(ts)
+    n = len(q["h"])
+    grad = np.zeros((len(ts), 8), dtype=np.float64)
+    pq = np.zeros((n, 8), dtype=np.float64)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    h, u, v = _f32(q["h"]), _f32(q["u"]), _f32(q["v"])
+    wi, wo = _f32(q["wi"]), _f32(q["wo"])
+    g = _f32(gE)
+    lib().orc_grad_fd(ts.structs, ts._tp, len(ts), n, _ptr(tpe, C.c_int32), _ptr(h, C.c_float),
+                      _ptr(u, C.c_float), _ptr(v, C.c_float), _ptr(wi, C.c_float),
+                      _ptr(wo, C.c_float), _ptr(g, C.c_float), rel_step,
+                      _ptr(grad, C.c_double), _ptr(pq, C.c_double), nthreads)
+    return grad, pq
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def set_margins(geo=1e-7, shade=2e-6, amplify=1e6, tir=1e-3, xi=1e-6):
+    lib().orc_set_margins(geo, shade, amplify, tir, xi)
+
+
+# thin wrappers of the closed-form internals (used by the pins)
+def fresnel(cos_i, eta_rel):
+    return lib().orc_fresnel(float(cos_i), float(eta_rel))
+
+
+def ggx_D(m, ax, ay):
+    a = np.ascontiguousarray(m, dtype=np.float64)
+    return lib().orc_ggx_D(_ptr(a, C.c_double), ax, ay)
+
+
+def smith_G1(w, m, ax, ay):
+    a = np.ascontiguousarray(w, dtype=np.float64)
+    b = np.ascontiguousarray(m, dtype=np.float64)
+    return lib().orc_smith_G1(_ptr(a, C.c_double), _ptr(b, C.c_double), ax, ay)
+
+
+def vndf(wi, ax, ay, u1, u2):
+    a = np.ascontiguousarray(wi, dtype=np.float64)
+    m = np.zeros(3, dtype=np.float64)
+    lib().orc_vndf(_ptr(a, C.c_double), ax, ay, u1, u2, _ptr(m, C.c_double))
+    return m
+
+
+def ls_albedo(mu):
+    return lib().orc_ls_albedo(float(mu))
+
+
+def ply_shadow_raw(d, a, phi):
+    p = params_struct(d)
+    return lib().orc_ply_shadow_raw(C.byref(p), float(a), float(phi))
+
+
+def ply_hit(d, h, u, v, wi):
+    p = params_struct(d)
+    w = np.ascontiguousarray(wi, dtype=np.float64)
+    out = np.zeros(10 + 8, dtype=np.float64)
+    fl = lib().orc_ply_hit(C.byref(p), float(h), float(u), float(v), _ptr(w, C.c_double),
+                           _ptr(out, C.c_double))
+    return out, fl
+
+
+def nodes(d, tab, h, u, v, wi, shift=None):
+    """Forward-node probe: (array[K,16], flags); columns kind N ell att T
+    wt(3) y(3) n_y(3) p2x p2y."""
+    p = params_struct(d)
+    w = np.ascontiguousarray(wi, dtype=np.float64)
+    t = np.ascontiguousarray(tab, dtype=np.float64)
+    out = np.zeros((d["K"], 16), dtype=np.float64)
+    sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
+    fl = lib().orc_nodes(C.byref(p), _ptr(t, C.c_double), float(h), float(u), float(v),
+                         _ptr(w, C.c_double), _ptr(sh, C.c_double), _ptr(out, C.c_double))
+    return out, fl
+
+
+def frame_x(d, tab, h, u, v, wi):
+    """Shading-frame probe: (array[16], flags): t b n Gp Gf mu_i w(4)."""
+    p = params_struct(d)
+    w = np.ascontiguousarray(wi, dtype=np.float64)
+    t = np.ascontiguousarray(tab, dtype=np.float64)
+    out = np.zeros(16, dtype=np.float64)
+    fl = lib().orc_frame_x(C.byref(p), _ptr(t, C.c_double), float(h), float(u), float(v),
+                           _ptr(w, C.c_double), _ptr(out, C.c_double))
+    return out, fl

@@ -1,0 +1,178 @@
+"""Seeded synthetic workloads for the BYSDF hot path.
+
+This module only draws inputs: parameter records and query arrays.  It holds
+none of the method's arithmetic, so both the HIP path and the test oracle can
+consume what it produces.  Every array is generated once on the host from
+``numpy.random.Generator(Philox(seed))`` and rounded to FP32.
+
+The paper's datasets (yarn-level cloth, knit models, measured fibers) are not
+available; these draws stand in for them with the shapes of the workloads:
+
+* ``single_type``    -- 65,536 queries of one 3-ply yarn type (N_p=3, M=64,
+                        ply twist 28 deg, fiber twist 15 deg, r_p=0.45,
+                        r_f=0.06 r_p, eta=1.55, albedo (0.8,0.6,0.4), beta=0.15)
+* ``per_block``      -- 2^24 queries in blocks of 256, beta and albedo drawn
+                        per block, xi drawn per query for the sampler
+* ``heterogeneous``  -- 4,096 yarn types, lognormal query counts (median 4,096,
+                        clipped to 256..65,536), sorted by type
+* ``fitting``        -- 64 types x 65,536 queries with hidden parameters
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+DEG = math.pi / 180.0
+
+
+def default_params(**over) -> dict:
+    """Parameter record of the single-type workload (defaults of the build)."""
+    p = dict(
+        n_plies=3, fibers_per_ply=64, K=4, n_iter=5, tex_size=512,
+        ply_radius=0.45, ply_center_radius=0.55, fiber_radius=0.06,
+        ply_twist=28.0 * DEG, fiber_twist=15.0 * DEG, eta=1.55,
+        albedo=(0.8, 0.6, 0.4), beta=0.15, aniso=1.0, k_spec=1.0,
+        B=0.5, r=0.5, sigma_t=0.5, ply_density=1.0, fiber_density=1.0,
+        shadow_halfwidth=0.1,
+    )
+    p.update(over)
+    if "ply_radius" in over and "ply_center_radius" not in over:
+        p["ply_center_radius"] = 1.0 - p["ply_radius"]
+    return p
+
+
+def packed_ply_radius(n_plies: int) -> float:
+    """Ply radius (in yarn radii) of N_p equal discs packed tightly inside the
+    yarn circle, each touching the boundary and its two neighbours."""
+    if n_plies == 1:
+        return 1.0
+    s = math.sin(math.pi / n_plies)
+    return s / (1.0 + s)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=seed))
+
+
+def _sphere(rng, n):
+    z = 1.0 - 2.0 * rng.random(n)
+    phi = 2.0 * math.pi * rng.random(n)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z]).astype(np.float32)
+
+
+def queries(n: int, seed: int, n_types: int = 1, type_ids=None, with_xi: bool = False,
+            v_max: float = 10.0) -> dict:
+    """n queries: h~U[-1,1], u~U[0,2pi), v~U[0,v_max), wi, wo uniform on S^2."""
+    rng = _rng(seed)
+    if type_ids is None:
+        type_ids = rng.integers(0, n_types, n) if n_types > 1 else np.zeros(n)
+    q = dict(
+        type=np.asarray(type_ids, dtype=np.int32),
+        h=(2.0 * rng.random(n) - 1.0).astype(np.float32),
+        u=(2.0 * math.pi * rng.random(n)).astype(np.float32),
+        v=(v_max * rng.random(n)).astype(np.float32),
+    )
+    q["wi"] = np.ascontiguousarray(_sphere(rng, n))
+    q["wo"] = np.ascontiguousarray(_sphere(rng, n))
+    if with_xi:
+        q["xi"] = np.ascontiguousarray(rng.random((3, n)).astype(np.float32))
+        # keep xi strictly inside [0, 1) after rounding to FP32
+        q["xi"] = np.minimum(q["xi"], np.float32(1.0 - 2.0 ** -24))
+    return q
+
+
+def single_type(n: int = 65536, seed: int = 0, with_xi: bool = False):
+    """One 3-ply yarn type; returns (param list, queries)."""
+    return [default_params()], queries(n, seed, with_xi=with_xi)
+
+
+def per_block(n_blocks: int = 65536, block: int = 256, seed: int = 1):
+    """Blocks of `block` queries sharing one parameter record whose beta ~
+    U[0.05, 0.3] and albedo ~ U[0.3, 0.95]^3; xi per query for the sampler."""
+    rng = _rng(seed + 1000)
+    betas = rng.uniform(0.05, 0.3, n_blocks)
+    albs = rng.uniform(0.3, 0.95, (n_blocks, 3))
+    params = [default_params(beta=float(betas[b]), albedo=tuple(float(a) for a in albs[b]))
+              for b in range(n_blocks)]
+    tid = np.repeat(np.arange(n_blocks, dtype=np.int32), block)
+    q = queries(n_blocks * block, seed, type_ids=tid, with_xi=True)
+    return params, q
+
+
+def heterogeneous_params(n_types: int = 4096, seed: int = 3):
+    """Per-type records: plies 2..5 (tightly packed), fibers 32..128, twist
+    angles U[10, 40] deg, beta U[0.05, 0.3], albedo U[0.2, 0.95]^3."""
+    rng = _rng(seed + 2000)
+    out = []
+    for _ in range(n_types):
+        npl = int(rng.integers(2, 6))
+        rp = packed_ply_radius(npl)
+        out.append(default_params(
+            n_plies=npl, fibers_per_ply=int(rng.integers(32, 129)),
+            ply_radius=rp, ply_center_radius=1.0 - rp,
+            ply_twist=float(rng.uniform(10.0, 40.0)) * DEG,
+            fiber_twist=float(rng.uniform(10.0, 40.0)) * DEG,
+            beta=float(rng.uniform(0.05, 0.3)),
+            albedo=tuple(float(a) for a in rng.uniform(0.2, 0.95, 3))))
+    return out
+
+
+def lognormal_counts(n_types: int = 4096, median: int = 4096, sigma: float = 2.49,
+                     lo: int = 256, hi: int = 65536, seed: int = 3) -> np.ndarray:
+    rng = _rng(seed + 3000)
+    c = np.exp(np.log(median) + sigma * rng.standard_normal(n_types))
+    return np.clip(np.rint(c), lo, hi).astype(np.int64)
+
+
+def heterogeneous(n_types: int = 4096, seed: int = 3, counts=None):
+    """Types with lognormal counts; queries sorted by type (CSR offsets)."""
+    params = heterogeneous_params(n_types, seed)
+    if counts is None:
+        counts = lognormal_counts(n_types, seed=seed)
+    offsets = np.zeros(n_types + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    tid = np.repeat(np.arange(n_types, dtype=np.int32), counts)
+    q = queries(int(offsets[-1]), seed, type_ids=tid)
+    return params, q, offsets
+
+
+def fitting(n_types: int = 64, per_type: int = 65536, seed: int = 4):
+    """Hidden parameters theta* per type (heterogeneous ranges, densities
+    U[0.5, 1]) and the starting point theta0 = range midpoints."""
+    rng = _rng(seed + 4000)
+    hidden, start = [], []
+    for _ in range(n_types):
+        base = dict(n_plies=3, fibers_per_ply=64)
+        hidden.append(default_params(
+            **base,
+            ply_twist=float(rng.uniform(10.0, 40.0)) * DEG,
+            fiber_twist=float(rng.uniform(10.0, 40.0)) * DEG,
+            beta=float(rng.uniform(0.05, 0.3)),
+            albedo=tuple(float(a) for a in rng.uniform(0.2, 0.95, 3)),
+            ply_density=float(rng.uniform(0.5, 1.0)),
+            fiber_density=float(rng.uniform(0.5, 1.0))))
+        start.append(default_params(
+            **base, ply_twist=25.0 * DEG, fiber_twist=25.0 * DEG, beta=0.175,
+            albedo=(0.575, 0.575, 0.575), ply_density=0.75, fiber_density=0.75))
+    tid = np.repeat(np.arange(n_types, dtype=np.int32), per_type)
+    q = queries(n_types * per_type, seed, type_ids=tid)
+    return hidden, start, q
+
+
+THETA_NAMES = ("albedo_r", "albedo_g", "albedo_b", "beta", "ply_twist", "fiber_twist",
+               "ply_density", "fiber_density")
+
+
+def theta_of(p: dict) -> np.ndarray:
+    return np.array([p["albedo"][0], p["albedo"][1], p["albedo"][2], p["beta"], p["ply_twist"],
+                     p["fiber_twist"], p["ply_density"], p["fiber_density"]], dtype=np.float64)
+
+
+def with_theta(p: dict, th) -> dict:
+    q = dict(p)
+    q["albedo"] = (float(th[0]), float(th[1]), float(th[2]))
+    q["beta"], q["ply_twist"], q["fiber_twist"] = float(th[3]), float(th[4]), float(th[5])
+    q["ply_density"], q["fiber_density"] = float(th[6]), float(th[7])
+    return q
