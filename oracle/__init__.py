@@ -254,7 +254,7 @@ def philox4x32_10(ctr, key):
     return o
 
 
-def set_margins(geo=1e-7, shade=2e-6, amplify=1e6, tir=1e-3, xi=1e-6):
+def set_margins(geo=1e-7, shade=2e-6, amplify=1e5, tir=1e-6, xi=1e-6):
     lib().orc_set_margins(geo, shade, amplify, tir, xi)
 
 

@@ -33,8 +33,8 @@
  * discrete decision is flagged; see the parity rule in the tests. */
 static double g_margin_geo = 1e-7;   /* decisions on O(1) geometric quantities */
 static double g_margin_shade = 2e-6; /* decisions on shading cosines */
-static double g_amplify_max = 1e6;   /* ply fixed-point error amplification */
-static double g_margin_tir = 1e-3;   /* |eta (wi'.m') + (wo.m')| */
+static double g_amplify_max = 1e5;   /* ply fixed point: max_k A_k * max(1, |kappa|) */
+static double g_margin_tir = 1e-6;   /* 1 - sin^2 of the transmitted angle at exit */
 static double g_margin_xi = 1e-6;    /* lobe / node selection edges */
 
 void orc_set_margins(double geo, double shade, double amplify, double tir, double xi)
@@ -250,9 +250,11 @@ int orc_table(const orc_params* p, double* tab)
             if (hi > lo) { iv[n].lo = lo; iv[n].hi = hi; ++n; }
         }
         double blocked = union_cos_measure(iv, n);
-        tab[3 * i + 0] = dn;
-        tab[3 * i + 1] = rh;
-        tab[3 * i + 2] = blocked < 1.0 ? 1.0 - blocked : 0.0;
+        /* the texture stores single-precision texels (Sec. 3.5.1 keeps these
+         * values in a 1D texture): compute in double, store rounded */
+        tab[3 * i + 0] = (double)(float)dn;
+        tab[3 * i + 1] = (double)(float)rh;
+        tab[3 * i + 2] = (double)(float)(blocked < 1.0 ? 1.0 - blocked : 0.0);
     }
     free(fx); free(fy); free(iv);
     return 0;
@@ -418,7 +420,13 @@ static void trace_plies(const orc_params* p, double h, double u, double v, v3 wi
         double m = mg * (g->amp[k] > g->amp[ks] ? g->amp[k] : g->amp[ks]);
         if (fabs(sk[k] - sk[ks]) < (m > mg ? m : mg)) g->flags |= ORC_NEARTIE;
     }
-    if (g->amp[ks] > g_amplify_max) g->flags |= ORC_ILLCOND;
+    /* Rounding of the phase (relative 1e-16 of up to ~50 rad) reaches v*
+     * amplified by A |kappa|; the steep fiber table then turns an error in
+     * v* into a value error a few thousand times larger. */
+    double amax = 0.0;
+    for (int k = 0; k < Np; ++k) amax = g->amp[k] > amax ? g->amp[k] : amax;
+    double ak = fabs(g->kappa);
+    if (amax * (ak > 1.0 ? ak : 1.0) > g_amplify_max) g->flags |= ORC_ILLCOND;
     g->kstar = ks;
     g->sstar = sk[ks];
     g->p2[0] = g->x2[0] + g->sstar * g->dh[0];
@@ -666,7 +674,10 @@ static void exit_btdf(const orc_params* p, const fnode* nd, v3 wo, double* val, 
     double im = vdot(wip, mh), om = vdot(wo, mh);
     if (!(im < 0.0 && om > 0.0)) return;
     double den = eta * im + om;
-    if (fabs(den) < g_margin_tir) *flags |= ORC_NEAR_TIR;
+    /* near the critical angle the transmittance falls like the cosine of
+     * the transmitted angle, whose derivative is unbounded */
+    double s2t_in = eta * eta * (1.0 - im * im);
+    if (1.0 - s2t_in < g_margin_tir) *flags |= ORC_NEAR_TIR;
     v3 ml3 = to_local(&nd->fy, mh);
     double D = D_l(ml3, ax, ay);
     double g1i = G1_l(to_local(&nd->fy, wip), ml3, ax, ay);

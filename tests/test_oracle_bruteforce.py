@@ -72,13 +72,14 @@ def test_fiber_table_bruteforce(oracle_mod, M, rho):
         e = np.array([math.cos(z), math.sin(z)])
         s, j = _first_inside(1.0000001 * e, -e, C, rho, 2.0, rho / 50)
         if j < 0:
-            assert tab[i, 1] == 0.0 and tab[i, 2] == 1.0 and tab[i, 0] == 0.0
+            assert tab[i, 1] == 0.0 and tab[i, 2] == 1.0 and tab[i, 0] == 0.0  # no fiber on the ray
             continue
         q = 1.0000001 * e - s * e
         n = (q - C[j]) / rho
         dn = math.atan2(e[0] * n[1] - e[1] * n[0], e @ n)
         assert abs(tab[i, 0] - dn) < 1e-5
-        assert abs(tab[i, 1] - np.linalg.norm(C[j]) / (1 - rho)) < 1e-9
+        # texels are stored in single precision
+        assert abs(tab[i, 1] - np.linalg.norm(C[j]) / (1 - rho)) < 1.2e-7
         others = np.delete(C, j, 0)
         gf = 1.0 - _blocked_fraction(q, n, others, rho)
         assert abs(tab[i, 2] - gf) < 2e-3
