@@ -1,0 +1,201 @@
+/*
+ * bysdf.h -- C ABI of the MI355X (gfx950) BYSDF library, libbysdf.so.
+ *
+ * Batched evaluation, importance sampling, white-furnace integration and the
+ * adjoint of the bidirectional yarn scattering distribution function of
+ * "A Multi-scale Yarn Appearance Model with Fiber Details" (Khattar, Zhu,
+ * Montazeri et al., arXiv 2401.12724), plus ray / yarn-tube intersection and
+ * a wavefront path tracer that feeds it.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Units: lengths of a query are in yarn radii; angles in radians.  A
+ *   query's local frame has the yarn tangent as +z and the yarn's reference
+ *   normal (a rotation-minimising frame, Sec. 3.3) as +x.  Directions are
+ *   unit vectors pointing away from the hit (towards the camera / light).
+ * - A hit is given by (h, u, v) (Sec. 3.3, Sec. 4.2): h in [-1, 1] is the
+ *   azimuthal offset of the incident ray from the yarn axis (the hit
+ *   azimuth is atan2(wi) + asin h), u the ply-helix phase at the reference
+ *   normal, v the longitudinal position along the yarn.
+ * - Memory: every query / output pointer is a caller-owned DEVICE pointer
+ *   (structure of arrays, one 4-byte element per query, 4-byte aligned).
+ *   The library owns opaque handles and the device tables behind them.
+ * - Streams: every call is asynchronous on the given hipStream_t (0 = the
+ *   null stream); no call synchronises the device except *_create /
+ *   *_destroy, which synchronise their stream.
+ * - Errors: every function returns 0 on success or a negative
+ *   BYSDF_ERR_*; bysdf_last_error() returns a thread-local message.
+ *   Per-query problems never fail a call: they set bits in the per-query
+ *   flags output and zero the query's outputs.
+ */
+#ifndef BYSDF_H
+#define BYSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define BYSDF_OK 0
+#define BYSDF_ERR_INVALID_ARG (-1)      /* null / misaligned pointer, bad size */
+#define BYSDF_ERR_INVALID_PARAM (-2)    /* a type parameter out of its range  */
+#define BYSDF_ERR_OOM (-3)              /* device allocation failed            */
+#define BYSDF_ERR_LAUNCH (-4)           /* kernel launch or HIP call failed    */
+#define BYSDF_ERR_UNSUPPORTED_DEVICE (-5)
+
+/* ------------------------------------------------------- per-query flag bits */
+#define BYSDF_FLAG_PASS_THROUGH (1u << 0) /* the ray misses every implicit ply
+                                             and continues through the yarn
+                                             (Sec. 3.2, Sec. 3.4)             */
+#define BYSDF_FLAG_AXIAL (1u << 4)        /* wi (almost) parallel to the yarn
+                                             axis: no cross-section hit        */
+#define BYSDF_FLAG_BACKFACING (1u << 5)   /* wi below the fiber normal         */
+#define BYSDF_FLAG_SAMPLE_FAIL (1u << 6)  /* no valid direction was drawn      */
+#define BYSDF_FLAG_BAD_INPUT (1u << 9)    /* non-finite input, |h| > 1, a
+                                             direction off unit length by more
+                                             than 1e-3, or a bad type id       */
+
+/* --------------------------------------------------------- type parameters */
+/* One yarn type.  Geometry follows Sec. 3 (plies as helices around the yarn
+ * axis, fibers through a 1D table around each ply), appearance Sec. 4.1
+ * (Eq. 2-6) with the shadowing terms of Sec. 4.1.4. */
+typedef struct {
+    int32_t n_plies;          /* N_p, 1..8                                   */
+    int32_t fibers_per_ply;   /* M, 1..256 (fiber table)                      */
+    int32_t K;                /* forward quadrature nodes of Eq. 1, 1..16     */
+    int32_t n_iter;           /* ply fixed-point updates (Sec. 3.4), 0..16    */
+    int32_t tex_size;         /* texels of the fiber table, 2..4096           */
+    float ply_radius;         /* r_p in yarn radii, (0, 1]                    */
+    float ply_center_radius;  /* R_pc in yarn radii; R_pc + r_p <= 1          */
+    float fiber_radius;       /* r_f / r_p, (0, 1)                            */
+    float ply_twist;          /* alpha_p, helix angle to the yarn axis        */
+    float fiber_twist;        /* alpha_f at the outermost fiber radius        */
+    float eta;                /* refractive index, > 1                        */
+    float albedo[3];          /* body albedo k^B (RGB), >= 0                  */
+    float beta;               /* GGX roughness along the fiber, > 0          */
+    float aniso;              /* roughness across / along the fiber, > 0      */
+    float k_spec;             /* specular albedo k^S, >= 0                    */
+    float B;                  /* body energy share, [0, 1]                    */
+    float r;                  /* reflected share of the body energy, [0, 1]   */
+    float sigma_t;            /* extinction per yarn radius (Eq. 4), >= 0     */
+    float ply_density;        /* rho_p in [0, 1]: G_p = 1 - rho_p (1 - G_raw) */
+    float fiber_density;      /* rho_f in [0, 1]: G_f = 1 - rho_f (1 - G_raw) */
+    float shadow_halfwidth;   /* half width of the G_p window, (0, pi/2]      */
+} bysdf_type_params;
+
+typedef struct bysdf_types bysdf_types_t; /* opaque: params + fiber tables */
+
+/* Query arrays (device, n elements each).  shift0/shift1 may be NULL: the
+ * per-query shift of the forward quadrature lattice (defaults to 0). */
+typedef struct {
+    const int32_t* type_id;
+    const float *h, *u, *v;
+    const float *wi_x, *wi_y, *wi_z;
+    const float *wo_x, *wo_y, *wo_z;
+    const float *shift0, *shift1;
+} bysdf_query_soa;
+
+/* Evaluation outputs (device, n elements each).  E is the value times the
+ * cosine of wo with each lobe's own normal (f |cos|), in RGB; E_xS / E_yS
+ * are the two specular lobes (white), E_xB / E_yB the two body lobes (RGB),
+ * pdf the solid-angle density of bysdf_sample_pdf drawing wo. */
+typedef struct {
+    float *E_r, *E_g, *E_b;
+    float *E_xS, *E_yS;
+    float *E_xB_r, *E_xB_g, *E_xB_b;
+    float *E_yB_r, *E_yB_g, *E_yB_b;
+    float* pdf;
+    uint32_t* flags;
+} bysdf_eval_out_soa;
+
+/* Sampler inputs: like bysdf_query_soa without wo, plus three uniform
+ * numbers in [0, 1) per query (xi0 picks the lobe and node, xi1 and xi2 the
+ * direction). */
+typedef struct {
+    const int32_t* type_id;
+    const float *h, *u, *v;
+    const float *wi_x, *wi_y, *wi_z;
+    const float *xi0, *xi1, *xi2;
+    const float *shift0, *shift1;
+} bysdf_sample_soa;
+
+/* Sampler outputs.  lobe: 0 specular at x, 1 specular through the yarn to
+ * an exit point y, 2 body at x, 3 body at y, 4 pass-through (wo = -wi,
+ * weight 1, pdf 0), -1 bad input.  exit_*: the point the path continues
+ * from (x for lobes 0/2, the node's exit point y for 1/3), in the query's
+ * local frame (x, y in yarn radii, z = height along the yarn). */
+typedef struct {
+    float *wo_x, *wo_y, *wo_z;
+    float *w_r, *w_g, *w_b;   /* E(wo) / pdf(wo), RGB */
+    float* pdf;
+    float *exit_x, *exit_y, *exit_z;
+    int32_t* lobe;
+    int32_t* node;
+    uint32_t* flags;
+} bysdf_sample_out_soa;
+
+/* Library version string. */
+const char* bysdf_version(void);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* bysdf_last_error(void);
+
+/* Create a handle for n_types yarn types (host array p).  Validates every
+ * record, uploads the parameters and builds each distinct fiber table on
+ * the device in double precision (Sec. 3.5.1: per texel, the first fiber
+ * hit when looking radially inwards from the ply rim, its normal
+ * perturbation, normalised radius and unoccluded fraction).  Types with
+ * equal (fibers_per_ply, fiber_radius, tex_size) share one table.
+ * Synchronises `stream`.  On error *out is left NULL. */
+int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, bysdf_types_t** out,
+                       hipStream_t stream);
+
+/* Release a handle and its device memory (NULL is accepted). */
+int bysdf_types_destroy(bysdf_types_t* types);
+
+/* Number of types in a handle, or a negative error. */
+int32_t bysdf_types_count(const bysdf_types_t* types);
+
+/* Copy the fiber table of type `type_index` to host memory: tex_size x 3
+ * floats (dn, rho_hat, G_f) into `host_out` (capacity `cap` floats).
+ * Synchronous. */
+int bysdf_types_table(const bysdf_types_t* types, int32_t type_index, float* host_out,
+                      int64_t cap);
+
+/* Replace the eight differentiable parameters of every type from a DEVICE
+ * array theta[n_types][8] = (albedo r, g, b, beta, ply_twist, fiber_twist,
+ * ply_density, fiber_density), recomputing the derived constants on the
+ * device; tables are untouched (they do not depend on theta).  Values are
+ * clamped into their valid ranges.  Asynchronous on `stream`. */
+int bysdf_types_set_theta(bysdf_types_t* types, const float* theta, hipStream_t stream);
+
+/* Evaluate the BYSDF (Eq. 1: the four lobes of Eq. 2, 3, 5, 6 with Fresnel,
+ * GGX, ply and fiber shadowing, the forward lobes through K quadrature
+ * nodes) and the sampling pdf for n queries.  n == 0 is a no-op. */
+int bysdf_eval(const bysdf_types_t* types, const bysdf_query_soa* q, int64_t n,
+               const bysdf_eval_out_soa* out, hipStream_t stream);
+
+/* Draw one direction per query with the importance sampling of Sec. 4.1.5
+ * and return its direction, weight E/pdf, pdf, lobe, node and exit point. */
+int bysdf_sample_pdf(const bysdf_types_t* types, const bysdf_sample_soa* q, int64_t n,
+                     const bysdf_sample_out_soa* out, hipStream_t stream);
+
+/* White-furnace integral per block (Sec. 4.3): block b (n / block blocks)
+ * draws `block` directions for the hit of query b*block (type, h, u, v, wi,
+ * shift) with the xi of queries b*block .. b*block+block-1, and writes the
+ * mean and sample variance of the weights E/pdf (RGB) to mean[3*b + c] and
+ * var[3*b + c] (device).  block must be a multiple of 64 in [64, 1024];
+ * a trailing partial block is ignored.  Reductions run in a fixed order, so
+ * results are bitwise reproducible. */
+int bysdf_furnace_blocks(const bysdf_types_t* types, const bysdf_sample_soa* q, int64_t n,
+                         int32_t block, float* mean, float* var, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

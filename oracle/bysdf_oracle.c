@@ -401,7 +401,9 @@ static void trace_plies(const orc_params* p, double h, double u, double v, v3 wi
             if (shi >= 0.0 && slo <= g->s_exit) {
                 hit[k] = 1;
                 sk[k] = slo > 0.0 ? slo : 0.0;
-                if (fabs(slo) < m || fabs(slo - g->s_exit) < m) g->flags |= ORC_NEARTIE;
+                /* s* = max(s_lo, 0) is continuous: only the hit/miss ends
+                 * (s_hi = 0, s_lo = s_exit) and ties are decisions */
+                if (fabs(shi) < m || fabs(slo - g->s_exit) < m) g->flags |= ORC_NEARTIE;
             } else if (fabs(shi) < m || fabs(slo - g->s_exit) < m) {
                 g->flags |= ORC_NEARTIE;
             }

@@ -1,0 +1,276 @@
+"""Python binding of libbysdf.so (include/bysdf.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors (``device='cuda'``), used as plain
+device memory; the stream is torch's current stream unless one is given.
+The functions carry the names of the C entry points.
+
+Layouts (device tensors):
+  queries   type int32[n]; h, u, v float32[n]; wi, wo, xi float32[3, n];
+            shift float32[2, n] (optional)
+  eval      float32[12, n] rows E_r E_g E_b E_xS E_yS E_xB_rgb E_yB_rgb pdf,
+            flags int32[n] (bit pattern of the uint32 flags)
+  sample    float32[10, n] rows wo_xyz w_rgb pdf exit_xyz, lobe int32[n],
+            node int32[n], flags int32[n]
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbysdf.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_INVALID_PARAM = -2
+ERR_OOM = -3
+ERR_LAUNCH = -4
+ERR_UNSUPPORTED_DEVICE = -5
+
+FLAG_PASS_THROUGH = 1 << 0
+FLAG_AXIAL = 1 << 4
+FLAG_BACKFACING = 1 << 5
+FLAG_SAMPLE_FAIL = 1 << 6
+FLAG_BAD_INPUT = 1 << 9
+
+_vp = C.c_void_p
+
+
+class TypeParams(C.Structure):
+    _fields_ = [
+        ("n_plies", C.c_int32), ("fibers_per_ply", C.c_int32), ("K", C.c_int32),
+        ("n_iter", C.c_int32), ("tex_size", C.c_int32),
+        ("ply_radius", C.c_float), ("ply_center_radius", C.c_float),
+        ("fiber_radius", C.c_float), ("ply_twist", C.c_float), ("fiber_twist", C.c_float),
+        ("eta", C.c_float), ("albedo", C.c_float * 3), ("beta", C.c_float),
+        ("aniso", C.c_float), ("k_spec", C.c_float), ("B", C.c_float), ("r", C.c_float),
+        ("sigma_t", C.c_float), ("ply_density", C.c_float), ("fiber_density", C.c_float),
+        ("shadow_halfwidth", C.c_float),
+    ]
+
+
+class QuerySoA(C.Structure):
+    _fields_ = [(n, _vp) for n in ("type_id", "h", "u", "v", "wi_x", "wi_y", "wi_z",
+                                   "wo_x", "wo_y", "wo_z", "shift0", "shift1")]
+
+
+class EvalOutSoA(C.Structure):
+    _fields_ = [(n, _vp) for n in ("E_r", "E_g", "E_b", "E_xS", "E_yS", "E_xB_r", "E_xB_g",
+                                   "E_xB_b", "E_yB_r", "E_yB_g", "E_yB_b", "pdf", "flags")]
+
+
+class SampleSoA(C.Structure):
+    _fields_ = [(n, _vp) for n in ("type_id", "h", "u", "v", "wi_x", "wi_y", "wi_z",
+                                   "xi0", "xi1", "xi2", "shift0", "shift1")]
+
+
+class SampleOutSoA(C.Structure):
+    _fields_ = [(n, _vp) for n in ("wo_x", "wo_y", "wo_z", "w_r", "w_g", "w_b", "pdf",
+                                   "exit_x", "exit_y", "exit_z", "lobe", "node", "flags")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbysdf.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbysdf.so is not built: run `python -m paper_2401_12724_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.bysdf_version.restype = C.c_char_p
+        L.bysdf_last_error.restype = C.c_char_p
+        L.bysdf_types_create.argtypes = [C.POINTER(TypeParams), C.c_int32, C.POINTER(_vp), _vp]
+        L.bysdf_types_destroy.argtypes = [_vp]
+        L.bysdf_types_count.argtypes = [_vp]
+        L.bysdf_types_count.restype = C.c_int32
+        L.bysdf_types_table.argtypes = [_vp, C.c_int32, C.POINTER(C.c_float), C.c_int64]
+        L.bysdf_types_set_theta.argtypes = [_vp, _vp, _vp]
+        L.bysdf_eval.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, C.POINTER(EvalOutSoA), _vp]
+        L.bysdf_sample_pdf.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64,
+                                       C.POINTER(SampleOutSoA), _vp]
+        L.bysdf_furnace_blocks.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64, C.c_int32, _vp,
+                                           _vp, _vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc, name):
+    if rc != 0:
+        msg = lib().bysdf_last_error().decode()
+        raise RuntimeError("%s failed (%d): %s" % (name, rc, msg))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream) if not hasattr(stream, "cuda_stream") else stream.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def params_array(dicts):
+    n = len(dicts)
+    arr = (TypeParams * n)()
+    for i, d in enumerate(dicts):
+        p = arr[i]
+        for name, _ in TypeParams._fields_:
+            if name == "albedo":
+                for c in range(3):
+                    p.albedo[c] = float(d["albedo"][c])
+            else:
+                setattr(p, name, d[name])
+    return arr
+
+
+class Types:
+    """Owning wrapper of a bysdf_types_t handle."""
+
+    def __init__(self, handle, n_types, dicts):
+        self.handle = handle
+        self.n_types = n_types
+        self.dicts = dicts
+
+    def __del__(self):
+        # at interpreter shutdown module globals may already be gone
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.bysdf_types_destroy(self.handle)
+            self.handle = None
+
+
+def bysdf_version() -> str:
+    return lib().bysdf_version().decode()
+
+
+def bysdf_types_create(param_dicts, stream=None) -> Types:
+    arr = params_array(param_dicts)
+    h = _vp()
+    _check(lib().bysdf_types_create(arr, len(param_dicts), C.byref(h), _stream(stream)),
+           "bysdf_types_create")
+    return Types(h, len(param_dicts), [dict(d) for d in param_dicts])
+
+
+def bysdf_types_destroy(types: Types):
+    if types.handle:
+        _check(lib().bysdf_types_destroy(types.handle), "bysdf_types_destroy")
+        types.handle = None
+
+
+def bysdf_types_table(types: Types, type_index: int) -> np.ndarray:
+    nu = types.dicts[type_index]["tex_size"]
+    out = np.zeros((nu, 3), dtype=np.float32)
+    _check(lib().bysdf_types_table(types.handle, type_index,
+                                   out.ctypes.data_as(C.POINTER(C.c_float)), out.size),
+           "bysdf_types_table")
+    return out
+
+
+def bysdf_types_set_theta(types: Types, theta, stream=None):
+    """theta: float32 cuda tensor [n_types, 8] (contiguous)."""
+    assert theta.is_cuda and theta.dtype.itemsize == 4 and theta.is_contiguous()
+    assert theta.numel() == 8 * types.n_types
+    _check(lib().bysdf_types_set_theta(types.handle, theta.data_ptr(), _stream(stream)),
+           "bysdf_types_set_theta")
+
+
+def to_device(q: dict, device="cuda"):
+    """numpy query dict -> dict of contiguous torch tensors on the device."""
+    import torch
+    out = {}
+    for k, v in q.items():
+        if v is None:
+            out[k] = None
+            continue
+        a = np.ascontiguousarray(v)
+        dt = torch.int32 if a.dtype.kind in "iu" else torch.float32
+        out[k] = torch.from_numpy(a.astype(np.int32 if dt == torch.int32 else np.float32)).to(device)
+    return out
+
+
+def _qsoa(q):
+    s = QuerySoA()
+    s.type_id, s.h, s.u, s.v = _ptr(q["type"]), _ptr(q["h"]), _ptr(q["u"]), _ptr(q["v"])
+    wi, wo = q["wi"], q["wo"]
+    s.wi_x, s.wi_y, s.wi_z = _ptr(wi[0]), _ptr(wi[1]), _ptr(wi[2])
+    s.wo_x, s.wo_y, s.wo_z = _ptr(wo[0]), _ptr(wo[1]), _ptr(wo[2])
+    sh = q.get("shift")
+    s.shift0, s.shift1 = (_ptr(sh[0]), _ptr(sh[1])) if sh is not None else (None, None)
+    return s
+
+
+def _ssoa(q):
+    s = SampleSoA()
+    s.type_id, s.h, s.u, s.v = _ptr(q["type"]), _ptr(q["h"]), _ptr(q["u"]), _ptr(q["v"])
+    wi, xi = q["wi"], q["xi"]
+    s.wi_x, s.wi_y, s.wi_z = _ptr(wi[0]), _ptr(wi[1]), _ptr(wi[2])
+    s.xi0, s.xi1, s.xi2 = _ptr(xi[0]), _ptr(xi[1]), _ptr(xi[2])
+    sh = q.get("shift")
+    s.shift0, s.shift1 = (_ptr(sh[0]), _ptr(sh[1])) if sh is not None else (None, None)
+    return s
+
+
+def alloc_eval_out(n, device="cuda"):
+    import torch
+    return (torch.empty((12, n), dtype=torch.float32, device=device),
+            torch.empty(n, dtype=torch.int32, device=device))
+
+
+def bysdf_eval(types: Types, q: dict, out=None, stream=None):
+    """Returns (vals float32[12, n], flags int32[n])."""
+    n = int(q["h"].numel())
+    vals, flags = out if out is not None else alloc_eval_out(n, q["h"].device)
+    o = EvalOutSoA()
+    names = ("E_r", "E_g", "E_b", "E_xS", "E_yS", "E_xB_r", "E_xB_g", "E_xB_b", "E_yB_r",
+             "E_yB_g", "E_yB_b", "pdf")
+    for i, nm in enumerate(names):
+        setattr(o, nm, _ptr(vals[i]))
+    o.flags = _ptr(flags)
+    qs = _qsoa(q)
+    _check(lib().bysdf_eval(types.handle, C.byref(qs), n, C.byref(o), _stream(stream)),
+           "bysdf_eval")
+    return vals, flags
+
+
+def alloc_sample_out(n, device="cuda"):
+    import torch
+    return (torch.empty((10, n), dtype=torch.float32, device=device),
+            torch.empty(n, dtype=torch.int32, device=device),
+            torch.empty(n, dtype=torch.int32, device=device),
+            torch.empty(n, dtype=torch.int32, device=device))
+
+
+def bysdf_sample_pdf(types: Types, q: dict, out=None, stream=None):
+    """Returns (vals float32[10, n], lobe int32[n], node int32[n], flags int32[n])."""
+    n = int(q["h"].numel())
+    vals, lobe, node, flags = out if out is not None else alloc_sample_out(n, q["h"].device)
+    o = SampleOutSoA()
+    names = ("wo_x", "wo_y", "wo_z", "w_r", "w_g", "w_b", "pdf", "exit_x", "exit_y", "exit_z")
+    for i, nm in enumerate(names):
+        setattr(o, nm, _ptr(vals[i]))
+    o.lobe, o.node, o.flags = _ptr(lobe), _ptr(node), _ptr(flags)
+    qs = _ssoa(q)
+    _check(lib().bysdf_sample_pdf(types.handle, C.byref(qs), n, C.byref(o), _stream(stream)),
+           "bysdf_sample_pdf")
+    return vals, lobe, node, flags
+
+
+def bysdf_furnace_blocks(types: Types, q: dict, block: int = 256, mean=None, var=None,
+                         stream=None):
+    """Returns (mean float32[nb, 3], var float32[nb, 3])."""
+    import torch
+    n = int(q["h"].numel())
+    nb = n // block
+    dev = q["h"].device
+    mean = mean if mean is not None else torch.empty((nb, 3), dtype=torch.float32, device=dev)
+    var = var if var is not None else torch.empty((nb, 3), dtype=torch.float32, device=dev)
+    qs = _ssoa(q)
+    _check(lib().bysdf_furnace_blocks(types.handle, C.byref(qs), n, block, _ptr(mean), _ptr(var),
+                                      _stream(stream)), "bysdf_furnace_blocks")
+    return mean, var

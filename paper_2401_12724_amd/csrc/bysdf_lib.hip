@@ -1,0 +1,658 @@
+// bysdf_lib.hip -- gfx950 kernels and C ABI of libbysdf (see include/bysdf.h).
+//
+// Kernels
+//   k_fiber_table   one workgroup per texel, FP64: first fiber hit along the
+//                   radial ray (LDS argmin), occluder intervals per fiber,
+//                   exact cosine measure of their union by endpoint coverage
+//   k_eval          one query per lane, grid-stride; the fiber table of a
+//                   single-table handle is staged in LDS once per workgroup
+//   k_sample        the importance sampler, same layout
+//   k_furnace       one workgroup per furnace block; weights reduced through
+//                   LDS in a fixed tree order (bitwise reproducible)
+//   k_set_theta     refresh the differentiable parameters on the device
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bysdf.h"
+#include "bysdf_model.hpp"
+
+using namespace bysdf;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? BYSDF_ERR_OOM : BYSDF_ERR_LAUNCH,     \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                   \
+    } while (0)
+
+extern "C" const char* bysdf_version(void) { return "bysdf-gfx950 0.1"; }
+extern "C" const char* bysdf_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ handle
+constexpr int kMaxLdsTexels = 2048;  // 32 KB of float4 texels
+
+struct bysdf_types {
+    int32_t n_types = 0;
+    int32_t n_tables = 0;
+    int32_t max_plies = 0, max_K = 0;
+    int32_t single_table = 0;   // every type uses table 0
+    int32_t table_texels = 0;   // texels of table 0 (LDS staging size)
+    int device = 0;
+    TypeRec* d_types = nullptr;
+    float4* d_tables = nullptr;
+    std::vector<TypeRec> h_types;
+    std::vector<int32_t> h_table_size;
+    std::vector<int32_t> h_table_off;
+    std::vector<int32_t> h_type_table;
+};
+
+struct TabPtr {
+    const float4* p;
+    __host__ __device__ float4 operator()(int i) const { return p[i]; }
+};
+
+// derived constants of one record (double precision), host and device
+__host__ __device__ static void fill_derived(TypeRec& t)
+{
+    double wp = t.Rpc > 0.0 ? tan(t.ply_twist) / t.Rpc : 0.0;
+    t.slope = t.Rpc * wp;
+    t.vply_scale = sqrt(1.0 + t.slope * t.slope);
+    t.tnorm_inv = 1.0 / t.vply_scale;
+    t.wp_turns = wp * kInvTwoPi;
+    t.tan_af = tan(t.fiber_twist);
+    t.wf_turns = t.tan_af / ((1.0 - t.rho_f_geom) * t.rp) * kInvTwoPi;
+    t.inv_np = 1.0 / t.n_plies;
+}
+
+static int validate(const bysdf_type_params& p, int i)
+{
+    auto bad = [&](const char* what) {
+        return fail(BYSDF_ERR_INVALID_PARAM, "type %d: %s", i, what);
+    };
+    if (p.n_plies < 1 || p.n_plies > kMaxPlies) return bad("n_plies must be in 1..8");
+    if (p.fibers_per_ply < 1 || p.fibers_per_ply > 256) return bad("fibers_per_ply must be in 1..256");
+    if (p.K < 1 || p.K > kMaxNodes) return bad("K must be in 1..16");
+    if (p.n_iter < 0 || p.n_iter > 16) return bad("n_iter must be in 0..16");
+    if (p.tex_size < 2 || p.tex_size > 4096) return bad("tex_size must be in 2..4096");
+    if (!(p.ply_radius > 0.0f && p.ply_radius <= 1.0f)) return bad("ply_radius must be in (0, 1]");
+    if (!(p.ply_center_radius >= 0.0f)) return bad("ply_center_radius must be >= 0");
+    if (!(p.ply_center_radius + p.ply_radius <= 1.0f + 1e-6f))
+        return bad("ply_center_radius + ply_radius must be <= 1");
+    if (p.n_plies > 1 && !(p.ply_center_radius > 0.0f)) return bad("several plies need ply_center_radius > 0");
+    if (!(p.fiber_radius > 0.0f && p.fiber_radius < 1.0f)) return bad("fiber_radius must be in (0, 1)");
+    if (!(fabsf(p.ply_twist) < 1.5f)) return bad("|ply_twist| must be < 1.5 rad");
+    if (!(fabsf(p.fiber_twist) < 1.5f)) return bad("|fiber_twist| must be < 1.5 rad");
+    if (!(p.eta > 1.0f && p.eta < 10.0f)) return bad("eta must be in (1, 10)");
+    for (int c = 0; c < 3; ++c)
+        if (!(p.albedo[c] >= 0.0f && p.albedo[c] < 1e6f)) return bad("albedo must be >= 0");
+    if (!(p.beta > 0.0f && p.beta < 10.0f)) return bad("beta must be in (0, 10)");
+    if (!(p.aniso > 0.0f && p.aniso < 100.0f)) return bad("aniso must be in (0, 100)");
+    if (!(p.k_spec >= 0.0f && p.k_spec < 1e6f)) return bad("k_spec must be >= 0");
+    if (!(p.B >= 0.0f && p.B <= 1.0f)) return bad("B must be in [0, 1]");
+    if (!(p.r >= 0.0f && p.r <= 1.0f)) return bad("r must be in [0, 1]");
+    if (!(p.sigma_t >= 0.0f && p.sigma_t < 1e6f)) return bad("sigma_t must be >= 0");
+    if (!(p.ply_density >= 0.0f && p.ply_density <= 1.0f)) return bad("ply_density must be in [0, 1]");
+    if (!(p.fiber_density >= 0.0f && p.fiber_density <= 1.0f)) return bad("fiber_density must be in [0, 1]");
+    if (!(p.shadow_halfwidth > 0.0f && p.shadow_halfwidth <= 1.5707964f))
+        return bad("shadow_halfwidth must be in (0, pi/2]");
+    return 0;
+}
+
+static TypeRec make_rec(const bysdf_type_params& p)
+{
+    TypeRec t;
+    memset(&t, 0, sizeof(t));
+    t.n_plies = p.n_plies;
+    t.K = p.K;
+    t.n_iter = p.n_iter;
+    t.tex_size = p.tex_size;
+    t.rp = p.ply_radius;
+    t.Rpc = p.ply_center_radius;
+    t.ply_twist = p.ply_twist;
+    t.fiber_twist = p.fiber_twist;
+    t.rho_f_geom = p.fiber_radius;
+    t.beta = p.beta;
+    t.aniso = p.aniso;
+    t.eta = p.eta;
+    for (int c = 0; c < 3; ++c) t.albedo[c] = p.albedo[c];
+    t.k_spec = p.k_spec;
+    t.B = p.B;
+    t.r = p.r;
+    t.sigma_t = p.sigma_t;
+    t.ply_density = p.ply_density;
+    t.fiber_density = p.fiber_density;
+    t.shadow_hw = p.shadow_halfwidth;
+    fill_derived(t);
+    return t;
+}
+
+// ------------------------------------------------------------------ K1 tables
+// One workgroup per texel (Sec. 3.5.1).  Fiber centres: Vogel spiral of M
+// centres within radius 1 - rho (ply radii).  The texel looks radially
+// inwards from the ply rim; lane j tests fiber j.
+__global__ __launch_bounds__(256) void k_fiber_table(int M, double rho, int Nu, float4* out)
+{
+    __shared__ double s_val[256];
+    __shared__ int s_idx[256];
+    __shared__ double s_lo[256], s_hi[256];
+    __shared__ unsigned char s_ok[256];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const double gold = kPi * (3.0 - sqrt(5.0));
+    double ze = kTwoPi * (i + 0.5) / Nu;
+    double ex = cos(ze), ey = sin(ze);
+    double ox = (1.0 + 1e-9) * ex, oy = (1.0 + 1e-9) * ey;
+    double fx = 0.0, fy = 0.0, s = INFINITY;
+    if (tid < M) {
+        double rj = (1.0 - rho) * sqrt((tid + 0.5) / M);
+        fx = rj * cos(tid * gold);
+        fy = rj * sin(tid * gold);
+        double wx = ox - fx, wy = oy - fy;
+        double b = -(wx * ex + wy * ey);
+        double c = wx * wx + wy * wy - rho * rho;
+        double disc = b * b - c;
+        if (disc >= 0.0) {
+            double sh = -b - sqrt(disc);
+            if (sh >= 0.0) s = sh;
+        }
+    }
+    s_val[tid] = s;
+    s_idx[tid] = tid;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) {
+            double a = s_val[tid], b = s_val[tid + st];
+            if (b < a || (b == a && s_idx[tid + st] < s_idx[tid])) {
+                s_val[tid] = b;
+                s_idx[tid] = s_idx[tid + st];
+            }
+        }
+        __syncthreads();
+    }
+    const double sb = s_val[0];
+    const int jb = s_idx[0];
+    if (!(sb < INFINITY)) {
+        if (tid == 0) out[i] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+        return;
+    }
+    double rb = (1.0 - rho) * sqrt((jb + 0.5) / M);
+    double bx = rb * cos(jb * gold), by = rb * sin(jb * gold);
+    double qx = ox - sb * ex, qy = oy - sb * ey;
+    double nx = (qx - bx) / rho, ny = (qy - by) / rho;
+    bool ok = false;
+    double lo = 0.0, hi = 0.0;
+    if (tid < M && tid != jb) {
+        double wx = fx - qx, wy = fy - qy;
+        double dist = sqrt(wx * wx + wy * wy);
+        double cen = atan2(nx * wy - ny * wx, nx * wx + ny * wy);
+        double rt = rho / dist;
+        double half = asin(rt < 1.0 ? rt : 1.0);
+        lo = fmax(cen - half, -0.5 * kPi);
+        hi = fmin(cen + half, 0.5 * kPi);
+        ok = hi > lo;
+    }
+    s_lo[tid] = lo;
+    s_hi[tid] = hi;
+    s_ok[tid] = ok;
+    __syncthreads();
+    // Cosine measure of the union: every merged piece has exactly one lower
+    // end and one upper end that no other interval covers (ties go to the
+    // lower index); sum sin(upper) - sin(lower) over those ends.
+    double contrib = 0.0;
+    if (ok) {
+        bool lo_cov = false, hi_cov = false;
+        for (int j = 0; j < M; ++j) {
+            if (j == tid || !s_ok[j]) continue;
+            double lj = s_lo[j], hj = s_hi[j];
+            if ((lj < lo && lo <= hj) || (lj == lo && j < tid)) lo_cov = true;
+            if ((lj <= hi && hi < hj) || (hj == hi && lj <= hi && j < tid)) hi_cov = true;
+        }
+        if (!hi_cov) contrib += sin(hi);
+        if (!lo_cov) contrib -= sin(lo);
+    }
+    s_val[tid] = contrib;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) s_val[tid] += s_val[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double blocked = 0.5 * s_val[0];
+        double gf = blocked < 1.0 ? 1.0 - blocked : 0.0;
+        double dn = atan2(ex * ny - ey * nx, ex * nx + ey * ny);
+        double rh = sqrt(bx * bx + by * by) / (1.0 - rho);
+        out[i] = make_float4((float)dn, (float)rh, (float)gf, 0.0f);
+    }
+}
+
+// ------------------------------------------------------------------ eval
+struct QPtrs {
+    const int32_t* type;
+    const float *h, *u, *v, *wix, *wiy, *wiz, *wox, *woy, *woz, *s0, *s1;
+};
+struct OPtrs {
+    float *Er, *Eg, *Eb, *ExS, *EyS, *ExBr, *ExBg, *ExBb, *EyBr, *EyBg, *EyBb, *pdf;
+    uint32_t* flags;
+};
+
+constexpr int kBlock = 256;
+
+template <bool kLds>
+__global__ __launch_bounds__(kBlock) void k_eval(const TypeRec* __restrict__ types, int n_types,
+                                                 const float4* __restrict__ tables, int lds_texels,
+                                                 QPtrs q, OPtrs o, int64_t n)
+{
+    extern __shared__ float4 s_tab[];
+    if (kLds) {
+        for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
+        __syncthreads();
+    }
+    int cur = -1;
+    Derived<double, float> P;
+    TabPtr tab;
+    tab.p = tables;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int t = q.type[i];
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+        float h = q.h[i], u = q.u[i], v = q.v[i];
+        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+        fl |= check_inputs(h, u, v, wi) | check_dir(wo);
+        EvalOut<float> e;
+        for (int c = 0; c < 3; ++c) e.E[c] = e.ExB[c] = e.EyB[c] = 0.0f;
+        e.ExS = e.EyS = e.pdf = 0.0f;
+        if (!fl) {
+            if (t != cur) {
+                const TypeRec rec = types[t];
+                P = derive(rec);
+                tab.p = kLds ? s_tab : tables + rec.table_off;
+                cur = t;
+            }
+            XState<double, float> X;
+            state_at_x(P, tab, h, u, v, wi, X);
+            fl = X.ph.flags;
+            if (!X.ph.pass) {
+                if (!(X.mu_i > 0.0f)) fl |= F_BACKFACING;
+                float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+                V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
+                lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
+            }
+        }
+        o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
+        o.ExS[i] = e.ExS; o.EyS[i] = e.EyS;
+        o.ExBr[i] = e.ExB[0]; o.ExBg[i] = e.ExB[1]; o.ExBb[i] = e.ExB[2];
+        o.EyBr[i] = e.EyB[0]; o.EyBg[i] = e.EyB[1]; o.EyBb[i] = e.EyB[2];
+        o.pdf[i] = e.pdf;
+        o.flags[i] = fl;
+    }
+}
+
+// ------------------------------------------------------------------ sample
+struct SPtrs {
+    const int32_t* type;
+    const float *h, *u, *v, *wix, *wiy, *wiz, *xi0, *xi1, *xi2, *s0, *s1;
+};
+struct SOPtrs {
+    float *wox, *woy, *woz, *wr, *wg, *wb, *pdf, *exx, *exy, *exz;
+    int32_t *lobe, *node;
+    uint32_t* flags;
+};
+
+template <bool kLds>
+__global__ __launch_bounds__(kBlock) void k_sample(const TypeRec* __restrict__ types, int n_types,
+                                                   const float4* __restrict__ tables,
+                                                   int lds_texels, SPtrs q, SOPtrs o, int64_t n)
+{
+    extern __shared__ float4 s_tab[];
+    if (kLds) {
+        for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
+        __syncthreads();
+    }
+    int cur = -1;
+    Derived<double, float> P;
+    TabPtr tab;
+    tab.p = tables;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int t = q.type[i];
+        SampleOut<float> so;
+        for (int c = 0; c < 3; ++c) so.wo[c] = so.wgt[c] = so.ex[c] = 0.0f;
+        so.pdf = 0.0f;
+        so.lobe = -1;
+        so.node = 0;
+        uint32_t fl;
+        if (t < 0 || t >= n_types) {
+            fl = F_BAD_INPUT;
+        } else {
+            if (t != cur) {
+                const TypeRec rec = types[t];
+                P = derive(rec);
+                tab.p = kLds ? s_tab : tables + rec.table_off;
+                cur = t;
+            }
+            V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+            fl = sample_query(P, tab, q.h[i], q.u[i], q.v[i], wi, q.xi0[i], q.xi1[i], q.xi2[i], s0,
+                              s1, q.s0 != nullptr, so);
+        }
+        o.wox[i] = so.wo[0]; o.woy[i] = so.wo[1]; o.woz[i] = so.wo[2];
+        o.wr[i] = so.wgt[0]; o.wg[i] = so.wgt[1]; o.wb[i] = so.wgt[2];
+        o.pdf[i] = so.pdf;
+        o.exx[i] = so.ex[0]; o.exy[i] = so.ex[1]; o.exz[i] = so.ex[2];
+        o.lobe[i] = so.lobe;
+        o.node[i] = so.node;
+        o.flags[i] = fl;
+    }
+}
+
+// ------------------------------------------------------------------ furnace
+// One workgroup per furnace block; lane j draws with the xi of query
+// b*block + j for the hit of query b*block.  Sum and sum of squared
+// deviations reduce through LDS in a fixed tree order.
+__global__ __launch_bounds__(1024) void k_furnace(const TypeRec* __restrict__ types, int n_types,
+                                                  const float4* __restrict__ tables, SPtrs q,
+                                                  int64_t n_blocks, float* mean, float* var)
+{
+    __shared__ float s_red[3][1024];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t q0 = b * B, qi = q0 + tid;
+    int t = q.type[q0];
+    float w[3] = {0.0f, 0.0f, 0.0f};
+    if (t >= 0 && t < n_types) {
+        const TypeRec rec = types[t];
+        Derived<double, float> P = derive(rec);
+        TabPtr tab;
+        tab.p = tables + rec.table_off;
+        V3<float> wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
+        float s0 = q.s0 ? q.s0[q0] : 0.0f, s1 = q.s1 ? q.s1[q0] : 0.0f;
+        SampleOut<float> so;
+        sample_query(P, tab, q.h[q0], q.u[q0], q.v[q0], wi, q.xi0[qi], q.xi1[qi], q.xi2[qi], s0, s1,
+                     q.s0 != nullptr, so);
+        for (int c = 0; c < 3; ++c) w[c] = so.wgt[c];
+    }
+    for (int c = 0; c < 3; ++c) s_red[c][tid] = w[c];
+    __syncthreads();
+    for (int st = B / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int c = 0; c < 3; ++c) s_red[c][tid] += s_red[c][tid + st];
+        __syncthreads();
+    }
+    float m[3];
+    for (int c = 0; c < 3; ++c) m[c] = s_red[c][0] / (float)B;
+    __syncthreads();
+    for (int c = 0; c < 3; ++c) {
+        float d = w[c] - m[c];
+        s_red[c][tid] = d * d;
+    }
+    __syncthreads();
+    for (int st = B / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int c = 0; c < 3; ++c) s_red[c][tid] += s_red[c][tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int c = 0; c < 3; ++c) {
+            mean[3 * b + c] = m[c];
+            var[3 * b + c] = s_red[c][0] / (float)(B - 1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ theta
+__global__ void k_set_theta(TypeRec* types, const float* theta, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    TypeRec t = types[i];
+    const float* th = theta + 8 * i;
+    for (int c = 0; c < 3; ++c) t.albedo[c] = fmaxf(th[c], 0.0f);
+    t.beta = fmin(fmax((double)th[3], 1e-4), 10.0);
+    t.ply_twist = fmin(fmax((double)th[4], -1.5), 1.5);
+    t.fiber_twist = fmin(fmax((double)th[5], -1.5), 1.5);
+    t.ply_density = fminf(fmaxf(th[6], 0.0f), 1.0f);
+    t.fiber_density = fminf(fmaxf(th[7], 0.0f), 1.0f);
+    fill_derived(t);
+    types[i] = t;
+}
+
+// ------------------------------------------------------------------ host API
+static bool aligned4(const void* p) { return p && ((uintptr_t)p & 3u) == 0; }
+
+extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, bysdf_types_t** out,
+                                  hipStream_t stream)
+{
+    if (!out) return fail(BYSDF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || n_types < 1) return fail(BYSDF_ERR_INVALID_ARG, "need p != NULL and n_types >= 1");
+    for (int i = 0; i < n_types; ++i) {
+        int rc = validate(p[i], i);
+        if (rc) return rc;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BYSDF_ERR_UNSUPPORTED_DEVICE, "device %d is %s, library is built for gfx950", dev,
+                    prop.gcnArchName);
+    bysdf_types* h = new bysdf_types();
+    h->n_types = n_types;
+    h->device = dev;
+    std::map<std::tuple<int, float, int>, int> uniq;
+    int32_t texels = 0;
+    std::vector<std::tuple<int, double, int>> jobs;
+    for (int i = 0; i < n_types; ++i) {
+        auto key = std::make_tuple(p[i].fibers_per_ply, p[i].fiber_radius, p[i].tex_size);
+        auto it = uniq.find(key);
+        int ti;
+        if (it == uniq.end()) {
+            ti = (int)h->h_table_size.size();
+            uniq[key] = ti;
+            h->h_table_size.push_back(p[i].tex_size);
+            h->h_table_off.push_back(texels);
+            texels += p[i].tex_size;
+            jobs.emplace_back(p[i].fibers_per_ply, (double)p[i].fiber_radius, p[i].tex_size);
+        } else {
+            ti = it->second;
+        }
+        TypeRec r = make_rec(p[i]);
+        r.table_off = h->h_table_off[ti];
+        h->h_types.push_back(r);
+        h->h_type_table.push_back(ti);
+        h->max_plies = std::max(h->max_plies, p[i].n_plies);
+        h->max_K = std::max(h->max_K, p[i].K);
+    }
+    h->n_tables = (int32_t)h->h_table_size.size();
+    // stage the table in LDS when one table serves every type and fits 32 KB
+    h->single_table = h->n_tables == 1 && h->h_table_size[0] <= kMaxLdsTexels;
+    h->table_texels = h->h_table_size[0];
+    auto cleanup = [&](int rc) {
+        if (h->d_types) (void)hipFree(h->d_types);
+        if (h->d_tables) (void)hipFree(h->d_tables);
+        delete h;
+        return rc;
+    };
+    hipError_t e = hipMalloc(&h->d_types, sizeof(TypeRec) * n_types);
+    if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_OOM, "hipMalloc(types): %s", hipGetErrorString(e)));
+    e = hipMalloc(&h->d_tables, sizeof(float4) * texels);
+    if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_OOM, "hipMalloc(tables): %s", hipGetErrorString(e)));
+    e = hipMemcpyAsync(h->d_types, h->h_types.data(), sizeof(TypeRec) * n_types, hipMemcpyHostToDevice,
+                       stream);
+    if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_LAUNCH, "upload: %s", hipGetErrorString(e)));
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        int M = std::get<0>(jobs[j]), Nu = std::get<2>(jobs[j]);
+        double rho = std::get<1>(jobs[j]);
+        hipLaunchKernelGGL(k_fiber_table, dim3(Nu), dim3(256), 0, stream, M, rho, Nu,
+                           h->d_tables + h->h_table_off[j]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_LAUNCH, "k_fiber_table: %s", hipGetErrorString(e)));
+    }
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_LAUNCH, "table build: %s", hipGetErrorString(e)));
+    *out = h;
+    return BYSDF_OK;
+}
+
+extern "C" int bysdf_types_destroy(bysdf_types_t* h)
+{
+    if (!h) return BYSDF_OK;
+    if (h->d_types) (void)hipFree(h->d_types);
+    if (h->d_tables) (void)hipFree(h->d_tables);
+    delete h;
+    return BYSDF_OK;
+}
+
+extern "C" int32_t bysdf_types_count(const bysdf_types_t* h)
+{
+    if (!h) return fail(BYSDF_ERR_INVALID_ARG, "types is NULL");
+    return h->n_types;
+}
+
+extern "C" int bysdf_types_table(const bysdf_types_t* h, int32_t ti, float* host_out, int64_t cap)
+{
+    if (!h || !host_out) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (ti < 0 || ti >= h->n_types) return fail(BYSDF_ERR_INVALID_ARG, "type index out of range");
+    int tb = h->h_type_table[ti];
+    int Nu = h->h_table_size[tb];
+    if (cap < 3LL * Nu) return fail(BYSDF_ERR_INVALID_ARG, "host_out needs %d floats", 3 * Nu);
+    std::vector<float4> tmp(Nu);
+    HIP_TRY(hipMemcpy(tmp.data(), h->d_tables + h->h_table_off[tb], sizeof(float4) * Nu,
+                      hipMemcpyDeviceToHost));
+    for (int i = 0; i < Nu; ++i) {
+        host_out[3 * i] = tmp[i].x;
+        host_out[3 * i + 1] = tmp[i].y;
+        host_out[3 * i + 2] = tmp[i].z;
+    }
+    return BYSDF_OK;
+}
+
+extern "C" int bysdf_types_set_theta(bysdf_types_t* h, const float* theta, hipStream_t stream)
+{
+    if (!h || !aligned4(theta)) return fail(BYSDF_ERR_INVALID_ARG, "NULL or misaligned argument");
+    int nb = (h->n_types + 255) / 256;
+    hipLaunchKernelGGL(k_set_theta, dim3(nb), dim3(256), 0, stream, h->d_types, theta, h->n_types);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+static int grid_for(int64_t n)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    const int64_t cap = 256 * 16;  // 16 workgroups per CU keeps LDS staging amortised
+    return (int)(g < cap ? g : cap);
+}
+
+extern "C" int bysdf_eval(const bysdf_types_t* h, const bysdf_query_soa* q, int64_t n,
+                          const bysdf_eval_out_soa* o, hipStream_t stream)
+{
+    if (!h || !q || !o) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return BYSDF_OK;
+    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y,
+                          q->wo_z, o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g,
+                          o->E_xB_b, o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query/output pointer is NULL or misaligned");
+    if ((q->shift0 == nullptr) != (q->shift1 == nullptr) ||
+        (q->shift0 && (!aligned4(q->shift0) || !aligned4(q->shift1))))
+        return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
+    QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
+             q->shift0, q->shift1};
+    OPtrs op{o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
+             o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    int grid = grid_for(n);
+    if (h->single_table) {
+        size_t lds = sizeof(float4) * h->table_texels;
+        hipLaunchKernelGGL(k_eval<true>, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                           h->d_tables, h->table_texels, qp, op, n);
+    } else {
+        hipLaunchKernelGGL(k_eval<false>, dim3(grid), dim3(kBlock), 0, stream, h->d_types, h->n_types,
+                           h->d_tables, 0, qp, op, n);
+    }
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+static int check_sample_args(const bysdf_sample_soa* q)
+{
+    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query pointer is NULL or misaligned");
+    if ((q->shift0 == nullptr) != (q->shift1 == nullptr) ||
+        (q->shift0 && (!aligned4(q->shift0) || !aligned4(q->shift1))))
+        return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
+    return 0;
+}
+
+extern "C" int bysdf_sample_pdf(const bysdf_types_t* h, const bysdf_sample_soa* q, int64_t n,
+                                const bysdf_sample_out_soa* o, hipStream_t stream)
+{
+    if (!h || !q || !o) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return BYSDF_OK;
+    if (int rc = check_sample_args(q)) return rc;
+    const void* need[] = {o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x,
+                          o->exit_y, o->exit_z, o->lobe, o->node, o->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "an output pointer is NULL or misaligned");
+    SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
+             q->shift0, q->shift1};
+    SOPtrs op{o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x, o->exit_y,
+              o->exit_z, o->lobe, o->node, o->flags};
+    int grid = grid_for(n);
+    if (h->single_table) {
+        size_t lds = sizeof(float4) * h->table_texels;
+        hipLaunchKernelGGL(k_sample<true>, dim3(grid), dim3(kBlock), lds, stream, h->d_types,
+                           h->n_types, h->d_tables, h->table_texels, sp, op, n);
+    } else {
+        hipLaunchKernelGGL(k_sample<false>, dim3(grid), dim3(kBlock), 0, stream, h->d_types,
+                           h->n_types, h->d_tables, 0, sp, op, n);
+    }
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_soa* q, int64_t n,
+                                    int32_t block, float* mean, float* var, hipStream_t stream)
+{
+    if (!h || !q) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (block < 64 || block > 1024 || block % 64)
+        return fail(BYSDF_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+    int64_t nb = n / block;
+    if (nb == 0) return BYSDF_OK;
+    if (int rc = check_sample_args(q)) return rc;
+    if (!aligned4(mean) || !aligned4(var)) return fail(BYSDF_ERR_INVALID_ARG, "mean/var NULL or misaligned");
+    if (nb > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many blocks");
+    SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
+             q->shift0, q->shift1};
+    hipLaunchKernelGGL(k_furnace, dim3((unsigned)nb), dim3(block), 0, stream, h->d_types, h->n_types,
+                       h->d_tables, sp, nb, mean, var);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}

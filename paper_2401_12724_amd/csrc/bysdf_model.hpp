@@ -1,0 +1,763 @@
+// bysdf_model.hpp -- per-query BYSDF model (arXiv 2401.12724, Sec. 3-4) for
+// one lane of a gfx950 wavefront.
+//
+// Precision split: the geometry chain (yarn hit, ply-centre fixed point,
+// phases, frames, forward chords) runs in the geometry scalar G, the lobes
+// in the shading scalar S.  The fiber normal turns by ~pi across one fiber,
+// so the specular lobes amplify a phase error by a few hundred; phases of
+// scene-scale v (hundreds of yarn radii) must not be rounded to float.
+//
+// Per-ply state lives in register arrays indexed by compile-time constants
+// (fully unrolled loops up to kMaxPlies with a runtime guard).
+#pragma once
+
+#include "bysdf_math.hpp"
+
+namespace bysdf {
+
+constexpr int kMaxPlies = 8;
+constexpr int kMaxNodes = 16;
+
+// flag bits (public numbering; see include/bysdf.h)
+constexpr uint32_t F_PASS_THROUGH = 1u << 0;
+constexpr uint32_t F_AXIAL = 1u << 4;
+constexpr uint32_t F_BACKFACING = 1u << 5;
+constexpr uint32_t F_SAMPLE_FAIL = 1u << 6;
+constexpr uint32_t F_BAD_INPUT = 1u << 9;
+
+// Per-type record resident in device memory (host fills it once).
+struct TypeRec {
+    int32_t n_plies, K, n_iter, tex_size, table_off, pad0;
+    // primary parameters
+    double rp, Rpc, ply_twist, fiber_twist, rho_f_geom;  // rho_f_geom = r_f / r_p
+    double beta, aniso, eta;
+    float albedo[3], k_spec, B, r, sigma_t, ply_density, fiber_density, shadow_hw;
+    // derived (host, double precision)
+    double slope;      // R_pc * w_p = tan(alpha_p) (0 when R_pc = 0)
+    double wp_turns;   // w_p / 2pi, turns per unit length along the yarn
+    double tnorm_inv;  // 1 / sqrt(1 + slope^2)
+    double vply_scale; // sqrt(1 + slope^2): ply arc length per yarn length
+    double wf_turns;   // w_f / 2pi with w_f = tan(alpha_f) / ((1 - r_f/r_p) r_p)
+    double tan_af;
+    double inv_np;
+};
+
+// Scalars one query needs, in the kernel's scalar types.
+template <class G, class S> struct Derived {
+    int Np, K, N_it, Nu;
+    double inv_np;
+    G rp, Rpc, slope, wp_turns, tnorm_inv, vply_scale, wf_turns, tan_af;
+    G ax_g, ay_g, eta_g;
+    S ax, ay, eta, kS, B, r, sigma_t, rho_p, rho_f, dP;
+    S alb[3];
+    S rp_s, Rpc_s;
+};
+
+__host__ __device__ inline Derived<double, float> derive(const TypeRec& t)
+{
+    Derived<double, float> d;
+    d.Np = t.n_plies; d.K = t.K; d.N_it = t.n_iter; d.Nu = t.tex_size;
+    d.inv_np = t.inv_np;
+    d.rp = t.rp; d.Rpc = t.Rpc; d.slope = t.slope; d.wp_turns = t.wp_turns;
+    d.tnorm_inv = t.tnorm_inv; d.vply_scale = t.vply_scale; d.wf_turns = t.wf_turns;
+    d.tan_af = t.tan_af;
+    d.ax_g = t.beta; d.ay_g = t.beta * t.aniso; d.eta_g = t.eta;
+    d.ax = (float)t.beta; d.ay = (float)(t.beta * t.aniso); d.eta = (float)t.eta;
+    d.kS = t.k_spec; d.B = t.B; d.r = t.r; d.sigma_t = t.sigma_t;
+    d.rho_p = t.ply_density; d.rho_f = t.fiber_density; d.dP = t.shadow_hw;
+    for (int c = 0; c < 3; ++c) d.alb[c] = t.albedo[c];
+    d.rp_s = (float)t.rp; d.Rpc_s = (float)t.Rpc;
+    return d;
+}
+
+// ---------------------------------------------------------------- microfacets
+
+// Dielectric Fresnel for cosine c >= 0 on the index-1 side of an interface
+// of relative index e; total internal reflection returns 1.
+template <class S> __host__ __device__ inline S fresnel(S c, S e)
+{
+    S s2t = (S(1) - c * c) / (e * e);
+    if (val(s2t) >= 1.0f) return S(1);
+    S ct = sqrt_(S(1) - s2t);
+    S rs = (c - e * ct) / (c + e * ct);
+    S rpp = (e * c - ct) / (e * c + ct);
+    return S(0.5f) * (rs * rs + rpp * rpp);
+}
+
+// Fresnel transmittance 1 - F written without the cancellation of 1 - F
+// near total internal reflection: 1 - r^2 = 4 c e c_t / (c + e c_t)^2 per
+// polarisation.
+template <class S> __host__ __device__ inline S fresnel_T(S c, S e)
+{
+    S s2t = (S(1) - c * c) / (e * e);
+    if (val(s2t) >= 1.0f) return S(0);
+    S ct = sqrt_(S(1) - s2t);
+    S a = c + e * ct, b = e * c + ct;
+    return S(2) * e * c * ct * (S(1) / (a * a) + S(1) / (b * b));
+}
+
+template <class S> __host__ __device__ inline S ggx_D(const V3<S>& m, S ax, S ay)
+{
+    if (!(val(m.z) > 0.0f)) return S(0);
+    S qx = m.x / ax, qy = m.y / ay;
+    S t = qx * qx + qy * qy + m.z * m.z;
+    return S(1) / (S(float(kPi)) * ax * ay * t * t);
+}
+
+template <class S> __host__ __device__ inline S smith_G1(const V3<S>& w, const V3<S>& m, S ax, S ay)
+{
+    S wm = dot(w, m);
+    if (!(val(wm) * val(w.z) > 0.0f)) return S(0);
+    S tx = ax * w.x, ty = ay * w.y;
+    S a2t2 = (tx * tx + ty * ty) / (w.z * w.z);
+    return S(2) / (S(1) + sqrt_(S(1) + a2t2));
+}
+
+// Visible-normal sampling of GGX (Heitz 2018): stretch the view to unit
+// roughness, build a basis around it, sample the projected hemisphere disc
+// with its far half compressed according to the view elevation, lift,
+// unstretch.  w local with w.z > 0; u1, u2 in [0, 1).
+template <class T> __host__ __device__ inline V3<T> sample_vndf(const V3<T>& w, T ax, T ay, T u1, T u2)
+{
+    V3<T> vh = normalize(mk3<T>(ax * w.x, ay * w.y, w.z));
+    T l2 = vh.x * vh.x + vh.y * vh.y;
+    V3<T> b1 = val(l2) > 0.0 ? mk3<T>(-vh.y, vh.x, T(0)) * (T(1) / sqrt_(l2))
+                             : mk3<T>(T(1), T(0), T(0));
+    V3<T> b2 = cross(vh, b1);
+    T rad = sqrt_(u1);
+    T ang = T(kTwoPi) * u2;
+    T d1 = rad * cos_(ang);
+    T d2 = rad * sin_(ang);
+    T blend = T(0.5) * (T(1) + vh.z);
+    d2 = (T(1) - blend) * sqrt_(T(1) - d1 * d1) + blend * d2;
+    T h2 = T(1) - d1 * d1 - d2 * d2;
+    T hz = val(h2) > 0.0 ? sqrt_(h2) : T(0);
+    V3<T> nh = b1 * d1 + b2 * d2 + vh * hz;
+    T nz = val(nh.z) > 0.0 ? nh.z : T(0);
+    return normalize(mk3<T>(ax * nh.x, ay * nh.y, nz));
+}
+
+// Lommel-Seeliger single-scatter albedo 1/2 [1 - mu ln(1 + 1/mu)].
+template <class S> __host__ __device__ inline S ls_albedo(S mu)
+{
+    if (!(val(mu) > 0.0f)) return S(0.5f);
+    return S(0.5f) * (S(1) - mu * log_(S(1) + S(1) / mu));
+}
+
+// ---------------------------------------------------------------- ply hit
+
+template <class G> struct PlyHit {
+    bool pass;
+    uint32_t flags;
+    G x2x, x2y, dhx, dhy, kappa;
+    G cx[kMaxPlies], cy[kMaxPlies], cth[kMaxPlies], sth[kMaxPlies];
+    int ks;
+    G p2x, p2y, n2x, n2y, vhit;
+};
+
+template <class G> __host__ __device__ inline void sincos_turns_g(const G& t, G* s, G* c);
+template <> __host__ __device__ inline void sincos_turns_g<double>(const double& t, double* s, double* c)
+{
+    sincos_turns(t, s, c);
+}
+
+// Yarn hit (Sec. 3.3) and implicit plies (Sec. 3.4): hit point x2 on the
+// unit yarn circle at offset h, then for each ply the fixed-point update of
+// the height at which the ply-centre helix crosses the ray's ellipse plane,
+// a 2D ray/disc test in the projected cross-section, and the closest ply.
+template <class G, class S>
+__host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, float u, float v,
+                                            const V3<float>& wi, PlyHit<G>& g)
+{
+    g.pass = false;
+    g.flags = 0;
+    g.ks = -1;
+    double sxy = sqrt((double)wi.x * wi.x + (double)wi.y * wi.y);
+    if (sxy < 1e-6) {
+        g.pass = true;
+        g.flags = F_AXIAL | F_PASS_THROUGH;
+        return;
+    }
+    double cx0 = wi.x / sxy, cy0 = wi.y / sxy;
+    double hh = h > 1.0f ? 1.0 : (h < -1.0f ? -1.0 : (double)h);
+    double cg = sqrt(1.0 - hh * hh);
+    g.x2x = G(cx0 * cg - cy0 * hh);
+    g.x2y = G(cy0 * cg + cx0 * hh);
+    g.dhx = G(-cx0);
+    g.dhy = G(-cy0);
+    g.kappa = G(-(double)wi.z / sxy);
+    G sexit = G(-2) * (g.x2x * g.dhx + g.x2y * g.dhy);
+    double u_turn = (double)u * kInvTwoPi;
+    G vv = G((double)v);
+    G best_s = G(0);
+    int best = -1;
+#pragma unroll
+    for (int k = 0; k < kMaxPlies; ++k) {
+        if (k >= P.Np) break;
+        G base = G(u_turn + k * P.inv_np);
+        G vj = vv;
+        G s, c;
+        for (int j = 0; j < P.N_it; ++j) {
+            sincos_turns_g(base + P.wp_turns * vj, &s, &c);
+            vj = vv + g.kappa * ((P.Rpc * c - g.x2x) * g.dhx + (P.Rpc * s - g.x2y) * g.dhy);
+        }
+        sincos_turns_g(base + P.wp_turns * vj, &s, &c);
+        g.cth[k] = c;
+        g.sth[k] = s;
+        g.cx[k] = P.Rpc * c;
+        g.cy[k] = P.Rpc * s;
+        G wx = g.x2x - g.cx[k], wy = g.x2y - g.cy[k];
+        G b = wx * g.dhx + wy * g.dhy;
+        G cc = wx * wx + wy * wy - P.rp * P.rp;
+        G disc = b * b - cc;
+        if (val(disc) >= 0.0) {
+            G sq = sqrt_(disc);
+            G slo = -b - sq, shi = -b + sq;
+            if (val(shi) >= 0.0 && val(slo) <= val(sexit)) {
+                G sk = val(slo) > 0.0 ? slo : G(0);
+                if (best < 0 || val(sk) < val(best_s)) {
+                    best = k;
+                    best_s = sk;
+                }
+            }
+        }
+    }
+    if (best < 0) {
+        g.pass = true;
+        g.flags |= F_PASS_THROUGH;
+        return;
+    }
+    g.ks = best;
+    G ccx = G(0), ccy = G(0);
+#pragma unroll
+    for (int k = 0; k < kMaxPlies; ++k)
+        if (k == best) { ccx = g.cx[k]; ccy = g.cy[k]; }
+    g.p2x = g.x2x + best_s * g.dhx;
+    g.p2y = g.x2y + best_s * g.dhy;
+    G nx = g.p2x - ccx, ny = g.p2y - ccy;
+    G inv = G(1) / sqrt_(nx * nx + ny * ny);
+    g.n2x = nx * inv;
+    g.n2y = ny * inv;
+    g.vhit = vv + g.kappa * best_s;
+}
+
+// ---------------------------------------------------------------- fibers
+
+template <class G> __host__ __device__ inline G floor_g(const G& x);
+template <> __host__ __device__ inline double floor_g<double>(const double& x) { return floor(x); }
+
+// Ply frame on the disc with phase (cth, sth) at 2D outward normal (n2x,
+// n2y) and yarn height z, then the fiber frame from the 1D fiber table
+// (Sec. 3.5.1): normal rotated about the ply tangent by dn, tangent tilted
+// against the ply twist by atan(rho_hat tan(alpha_f)).
+template <class G, class S, class Tab>
+__host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Tab& tab, G cth, G sth,
+                                                G n2x, G n2y, G z, S* gf_out, G* a_out)
+{
+    V3<G> tp = mk3<G>(-P.slope * sth * P.tnorm_inv, P.slope * cth * P.tnorm_inv, P.tnorm_inv);
+    V3<G> n23 = mk3<G>(n2x, n2y, G(0));
+    V3<G> np = normalize(n23 - tp * dot(n23, tp));
+    G a = atan2_(cth * n2y - sth * n2x, cth * n2x + sth * n2y);
+    G turns = a * G(kInvTwoPi) + P.wf_turns * (z * P.vply_scale);
+    // periodic linear interpolation between texel centres
+    G fl = floor_g(turns);
+    G x = (turns - fl) * G((double)P.Nu) - G(0.5);
+    G xf = floor_g(x);
+    G f = x - xf;
+    // texel index in [0, Nu): x lies in [-1/2, Nu - 1/2) for a finite phase;
+    // anything else (a non-finite phase) reads texel 0
+    double xi0 = val(xf) < 0.0 ? val(xf) + P.Nu : val(xf);
+    int i0 = (xi0 >= 0.0 && xi0 < (double)P.Nu) ? (int)xi0 : 0;
+    int i1 = i0 + 1 == P.Nu ? 0 : i0 + 1;
+    float4 t0 = tab(i0), t1 = tab(i1);
+    G omf = G(1) - f;
+    G dn = omf * G((double)t0.x) + f * G((double)t1.x);
+    G rh = omf * G((double)t0.y) + f * G((double)t1.y);
+    G gfv = omf * G((double)t0.z) + f * G((double)t1.z);
+    V3<G> bp = cross(tp, np);
+    V3<G> npr = np * cos_(dn) + bp * sin_(dn);
+    G tfa = rh * P.tan_af;
+    G ca = G(1) / sqrt_(G(1) + tfa * tfa);
+    G sa = tfa * ca;
+    Frame<G> fr;
+    fr.t = tp * ca - bp * sa;
+    fr.n = normalize(npr - fr.t * dot(npr, fr.t));
+    fr.b = cross(fr.n, fr.t);
+    if (gf_out) *gf_out = Narrow<S>::from(gfv);
+    if (a_out) *a_out = a;
+    return fr;
+}
+
+// ---------------------------------------------------------------- shadowing
+
+// Raw ply visibility (Sec. 4.1.4): at angle a around ply 0 of the nominal
+// cross-section, the share of the window [phi - dP, phi + dP] of incident
+// 2D directions (measured from the local normal) that is neither below the
+// ply's tangent line nor towards another ply's disc.  Each occluded set
+// meets the window in at most one piece (the window is shorter than the
+// gap between a set's 2 pi copies); the union length uses a sorting network.
+template <class S>
+__host__ __device__ inline S ply_shadow_raw(int Np, S rp, S Rpc, S dP, S a, S phi)
+{
+    S lo[kMaxPlies], hi[kMaxPlies];
+    S wlo = phi - dP, whi = phi + dP;
+    S na_x = cos_(a), na_y = sin_(a);
+    S Px = Rpc + rp * na_x, Py = rp * na_y;
+    const S big = S(1e30f);
+#pragma unroll
+    for (int s = 0; s < kMaxPlies; ++s) {
+        S cen, half;
+        bool live = s < Np;
+        if (s == 0) {
+            cen = S(float(kPi));
+            half = S(float(0.5 * kPi));
+        } else if (live) {
+            S ang = S(float(kTwoPi)) * S(float(s)) / S(float(Np));
+            S cxj = Rpc * cos_(ang), cyj = Rpc * sin_(ang);
+            S wx = cxj - Px, wy = cyj - Py;
+            S dist = sqrt_(wx * wx + wy * wy);
+            cen = atan2_(na_x * wy - na_y * wx, na_x * wx + na_y * wy);
+            S ratio = rp / dist;
+            half = asin_(val(ratio) < 1.0f ? ratio : S(1));
+        } else {
+            cen = S(0);
+            half = S(0);
+        }
+        // copy of the set closest to the window
+        S turns = (cen - phi) * S(float(kInvTwoPi));
+        S shift = S(float(kTwoPi)) * S(rintf(val(turns)));
+        S l = cen - half - shift, h2 = cen + half - shift;
+        l = val(l) > val(wlo) ? l : wlo;
+        h2 = val(h2) < val(whi) ? h2 : whi;
+        bool ok = live && val(h2) > val(l);
+        lo[s] = ok ? l : big;
+        hi[s] = ok ? h2 : big;
+    }
+    // sort by lower end (odd-even transposition network, kMaxPlies passes)
+#pragma unroll
+    for (int pass = 0; pass < kMaxPlies; ++pass) {
+#pragma unroll
+        for (int i = pass & 1; i + 1 < kMaxPlies; i += 2) {
+            bool sw = val(lo[i + 1]) < val(lo[i]);
+            S a0 = sw ? lo[i + 1] : lo[i], a1 = sw ? lo[i] : lo[i + 1];
+            S b0 = sw ? hi[i + 1] : hi[i], b1 = sw ? hi[i] : hi[i + 1];
+            lo[i] = a0; lo[i + 1] = a1; hi[i] = b0; hi[i + 1] = b1;
+        }
+    }
+    S occ = S(0), cl = lo[0], ch = hi[0];
+    bool any = val(lo[0]) < 1e29f;
+#pragma unroll
+    for (int i = 1; i < kMaxPlies; ++i) {
+        bool live = val(lo[i]) < 1e29f;
+        if (live && val(lo[i]) > val(ch)) {
+            occ = occ + (ch - cl);
+            cl = lo[i];
+            ch = hi[i];
+        } else if (live && val(hi[i]) > val(ch)) {
+            ch = hi[i];
+        }
+    }
+    if (any) occ = occ + (ch - cl);
+    S vis = S(1) - occ / (S(2) * dP);
+    return val(vis) < 0.0f ? S(0) : (val(vis) > 1.0f ? S(1) : vis);
+}
+
+// ---------------------------------------------------------------- state at x
+
+template <class G, class S> struct XState {
+    PlyHit<G> ph;
+    Frame<G> fx;      // fiber frame at x (geometry precision)
+    Frame<S> fxs;     // the same, shading precision
+    V3<G> wi_g;
+    V3<S> wi_s;
+    S Gp, Gf, mu_i;
+    S w[4];           // lobe selection weights
+    G a;
+};
+
+template <class G, class S, class Tab>
+__host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& tab, float h, float u,
+                                           float v, const V3<float>& wi, XState<G, S>& X)
+{
+    trace_plies(P, h, u, v, wi, X.ph);
+    X.wi_g = mk3<G>(G((double)wi.x), G((double)wi.y), G((double)wi.z));
+    X.wi_s = mk3<S>(S(wi.x), S(wi.y), S(wi.z));
+    if (X.ph.pass) return;
+    G cth = G(0), sth = G(0);
+#pragma unroll
+    for (int k = 0; k < kMaxPlies; ++k)
+        if (k == X.ph.ks) { cth = X.ph.cth[k]; sth = X.ph.sth[k]; }
+    S gft;
+    X.fx = fiber_frame(P, tab, cth, sth, X.ph.n2x, X.ph.n2y, X.ph.vhit, &gft, &X.a);
+    X.fxs = narrowf<S>(X.fx);
+    S n2x = Narrow<S>::from(X.ph.n2x), n2y = Narrow<S>::from(X.ph.n2y);
+    S phi = atan2_(n2x * X.wi_s.y - n2y * X.wi_s.x, n2x * X.wi_s.x + n2y * X.wi_s.y);
+    S raw = ply_shadow_raw<S>(P.Np, P.rp_s, P.Rpc_s, P.dP, Narrow<S>::from(X.a), phi);
+    X.Gp = S(1) - P.rho_p * (S(1) - raw);
+    X.Gf = S(1) - P.rho_f * (S(1) - gft);
+    X.mu_i = Narrow<S>::from(dot(X.wi_g, X.fx.n));
+    S PR = fresnel<S>(val(X.mu_i) > 0.0f ? X.mu_i : S(0), P.eta);
+    X.w[0] = (S(1) - P.B) * PR;
+    X.w[1] = (S(1) - P.B) * (S(1) - PR);
+    X.w[2] = P.B * P.r;
+    X.w[3] = P.B * (S(1) - P.r);
+}
+
+// ---------------------------------------------------------------- forward nodes
+
+template <class G, class S> struct Node {
+    S T, att;        // refraction weight at x, tau^N
+    V3<G> wt;        // refracted direction
+    Frame<G> fy;     // fiber frame at the exit point
+    V3<G> y;         // exit point (x, y, height)
+};
+
+// Node k of the integral over exit points (Eq. 1): a visible normal at x
+// from a rank-1 lattice point, refraction into the yarn, the chord through
+// the projected cross-section, the plies it enters, the exit ply and the
+// fiber frame there (Eq. 3-4).
+template <class G, class S, class Tab>
+__host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& tab,
+                                             const XState<G, S>& X, int k, float s0, float s1,
+                                             bool has_shift, Node<G, S>& nd)
+{
+    const PlyHit<G>& ph = X.ph;
+    V3<G> xp = mk3<G>(ph.p2x, ph.p2y, ph.vhit);
+    if (!(val(X.mu_i) > 0.0f)) {
+        nd.T = S(0);
+        nd.att = S(1);
+        nd.wt = mk3<G>(G(0), G(0), G(0));
+        nd.fy.t = X.fx.t;
+        nd.fy.n = -X.fx.n;
+        nd.fy.b = cross(nd.fy.n, nd.fy.t);
+        nd.y = xp;
+        return;
+    }
+    const double phig = 0.61803398874989484820;
+    double a1 = (k + 0.5) / P.K, a2 = (k + 0.5) * phig;
+    if (has_shift) {
+        a1 += s0;
+        a2 += s1;
+    }
+    double xi1 = a1 - floor(a1), xi2 = a2 - floor(a2);
+    V3<G> wl = to_local(X.fx, X.wi_g);
+    V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, G(xi1), G(xi2));
+    V3<G> m = to_world(X.fx, ml);
+    G c = dot(X.wi_g, m);
+    c = val(c) > 0.0 ? c : G(0);
+    G ie = G(1) / P.eta_g;
+    G s2t = (G(1) - c * c) * ie * ie;
+    G ct = sqrt_(G(1) - s2t);
+    V3<G> wt = X.wi_g * (-ie) + m * (c * ie - ct);
+    nd.wt = wt;
+    S cs = Narrow<S>::from(c);
+    nd.T = fresnel_T<S>(cs, P.eta) *
+           smith_G1<S>(narrow3<S>(to_local(X.fx, wt)), narrow3<S>(ml), P.ax, P.ay);
+    // chord in the projected cross-section, starting at the ply hit
+    G le = sqrt_(wt.x * wt.x + wt.y * wt.y);
+    G en = wt.x * ph.n2x + wt.y * ph.n2y;
+    if (val(le) < 1e-6 || val(en) >= 0.0) {
+        nd.att = S(1);
+        nd.fy.t = X.fx.t;
+        nd.fy.n = -X.fx.n;
+        nd.fy.b = cross(nd.fy.n, nd.fy.t);
+        nd.y = xp;
+        return;
+    }
+    G il = G(1) / le;
+    G ex = wt.x * il, ey = wt.y * il;
+    G bq = ph.p2x * ex + ph.p2y * ey;
+    G cq = ph.p2x * ph.p2x + ph.p2y * ph.p2y - G(1);
+    G dq = bq * bq - cq;
+    G syarn = -bq + (val(dq) > 0.0 ? sqrt_(dq) : G(0));
+    int N = 0, jl = -1;
+    G sbest = G(0), cxl = G(0), cyl = G(0), cthl = G(0), sthl = G(0);
+#pragma unroll
+    for (int j = 0; j < kMaxPlies; ++j) {
+        if (j >= P.Np) break;
+        bool ent = false;
+        G so = G(0);
+        if (j == ph.ks) {
+            // the chord starts on this disc's rim and heads inside
+            G sx = G(-2) * P.rp * en * il;
+            so = val(sx) < val(syarn) ? sx : syarn;
+            ent = true;
+        } else {
+            G wx = ph.p2x - ph.cx[j], wy = ph.p2y - ph.cy[j];
+            G b = wx * ex + wy * ey;
+            G cc = wx * wx + wy * wy - P.rp * P.rp;
+            G disc = b * b - cc;
+            if (val(disc) > 0.0) {
+                G sq = sqrt_(disc);
+                G slo = -b - sq, shi = -b + sq;
+                if (val(shi) > 0.0 && val(slo) < val(syarn)) {
+                    ent = true;
+                    so = val(shi) < val(syarn) ? shi : syarn;
+                }
+            }
+        }
+        if (ent) {
+            ++N;
+            if (jl < 0 || val(so) > val(sbest)) {
+                jl = j;
+                sbest = so;
+                cxl = ph.cx[j];
+                cyl = ph.cy[j];
+                cthl = ph.cth[j];
+                sthl = ph.sth[j];
+            }
+        }
+    }
+    G y2x = ph.p2x + sbest * ex, y2y = ph.p2y + sbest * ey;
+    G ell = sbest * il;
+    G zy = ph.vhit + wt.z * ell;
+    G nyx = y2x - cxl, nyy = y2y - cyl;
+    G ninv = G(1) / sqrt_(nyx * nyx + nyy * nyy);
+    nd.att = exp_(-P.sigma_t * Narrow<S>::from(ell) * S(float(N)));
+    nd.fy = fiber_frame<G, S, Tab>(P, tab, cthl, sthl, nyx * ninv, nyy * ninv, zy, nullptr,
+                                   nullptr);
+    nd.y = mk3<G>(y2x, y2y, zy);
+}
+
+// Exit refraction at y (Eq. 3): Walter's BTDF from inside (index eta) to
+// outside for wi' = -wt, times |wo.n_y|, and the solid-angle pdf of drawing
+// wo through this node.  The half vector, the cosines and the transmittance
+// use the geometry scalar: next to the critical angle the transmittance
+// falls like the transmitted cosine, whose derivative is unbounded.
+template <class G, class S>
+__host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& wt, const Frame<G>& fy,
+                                          const V3<G>& wo, S* val_out, S* pdf_out)
+{
+    *val_out = S(0);
+    *pdf_out = S(0);
+    V3<G> wip = -wt;
+    G ci = dot(wip, fy.n), co = dot(wo, fy.n);
+    if (!(val(ci) < 0.0 && val(co) > 0.0)) return;
+    V3<G> mh = -(wip * P.eta_g + wo);
+    G ml2 = dot(mh, mh);
+    if (!(val(ml2) > 0.0)) return;
+    mh = mh * (G(1) / sqrt_(ml2));
+    if (val(dot(mh, fy.n)) < 0.0) mh = -mh;
+    G im = dot(wip, mh), om = dot(wo, mh);
+    if (!(val(im) < 0.0 && val(om) > 0.0)) return;
+    G den = P.eta_g * im + om;
+    G Ft = fresnel_T<G>(-im, G(1) / P.eta_g);
+    V3<S> ml = narrow3<S>(to_local(fy, mh));
+    S D = ggx_D<S>(ml, P.ax, P.ay);
+    S g1i = smith_G1<S>(narrow3<S>(to_local(fy, wip)), ml, P.ax, P.ay);
+    S g1o = smith_G1<S>(narrow3<S>(to_local(fy, wo)), ml, P.ax, P.ay);
+    // |wi'.m| |wo.m| / (|wi'.n| |wo.n|) * Jacobian / (eta wi'.m + wo.m)^2,
+    // times |wo.n| for the returned value
+    S geo = Narrow<S>::from(-im / -ci * om / (den * den));
+    *val_out = geo * Narrow<S>::from(Ft) * g1i * g1o * D;
+    *pdf_out = geo * g1i * D;
+}
+
+// ---------------------------------------------------------------- lobes
+
+template <class S> struct EvalOut {
+    S E[3], ExS, EyS, ExB[3], EyB[3], pdf;
+};
+
+// The four lobes of Eq. 1 and the mixture pdf of Sec. 4.1.5 at wo.  Dot
+// products, the half vector and local coordinates are formed in the
+// geometry scalar (a grazing cosine or a near-opposite pair cancels), the
+// lobe formulas then run in the shading scalar.
+template <class G, class S, class Tab>
+__host__ __device__ inline void lobes(const Derived<G, S>& P, const Tab& tab, const XState<G, S>& X,
+                                      const V3<G>& wo_g, float s0, float s1, bool has_shift,
+                                      EvalOut<S>& o)
+{
+    S mu_i = X.mu_i;
+    G mu_o_g = dot(wo_g, X.fx.n);
+    S mu_o = Narrow<S>::from(mu_o_g);
+    S ExS = S(0), pxS = S(0);
+    bool front_i = val(mu_i) > 0.0f;
+    if (front_i && val(mu_o_g) > 0.0) {
+        V3<G> hv = normalize(X.wi_g + wo_g);
+        V3<S> hl = narrow3<S>(to_local(X.fx, hv));
+        S D = ggx_D<S>(hl, P.ax, P.ay);
+        S g1i = smith_G1<S>(narrow3<S>(to_local(X.fx, X.wi_g)), hl, P.ax, P.ay);
+        S g1o = smith_G1<S>(narrow3<S>(to_local(X.fx, wo_g)), hl, P.ax, P.ay);
+        S ih = Narrow<S>::from(dot(X.wi_g, hv)), oh = Narrow<S>::from(dot(wo_g, hv));
+        S ihp = val(ih) > 0.0f ? ih : S(0);
+        ExS = (S(1) - P.B) * P.kS * fresnel<S>(ihp, P.eta) * g1i * g1o * D / (S(4) * mu_i);
+        if (val(oh) > 0.0f) pxS = g1i * ihp * D / mu_i / (S(4) * oh);
+    }
+    S bx = S(0), pxB = S(0);
+    if (val(mu_o_g) > 0.0) {
+        S mp = front_i ? mu_i : S(0);
+        S fls = S(1) / (S(float(4.0 * kPi)) * (mp + mu_o));
+        bx = P.B * P.r * X.Gp * X.Gf * (fls + S(float(1.0 / kPi))) * mu_o / (S(1) + ls_albedo<S>(mp));
+        pxB = mu_o * S(float(1.0 / kPi));
+    }
+    S EyS = S(0), pyS = S(0), by = S(0), pyB = S(0);
+    for (int k = 0; k < P.K; ++k) {
+        Node<G, S> nd;
+        forward_node(P, tab, X, k, s0, s1, has_shift, nd);
+        G cyg = dot(wo_g, nd.fy.n);
+        if (val(cyg) > 0.0) {
+            S c = Narrow<S>::from(cyg) * S(float(1.0 / kPi));
+            by = by + c;
+            pyB = pyB + c;
+        }
+        if (front_i) {
+            S vv, pd;
+            exit_btdf(P, nd.wt, nd.fy, wo_g, &vv, &pd);
+            EyS = EyS + nd.T * nd.att * vv;
+            pyS = pyS + pd;
+        }
+    }
+    S invK = S(1) / S(float(P.K));
+    EyS = EyS * (S(1) - P.B) * P.kS * invK;
+    pyS = pyS * invK;
+    by = by * P.B * (S(1) - P.r) * X.Gp * X.Gf * invK;
+    pyB = pyB * invK;
+    o.ExS = ExS;
+    o.EyS = EyS;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o.ExB[c] = bx * P.alb[c];
+        o.EyB[c] = by * P.alb[c];
+        o.E[c] = ExS + EyS + o.ExB[c] + o.EyB[c];
+    }
+    o.pdf = X.w[0] * pxS + X.w[1] * pyS + X.w[2] * pxB + X.w[3] * pyB;
+}
+
+__host__ __device__ inline uint32_t check_inputs(float h, float u, float v, const V3<float>& a)
+{
+    bool bad = !(h >= -1.0f && h <= 1.0f) || !__builtin_isfinite(u) || !__builtin_isfinite(v);
+    bad = bad || !__builtin_isfinite(a.x) || !__builtin_isfinite(a.y) || !__builtin_isfinite(a.z);
+    if (!bad) {
+        float l = sqrtf(a.x * a.x + a.y * a.y + a.z * a.z);
+        bad = fabsf(l - 1.0f) > 1e-3f;
+    }
+    return bad ? F_BAD_INPUT : 0u;
+}
+
+__host__ __device__ inline uint32_t check_dir(const V3<float>& a)
+{
+    bool bad = !__builtin_isfinite(a.x) || !__builtin_isfinite(a.y) || !__builtin_isfinite(a.z);
+    if (!bad) bad = fabsf(sqrtf(a.x * a.x + a.y * a.y + a.z * a.z) - 1.0f) > 1e-3f;
+    return bad ? F_BAD_INPUT : 0u;
+}
+
+
+// ---------------------------------------------------------------- sampler
+
+template <class S> struct SampleOut {
+    S wo[3], wgt[3], pdf, ex[3];
+    int lobe, node;
+};
+
+// Importance sampling (Sec. 4.1.5): xi0 picks a lobe with the selection
+// weights (and, for the forward lobes, a node); visible-normal GGX samples
+// the specular lobes (reflection at x, refraction out of the yarn at y),
+// cosine lobes the body lobes.  The weight is the full value over the full
+// mixture pdf at the drawn direction.  Lobes: 0 x-specular, 1 y-specular,
+// 2 x-body, 3 y-body, 4 pass-through.
+template <class G, class S, class Tab>
+__host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const Tab& tab, float h,
+                                                 float u, float v, const V3<float>& wi, float xi0,
+                                                 float xi1, float xi2, float s0, float s1,
+                                                 bool has_shift, SampleOut<S>& so)
+{
+    for (int c = 0; c < 3; ++c) {
+        so.wo[c] = S(0); so.wgt[c] = S(0); so.ex[c] = S(0);
+    }
+    so.pdf = S(0);
+    so.lobe = -1;
+    so.node = 0;
+    uint32_t flags = check_inputs(h, u, v, wi);
+    if (flags) return flags;
+    XState<G, S> X;
+    state_at_x(P, tab, h, u, v, wi, X);
+    flags = X.ph.flags;
+    if (X.ph.pass) {
+        so.wo[0] = S(-wi.x); so.wo[1] = S(-wi.y); so.wo[2] = S(-wi.z);
+        so.wgt[0] = so.wgt[1] = so.wgt[2] = S(1);
+        so.lobe = 4;
+        return flags;
+    }
+    if (!(val(X.mu_i) > 0.0f)) flags |= F_BACKFACING;
+    S c0 = X.w[0], c1 = c0 + X.w[1], c2 = c1 + X.w[2];
+    float x0 = xi0;
+    int lobe = x0 < val(c0) ? 0 : (x0 < val(c1) ? 1 : (x0 < val(c2) ? 2 : 3));
+    int node = 0;
+    if (lobe == 1 || lobe == 3) {
+        S lo = lobe == 1 ? c0 : c2;
+        S xk = (S(x0) - lo) / X.w[lobe] * S(float(P.K));
+        int nk = (int)floorf(val(xk));
+        node = nk > P.K - 1 ? P.K - 1 : (nk < 0 ? 0 : nk);
+    }
+    so.lobe = lobe;
+    so.node = node;
+    V3<G> wo = mk3<G>(G(0), G(0), G(0));
+    bool ok = false;
+    V3<G> ex = mk3<G>(X.ph.p2x, X.ph.p2y, X.ph.vhit);
+    const G gx1 = G((double)xi1), gx2 = G((double)xi2);
+    if (lobe == 0) {
+        V3<G> wl = to_local(X.fx, X.wi_g);
+        if (val(wl.z) > 0.0) {
+            V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, gx1, gx2);
+            V3<G> mw = to_world(X.fx, ml);
+            wo = mw * (G(2) * dot(X.wi_g, mw)) - X.wi_g;
+            ok = val(dot(wo, X.fx.n)) > 0.0;
+        }
+    } else if (lobe == 1) {
+        // refraction out of the yarn at the node's exit point
+        Node<G, S> nd;
+        forward_node(P, tab, X, node, s0, s1, has_shift, nd);
+        ex = nd.y;
+        V3<G> wip = -nd.wt;
+        Frame<G> fi;
+        fi.t = nd.fy.t;
+        fi.n = -nd.fy.n;
+        fi.b = cross(fi.n, fi.t);
+        V3<G> wl = to_local(fi, wip);
+        if (val(wl.z) > 0.0 && val(X.mu_i) > 0.0f) {
+            V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, gx1, gx2);
+            V3<G> mw = to_world(fi, ml);
+            G c = dot(wip, mw);
+            c = val(c) > 0.0 ? c : G(0);
+            G s2t = P.eta_g * P.eta_g * (G(1) - c * c);
+            if (val(s2t) < 1.0) {
+                G ct = sqrt_(G(1) - s2t);
+                wo = wip * (-P.eta_g) + mw * (P.eta_g * c - ct);
+                ok = val(dot(wo, nd.fy.n)) > 0.0;
+            }
+        }
+    } else {
+        Frame<G> fr;
+        if (lobe == 2) {
+            fr = X.fx;
+        } else {
+            Node<G, S> nd;
+            forward_node(P, tab, X, node, s0, s1, has_shift, nd);
+            fr = nd.fy;
+            ex = nd.y;
+        }
+        G rad = sqrt_(gx1);
+        G ang = G(kTwoPi) * gx2;
+        G z = G(1) - gx1;
+        wo = to_world(fr, mk3<G>(rad * cos_(ang), rad * sin_(ang), val(z) > 0.0 ? sqrt_(z) : G(0)));
+        ok = true;
+    }
+    so.ex[0] = Narrow<S>::from(ex.x);
+    so.ex[1] = Narrow<S>::from(ex.y);
+    so.ex[2] = Narrow<S>::from(ex.z);
+    if (!ok) return flags | F_SAMPLE_FAIL;
+    wo = normalize(wo);
+    EvalOut<S> e;
+    lobes(P, tab, X, wo, s0, s1, has_shift, e);
+    if (!(val(e.pdf) > 0.0f)) return flags | F_SAMPLE_FAIL;
+    so.wo[0] = Narrow<S>::from(wo.x);
+    so.wo[1] = Narrow<S>::from(wo.y);
+    so.wo[2] = Narrow<S>::from(wo.z);
+    S ip = S(1) / e.pdf;
+    for (int c = 0; c < 3; ++c) so.wgt[c] = e.E[c] * ip;
+    so.pdf = e.pdf;
+    return flags;
+}
+
+}  // namespace bysdf

@@ -39,7 +39,25 @@ def default_params(**over) -> dict:
     p.update(over)
     if "ply_radius" in over and "ply_center_radius" not in over:
         p["ply_center_radius"] = 1.0 - p["ply_radius"]
-    return p
+    return as_f32(p)
+
+
+INT_FIELDS = ("n_plies", "fibers_per_ply", "K", "n_iter", "tex_size")
+
+
+def as_f32(p: dict) -> dict:
+    """Round every real parameter to a single-precision value: parameter
+    records are FP32 inputs of the library, and the oracle must see the same
+    numbers."""
+    q = dict(p)
+    for k, v in p.items():
+        if k in INT_FIELDS:
+            q[k] = int(v)
+        elif k == "albedo":
+            q[k] = tuple(float(np.float32(a)) for a in v)
+        else:
+            q[k] = float(np.float32(v))
+    return q
 
 
 def packed_ply_radius(n_plies: int) -> float:
@@ -175,4 +193,4 @@ def with_theta(p: dict, th) -> dict:
     q["albedo"] = (float(th[0]), float(th[1]), float(th[2]))
     q["beta"], q["ply_twist"], q["fiber_twist"] = float(th[3]), float(th[4]), float(th[5])
     q["ply_density"], q["fiber_density"] = float(th[6]), float(th[7])
-    return q
+    return as_f32(q)

@@ -1,0 +1,40 @@
+"""Parity rule shared by the GPU tests.
+
+A query counts when the oracle sets none of its margin flags (the query sits
+within the rounding margin of one of the method's discrete decisions, or
+the ply fixed point amplifies double rounding beyond 1e5).  On those
+queries every floating-point output must satisfy
+    |gpu - oracle| <= 1e-4 |oracle| + 1e-6
+and the structural flags (pass-through, axial, back-facing, sample failure,
+bad input) must agree exactly.
+"""
+import numpy as np
+
+import oracle
+
+REL = 1e-4
+ABS = 1e-6
+STRUCT = (oracle.PASS_THROUGH | oracle.AXIAL | oracle.BACKFACING | oracle.SAMPLE_FAIL
+          | oracle.BAD_INPUT)
+
+
+def compare(gpu, gflags, ref, rflags, extra_ok=None):
+    """gpu, ref: [n, m] arrays; flags uint32 [n].  Returns a report dict."""
+    gflags = np.asarray(gflags).view(np.uint32)
+    ok = (rflags & oracle.MARGIN_MASK) == 0
+    if extra_ok is not None:
+        ok &= extra_ok
+    tol = REL * np.abs(ref) + ABS
+    err = np.abs(gpu - ref)
+    bad = (err > tol) & ok[:, None]
+    fmis = ((gflags & STRUCT) != (rflags & STRUCT)) & ok
+    rel = err / np.maximum(np.abs(ref), ABS / REL)
+    return dict(n=len(ok), counted=int(ok.sum()), flagged_share=float(1 - ok.mean()),
+                n_bad=int(bad.any(1).sum()), n_flag_mismatch=int(fmis.sum()),
+                bad_idx=np.nonzero(bad.any(1) | fmis)[0][:20],
+                max_rel=float(rel[ok].max()) if ok.any() else 0.0)
+
+
+def assert_parity(rep, max_flagged=0.02):
+    assert rep["n_bad"] == 0 and rep["n_flag_mismatch"] == 0, rep
+    assert rep["flagged_share"] <= max_flagged, rep

@@ -1,0 +1,73 @@
+"""C ABI checks that need no GPU: libbysdf.so loads, exports every entry
+point include/bysdf.h declares, and rejects bad arguments and parameter
+records on the host before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2401_12724_amd import build as hip_build
+from paper_2401_12724_amd import bysdf, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if hip_build.stale():
+        hip_build.build()
+    return bysdf.lib()
+
+
+def _declared():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names += re.findall(r"^(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+(\w+)\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "bysdf_eval" in names and "bysdf_sample_pdf" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version(L):
+    assert bysdf.bysdf_version().startswith("bysdf-gfx950")
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_plies", 0), ("n_plies", 9), ("fibers_per_ply", 0), ("fibers_per_ply", 300),
+    ("K", 0), ("K", 17), ("n_iter", -1), ("tex_size", 1), ("ply_radius", 0.0),
+    ("ply_radius", 1.2), ("ply_center_radius", 0.9), ("fiber_radius", 1.0),
+    ("ply_twist", 1.6), ("eta", 1.0), ("beta", 0.0), ("aniso", 0.0), ("B", 1.5),
+    ("r", -0.1), ("sigma_t", -1.0), ("ply_density", 1.1), ("fiber_density", -0.5),
+    ("shadow_halfwidth", 0.0), ("shadow_halfwidth", 2.0), ("albedo", (0.5, -0.1, 0.5)),
+])
+def test_invalid_params_rejected(L, field, value):
+    p = workloads.default_params()
+    p[field] = value
+    arr = bysdf.params_array([workloads.default_params(), p])
+    h = C.c_void_p()
+    rc = L.bysdf_types_create(arr, 2, C.byref(h), None)
+    assert rc == bysdf.ERR_INVALID_PARAM
+    assert h.value is None
+    msg = L.bysdf_last_error().decode()
+    assert msg.startswith("type 1:"), msg
+
+
+def test_null_arguments_rejected(L):
+    h = C.c_void_p()
+    assert L.bysdf_types_create(None, 1, C.byref(h), None) == bysdf.ERR_INVALID_ARG
+    arr = bysdf.params_array([workloads.default_params()])
+    assert L.bysdf_types_create(arr, 0, C.byref(h), None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_types_create(arr, 1, None, None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_eval(None, None, 0, None, None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_sample_pdf(None, None, 0, None, None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_types_destroy(None) == bysdf.OK
+    assert L.bysdf_types_count(None) == bysdf.ERR_INVALID_ARG
