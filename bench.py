@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the BYSDF hot path on one MI355X.
+
+One step = one pass of the path over the per-block workload: 2^24 queries in
+65,536 parameter blocks of 256 (one 3-ply yarn geometry; beta and albedo
+drawn per block), inputs resident in HBM:
+    bysdf_eval            value, lobes and pdf at (wi, wo)
+    bysdf_sample_pdf      one importance-sampled direction per query
+    bysdf_eval            value and pdf at the sampled directions
+    bysdf_furnace_blocks  per-block white-furnace mean/variance (256 draws)
+value = queries per second (2^24 queries per step / step time).
+
+Prints ONE JSON line.  `roofline` is for the kernel with the largest time
+per step, priced with the algorithmic operation count of the kernels'
+formulation (bysdf_count_ops) against the VALU issue peak; `cpu_baseline`
+is the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s; an FMA
+# counts 2 flops.  FP64 FMA and unpacked FP32 FMA issue at this rate (packed
+# FP32, which doubles FP32 to 157.3 TFLOP/s, is not used by these kernels).
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.64
+PEAK_HBM_GBS = 8000.0
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2401_12724_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _op_counts(bysdf, T, P, q, mode, n=4096):
+    L = bysdf.lib()
+    L.bysdf_count_ops.argtypes = ([C.POINTER(bysdf.TypeParams), C.c_void_p, C.c_int64]
+                                  + [C.c_void_p] * 6 + [C.c_int32, C.c_void_p])
+    arr = bysdf.params_array(P[:1])
+    tab = np.ascontiguousarray(bysdf.bysdf_types_table(T, 0))
+    f = lambda a: np.ascontiguousarray(a, np.float32).ctypes.data_as(C.c_void_p)
+    c = np.zeros(10)
+    rc = L.bysdf_count_ops(arr, tab.ctypes.data_as(C.c_void_p), n, f(q["h"][:n]), f(q["u"][:n]),
+                           f(q["v"][:n]), f(q["wi"][:, :n]), f(q["wo"][:, :n]),
+                           f(q["xi"][:, :n]), mode, c.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise RuntimeError("bysdf_count_ops failed")
+    return c
+
+
+def _cpu_baseline(P, q, target_s):
+    """FP64 oracle on the first blocks of the workload, same four stages."""
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+
+    def run(nb):
+        n = nb * 256
+        sub = {k: (v[..., :n] if v is not None else None) for k, v in q.items()}
+        sub["type"] = sub["type"].copy()
+        ts = oracle.TypeSet(P[:nb])
+        t0 = time.perf_counter()
+        oracle.eval(ts, sub, nthreads=cores)
+        so, _ = oracle.sample(ts, sub, nthreads=cores)
+        s2 = dict(sub)
+        s2["wo"] = np.ascontiguousarray(so[:, :3].T.astype(np.float32))
+        oracle.eval(ts, s2, nthreads=cores)
+        oracle.furnace(ts, sub, 256, nthreads=cores)
+        return time.perf_counter() - t0
+
+    nb = 16
+    dt = run(nb)
+    nb = int(min(len(P), max(16, nb * target_s / max(dt, 1e-3))))
+    dt = run(nb)
+    n = nb * 256
+    return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d blocks (%d queries) of the per-block workload, same four "
+                      "stages (eval, sample, eval at sampled wo, furnace), %.1f s" % (nb, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--blocks", type=int, default=65536, help="parameter blocks of 256 queries")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for PMC byte scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs single-GPU only "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2401_12724_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
+    from paper_2401_12724_amd import bysdf, workloads as W
+
+    torch.cuda.set_device(0)
+    P, q = W.per_block(args.blocks, 256, seed=1)
+    N = len(q["h"])
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev = bysdf.alloc_eval_out(N)
+    sv = bysdf.alloc_sample_out(N)
+    ev2 = bysdf.alloc_eval_out(N)
+    fm = torch.empty((N // 256, 3), dtype=torch.float32, device="cuda")
+    fv = torch.empty_like(fm)
+    q2 = dict(qd)
+    q2["wo"] = sv[0][0:3]  # sampled directions, rows of the sample output
+    torch.cuda.synchronize()
+
+    names = ("eval", "sample", "eval_at_sample", "furnace")
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        calls = (lambda: bysdf.bysdf_eval(T, qd, ev),
+                 lambda: bysdf.bysdf_sample_pdf(T, qd, sv),
+                 lambda: bysdf.bysdf_eval(T, q2, ev2),
+                 lambda: bysdf.bysdf_furnace_blocks(T, qd, 256, fm, fv))
+        for k, c in enumerate(calls):
+            if events is not None:
+                events[k][0].record(stream)
+            c()
+            if events is not None:
+                events[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in names] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktime = {nm: float(np.mean([evs[s][k][0].elapsed_time(evs[s][k][1])
+                                for s in range(args.steps)])) for k, nm in enumerate(names)}
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N * args.steps / elapsed
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    # algorithmic operations per query (kernels' own formulation)
+    ops_eval = _op_counts(bysdf, T, P, q, 0)
+    ops_samp = _op_counts(bysdf, T, P, q, 1)
+    per_query = {"eval": ops_eval.sum(), "sample": ops_samp.sum(),
+                 "eval_at_sample": ops_eval.sum(), "furnace": ops_samp.sum()}
+    dom = max(ktime, key=ktime.get)
+    achieved = per_query[dom] * N / (ktime[dom] * 1e-3) / 1e12
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        tj = json.load(open(tpath))
+        if tj.get("src_hash") == _src_hash() and dom in tj.get("kernels", {}):
+            traffic = tj["kernels"][dom]
+    # algorithmic bytes per query of each kernel (SoA records, 4 B fields)
+    bytes_q = {"eval": 40 + 52, "sample": 40 + 52, "eval_at_sample": 40 + 52,
+               "furnace": 4 * 8 + 24.0 / 256}
+    out = {
+        "metric": "BYSDF queries/s (eval+sample, fp32), % VALU peak; fwd+bwd vs plain fwd",
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 geometry + f32 lobes",
+        "data": "synthetic",
+        "config": {"workload": "per-block: %d queries in %d blocks of 256, 3-ply yarn "
+                               "(64 fibers/ply, twist 28/15 deg, r_p 0.45, eta 1.55), beta "
+                               "U[0.05,0.3] and albedo U[0.3,0.95]^3 per block; step = eval, "
+                               "sample, eval at sampled wo, furnace per block" % (N, N // 256),
+                   "queries": N, "blocks": N // 256, "K": 4, "n_iter": 5},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
+                     "ops_per_query": per_query[dom]},
+        "kernels_ms": ktime,
+        "kernel_gbs": {k: bytes_q[k] * N / (ktime[k] * 1e-3) / 1e9 for k in names},
+        "ops_per_query": {"eval": {"fp64": ops_eval[:5].tolist(), "fp32": ops_eval[5:].tolist()},
+                          "sample": {"fp64": ops_samp[:5].tolist(), "fp32": ops_samp[5:].tolist()},
+                          "order": "add mul div sqrt transcendental"},
+        "src_hash": _src_hash(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(P, q, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,18 @@ int bysdf_sample_pdf(const bysdf_types_t* types, const bysdf_sample_soa* q, int6
 int bysdf_furnace_blocks(const bysdf_types_t* types, const bysdf_sample_soa* q, int64_t n,
                          int32_t block, float* mean, float* var, hipStream_t stream);
 
+/* Host-only: algorithmic operation count of the kernels' formulation.
+ * Runs the per-query model on the host with counting scalars over n
+ * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type
+ * *p, whose fiber table (tex_size x 3 floats: dn, rho_hat, G_f) is given in
+ * host memory.  mode 0 counts bysdf_eval (wo needed), mode 1
+ * bysdf_sample_pdf (xi needed).  counts[10] receives the mean per query of
+ * (add, mul, div, sqrt, transcendental) for the FP64 geometry scalar,
+ * then the same five for the FP32 shading scalar.  Touches no device. */
+int bysdf_count_ops(const bysdf_type_params* p, const float* table, int64_t n, const float* h,
+                    const float* u, const float* v, const float* wi, const float* wo,
+                    const float* xi, int32_t mode, double* counts);
+
 #ifdef __cplusplus
 }
 #endif

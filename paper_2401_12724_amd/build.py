@@ -16,11 +16,14 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbysdf.so")
 SOURCES = ["bysdf_lib.hip"]
-HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp"]
+HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_opcount.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 division and square root from the hardware reciprocal / root
+    # (about 1 ulp); FP64 stays correctly rounded
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -21,7 +21,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbysdf.so")
+# BYSDF_LIB selects another build of the same library (tuning experiments)
+LIB_PATH = os.environ.get("BYSDF_LIB", os.path.join(_HERE, "libbysdf.so"))
 
 OK = 0
 ERR_INVALID_ARG = -1

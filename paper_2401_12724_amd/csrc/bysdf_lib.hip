@@ -23,6 +23,7 @@
 
 #include "../../include/bysdf.h"
 #include "bysdf_model.hpp"
+#include "bysdf_opcount.hpp"
 
 using namespace bysdf;
 
@@ -74,19 +75,6 @@ struct TabPtr {
     const float4* p;
     __host__ __device__ float4 operator()(int i) const { return p[i]; }
 };
-
-// derived constants of one record (double precision), host and device
-__host__ __device__ static void fill_derived(TypeRec& t)
-{
-    double wp = t.Rpc > 0.0 ? tan(t.ply_twist) / t.Rpc : 0.0;
-    t.slope = t.Rpc * wp;
-    t.vply_scale = sqrt(1.0 + t.slope * t.slope);
-    t.tnorm_inv = 1.0 / t.vply_scale;
-    t.wp_turns = wp * kInvTwoPi;
-    t.tan_af = tan(t.fiber_twist);
-    t.wf_turns = t.tan_af / ((1.0 - t.rho_f_geom) * t.rp) * kInvTwoPi;
-    t.inv_np = 1.0 / t.n_plies;
-}
 
 static int validate(const bysdf_type_params& p, int i)
 {
@@ -259,9 +247,33 @@ struct OPtrs {
 };
 
 constexpr int kBlock = 256;
+// minimum wavefronts per SIMD (register budget) chosen by measurement
+#ifndef BYSDF_EVAL_MIN_WAVES
+#define BYSDF_EVAL_MIN_WAVES 1
+#endif
+#ifndef BYSDF_SAMPLE_MIN_WAVES
+#define BYSDF_SAMPLE_MIN_WAVES 2
+#endif
 
-template <bool kLds>
-__global__ __launch_bounds__(kBlock) void k_eval(const TypeRec* __restrict__ types, int n_types,
+// Lanes of a wavefront are served one distinct type at a time (a wavefront
+// of one type -- sorted or per-block input -- takes a single pass): the
+// type index is made wavefront-uniform, so its record is read with scalar
+// loads and its scalars stay out of the vector registers.
+template <class F>
+__device__ inline void for_each_wave_type(int t, bool need, F&& body)
+{
+    unsigned long long pending = __ballot(need);
+    while (pending) {
+        const int lead = __ffsll(pending) - 1;
+        const int tu = __builtin_amdgcn_readlane(t, lead);
+        const bool mine = need && t == tu;
+        if (mine) body(tu);
+        pending &= ~__ballot(mine);
+    }
+}
+
+template <bool kLds, int MP>
+__global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const TypeRec* __restrict__ types, int n_types,
                                                  const float4* __restrict__ tables, int lds_texels,
                                                  QPtrs q, OPtrs o, int64_t n)
 {
@@ -270,10 +282,6 @@ __global__ __launch_bounds__(kBlock) void k_eval(const TypeRec* __restrict__ typ
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
         __syncthreads();
     }
-    int cur = -1;
-    Derived<double, float> P;
-    TabPtr tab;
-    tab.p = tables;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         int t = q.type[i];
@@ -285,14 +293,12 @@ __global__ __launch_bounds__(kBlock) void k_eval(const TypeRec* __restrict__ typ
         EvalOut<float> e;
         for (int c = 0; c < 3; ++c) e.E[c] = e.ExB[c] = e.EyB[c] = 0.0f;
         e.ExS = e.EyS = e.pdf = 0.0f;
-        if (!fl) {
-            if (t != cur) {
-                const TypeRec rec = types[t];
-                P = derive(rec);
-                tab.p = kLds ? s_tab : tables + rec.table_off;
-                cur = t;
-            }
-            XState<double, float> X;
+        const bool need = fl == 0u;
+        for_each_wave_type(t, need, [&](int tu) {
+            const Derived<double, float>& P = types[tu].d;
+            TabPtr tab;
+            tab.p = kLds ? s_tab : tables + types[tu].table_off;
+            XState<double, float, MP> X;
             state_at_x(P, tab, h, u, v, wi, X);
             fl = X.ph.flags;
             if (!X.ph.pass) {
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(const TypeRec* __restrict__ typ
                 V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
                 lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
             }
-        }
+        });
         o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
         o.ExS[i] = e.ExS; o.EyS[i] = e.EyS;
         o.ExBr[i] = e.ExB[0]; o.ExBg[i] = e.ExB[1]; o.ExBb[i] = e.ExB[2];
@@ -322,8 +328,8 @@ struct SOPtrs {
     uint32_t* flags;
 };
 
-template <bool kLds>
-__global__ __launch_bounds__(kBlock) void k_sample(const TypeRec* __restrict__ types, int n_types,
+template <bool kLds, int MP>
+__global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const TypeRec* __restrict__ types, int n_types,
                                                    const float4* __restrict__ tables,
                                                    int lds_texels, SPtrs q, SOPtrs o, int64_t n)
 {
@@ -332,10 +338,6 @@ __global__ __launch_bounds__(kBlock) void k_sample(const TypeRec* __restrict__ t
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
         __syncthreads();
     }
-    int cur = -1;
-    Derived<double, float> P;
-    TabPtr tab;
-    tab.p = tables;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         int t = q.type[i];
@@ -344,21 +346,18 @@ __global__ __launch_bounds__(kBlock) void k_sample(const TypeRec* __restrict__ t
         so.pdf = 0.0f;
         so.lobe = -1;
         so.node = 0;
-        uint32_t fl;
-        if (t < 0 || t >= n_types) {
-            fl = F_BAD_INPUT;
-        } else {
-            if (t != cur) {
-                const TypeRec rec = types[t];
-                P = derive(rec);
-                tab.p = kLds ? s_tab : tables + rec.table_off;
-                cur = t;
-            }
-            V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
-            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
-            fl = sample_query(P, tab, q.h[i], q.u[i], q.v[i], wi, q.xi0[i], q.xi1[i], q.xi2[i], s0,
-                              s1, q.s0 != nullptr, so);
-        }
+        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+        const bool need = fl == 0u;
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+        float h = q.h[i], u = q.u[i], v = q.v[i], x0 = q.xi0[i], x1 = q.xi1[i], x2 = q.xi2[i];
+        for_each_wave_type(t, need, [&](int tu) {
+            const Derived<double, float>& P = types[tu].d;
+            TabPtr tab;
+            tab.p = kLds ? s_tab : tables + types[tu].table_off;
+            fl = sample_query<double, float, MP>(P, tab, h, u, v, wi, x0, x1, x2, s0, s1,
+                                                 q.s0 != nullptr, so);
+        });
         o.wox[i] = so.wo[0]; o.woy[i] = so.wo[1]; o.woz[i] = so.wo[2];
         o.wr[i] = so.wgt[0]; o.wg[i] = so.wgt[1]; o.wb[i] = so.wgt[2];
         o.pdf[i] = so.pdf;
@@ -370,47 +369,82 @@ __global__ __launch_bounds__(kBlock) void k_sample(const TypeRec* __restrict__ t
 }
 
 // ------------------------------------------------------------------ furnace
-// One workgroup per furnace block; lane j draws with the xi of query
-// b*block + j for the hit of query b*block.  Sum and sum of squared
-// deviations reduce through LDS in a fixed tree order.
-__global__ __launch_bounds__(1024) void k_furnace(const TypeRec* __restrict__ types, int n_types,
-                                                  const float4* __restrict__ tables, SPtrs q,
-                                                  int64_t n_blocks, float* mean, float* var)
+// One workgroup per furnace block.  Every draw shares the block's hit, so
+// the state at x is computed per lane (identical values) while the K
+// forward nodes -- the costly part of each evaluation -- are computed once
+// by lanes 0..K-1 into LDS and read by every draw.  Lane j draws with the xi
+// of queries b*block + j, j + 256, ...; sums reduce through LDS in a fixed
+// tree order (bitwise reproducible).
+constexpr int kMaxDrawsPerLane = 4;  // block <= 1024 = 4 x 256
+
+template <int MP>
+__global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ types, int n_types,
+                                                    const float4* __restrict__ tables, SPtrs q,
+                                                    int block, float* mean, float* var)
 {
-    __shared__ float s_red[3][1024];
+    __shared__ Node<double, float> s_nodes[kMaxNodes];
+    __shared__ float s_red[3][kBlock];
     const int64_t b = blockIdx.x;
-    const int tid = threadIdx.x, B = blockDim.x;
-    const int64_t q0 = b * B, qi = q0 + tid;
-    int t = q.type[q0];
-    float w[3] = {0.0f, 0.0f, 0.0f};
-    if (t >= 0 && t < n_types) {
-        const TypeRec rec = types[t];
-        Derived<double, float> P = derive(rec);
-        TabPtr tab;
-        tab.p = tables + rec.table_off;
-        V3<float> wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
-        float s0 = q.s0 ? q.s0[q0] : 0.0f, s1 = q.s1 ? q.s1[q0] : 0.0f;
-        SampleOut<float> so;
-        sample_query(P, tab, q.h[q0], q.u[q0], q.v[q0], wi, q.xi0[qi], q.xi1[qi], q.xi2[qi], s0, s1,
-                     q.s0 != nullptr, so);
-        for (int c = 0; c < 3; ++c) w[c] = so.wgt[c];
+    const int tid = threadIdx.x;
+    const int64_t q0 = b * (int64_t)block;
+    const int t = __builtin_amdgcn_readfirstlane(q.type[q0]);
+    const bool valid = t >= 0 && t < n_types;
+    const TypeRec& rec = types[valid ? t : 0];
+    const Derived<double, float>& P = rec.d;
+    TabPtr tab;
+    tab.p = tables + rec.table_off;
+    V3<float> wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
+    const float h = q.h[q0], u = q.u[q0], v = q.v[q0];
+    const float s0 = q.s0 ? q.s0[q0] : 0.0f, s1 = q.s1 ? q.s1[q0] : 0.0f;
+    const bool bad = !valid || check_inputs(h, u, v, wi) != 0u;
+    XState<double, float, MP> X;
+    if (!bad) {
+        state_at_x(P, tab, h, u, v, wi, X);
+        if (!X.ph.pass && tid < P.K) {
+            Node<double, float> nd;
+            forward_node(P, tab, X, tid, s0, s1, q.s0 != nullptr, nd);
+            s_nodes[tid] = nd;
+        }
     }
-    for (int c = 0; c < 3; ++c) s_red[c][tid] = w[c];
     __syncthreads();
-    for (int st = B / 2; st > 0; st >>= 1) {
+    NodesStored<double, float> nodes{s_nodes};
+    float w[kMaxDrawsPerLane][3];
+    float sum[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+        const int j = tid + d * kBlock;
+        w[d][0] = w[d][1] = w[d][2] = 0.0f;
+        if (j < block && !bad) {
+            const int64_t qi = q0 + j;
+            SampleOut<float> so;
+            sample_from_x(P, X, wi, q.xi0[qi], q.xi1[qi], q.xi2[qi], nodes, so);
+            for (int c = 0; c < 3; ++c) w[d][c] = so.wgt[c];
+        }
+        for (int c = 0; c < 3; ++c) sum[c] += w[d][c];
+    }
+    for (int c = 0; c < 3; ++c) s_red[c][tid] = sum[c];
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
         if (tid < st)
             for (int c = 0; c < 3; ++c) s_red[c][tid] += s_red[c][tid + st];
         __syncthreads();
     }
     float m[3];
-    for (int c = 0; c < 3; ++c) m[c] = s_red[c][0] / (float)B;
+    for (int c = 0; c < 3; ++c) m[c] = s_red[c][0] / (float)block;
     __syncthreads();
-    for (int c = 0; c < 3; ++c) {
-        float d = w[c] - m[c];
-        s_red[c][tid] = d * d;
+    float sq[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+        const int j = tid + d * kBlock;
+        if (j < block)
+            for (int c = 0; c < 3; ++c) {
+                float dv = w[d][c] - m[c];
+                sq[c] += dv * dv;
+            }
     }
+    for (int c = 0; c < 3; ++c) s_red[c][tid] = sq[c];
     __syncthreads();
-    for (int st = B / 2; st > 0; st >>= 1) {
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
         if (tid < st)
             for (int c = 0; c < 3; ++c) s_red[c][tid] += s_red[c][tid + st];
         __syncthreads();
@@ -418,7 +452,7 @@ __global__ __launch_bounds__(1024) void k_furnace(const TypeRec* __restrict__ ty
     if (tid == 0) {
         for (int c = 0; c < 3; ++c) {
             mean[3 * b + c] = m[c];
-            var[3 * b + c] = s_red[c][0] / (float)(B - 1);
+            var[3 * b + c] = s_red[c][0] / (float)(block - 1);
         }
     }
 }
@@ -586,14 +620,12 @@ extern "C" int bysdf_eval(const bysdf_types_t* h, const bysdf_query_soa* q, int6
     OPtrs op{o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
              o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
     int grid = grid_for(n);
-    if (h->single_table) {
-        size_t lds = sizeof(float4) * h->table_texels;
-        hipLaunchKernelGGL(k_eval<true>, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
-                           h->d_tables, h->table_texels, qp, op, n);
-    } else {
-        hipLaunchKernelGGL(k_eval<false>, dim3(grid), dim3(kBlock), 0, stream, h->d_types, h->n_types,
-                           h->d_tables, 0, qp, op, n);
-    }
+    size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
+    int tx = h->single_table ? h->table_texels : 0;
+    auto kern = h->max_plies <= 4 ? (h->single_table ? k_eval<true, 4> : k_eval<false, 4>)
+                                   : (h->single_table ? k_eval<true, 8> : k_eval<false, 8>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                       h->d_tables, tx, qp, op, n);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }
@@ -625,14 +657,12 @@ extern "C" int bysdf_sample_pdf(const bysdf_types_t* h, const bysdf_sample_soa* 
     SOPtrs op{o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x, o->exit_y,
               o->exit_z, o->lobe, o->node, o->flags};
     int grid = grid_for(n);
-    if (h->single_table) {
-        size_t lds = sizeof(float4) * h->table_texels;
-        hipLaunchKernelGGL(k_sample<true>, dim3(grid), dim3(kBlock), lds, stream, h->d_types,
-                           h->n_types, h->d_tables, h->table_texels, sp, op, n);
-    } else {
-        hipLaunchKernelGGL(k_sample<false>, dim3(grid), dim3(kBlock), 0, stream, h->d_types,
-                           h->n_types, h->d_tables, 0, sp, op, n);
-    }
+    size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
+    int tx = h->single_table ? h->table_texels : 0;
+    auto kern = h->max_plies <= 4 ? (h->single_table ? k_sample<true, 4> : k_sample<false, 4>)
+                                   : (h->single_table ? k_sample<true, 8> : k_sample<false, 8>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                       h->d_tables, tx, sp, op, n);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }
@@ -651,8 +681,64 @@ extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_s
     if (nb > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many blocks");
     SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
              q->shift0, q->shift1};
-    hipLaunchKernelGGL(k_furnace, dim3((unsigned)nb), dim3(block), 0, stream, h->d_types, h->n_types,
-                       h->d_tables, sp, nb, mean, var);
+    auto kern = h->max_plies <= 4 ? k_furnace<4> : k_furnace<8>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, stream, h->d_types, h->n_types,
+                       h->d_tables, sp, block, mean, var);
     HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+// ------------------------------------------------------------------ op count
+namespace bysdf {
+thread_local OpTally* g_tally = nullptr;
+}
+
+struct HostTab {
+    const float4* p;
+    float4 operator()(int i) const { return p[i]; }
+};
+
+extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, int64_t n,
+                               const float* h, const float* u, const float* v, const float* wi,
+                               const float* wo, const float* xi, int32_t mode, double* counts)
+{
+    if (!p || !table || !h || !u || !v || !wi || !counts || n < 1 || (mode != 0 && mode != 1))
+        return fail(BYSDF_ERR_INVALID_ARG, "bad argument");
+    if (mode == 0 && !wo) return fail(BYSDF_ERR_INVALID_ARG, "mode 0 needs wo");
+    if (mode == 1 && !xi) return fail(BYSDF_ERR_INVALID_ARG, "mode 1 needs xi");
+    if (int rc = validate(*p, 0)) return rc;
+    TypeRec rec = make_rec(*p);
+    std::vector<float4> tb(p->tex_size);
+    for (int i = 0; i < p->tex_size; ++i)
+        tb[i] = make_float4(table[3 * i], table[3 * i + 1], table[3 * i + 2], 0.0f);
+    HostTab tab{tb.data()};
+    Derived<CD, CF> P = derive_counted(rec);
+    OpTally tally;
+    memset(&tally, 0, sizeof(tally));
+    g_tally = &tally;
+    for (int64_t i = 0; i < n; ++i) {
+        V3<float> a = mk3<float>(wi[i], wi[n + i], wi[2 * n + i]);
+        if (check_inputs(h[i], u[i], v[i], a)) continue;
+        if (mode == 0) {
+            XState<CD, CF, kMaxPlies> X;
+            state_at_x(P, tab, h[i], u[i], v[i], a, X);
+            if (X.ph.pass) continue;
+            V3<CD> b = mk3<CD>(CD((double)wo[i]), CD((double)wo[n + i]), CD((double)wo[2 * n + i]));
+            EvalOut<CF> e;
+            lobes(P, tab, X, b, 0.0f, 0.0f, false, e);
+        } else {
+            SampleOut<CF> so;
+            sample_query<CD, CF, kMaxPlies>(P, tab, h[i], u[i], v[i], a, xi[i], xi[n + i],
+                                            xi[2 * n + i], 0.0f, 0.0f, false, so);
+        }
+    }
+    g_tally = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        counts[5 * k + 0] = tally.add[k] / n;
+        counts[5 * k + 1] = tally.mul[k] / n;
+        counts[5 * k + 2] = tally.div[k] / n;
+        counts[5 * k + 3] = tally.sqrt[k] / n;
+        counts[5 * k + 4] = tally.trans[k] / n;
+    }
     return BYSDF_OK;
 }

@@ -21,12 +21,64 @@ __host__ __device__ inline double val(double x) { return x; }
 
 __host__ __device__ inline float sqrt_(float x) { return sqrtf(x); }
 __host__ __device__ inline double sqrt_(double x) { return sqrt(x); }
+// reciprocal square root (the device uses the hardware estimate refined by
+// the math library; the host path only serves host-side tools)
+__host__ __device__ inline float rsqrt_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return rsqrtf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+__host__ __device__ inline double rsqrt_(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return rsqrt(x);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
 __host__ __device__ inline float sin_(float x) { return sinf(x); }
 __host__ __device__ inline double sin_(double x) { return sin(x); }
 __host__ __device__ inline float cos_(float x) { return cosf(x); }
 __host__ __device__ inline double cos_(double x) { return cos(x); }
 __host__ __device__ inline float atan2_(float y, float x) { return atan2f(y, x); }
-__host__ __device__ inline double atan2_(double y, double x) { return atan2(y, x); }
+
+// atan2 in double precision: fold to the first octant (t = min/max in
+// [0, 1]), reduce once more with atan t = pi/6 + atan((sqrt3 t - 1)/(sqrt3 +
+// t)) to |t| <= tan(pi/12), then sum the odd Taylor series of atan to t^27
+// (remainder below 1e-18) and unfold.
+__host__ __device__ inline double atan2_(double y, double x)
+{
+    const double ax = fabs(x), ay = fabs(y);
+    const double mx = fmax(ax, ay), mn = fmin(ax, ay);
+    const double t = mx > 0.0 ? mn / mx : 0.0;
+    const double k3 = 1.73205080756887729353;   // sqrt(3)
+    const double t12 = 0.26794919243112270647;  // tan(pi/12)
+    const bool big = t > t12;
+    const double tr = big ? (k3 * t - 1.0) / (k3 + t) : t;
+    const double z = tr * tr;
+    double p = -1.0 / 27.0;
+    p = fma(p, z, 1.0 / 25.0);
+    p = fma(p, z, -1.0 / 23.0);
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, -1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, -1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, -1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, -1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, -1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    double a = tr * p;
+    if (big) a += kPi / 6.0;
+    if (ay > ax) a = 0.5 * kPi - a;
+    if (x < 0.0) a = kPi - a;
+    return y < 0.0 ? -a : a;
+}
 __host__ __device__ inline float asin_(float x) { return asinf(x); }
 __host__ __device__ inline double asin_(double x) { return asin(x); }
 __host__ __device__ inline float exp_(float x) { return expf(x); }
@@ -40,12 +92,40 @@ __host__ __device__ inline double min_(double a, double b) { return a < b ? a : 
 __host__ __device__ inline float max_(float a, float b) { return a > b ? a : b; }
 __host__ __device__ inline double max_(double a, double b) { return a > b ? a : b; }
 
-// sin and cos of 2 pi t for a phase t measured in turns: reduce exactly to
-// [-1/2, 1/2] turns first so large phases keep their accuracy.
+// sin and cos of 2 pi t for a phase t measured in turns.  The reduction is
+// exact: drop whole turns, then quarter turns, leaving |x| <= 1/8 turn
+// (|a| <= pi/4 rad).  Taylor series to a^15 (sin) and a^16 (cos) leave a
+// remainder below 5e-17 there, so the result is as accurate as a library
+// sin/cos while costing about twenty fused multiply-adds.
 __host__ __device__ inline void sincos_turns(double t, double* s, double* c)
 {
     double r = t - rint(t);
-    sincos(kTwoPi * r, s, c);
+    double q = rint(4.0 * r);
+    double a = (r - 0.25 * q) * kTwoPi;
+    double a2 = a * a;
+    double sp = 1.0 / 1307674368000.0;
+    sp = fma(sp, -a2, 1.0 / 6227020800.0);
+    sp = fma(sp, -a2, 1.0 / 39916800.0);
+    sp = fma(sp, -a2, 1.0 / 362880.0);
+    sp = fma(sp, -a2, 1.0 / 5040.0);
+    sp = fma(sp, -a2, 1.0 / 120.0);
+    sp = fma(sp, -a2, 1.0 / 6.0);
+    sp = fma(sp, -a2, 1.0);
+    sp = sp * a;
+    double cp = 1.0 / 20922789888000.0;
+    cp = fma(cp, -a2, 1.0 / 87178291200.0);
+    cp = fma(cp, -a2, 1.0 / 479001600.0);
+    cp = fma(cp, -a2, 1.0 / 3628800.0);
+    cp = fma(cp, -a2, 1.0 / 40320.0);
+    cp = fma(cp, -a2, 1.0 / 720.0);
+    cp = fma(cp, -a2, 1.0 / 24.0);
+    cp = fma(cp, -a2, 0.5);
+    cp = fma(cp, -a2, 1.0);
+    int qi = ((int)q) & 3;
+    double s0 = (qi & 1) ? cp : sp;
+    double c0 = (qi & 1) ? sp : cp;
+    *s = (qi == 2 || qi == 3) ? -s0 : s0;
+    *c = (qi == 1 || qi == 2) ? -c0 : c0;
 }
 
 // narrowing to the shading scalar
@@ -96,8 +176,7 @@ template <class T> __host__ __device__ inline V3<T> cross(const V3<T>& a, const 
 }
 template <class T> __host__ __device__ inline V3<T> normalize(const V3<T>& a)
 {
-    T inv = T(1) / sqrt_(dot(a, a));
-    return a * inv;
+    return a * rsqrt_(dot(a, a));
 }
 template <class To, class From> __host__ __device__ inline V3<To> narrow3(const V3<From>& a)
 {

@@ -25,49 +25,66 @@ constexpr uint32_t F_BACKFACING = 1u << 5;
 constexpr uint32_t F_SAMPLE_FAIL = 1u << 6;
 constexpr uint32_t F_BAD_INPUT = 1u << 9;
 
-// Per-type record resident in device memory (host fills it once).
+// Scalars one query needs, in the kernel's scalar types.
+template <class G, class S> struct Derived {
+    int Np, K, N_it, Nu;
+    double inv_np;
+    G rp, Rpc, slope, wp_turns, tnorm_inv, vply_scale, wf_turns, tan_af;
+    G ax_g, ay_g, eta_g, inv_eta_g;
+    S ax, ay, eta, kS, B, r, sigma_t, rho_p, rho_f, dP;
+    S alb[3];
+    S rp_s, Rpc_s;
+};
+
+// Per-type record resident in device memory: the primary parameters and
+// everything derived from them, ready to be read with scalar loads when a
+// wavefront serves one type.
 struct TypeRec {
     int32_t n_plies, K, n_iter, tex_size, table_off, pad0;
     // primary parameters
     double rp, Rpc, ply_twist, fiber_twist, rho_f_geom;  // rho_f_geom = r_f / r_p
     double beta, aniso, eta;
     float albedo[3], k_spec, B, r, sigma_t, ply_density, fiber_density, shadow_hw;
-    // derived (host, double precision)
-    double slope;      // R_pc * w_p = tan(alpha_p) (0 when R_pc = 0)
-    double wp_turns;   // w_p / 2pi, turns per unit length along the yarn
-    double tnorm_inv;  // 1 / sqrt(1 + slope^2)
-    double vply_scale; // sqrt(1 + slope^2): ply arc length per yarn length
-    double wf_turns;   // w_f / 2pi with w_f = tan(alpha_f) / ((1 - r_f/r_p) r_p)
-    double tan_af;
-    double inv_np;
-};
-
-// Scalars one query needs, in the kernel's scalar types.
-template <class G, class S> struct Derived {
-    int Np, K, N_it, Nu;
-    double inv_np;
-    G rp, Rpc, slope, wp_turns, tnorm_inv, vply_scale, wf_turns, tan_af;
-    G ax_g, ay_g, eta_g;
-    S ax, ay, eta, kS, B, r, sigma_t, rho_p, rho_f, dP;
-    S alb[3];
-    S rp_s, Rpc_s;
-};
-
-__host__ __device__ inline Derived<double, float> derive(const TypeRec& t)
-{
     Derived<double, float> d;
+};
+
+// Fill the derived scalars of a record (host at creation, device when the
+// differentiable parameters change).
+__host__ __device__ inline void fill_derived(TypeRec& t)
+{
+    Derived<double, float>& d = t.d;
+    double wp = t.Rpc > 0.0 ? tan(t.ply_twist) / t.Rpc : 0.0;
     d.Np = t.n_plies; d.K = t.K; d.N_it = t.n_iter; d.Nu = t.tex_size;
-    d.inv_np = t.inv_np;
-    d.rp = t.rp; d.Rpc = t.Rpc; d.slope = t.slope; d.wp_turns = t.wp_turns;
-    d.tnorm_inv = t.tnorm_inv; d.vply_scale = t.vply_scale; d.wf_turns = t.wf_turns;
-    d.tan_af = t.tan_af;
-    d.ax_g = t.beta; d.ay_g = t.beta * t.aniso; d.eta_g = t.eta;
-    d.ax = (float)t.beta; d.ay = (float)(t.beta * t.aniso); d.eta = (float)t.eta;
+    d.inv_np = 1.0 / t.n_plies;
+    d.rp = t.rp;
+    d.Rpc = t.Rpc;
+    d.slope = t.Rpc * wp;                        // tan(alpha_p), 0 without a helix
+    d.vply_scale = sqrt(1.0 + d.slope * d.slope); // ply arc length per yarn length
+    d.tnorm_inv = 1.0 / d.vply_scale;
+    d.wp_turns = wp * kInvTwoPi;                 // helix turns per unit length
+    d.tan_af = tan(t.fiber_twist);
+    d.wf_turns = d.tan_af / ((1.0 - t.rho_f_geom) * t.rp) * kInvTwoPi;
+    d.ax_g = t.beta;
+    d.ay_g = t.beta * t.aniso;
+    d.eta_g = t.eta;
+    d.inv_eta_g = 1.0 / t.eta;
+    d.ax = (float)t.beta;
+    d.ay = (float)(t.beta * t.aniso);
+    d.eta = (float)t.eta;
     d.kS = t.k_spec; d.B = t.B; d.r = t.r; d.sigma_t = t.sigma_t;
     d.rho_p = t.ply_density; d.rho_f = t.fiber_density; d.dP = t.shadow_hw;
     for (int c = 0; c < 3; ++c) d.alb[c] = t.albedo[c];
-    d.rp_s = (float)t.rp; d.Rpc_s = (float)t.Rpc;
-    return d;
+    d.rp_s = (float)t.rp;
+    d.Rpc_s = (float)t.Rpc;
+}
+
+__host__ __device__ inline Derived<double, float> derive(const TypeRec& t) { return t.d; }
+
+// sin and cos of 2 pi t (t in turns) for the geometry scalar
+template <class G> __host__ __device__ inline void sincos_turns_g(const G& t, G* s, G* c);
+template <> __host__ __device__ inline void sincos_turns_g<double>(const double& t, double* s, double* c)
+{
+    sincos_turns(t, s, c);
 }
 
 // ---------------------------------------------------------------- microfacets
@@ -121,13 +138,14 @@ template <class T> __host__ __device__ inline V3<T> sample_vndf(const V3<T>& w, 
 {
     V3<T> vh = normalize(mk3<T>(ax * w.x, ay * w.y, w.z));
     T l2 = vh.x * vh.x + vh.y * vh.y;
-    V3<T> b1 = val(l2) > 0.0 ? mk3<T>(-vh.y, vh.x, T(0)) * (T(1) / sqrt_(l2))
+    V3<T> b1 = val(l2) > 0.0 ? mk3<T>(-vh.y, vh.x, T(0)) * rsqrt_(l2)
                              : mk3<T>(T(1), T(0), T(0));
     V3<T> b2 = cross(vh, b1);
     T rad = sqrt_(u1);
-    T ang = T(kTwoPi) * u2;
-    T d1 = rad * cos_(ang);
-    T d2 = rad * sin_(ang);
+    T su, cu;
+    sincos_turns_g(u2, &su, &cu);
+    T d1 = rad * cu;
+    T d2 = rad * su;
     T blend = T(0.5) * (T(1) + vh.z);
     d2 = (T(1) - blend) * sqrt_(T(1) - d1 * d1) + blend * d2;
     T h2 = T(1) - d1 * d1 - d2 * d2;
@@ -146,28 +164,24 @@ template <class S> __host__ __device__ inline S ls_albedo(S mu)
 
 // ---------------------------------------------------------------- ply hit
 
-template <class G> struct PlyHit {
+// MP: compile-time bound on the plies of the types a kernel serves
+template <class G, int MP> struct PlyHit {
     bool pass;
     uint32_t flags;
     G x2x, x2y, dhx, dhy, kappa;
-    G cx[kMaxPlies], cy[kMaxPlies], cth[kMaxPlies], sth[kMaxPlies];
+    G cth[MP], sth[MP];  // converged phase of each ply centre (centre = R_pc (cth, sth))
     int ks;
     G p2x, p2y, n2x, n2y, vhit;
 };
 
-template <class G> __host__ __device__ inline void sincos_turns_g(const G& t, G* s, G* c);
-template <> __host__ __device__ inline void sincos_turns_g<double>(const double& t, double* s, double* c)
-{
-    sincos_turns(t, s, c);
-}
 
 // Yarn hit (Sec. 3.3) and implicit plies (Sec. 3.4): hit point x2 on the
 // unit yarn circle at offset h, then for each ply the fixed-point update of
 // the height at which the ply-centre helix crosses the ray's ellipse plane,
 // a 2D ray/disc test in the projected cross-section, and the closest ply.
-template <class G, class S>
+template <class G, class S, int MP>
 __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, float u, float v,
-                                            const V3<float>& wi, PlyHit<G>& g)
+                                            const V3<float>& wi, PlyHit<G, MP>& g)
 {
     g.pass = false;
     g.flags = 0;
@@ -192,7 +206,7 @@ __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, flo
     G best_s = G(0);
     int best = -1;
 #pragma unroll
-    for (int k = 0; k < kMaxPlies; ++k) {
+    for (int k = 0; k < MP; ++k) {
         if (k >= P.Np) break;
         G base = G(u_turn + k * P.inv_np);
         G vj = vv;
@@ -204,9 +218,7 @@ __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, flo
         sincos_turns_g(base + P.wp_turns * vj, &s, &c);
         g.cth[k] = c;
         g.sth[k] = s;
-        g.cx[k] = P.Rpc * c;
-        g.cy[k] = P.Rpc * s;
-        G wx = g.x2x - g.cx[k], wy = g.x2y - g.cy[k];
+        G wx = g.x2x - P.Rpc * c, wy = g.x2y - P.Rpc * s;
         G b = wx * g.dhx + wy * g.dhy;
         G cc = wx * wx + wy * wy - P.rp * P.rp;
         G disc = b * b - cc;
@@ -230,12 +242,12 @@ __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, flo
     g.ks = best;
     G ccx = G(0), ccy = G(0);
 #pragma unroll
-    for (int k = 0; k < kMaxPlies; ++k)
-        if (k == best) { ccx = g.cx[k]; ccy = g.cy[k]; }
+    for (int k = 0; k < MP; ++k)
+        if (k == best) { ccx = P.Rpc * g.cth[k]; ccy = P.Rpc * g.sth[k]; }
     g.p2x = g.x2x + best_s * g.dhx;
     g.p2y = g.x2y + best_s * g.dhy;
     G nx = g.p2x - ccx, ny = g.p2y - ccy;
-    G inv = G(1) / sqrt_(nx * nx + ny * ny);
+    G inv = rsqrt_(nx * nx + ny * ny);
     g.n2x = nx * inv;
     g.n2y = ny * inv;
     g.vhit = vv + g.kappa * best_s;
@@ -252,7 +264,7 @@ template <> __host__ __device__ inline double floor_g<double>(const double& x) {
 // against the ply twist by atan(rho_hat tan(alpha_f)).
 template <class G, class S, class Tab>
 __host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Tab& tab, G cth, G sth,
-                                                G n2x, G n2y, G z, S* gf_out, G* a_out)
+                                                G n2x, G n2y, G z, G* gf_out, G* a_out)
 {
     V3<G> tp = mk3<G>(-P.slope * sth * P.tnorm_inv, P.slope * cth * P.tnorm_inv, P.tnorm_inv);
     V3<G> n23 = mk3<G>(n2x, n2y, G(0));
@@ -275,15 +287,17 @@ __host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Ta
     G rh = omf * G((double)t0.y) + f * G((double)t1.y);
     G gfv = omf * G((double)t0.z) + f * G((double)t1.z);
     V3<G> bp = cross(tp, np);
-    V3<G> npr = np * cos_(dn) + bp * sin_(dn);
+    G sdn, cdn;
+    sincos_turns_g(dn * G(kInvTwoPi), &sdn, &cdn);
+    V3<G> npr = np * cdn + bp * sdn;
     G tfa = rh * P.tan_af;
-    G ca = G(1) / sqrt_(G(1) + tfa * tfa);
+    G ca = rsqrt_(G(1) + tfa * tfa);
     G sa = tfa * ca;
     Frame<G> fr;
     fr.t = tp * ca - bp * sa;
     fr.n = normalize(npr - fr.t * dot(npr, fr.t));
     fr.b = cross(fr.n, fr.t);
-    if (gf_out) *gf_out = Narrow<S>::from(gfv);
+    if (gf_out) *gf_out = gfv;
     if (a_out) *a_out = a;
     return fr;
 }
@@ -296,59 +310,60 @@ __host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Ta
 // ply's tangent line nor towards another ply's disc.  Each occluded set
 // meets the window in at most one piece (the window is shorter than the
 // gap between a set's 2 pi copies); the union length uses a sorting network.
-template <class S>
-__host__ __device__ inline S ply_shadow_raw(int Np, S rp, S Rpc, S dP, S a, S phi)
+template <class G, int MP>
+__host__ __device__ inline G ply_shadow_raw(int Np, G rp, G Rpc, G dP, G a, G phi)
 {
-    S lo[kMaxPlies], hi[kMaxPlies];
-    S wlo = phi - dP, whi = phi + dP;
-    S na_x = cos_(a), na_y = sin_(a);
-    S Px = Rpc + rp * na_x, Py = rp * na_y;
-    const S big = S(1e30f);
+    G lo[MP], hi[MP];
+    G wlo = phi - dP, whi = phi + dP;
+    G na_x, na_y;
+    sincos_turns_g(a * G(kInvTwoPi), &na_y, &na_x);
+    G Px = Rpc + rp * na_x, Py = rp * na_y;
+    const G big = G(1e30);
 #pragma unroll
-    for (int s = 0; s < kMaxPlies; ++s) {
-        S cen, half;
+    for (int s = 0; s < MP; ++s) {
+        G cen, half;
         bool live = s < Np;
         if (s == 0) {
-            cen = S(float(kPi));
-            half = S(float(0.5 * kPi));
+            cen = G(kPi);
+            half = G(0.5 * kPi);
         } else if (live) {
-            S ang = S(float(kTwoPi)) * S(float(s)) / S(float(Np));
-            S cxj = Rpc * cos_(ang), cyj = Rpc * sin_(ang);
-            S wx = cxj - Px, wy = cyj - Py;
-            S dist = sqrt_(wx * wx + wy * wy);
+            G cs, sn;
+            sincos_turns_g(G((double)s / (double)Np), &sn, &cs);
+            G wx = Rpc * cs - Px, wy = Rpc * sn - Py;
+            G d2 = wx * wx + wy * wy;
             cen = atan2_(na_x * wy - na_y * wx, na_x * wx + na_y * wy);
-            S ratio = rp / dist;
-            half = asin_(val(ratio) < 1.0f ? ratio : S(1));
+            // asin(r_p / d) = atan2(r_p, sqrt(d^2 - r_p^2)); inside the disc: pi/2
+            G e2 = d2 - rp * rp;
+            half = val(e2) > 0.0 ? atan2_(rp, sqrt_(e2)) : G(0.5 * kPi);
         } else {
-            cen = S(0);
-            half = S(0);
+            cen = G(0);
+            half = G(0);
         }
         // copy of the set closest to the window
-        S turns = (cen - phi) * S(float(kInvTwoPi));
-        S shift = S(float(kTwoPi)) * S(rintf(val(turns)));
-        S l = cen - half - shift, h2 = cen + half - shift;
+        G shift = G(kTwoPi * rint(val((cen - phi) * G(kInvTwoPi))));
+        G l = cen - half - shift, h2 = cen + half - shift;
         l = val(l) > val(wlo) ? l : wlo;
         h2 = val(h2) < val(whi) ? h2 : whi;
         bool ok = live && val(h2) > val(l);
         lo[s] = ok ? l : big;
         hi[s] = ok ? h2 : big;
     }
-    // sort by lower end (odd-even transposition network, kMaxPlies passes)
+    // sort by lower end (odd-even transposition network, MP passes)
 #pragma unroll
-    for (int pass = 0; pass < kMaxPlies; ++pass) {
+    for (int pass = 0; pass < MP; ++pass) {
 #pragma unroll
-        for (int i = pass & 1; i + 1 < kMaxPlies; i += 2) {
+        for (int i = pass & 1; i + 1 < MP; i += 2) {
             bool sw = val(lo[i + 1]) < val(lo[i]);
-            S a0 = sw ? lo[i + 1] : lo[i], a1 = sw ? lo[i] : lo[i + 1];
-            S b0 = sw ? hi[i + 1] : hi[i], b1 = sw ? hi[i] : hi[i + 1];
+            G a0 = sw ? lo[i + 1] : lo[i], a1 = sw ? lo[i] : lo[i + 1];
+            G b0 = sw ? hi[i + 1] : hi[i], b1 = sw ? hi[i] : hi[i + 1];
             lo[i] = a0; lo[i + 1] = a1; hi[i] = b0; hi[i + 1] = b1;
         }
     }
-    S occ = S(0), cl = lo[0], ch = hi[0];
-    bool any = val(lo[0]) < 1e29f;
+    G occ = G(0), cl = lo[0], ch = hi[0];
+    bool any = val(lo[0]) < 1e29;
 #pragma unroll
-    for (int i = 1; i < kMaxPlies; ++i) {
-        bool live = val(lo[i]) < 1e29f;
+    for (int i = 1; i < MP; ++i) {
+        bool live = val(lo[i]) < 1e29;
         if (live && val(lo[i]) > val(ch)) {
             occ = occ + (ch - cl);
             cl = lo[i];
@@ -358,14 +373,14 @@ __host__ __device__ inline S ply_shadow_raw(int Np, S rp, S Rpc, S dP, S a, S ph
         }
     }
     if (any) occ = occ + (ch - cl);
-    S vis = S(1) - occ / (S(2) * dP);
-    return val(vis) < 0.0f ? S(0) : (val(vis) > 1.0f ? S(1) : vis);
+    G vis = G(1) - occ / (G(2) * dP);
+    return val(vis) < 0.0 ? G(0) : (val(vis) > 1.0 ? G(1) : vis);
 }
 
 // ---------------------------------------------------------------- state at x
 
-template <class G, class S> struct XState {
-    PlyHit<G> ph;
+template <class G, class S, int MP> struct XState {
+    PlyHit<G, MP> ph;
     Frame<G> fx;      // fiber frame at x (geometry precision)
     Frame<S> fxs;     // the same, shading precision
     V3<G> wi_g;
@@ -375,9 +390,9 @@ template <class G, class S> struct XState {
     G a;
 };
 
-template <class G, class S, class Tab>
+template <class G, class S, int MP, class Tab>
 __host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& tab, float h, float u,
-                                           float v, const V3<float>& wi, XState<G, S>& X)
+                                           float v, const V3<float>& wi, XState<G, S, MP>& X)
 {
     trace_plies(P, h, u, v, wi, X.ph);
     X.wi_g = mk3<G>(G((double)wi.x), G((double)wi.y), G((double)wi.z));
@@ -385,16 +400,17 @@ __host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& ta
     if (X.ph.pass) return;
     G cth = G(0), sth = G(0);
 #pragma unroll
-    for (int k = 0; k < kMaxPlies; ++k)
+    for (int k = 0; k < MP; ++k)
         if (k == X.ph.ks) { cth = X.ph.cth[k]; sth = X.ph.sth[k]; }
-    S gft;
+    G gft;
     X.fx = fiber_frame(P, tab, cth, sth, X.ph.n2x, X.ph.n2y, X.ph.vhit, &gft, &X.a);
     X.fxs = narrowf<S>(X.fx);
-    S n2x = Narrow<S>::from(X.ph.n2x), n2y = Narrow<S>::from(X.ph.n2y);
-    S phi = atan2_(n2x * X.wi_s.y - n2y * X.wi_s.x, n2x * X.wi_s.x + n2y * X.wi_s.y);
-    S raw = ply_shadow_raw<S>(P.Np, P.rp_s, P.Rpc_s, P.dP, Narrow<S>::from(X.a), phi);
-    X.Gp = S(1) - P.rho_p * (S(1) - raw);
-    X.Gf = S(1) - P.rho_f * (S(1) - gft);
+    // shadowing in the geometry scalar: a mostly occluded window leaves a
+    // small visible share that single precision cannot resolve
+    G phi = atan2_(X.ph.n2x * X.wi_g.y - X.ph.n2y * X.wi_g.x, X.ph.n2x * X.wi_g.x + X.ph.n2y * X.wi_g.y);
+    G raw = ply_shadow_raw<G, MP>(P.Np, P.rp, P.Rpc, G(val(P.dP)), X.a, phi);
+    X.Gp = Narrow<S>::from(G(1) - G(val(P.rho_p)) * (G(1) - raw));
+    X.Gf = Narrow<S>::from(G(1) - G(val(P.rho_f)) * (G(1) - gft));
     X.mu_i = Narrow<S>::from(dot(X.wi_g, X.fx.n));
     S PR = fresnel<S>(val(X.mu_i) > 0.0f ? X.mu_i : S(0), P.eta);
     X.w[0] = (S(1) - P.B) * PR;
@@ -416,12 +432,12 @@ template <class G, class S> struct Node {
 // from a rank-1 lattice point, refraction into the yarn, the chord through
 // the projected cross-section, the plies it enters, the exit ply and the
 // fiber frame there (Eq. 3-4).
-template <class G, class S, class Tab>
+template <class G, class S, int MP, class Tab>
 __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& tab,
-                                             const XState<G, S>& X, int k, float s0, float s1,
+                                             const XState<G, S, MP>& X, int k, float s0, float s1,
                                              bool has_shift, Node<G, S>& nd)
 {
-    const PlyHit<G>& ph = X.ph;
+    const PlyHit<G, MP>& ph = X.ph;
     V3<G> xp = mk3<G>(ph.p2x, ph.p2y, ph.vhit);
     if (!(val(X.mu_i) > 0.0f)) {
         nd.T = S(0);
@@ -445,7 +461,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
     V3<G> m = to_world(X.fx, ml);
     G c = dot(X.wi_g, m);
     c = val(c) > 0.0 ? c : G(0);
-    G ie = G(1) / P.eta_g;
+    G ie = P.inv_eta_g;
     G s2t = (G(1) - c * c) * ie * ie;
     G ct = sqrt_(G(1) - s2t);
     V3<G> wt = X.wi_g * (-ie) + m * (c * ie - ct);
@@ -454,7 +470,9 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
     nd.T = fresnel_T<S>(cs, P.eta) *
            smith_G1<S>(narrow3<S>(to_local(X.fx, wt)), narrow3<S>(ml), P.ax, P.ay);
     // chord in the projected cross-section, starting at the ply hit
-    G le = sqrt_(wt.x * wt.x + wt.y * wt.y);
+    G le2 = wt.x * wt.x + wt.y * wt.y;
+    G il = val(le2) > 0.0 ? rsqrt_(le2) : G(0);
+    G le = le2 * il;
     G en = wt.x * ph.n2x + wt.y * ph.n2y;
     if (val(le) < 1e-6 || val(en) >= 0.0) {
         nd.att = S(1);
@@ -464,7 +482,6 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
         nd.y = xp;
         return;
     }
-    G il = G(1) / le;
     G ex = wt.x * il, ey = wt.y * il;
     G bq = ph.p2x * ex + ph.p2y * ey;
     G cq = ph.p2x * ph.p2x + ph.p2y * ph.p2y - G(1);
@@ -473,7 +490,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
     int N = 0, jl = -1;
     G sbest = G(0), cxl = G(0), cyl = G(0), cthl = G(0), sthl = G(0);
 #pragma unroll
-    for (int j = 0; j < kMaxPlies; ++j) {
+    for (int j = 0; j < MP; ++j) {
         if (j >= P.Np) break;
         bool ent = false;
         G so = G(0);
@@ -483,7 +500,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
             so = val(sx) < val(syarn) ? sx : syarn;
             ent = true;
         } else {
-            G wx = ph.p2x - ph.cx[j], wy = ph.p2y - ph.cy[j];
+            G wx = ph.p2x - P.Rpc * ph.cth[j], wy = ph.p2y - P.Rpc * ph.sth[j];
             G b = wx * ex + wy * ey;
             G cc = wx * wx + wy * wy - P.rp * P.rp;
             G disc = b * b - cc;
@@ -501,8 +518,8 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
             if (jl < 0 || val(so) > val(sbest)) {
                 jl = j;
                 sbest = so;
-                cxl = ph.cx[j];
-                cyl = ph.cy[j];
+                cxl = P.Rpc * ph.cth[j];
+                cyl = P.Rpc * ph.sth[j];
                 cthl = ph.cth[j];
                 sthl = ph.sth[j];
             }
@@ -512,7 +529,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
     G ell = sbest * il;
     G zy = ph.vhit + wt.z * ell;
     G nyx = y2x - cxl, nyy = y2y - cyl;
-    G ninv = G(1) / sqrt_(nyx * nyx + nyy * nyy);
+    G ninv = rsqrt_(nyx * nyx + nyy * nyy);
     nd.att = exp_(-P.sigma_t * Narrow<S>::from(ell) * S(float(N)));
     nd.fy = fiber_frame<G, S, Tab>(P, tab, cthl, sthl, nyx * ninv, nyy * ninv, zy, nullptr,
                                    nullptr);
@@ -536,12 +553,12 @@ __host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& w
     V3<G> mh = -(wip * P.eta_g + wo);
     G ml2 = dot(mh, mh);
     if (!(val(ml2) > 0.0)) return;
-    mh = mh * (G(1) / sqrt_(ml2));
+    mh = mh * rsqrt_(ml2);
     if (val(dot(mh, fy.n)) < 0.0) mh = -mh;
     G im = dot(wip, mh), om = dot(wo, mh);
     if (!(val(im) < 0.0 && val(om) > 0.0)) return;
     G den = P.eta_g * im + om;
-    G Ft = fresnel_T<G>(-im, G(1) / P.eta_g);
+    G Ft = fresnel_T<G>(-im, P.inv_eta_g);
     V3<S> ml = narrow3<S>(to_local(fy, mh));
     S D = ggx_D<S>(ml, P.ax, P.ay);
     S g1i = smith_G1<S>(narrow3<S>(to_local(fy, wip)), ml, P.ax, P.ay);
@@ -563,10 +580,9 @@ template <class S> struct EvalOut {
 // products, the half vector and local coordinates are formed in the
 // geometry scalar (a grazing cosine or a near-opposite pair cancels), the
 // lobe formulas then run in the shading scalar.
-template <class G, class S, class Tab>
-__host__ __device__ inline void lobes(const Derived<G, S>& P, const Tab& tab, const XState<G, S>& X,
-                                      const V3<G>& wo_g, float s0, float s1, bool has_shift,
-                                      EvalOut<S>& o)
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline void lobes_nodes(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                            const V3<G>& wo_g, const NodeFn& node_of, EvalOut<S>& o)
 {
     S mu_i = X.mu_i;
     G mu_o_g = dot(wo_g, X.fx.n);
@@ -594,7 +610,7 @@ __host__ __device__ inline void lobes(const Derived<G, S>& P, const Tab& tab, co
     S EyS = S(0), pyS = S(0), by = S(0), pyB = S(0);
     for (int k = 0; k < P.K; ++k) {
         Node<G, S> nd;
-        forward_node(P, tab, X, k, s0, s1, has_shift, nd);
+        node_of(k, nd);
         G cyg = dot(wo_g, nd.fy.n);
         if (val(cyg) > 0.0) {
             S c = Narrow<S>::from(cyg) * S(float(1.0 / kPi));
@@ -622,6 +638,33 @@ __host__ __device__ inline void lobes(const Derived<G, S>& P, const Tab& tab, co
         o.E[c] = ExS + EyS + o.ExB[c] + o.EyB[c];
     }
     o.pdf = X.w[0] * pxS + X.w[1] * pyS + X.w[2] * pxB + X.w[3] * pyB;
+}
+
+// node providers: compute node k from the state at x, or read it from an
+// array filled beforehand (hits shared by many directions)
+template <class G, class S, int MP, class Tab> struct NodesComputed {
+    const Derived<G, S>& P;
+    const Tab& tab;
+    const XState<G, S, MP>& X;
+    float s0, s1;
+    bool has_shift;
+    __host__ __device__ void operator()(int k, Node<G, S>& nd) const
+    {
+        forward_node(P, tab, X, k, s0, s1, has_shift, nd);
+    }
+};
+template <class G, class S> struct NodesStored {
+    const Node<G, S>* nodes;
+    __host__ __device__ void operator()(int k, Node<G, S>& nd) const { nd = nodes[k]; }
+};
+
+template <class G, class S, int MP, class Tab>
+__host__ __device__ inline void lobes(const Derived<G, S>& P, const Tab& tab, const XState<G, S, MP>& X,
+                                      const V3<G>& wo_g, float s0, float s1, bool has_shift,
+                                      EvalOut<S>& o)
+{
+    NodesComputed<G, S, MP, Tab> nf{P, tab, X, s0, s1, has_shift};
+    lobes_nodes(P, X, wo_g, nf, o);
 }
 
 __host__ __device__ inline uint32_t check_inputs(float h, float u, float v, const V3<float>& a)
@@ -656,11 +699,11 @@ template <class S> struct SampleOut {
 // cosine lobes the body lobes.  The weight is the full value over the full
 // mixture pdf at the drawn direction.  Lobes: 0 x-specular, 1 y-specular,
 // 2 x-body, 3 y-body, 4 pass-through.
-template <class G, class S, class Tab>
-__host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const Tab& tab, float h,
-                                                 float u, float v, const V3<float>& wi, float xi0,
-                                                 float xi1, float xi2, float s0, float s1,
-                                                 bool has_shift, SampleOut<S>& so)
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                  const V3<float>& wi, float xi0, float xi1,
+                                                  float xi2, const NodeFn& node_of,
+                                                  SampleOut<S>& so)
 {
     for (int c = 0; c < 3; ++c) {
         so.wo[c] = S(0); so.wgt[c] = S(0); so.ex[c] = S(0);
@@ -668,11 +711,7 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
     so.pdf = S(0);
     so.lobe = -1;
     so.node = 0;
-    uint32_t flags = check_inputs(h, u, v, wi);
-    if (flags) return flags;
-    XState<G, S> X;
-    state_at_x(P, tab, h, u, v, wi, X);
-    flags = X.ph.flags;
+    uint32_t flags = X.ph.flags;
     if (X.ph.pass) {
         so.wo[0] = S(-wi.x); so.wo[1] = S(-wi.y); so.wo[2] = S(-wi.z);
         so.wgt[0] = so.wgt[1] = so.wgt[2] = S(1);
@@ -686,7 +725,8 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
     int node = 0;
     if (lobe == 1 || lobe == 3) {
         S lo = lobe == 1 ? c0 : c2;
-        S xk = (S(x0) - lo) / X.w[lobe] * S(float(P.K));
+        S wl = lobe == 1 ? X.w[1] : X.w[3];
+        S xk = (S(x0) - lo) / wl * S(float(P.K));
         int nk = (int)floorf(val(xk));
         node = nk > P.K - 1 ? P.K - 1 : (nk < 0 ? 0 : nk);
     }
@@ -707,7 +747,7 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
     } else if (lobe == 1) {
         // refraction out of the yarn at the node's exit point
         Node<G, S> nd;
-        forward_node(P, tab, X, node, s0, s1, has_shift, nd);
+        node_of(node, nd);
         ex = nd.y;
         V3<G> wip = -nd.wt;
         Frame<G> fi;
@@ -733,14 +773,15 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
             fr = X.fx;
         } else {
             Node<G, S> nd;
-            forward_node(P, tab, X, node, s0, s1, has_shift, nd);
+            node_of(node, nd);
             fr = nd.fy;
             ex = nd.y;
         }
         G rad = sqrt_(gx1);
-        G ang = G(kTwoPi) * gx2;
+        G su, cu;
+        sincos_turns_g(gx2, &su, &cu);
         G z = G(1) - gx1;
-        wo = to_world(fr, mk3<G>(rad * cos_(ang), rad * sin_(ang), val(z) > 0.0 ? sqrt_(z) : G(0)));
+        wo = to_world(fr, mk3<G>(rad * cu, rad * su, val(z) > 0.0 ? sqrt_(z) : G(0)));
         ok = true;
     }
     so.ex[0] = Narrow<S>::from(ex.x);
@@ -749,7 +790,7 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
     if (!ok) return flags | F_SAMPLE_FAIL;
     wo = normalize(wo);
     EvalOut<S> e;
-    lobes(P, tab, X, wo, s0, s1, has_shift, e);
+    lobes_nodes(P, X, wo, node_of, e);
     if (!(val(e.pdf) > 0.0f)) return flags | F_SAMPLE_FAIL;
     so.wo[0] = Narrow<S>::from(wo.x);
     so.wo[1] = Narrow<S>::from(wo.y);
@@ -758,6 +799,28 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
     for (int c = 0; c < 3; ++c) so.wgt[c] = e.E[c] * ip;
     so.pdf = e.pdf;
     return flags;
+}
+
+template <class G, class S, int MP, class Tab>
+__host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const Tab& tab, float h,
+                                                 float u, float v, const V3<float>& wi, float xi0,
+                                                 float xi1, float xi2, float s0, float s1,
+                                                 bool has_shift, SampleOut<S>& so)
+{
+    uint32_t bad = check_inputs(h, u, v, wi);
+    if (bad) {
+        for (int c = 0; c < 3; ++c) {
+            so.wo[c] = S(0); so.wgt[c] = S(0); so.ex[c] = S(0);
+        }
+        so.pdf = S(0);
+        so.lobe = -1;
+        so.node = 0;
+        return bad;
+    }
+    XState<G, S, MP> X;
+    state_at_x(P, tab, h, u, v, wi, X);
+    NodesComputed<G, S, MP, Tab> nf{P, tab, X, s0, s1, has_shift};
+    return sample_from_x(P, X, wi, xi0, xi1, xi2, nf, so);
 }
 
 }  // namespace bysdf
