@@ -195,6 +195,34 @@ int bysdf_sample_pdf(const bysdf_types_t* types, const bysdf_sample_soa* q, int6
 int bysdf_furnace_blocks(const bysdf_types_t* types, const bysdf_sample_soa* q, int64_t n,
                          int32_t block, float* mean, float* var, hipStream_t stream);
 
+/* Bytes of device workspace bysdf_eval_backward needs for n queries of a
+ * handle with n_types types (0 on bad arguments). */
+size_t bysdf_backward_workspace_size(int64_t n, int32_t n_types);
+
+/* Adjoint of bysdf_eval with respect to the eight differentiable parameters
+ * theta = (albedo r, g, b, beta, ply_twist, fiber_twist, ply_density,
+ * fiber_density) of every type (the parameters a fitting loop adjusts, in
+ * the spirit of the differentiable fitting of Sec. 5.2):
+ *   grad_theta[t][k] = sum over queries q of type t of
+ *                      sum_c grad_E[q][c] * dE_c(q) / d theta_k.
+ * Queries are grouped by type: type t owns queries
+ * [type_offsets[t], type_offsets[t+1]) (DEVICE int64 array of n_types + 1
+ * entries, type_offsets[n_types] == n; q->type_id is not read).  grad_E is
+ * a DEVICE float array n x 3 (row-major), grad_theta DEVICE n_types x 8,
+ * per_query (nullable) DEVICE n x 8 receives each query's terms.  beta and
+ * the twists are differentiated by forward-mode tangents through the whole
+ * model (shadowing recomputed, nothing stored by the forward pass); the
+ * albedo and the densities enter linearly and use closed forms.  Away from
+ * the model's discrete decisions this is the derivative; at a texel centre
+ * of the fiber table it is one-sided.  Each tile of at most 256 queries of
+ * one type reduces to a partial in a fixed tree order and partials add up
+ * per type in tile order: results are bitwise reproducible.  workspace is a
+ * DEVICE buffer of bysdf_backward_workspace_size(n, n_types) bytes,
+ * 256-byte aligned, owned by the caller. */
+int bysdf_eval_backward(const bysdf_types_t* types, const bysdf_query_soa* q, int64_t n,
+                        const int64_t* type_offsets, const float* grad_E, float* grad_theta,
+                        float* per_query, void* workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Host-only: algorithmic operation count of the kernels' formulation.
  * Runs the per-query model on the host with counting scalars over n
  * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type

@@ -1,0 +1,42 @@
+"""torch.autograd.Function around the BYSDF and its hand-written adjoint.
+
+BYSDFEval.apply(theta, types, q, offsets) returns E (n x 3, RGB) for the
+queries q grouped by type (offsets: int64 CSR on the device) at the per-type
+parameters theta (n_types x 8: albedo r g b, beta, ply twist, fiber twist,
+ply density, fiber density).  The forward pass writes theta into the handle
+(bysdf_types_set_theta) and runs bysdf_eval; the backward pass runs
+bysdf_eval_backward, which recomputes the model (shadowing included) with
+forward-mode tangents, so nothing but the inputs is kept between the passes.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import bysdf
+
+
+class BYSDFEval(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, types, q, offsets):
+        assert theta.is_cuda and theta.dtype == torch.float32
+        th = theta.detach().contiguous()
+        bysdf.bysdf_types_set_theta(types, th)
+        vals, _ = bysdf.bysdf_eval(types, q)
+        ctx.types, ctx.q, ctx.offsets = types, q, offsets
+        ctx.keep = th  # keeps theta alive until the handle's copy has run
+        return vals[0:3].t().contiguous()
+
+    @staticmethod
+    def backward(ctx, grad_E):
+        g, _ = bysdf.bysdf_eval_backward(ctx.types, ctx.q, ctx.offsets, grad_E.contiguous())
+        return g, None, None, None
+
+
+def bysdf_fit_step(theta, types, q, offsets, target, opt):
+    """One step of the least-squares fit sum (E - target)^2 with optimiser opt."""
+    opt.zero_grad(set_to_none=True)
+    E = BYSDFEval.apply(theta, types, q, offsets)
+    loss = ((E - target) ** 2).sum()
+    loss.backward()
+    opt.step()
+    return loss.detach()

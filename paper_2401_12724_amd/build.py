@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbysdf.so")
 SOURCES = ["bysdf_lib.hip"]
-HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_opcount.hpp"]
+HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_opcount.hpp", "bysdf_dual.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -96,6 +96,10 @@ def lib():
                                        C.POINTER(SampleOutSoA), _vp]
         L.bysdf_furnace_blocks.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64, C.c_int32, _vp,
                                            _vp, _vp]
+        L.bysdf_backward_workspace_size.argtypes = [C.c_int64, C.c_int32]
+        L.bysdf_backward_workspace_size.restype = C.c_size_t
+        L.bysdf_eval_backward.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, _vp, _vp, _vp, _vp,
+                                          _vp, C.c_size_t, _vp]
         _lib = L
     return _lib
 
@@ -275,3 +279,36 @@ def bysdf_furnace_blocks(types: Types, q: dict, block: int = 256, mean=None, var
     _check(lib().bysdf_furnace_blocks(types.handle, C.byref(qs), n, block, _ptr(mean), _ptr(var),
                                       _stream(stream)), "bysdf_furnace_blocks")
     return mean, var
+
+
+def bysdf_backward_workspace_size(n: int, n_types: int) -> int:
+    return int(lib().bysdf_backward_workspace_size(n, n_types))
+
+
+def bysdf_eval_backward(types: Types, q: dict, offsets, grad_E, grad_theta=None,
+                        per_query=False, workspace=None, stream=None):
+    """Adjoint of bysdf_eval.  offsets: int64 cuda tensor [n_types + 1] (queries
+    grouped by type); grad_E: float32 cuda tensor [n, 3].  Returns
+    (grad_theta float32[n_types, 8], per_query float32[n, 8] or None)."""
+    import torch
+    n = int(q["h"].numel())
+    dev = q["h"].device
+    assert offsets.dtype == torch.int64 and offsets.is_cuda and offsets.numel() == types.n_types + 1
+    assert grad_E.is_contiguous() and grad_E.dtype == torch.float32 and grad_E.numel() == 3 * n
+    if grad_theta is None:
+        grad_theta = torch.empty((types.n_types, 8), dtype=torch.float32, device=dev)
+    pq = None
+    if per_query is True:
+        pq = torch.empty((n, 8), dtype=torch.float32, device=dev)
+    elif per_query is not False and per_query is not None:
+        pq = per_query
+    ws = bysdf_backward_workspace_size(n, types.n_types)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) & ~255
+    qs = _qsoa(q)
+    _check(lib().bysdf_eval_backward(types.handle, C.byref(qs), n, offsets.data_ptr(),
+                                     grad_E.data_ptr(), grad_theta.data_ptr(), _ptr(pq),
+                                     aligned, ws, _stream(stream)), "bysdf_eval_backward")
+    return grad_theta, pq

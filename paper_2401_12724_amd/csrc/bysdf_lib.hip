@@ -24,6 +24,7 @@
 #include "../../include/bysdf.h"
 #include "bysdf_model.hpp"
 #include "bysdf_opcount.hpp"
+#include "bysdf_dual.hpp"
 
 using namespace bysdf;
 
@@ -457,6 +458,138 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ tiles
+// Queries grouped by type (CSR offsets, device int64[n_types + 1]) are cut
+// into tiles of at most kBlock queries that never straddle a type.
+// tile_first[t] = index of the first tile of type t (exclusive scan of
+// ceil(count_t / kBlock)); tile_first[n_types] = number of tiles.
+__global__ __launch_bounds__(1024) void k_tile_scan(const int64_t* __restrict__ off, int n_types,
+                                                    int32_t* __restrict__ tile_first)
+{
+    __shared__ int32_t s[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int chunk = (n_types + nt - 1) / nt;
+    const int lo = min(n_types, tid * chunk), hi = min(n_types, lo + chunk);
+    int32_t sum = 0;
+    for (int t = lo; t < hi; ++t) sum += (int32_t)((off[t + 1] - off[t] + kBlock - 1) / kBlock);
+    s[tid] = sum;
+    __syncthreads();
+    for (int st = 1; st < nt; st <<= 1) {  // inclusive Hillis-Steele scan
+        int32_t add = tid >= st ? s[tid - st] : 0;
+        __syncthreads();
+        s[tid] += add;
+        __syncthreads();
+    }
+    int32_t run = s[tid] - sum;  // exclusive prefix of this chunk
+    for (int t = lo; t < hi; ++t) {
+        tile_first[t] = run;
+        run += (int32_t)((off[t + 1] - off[t] + kBlock - 1) / kBlock);
+    }
+    if (tid == nt - 1) tile_first[n_types] = s[tid];
+}
+
+// tile -> (type, first query, count); false past the last tile
+__device__ inline bool locate_tile(int tile, const int32_t* __restrict__ tile_first, int n_types,
+                                   const int64_t* __restrict__ off, int* type, int64_t* start,
+                                   int* count)
+{
+    if (tile >= tile_first[n_types]) return false;
+    int lo = 0, hi = n_types - 1;  // last t with tile_first[t] <= tile
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tile_first[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    *type = lo;
+    *start = off[lo] + (int64_t)(tile - tile_first[lo]) * kBlock;
+    int64_t left = off[lo + 1] - *start;
+    *count = (int)(left < kBlock ? left : kBlock);
+    return true;
+}
+
+// ------------------------------------------------------------------ adjoint
+// One workgroup per tile.  Each lane recomputes its query three times with
+// the tangent seeded on beta, ply twist and fiber twist (forward-mode dual
+// scalars through the same model, shadowing included), contracts the
+// tangents of E with grad_E, and adds the closed-form derivatives of the
+// linear parameters (albedo, densities).  The tile's lanes reduce in a
+// fixed tree order to one partial per tile.
+template <int MP>
+__global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__ types,
+                                                     const float4* __restrict__ tables, QPtrs q,
+                                                     const int64_t* __restrict__ off, int n_types,
+                                                     const int32_t* __restrict__ tile_first,
+                                                     const float* __restrict__ gE,
+                                                     float* __restrict__ partials,
+                                                     float* __restrict__ per_query)
+{
+    __shared__ float s_red[8][kBlock];
+    int t = 0, count = 0;
+    int64_t start = 0;
+    if (!locate_tile(blockIdx.x, tile_first, n_types, off, &t, &start, &count)) return;
+    t = __builtin_amdgcn_readfirstlane(t);
+    const int tid = threadIdx.x;
+    const TypeRec& rec = types[t];
+    TabPtr tab;
+    tab.p = tables + rec.table_off;
+    float g[8];
+    for (int k = 0; k < 8; ++k) g[k] = 0.0f;
+    if (tid < count) {
+        const int64_t i = start + tid;
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+        const float h = q.h[i], u = q.u[i], v = q.v[i];
+        const bool bad = (check_inputs(h, u, v, wi) | check_dir(wo)) != 0u;
+        if (!bad) {
+            const float ge[3] = {gE[3 * i], gE[3 * i + 1], gE[3 * i + 2]};
+            const float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+            V3<DD> wo_d = mk3<DD>(DD((double)wo.x), DD((double)wo.y), DD((double)wo.z));
+            for (int p = 0; p < 3; ++p) {
+                Derived<DD, DF> P = derive_dual(rec, p);
+                XState<DD, DF, MP> X;
+                state_at_x(P, tab, h, u, v, wi, X);
+                if (X.ph.pass) break;
+                EvalOut<DF> e;
+                lobes(P, tab, X, wo_d, s0, s1, q.s0 != nullptr, e);
+                g[3 + p] = ge[0] * e.E[0].d + ge[1] * e.E[1].d + ge[2] * e.E[2].d;
+                if (p == 0) {
+                    const float b0 = e.body0.v, Gp = X.Gp.v, Gf = X.Gf.v;
+                    const float op = 1.0f - (float)X.rawp.v, of = 1.0f - (float)X.rawf.v;
+                    float sa = 0.0f;
+                    for (int c = 0; c < 3; ++c) {
+                        g[c] = ge[c] * b0 * Gp * Gf;
+                        sa += ge[c] * rec.d.alb[c];
+                    }
+                    g[6] = -sa * b0 * Gf * op;
+                    g[7] = -sa * b0 * Gp * of;
+                }
+            }
+        }
+        if (per_query)
+            for (int k = 0; k < 8; ++k) per_query[8 * i + k] = g[k];
+    }
+    for (int k = 0; k < 8; ++k) s_red[k][tid] = g[k];
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int k = 0; k < 8; ++k) s_red[k][tid] += s_red[k][tid + st];
+        __syncthreads();
+    }
+    if (tid < 8) partials[8 * (int64_t)blockIdx.x + tid] = s_red[tid][0];
+}
+
+// grad[t] = sum of the partials of type t's tiles, in tile order
+__global__ void k_backward_sum(const int32_t* __restrict__ tile_first, int n_types,
+                               const float* __restrict__ partials, float* __restrict__ grad)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_types) return;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int tl = tile_first[t]; tl < tile_first[t + 1]; ++tl)
+        for (int k = 0; k < 8; ++k) acc[k] += partials[8 * (int64_t)tl + k];
+    for (int k = 0; k < 8; ++k) grad[8 * (int64_t)t + k] = acc[k];
+}
+
 // ------------------------------------------------------------------ theta
 __global__ void k_set_theta(TypeRec* types, const float* theta, int n)
 {
@@ -740,5 +873,53 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
         counts[5 * k + 3] = tally.sqrt[k] / n;
         counts[5 * k + 4] = tally.trans[k] / n;
     }
+    return BYSDF_OK;
+}
+
+// ------------------------------------------------------------------ adjoint API
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int64_t max_tiles(int64_t n, int32_t n_types) { return (n + kBlock - 1) / kBlock + n_types; }
+
+extern "C" size_t bysdf_backward_workspace_size(int64_t n, int32_t n_types)
+{
+    if (n < 0 || n_types < 1) return 0;
+    return align256(sizeof(int32_t) * (size_t)(n_types + 1)) +
+           sizeof(float) * 8 * (size_t)max_tiles(n, n_types);
+}
+
+extern "C" int bysdf_eval_backward(const bysdf_types_t* h, const bysdf_query_soa* q, int64_t n,
+                                   const int64_t* type_offsets, const float* grad_E,
+                                   float* grad_theta, float* per_query, void* workspace,
+                                   size_t ws_bytes, hipStream_t stream)
+{
+    if (!h || !q || !type_offsets || !aligned4(grad_E) || !aligned4(grad_theta))
+        return fail(BYSDF_ERR_INVALID_ARG, "NULL or misaligned argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    const void* need[] = {q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query pointer is NULL or misaligned");
+    if (((uintptr_t)type_offsets & 7u) != 0) return fail(BYSDF_ERR_INVALID_ARG, "type_offsets misaligned");
+    if (per_query && !aligned4(per_query)) return fail(BYSDF_ERR_INVALID_ARG, "per_query misaligned");
+    if ((q->shift0 == nullptr) != (q->shift1 == nullptr))
+        return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
+    size_t need_ws = bysdf_backward_workspace_size(n, h->n_types);
+    if (!workspace || ws_bytes < need_ws || ((uintptr_t)workspace & 255u))
+        return fail(BYSDF_ERR_INVALID_ARG, "workspace needs %zu bytes, 256-byte aligned", need_ws);
+    int32_t* tile_first = (int32_t*)workspace;
+    float* partials = (float*)((char*)workspace + align256(sizeof(int32_t) * (h->n_types + 1)));
+    QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
+             q->shift0, q->shift1};
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, type_offsets, h->n_types, tile_first);
+    HIP_TRY(hipGetLastError());
+    int64_t tiles = max_tiles(n, h->n_types);
+    if (tiles > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many tiles");
+    auto kern = h->max_plies <= 4 ? k_backward<4> : k_backward<8>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(kBlock), 0, stream, h->d_types, h->d_tables, qp,
+                       type_offsets, h->n_types, tile_first, grad_E, partials, per_query);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_backward_sum, dim3((h->n_types + 255) / 256), dim3(256), 0, stream, tile_first,
+                       h->n_types, partials, grad_theta);
+    HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }

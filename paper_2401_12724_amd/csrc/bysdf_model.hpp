@@ -388,6 +388,7 @@ template <class G, class S, int MP> struct XState {
     S Gp, Gf, mu_i;
     S w[4];           // lobe selection weights
     G a;
+    G rawp, rawf;     // visibilities before the density blends
 };
 
 template <class G, class S, int MP, class Tab>
@@ -409,6 +410,8 @@ __host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& ta
     // small visible share that single precision cannot resolve
     G phi = atan2_(X.ph.n2x * X.wi_g.y - X.ph.n2y * X.wi_g.x, X.ph.n2x * X.wi_g.x + X.ph.n2y * X.wi_g.y);
     G raw = ply_shadow_raw<G, MP>(P.Np, P.rp, P.Rpc, G(val(P.dP)), X.a, phi);
+    X.rawp = raw;
+    X.rawf = gft;
     X.Gp = Narrow<S>::from(G(1) - G(val(P.rho_p)) * (G(1) - raw));
     X.Gf = Narrow<S>::from(G(1) - G(val(P.rho_f)) * (G(1) - gft));
     X.mu_i = Narrow<S>::from(dot(X.wi_g, X.fx.n));
@@ -574,6 +577,7 @@ __host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& w
 
 template <class S> struct EvalOut {
     S E[3], ExS, EyS, ExB[3], EyB[3], pdf;
+    S body0;  // body lobes per unit albedo without G_p G_f (closed-form derivatives)
 };
 
 // The four lobes of Eq. 1 and the mixture pdf of Sec. 4.1.5 at wo.  Dot
@@ -600,11 +604,11 @@ __host__ __device__ inline void lobes_nodes(const Derived<G, S>& P, const XState
         ExS = (S(1) - P.B) * P.kS * fresnel<S>(ihp, P.eta) * g1i * g1o * D / (S(4) * mu_i);
         if (val(oh) > 0.0f) pxS = g1i * ihp * D / mu_i / (S(4) * oh);
     }
-    S bx = S(0), pxB = S(0);
+    S bxu = S(0), pxB = S(0);
     if (val(mu_o_g) > 0.0) {
         S mp = front_i ? mu_i : S(0);
         S fls = S(1) / (S(float(4.0 * kPi)) * (mp + mu_o));
-        bx = P.B * P.r * X.Gp * X.Gf * (fls + S(float(1.0 / kPi))) * mu_o / (S(1) + ls_albedo<S>(mp));
+        bxu = P.B * P.r * (fls + S(float(1.0 / kPi))) * mu_o / (S(1) + ls_albedo<S>(mp));
         pxB = mu_o * S(float(1.0 / kPi));
     }
     S EyS = S(0), pyS = S(0), by = S(0), pyB = S(0);
@@ -627,14 +631,17 @@ __host__ __device__ inline void lobes_nodes(const Derived<G, S>& P, const XState
     S invK = S(1) / S(float(P.K));
     EyS = EyS * (S(1) - P.B) * P.kS * invK;
     pyS = pyS * invK;
-    by = by * P.B * (S(1) - P.r) * X.Gp * X.Gf * invK;
+    S byu = by * P.B * (S(1) - P.r) * invK;
     pyB = pyB * invK;
+    S gg = X.Gp * X.Gf;
+    S bx = bxu * gg, byg = byu * gg;
+    o.body0 = bxu + byu;
     o.ExS = ExS;
     o.EyS = EyS;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         o.ExB[c] = bx * P.alb[c];
-        o.EyB[c] = by * P.alb[c];
+        o.EyB[c] = byg * P.alb[c];
         o.E[c] = ExS + EyS + o.ExB[c] + o.EyB[c];
     }
     o.pdf = X.w[0] * pxS + X.w[1] * pyS + X.w[2] * pxB + X.w[3] * pyB;
