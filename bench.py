@@ -92,6 +92,78 @@ def _cpu_baseline(P, q, target_s):
                       "stages (eval, sample, eval at sampled wo, furnace), %.1f s" % (nb, n, dt)}
 
 
+def _timed(torch, fn, reps):
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return float(np.median(ms))
+
+
+def _hetero(torch, bysdf, W, single_type_eval_qps):
+    """4,096 types with lognormal counts (~2^26 queries) in one persistent
+    launch: autotuned schedule, captured in a graph, replayed."""
+    from paper_2401_12724_amd import autotune
+    P, q, off = W.heterogeneous(4096, 3)
+    n = len(q["h"])
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    del q
+    offd = torch.from_numpy(off).cuda()
+    out = bysdf.alloc_eval_out(n)
+    cands = [dict(chunk=c, grid=g, use_lds=l) for c in (1, 4, 16) for g in (1024, 4096)
+             for l in (1, 0)]
+    tune = autotune.autotune_batched(T, offd, qd, off, out=out, candidates=cands, reps=2)
+    ws = bysdf.alloc_workspace(bysdf.bysdf_batched_workspace_size(T.n_types))
+    sc = tune["schedule"]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bysdf.bysdf_eval_batched(T, offd, qd, out, sc, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bysdf.bysdf_eval_batched(T, offd, qd, out, sc, ws)
+    ms = _timed(torch, g.replay, 5)
+    qps = n / (ms * 1e-3)
+    return {"queries": n, "types": 4096, "ms": ms, "queries_per_s": qps,
+            "schedule": sc, "single_type_eval_queries_per_s": single_type_eval_qps,
+            "vs_single_type": qps / single_type_eval_qps, "launch": "hipGraph replay",
+            "candidates": len(cands)}
+
+
+def _fwd_bwd(torch, bysdf, W):
+    """64 types x 65,536 queries grouped by type: plain forward (bysdf_eval)
+    against forward + adjoint (bysdf_eval + bysdf_eval_backward)."""
+    hidden, start, q = W.fitting(64, 65536, 4)
+    n = len(q["h"])
+    off = torch.from_numpy(np.arange(65, dtype=np.int64) * 65536).cuda()
+    T = bysdf.bysdf_types_create(hidden)
+    qd = bysdf.to_device(q)
+    out = bysdf.alloc_eval_out(n)
+    gE = torch.randn((n, 3), dtype=torch.float32, device="cuda")
+    gt = torch.empty((64, 8), dtype=torch.float32, device="cuda")
+    ws = torch.empty(bysdf.bysdf_backward_workspace_size(n, 64) + 256, dtype=torch.uint8,
+                     device="cuda")
+    fwd = lambda: bysdf.bysdf_eval(T, qd, out)
+    both = lambda: (bysdf.bysdf_eval(T, qd, out),
+                    bysdf.bysdf_eval_backward(T, qd, off, gE, gt, workspace=ws))
+    fwd()
+    both()
+    torch.cuda.synchronize()
+    f_ms = _timed(torch, fwd, 5)
+    b_ms = _timed(torch, both, 3)
+    return {"queries": n, "types": 64, "fwd_ms": f_ms, "fwd_bwd_ms": b_ms,
+            "fwd_queries_per_s": n / (f_ms * 1e-3), "fwd_bwd_queries_per_s": n / (b_ms * 1e-3),
+            "fwd_bwd_over_fwd_time": b_ms / f_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +174,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for PMC byte scaling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the heterogeneous-batch and adjoint measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs single-GPU only "
@@ -210,6 +284,11 @@ def main():
                           "order": "add mul div sqrt transcendental"},
         "src_hash": _src_hash(),
     }
+    if not args.no_extras:
+        eval_qps = N / (ktime["eval"] * 1e-3)
+        del ev, sv, ev2, q2
+        out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
+        out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(P, q, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -195,6 +195,34 @@ int bysdf_sample_pdf(const bysdf_types_t* types, const bysdf_sample_soa* q, int6
 int bysdf_furnace_blocks(const bysdf_types_t* types, const bysdf_sample_soa* q, int64_t n,
                          int32_t block, float* mean, float* var, hipStream_t stream);
 
+/* Schedule of bysdf_eval_batched (see paper_2401_12724_amd/autotune.py,
+ * which picks one by timing candidates on the workload at hand). */
+typedef struct {
+    int32_t chunk;    /* consecutive tiles a workgroup takes per visit, 1..64 */
+    int32_t grid;     /* persistent workgroups (0: 2048)                      */
+    int32_t use_lds;  /* stage each tile's fiber table in LDS (when <= 2048
+                         texels) instead of reading it through the caches     */
+    int32_t reserved;
+} bysdf_schedule;
+
+/* Bytes of device workspace bysdf_eval_batched needs (0 on bad arguments). */
+size_t bysdf_batched_workspace_size(int32_t n_types);
+
+/* bysdf_eval for a heterogeneous batch in one persistent launch: queries
+ * grouped by type (type t owns [type_offsets[t], type_offsets[t+1]),
+ * DEVICE int64 CSR of n_types + 1 entries, type_offsets[n_types] == n;
+ * q->type_id is not read), cut into tiles of at most 256 queries of one
+ * type that workgroups take from a device queue.  Same outputs as
+ * bysdf_eval.  sched may be NULL (chunk 4, grid 2048, LDS staging).  The
+ * launch sequence (a scan, a counter reset, the persistent kernel) contains
+ * no memset and no host synchronisation, so it can be captured in a graph;
+ * calls sharing one workspace must not overlap.  workspace: DEVICE buffer
+ * of bysdf_batched_workspace_size(n_types) bytes, 256-byte aligned. */
+int bysdf_eval_batched(const bysdf_types_t* types, const int64_t* type_offsets, int64_t n,
+                       const bysdf_query_soa* q, const bysdf_eval_out_soa* out,
+                       const bysdf_schedule* sched, void* workspace, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* Bytes of device workspace bysdf_eval_backward needs for n queries of a
  * handle with n_types types (0 on bad arguments). */
 size_t bysdf_backward_workspace_size(int64_t n, int32_t n_types);

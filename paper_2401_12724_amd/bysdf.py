@@ -68,6 +68,11 @@ class SampleSoA(C.Structure):
                                    "xi0", "xi1", "xi2", "shift0", "shift1")]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("grid", C.c_int32), ("use_lds", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class SampleOutSoA(C.Structure):
     _fields_ = [(n, _vp) for n in ("wo_x", "wo_y", "wo_z", "w_r", "w_g", "w_b", "pdf",
                                    "exit_x", "exit_y", "exit_z", "lobe", "node", "flags")]
@@ -96,6 +101,11 @@ def lib():
                                        C.POINTER(SampleOutSoA), _vp]
         L.bysdf_furnace_blocks.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64, C.c_int32, _vp,
                                            _vp, _vp]
+        L.bysdf_batched_workspace_size.argtypes = [C.c_int32]
+        L.bysdf_batched_workspace_size.restype = C.c_size_t
+        L.bysdf_eval_batched.argtypes = [_vp, _vp, C.c_int64, C.POINTER(QuerySoA),
+                                         C.POINTER(EvalOutSoA), C.POINTER(Schedule), _vp,
+                                         C.c_size_t, _vp]
         L.bysdf_backward_workspace_size.argtypes = [C.c_int64, C.c_int32]
         L.bysdf_backward_workspace_size.restype = C.c_size_t
         L.bysdf_eval_backward.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, _vp, _vp, _vp, _vp,
@@ -240,6 +250,48 @@ def bysdf_eval(types: Types, q: dict, out=None, stream=None):
     qs = _qsoa(q)
     _check(lib().bysdf_eval(types.handle, C.byref(qs), n, C.byref(o), _stream(stream)),
            "bysdf_eval")
+    return vals, flags
+
+
+def _eval_out_soa(vals, flags):
+    o = EvalOutSoA()
+    names = ("E_r", "E_g", "E_b", "E_xS", "E_yS", "E_xB_r", "E_xB_g", "E_xB_b", "E_yB_r",
+             "E_yB_g", "E_yB_b", "pdf")
+    for i, nm in enumerate(names):
+        setattr(o, nm, _ptr(vals[i]))
+    o.flags = _ptr(flags)
+    return o
+
+
+def bysdf_batched_workspace_size(n_types: int) -> int:
+    return int(lib().bysdf_batched_workspace_size(n_types))
+
+
+def alloc_workspace(nbytes, device="cuda"):
+    """Device workspace with a 256-byte aligned pointer: (tensor, ptr)."""
+    import torch
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return t, (t.data_ptr() + 255) & ~255
+
+
+def bysdf_eval_batched(types: Types, offsets, q: dict, out=None, sched=None, workspace=None,
+                       stream=None):
+    """Heterogeneous batch grouped by type (offsets: int64 cuda CSR).
+    sched: dict(chunk, grid, use_lds) or None.  workspace: (tensor, ptr) from
+    alloc_workspace or None.  Returns (vals float32[12, n], flags int32[n])."""
+    n = int(q["h"].numel())
+    vals, flags = out if out is not None else alloc_eval_out(n, q["h"].device)
+    o = _eval_out_soa(vals, flags)
+    ws = bysdf_batched_workspace_size(types.n_types)
+    if workspace is None:
+        workspace = alloc_workspace(ws, q["h"].device)
+    sc = None
+    if sched is not None:
+        sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]), 0)
+    qs = _qsoa(q)
+    _check(lib().bysdf_eval_batched(types.handle, offsets.data_ptr(), n, C.byref(qs), C.byref(o),
+                                    C.byref(sc) if sc is not None else None, workspace[1], ws,
+                                    _stream(stream)), "bysdf_eval_batched")
     return vals, flags
 
 

@@ -590,6 +590,82 @@ __global__ void k_backward_sum(const int32_t* __restrict__ tile_first, int n_typ
     for (int k = 0; k < 8; ++k) grad[8 * (int64_t)t + k] = acc[k];
 }
 
+// ------------------------------------------------------------------ hetero
+// Persistent evaluation of a batch grouped by type.  Workgroups take
+// `chunk` consecutive tiles at a time from a device counter (reset by
+// k_reset_counter on the same stream, so the pair can be captured in a
+// graph); a tile holds at most kBlock queries of one type, whose scalars
+// are read with scalar loads and whose fiber table is staged in LDS when
+// the type changes.  Every workgroup loops until the counter passes the
+// last tile, so the grid always drains.
+__global__ void k_reset_counter(int* counter) { *counter = 0; }
+
+template <int MP, bool kLds>
+__global__ __launch_bounds__(kBlock) void k_eval_batched(
+    const TypeRec* __restrict__ types, const float4* __restrict__ tables,
+    const int64_t* __restrict__ off, int n_types, const int32_t* __restrict__ tile_first,
+    int* counter, QPtrs q, OPtrs o, int chunk)
+{
+    __shared__ float4 s_tab[kLds ? kMaxLdsTexels : 1];
+    __shared__ int s_next;
+    const int tid = threadIdx.x;
+    const int n_tiles = tile_first[n_types];
+    int staged = -1;
+    for (;;) {
+        if (tid == 0) s_next = atomicAdd(counter, chunk);
+        __syncthreads();
+        const int t0 = s_next;
+        __syncthreads();
+        if (t0 >= n_tiles) break;
+        for (int c = 0; c < chunk; ++c) {
+            int type = 0, count = 0;
+            int64_t start = 0;
+            if (!locate_tile(t0 + c, tile_first, n_types, off, &type, &start, &count)) break;
+            type = __builtin_amdgcn_readfirstlane(type);
+            const TypeRec& rec = types[type];
+            TabPtr tab;
+            if (kLds) {
+                if (type != staged) {
+                    __syncthreads();
+                    for (int k = tid; k < rec.tex_size; k += kBlock) s_tab[k] = tables[rec.table_off + k];
+                    __syncthreads();
+                    staged = type;
+                }
+                tab.p = s_tab;
+            } else {
+                tab.p = tables + rec.table_off;
+            }
+            if (tid >= count) continue;
+            const int64_t i = start + tid;
+            V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+            V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+            const float h = q.h[i], u = q.u[i], v = q.v[i];
+            uint32_t fl = check_inputs(h, u, v, wi) | check_dir(wo);
+            EvalOut<float> e;
+            for (int k = 0; k < 3; ++k) e.E[k] = e.ExB[k] = e.EyB[k] = 0.0f;
+            e.ExS = e.EyS = e.pdf = 0.0f;
+            if (!fl) {
+                const Derived<double, float>& P = rec.d;
+                XState<double, float, MP> X;
+                state_at_x(P, tab, h, u, v, wi, X);
+                fl = X.ph.flags;
+                if (!X.ph.pass) {
+                    if (!(X.mu_i > 0.0f)) fl |= F_BACKFACING;
+                    const float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+                    V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
+                    lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
+                }
+            }
+            o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
+            o.ExS[i] = e.ExS; o.EyS[i] = e.EyS;
+            o.ExBr[i] = e.ExB[0]; o.ExBg[i] = e.ExB[1]; o.ExBb[i] = e.ExB[2];
+            o.EyBr[i] = e.EyB[0]; o.EyBg[i] = e.EyB[1]; o.EyBb[i] = e.EyB[2];
+            o.pdf[i] = e.pdf;
+            o.flags[i] = fl;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ theta
 __global__ void k_set_theta(TypeRec* types, const float* theta, int n)
 {
@@ -920,6 +996,75 @@ extern "C" int bysdf_eval_backward(const bysdf_types_t* h, const bysdf_query_soa
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_backward_sum, dim3((h->n_types + 255) / 256), dim3(256), 0, stream, tile_first,
                        h->n_types, partials, grad_theta);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+// ------------------------------------------------------------------ hetero API
+extern "C" size_t bysdf_batched_workspace_size(int32_t n_types)
+{
+    if (n_types < 1) return 0;
+    return align256(sizeof(int32_t) * (size_t)(n_types + 1)) + 256;
+}
+
+template <int MP>
+static void launch_batched(const bysdf_types_t* h, bool lds, int grid, hipStream_t stream,
+                           const int64_t* off, const int32_t* tile_first, int* counter, QPtrs qp,
+                           OPtrs op, int chunk)
+{
+    if (lds)
+        hipLaunchKernelGGL((k_eval_batched<MP, true>), dim3(grid), dim3(kBlock), 0, stream, h->d_types,
+                           h->d_tables, off, h->n_types, tile_first, counter, qp, op, chunk);
+    else
+        hipLaunchKernelGGL((k_eval_batched<MP, false>), dim3(grid), dim3(kBlock), 0, stream, h->d_types,
+                           h->d_tables, off, h->n_types, tile_first, counter, qp, op, chunk);
+}
+
+extern "C" int bysdf_eval_batched(const bysdf_types_t* h, const int64_t* type_offsets, int64_t n,
+                                  const bysdf_query_soa* q, const bysdf_eval_out_soa* o,
+                                  const bysdf_schedule* sched, void* workspace, size_t ws_bytes,
+                                  hipStream_t stream)
+{
+    if (!h || !q || !o || !type_offsets) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (((uintptr_t)type_offsets & 7u) != 0) return fail(BYSDF_ERR_INVALID_ARG, "type_offsets misaligned");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    const void* need[] = {q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
+                          o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
+                          o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query/output pointer is NULL or misaligned");
+    if ((q->shift0 == nullptr) != (q->shift1 == nullptr))
+        return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
+    size_t need_ws = bysdf_batched_workspace_size(h->n_types);
+    if (!workspace || ws_bytes < need_ws || ((uintptr_t)workspace & 255u))
+        return fail(BYSDF_ERR_INVALID_ARG, "workspace needs %zu bytes, 256-byte aligned", need_ws);
+    int chunk = 4, grid = 0, use_lds = 1;
+    if (sched) {
+        chunk = sched->chunk;
+        grid = sched->grid;
+        use_lds = sched->use_lds;
+    }
+    if (chunk < 1 || chunk > 64) return fail(BYSDF_ERR_INVALID_ARG, "schedule chunk must be in 1..64");
+    if (grid < 0 || grid > (1 << 20)) return fail(BYSDF_ERR_INVALID_ARG, "schedule grid out of range");
+    bool lds = use_lds != 0;
+    for (int i = 0; lds && i < h->n_tables; ++i)
+        if (h->h_table_size[i] > kMaxLdsTexels) lds = false;
+    if (grid == 0) grid = 256 * 8;
+    if (n == 0) return BYSDF_OK;
+    int32_t* tile_first = (int32_t*)workspace;
+    int* counter = (int*)((char*)workspace + align256(sizeof(int32_t) * (h->n_types + 1)));
+    QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
+             q->shift0, q->shift1};
+    OPtrs op{o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
+             o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, type_offsets, h->n_types, tile_first);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, stream, counter);
+    if (h->max_plies <= 4)
+        launch_batched<4>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
+    else if (h->max_plies <= 6)
+        launch_batched<6>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
+    else
+        launch_batched<8>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }
