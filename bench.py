@@ -38,12 +38,151 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.64
 PEAK_HBM_GBS = 8000.0
 
 
+# sources the BYSDF kernels are built from: counters taken on another
+# version of these no longer describe the kernels
+_KERNEL_SOURCES = ("bysdf_lib.hip", "bysdf_math.hpp", "bysdf_model.hpp", "bysdf_dual.hpp",
+                   "bysdf_opcount.hpp")
+
+
 def _src_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2401_12724_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in _KERNEL_SOURCES:
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+# bench stage -> kernel name prefix in rocprofv3 output
+_STAGE_KERNEL = {"eval": "k_eval<", "sample": "k_sample<", "eval_at_sample": "k_eval<",
+                 "furnace": "k_furnace<"}
+
+
+def _kname(full):
+    return full.split("(")[0].replace("void ", "").strip()
+
+
+def _summarize(prof_dir, bench_json, workload_tag):
+    """Turn the rocprofv3 CSV output of the profiling passes under prof_dir
+    (stats/, inst/, flops/, fetch/, write/) into short text summaries under
+    profiles/ and profiles/traffic.json (HBM bytes per launch of each stage's
+    kernel, FETCH_SIZE and WRITE_SIZE scaled by what the same counters read
+    for the 1 GiB device copy of --copy-calibration)."""
+    import csv
+    import collections
+
+    def counters(pas):
+        f = os.path.join(prof_dir, pas, "run_counter_collection.csv")
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        meta = {}
+        for r in csv.DictReader(open(f)):
+            k = _kname(r["Kernel_Name"])
+            per[k][r["Counter_Name"]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"]),
+                                              int(r["Grid_Size"])))
+            meta[k] = {c: r[c] for c in ("VGPR_Count", "Accum_VGPR_Count", "SGPR_Count",
+                                         "Scratch_Size", "LDS_Block_Size", "Workgroup_Size")}
+        return per, meta
+
+    stats = {}
+    for r in csv.DictReader(open(os.path.join(prof_dir, "stats", "run_kernel_stats.csv"))):
+        stats[_kname(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                                    float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                                    float(r["Percentage"]))
+    bj = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    cmd = open(os.path.join(prof_dir, "commands.txt")).read().strip()
+    N = bj["config"]["queries"]
+    lines = ["# rocprofv3 kernel trace: %s" % workload_tag, "",
+             "Commands (repo root on the GPU host):", "", cmd, "",
+             "Average kernel durations from the trace against the HIP-event times that "
+             "bench.py measured in the same run (ms per launch):", "",
+             "| kernel | calls | trace avg us | min us | max us | % of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for k, (c, a, mn, mx, pc) in sorted(stats.items(), key=lambda kv: -kv[1][4]):
+        lines.append("| `%s` | %d | %.1f | %.1f | %.1f | %.2f |" % (k, c, a, mn, mx, pc))
+    # per-dispatch durations of the step's launches: in dispatch order the
+    # bench issues eval, sample, eval (at the sampled directions), furnace,
+    # step after step, before any other work
+    trace = sorted(csv.DictReader(open(os.path.join(prof_dir, "stats", "run_kernel_trace.csv"))),
+                   key=lambda r: int(r["Dispatch_Id"]))
+    stages = list(bj["kernels_ms"])
+    seq = [r for r in trace if _kname(r["Kernel_Name"]) != "k_fiber_table"]
+    per_stage = collections.defaultdict(list)
+    for i, r in enumerate(seq):
+        st = stages[i % len(stages)]
+        if not _kname(r["Kernel_Name"]).startswith(_STAGE_KERNEL[st]):
+            break
+        per_stage[st].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    lines += ["", "| bench stage | kernel | HIP events ms (timed steps) | trace avg ms "
+              "(warm-up + timed launches) |", "|---|---|---|---|"]
+    for st, ms in bj["kernels_ms"].items():
+        d = per_stage.get(st, [])
+        lines.append("| %s | `%s` | %.3f | %s (%d launches) |" % (
+            st, _STAGE_KERNEL[st].rstrip("<"), ms, ("%.3f" % (sum(d) / len(d))) if d else "n/a",
+            len(d)))
+    lines += ["", "bench.py line of the traced run: value %.4g queries/s, %.3f ms/step"
+              % (bj["value"], bj["ms_per_step"])]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    tag = workload_tag.replace(" ", "_")
+    open(os.path.join(ROOT, "profiles", "bysdf_%s_kernel_trace.md" % tag), "w").write(
+        "\n".join(lines) + "\n")
+
+    inst, meta = counters("inst")
+    flops, _ = counters("flops")
+    fetch, _ = counters("fetch")
+    write, _ = counters("write")
+    copy = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()]
+    fmax = max(v for k in copy for (_, v, _) in fetch[k]["FETCH_SIZE"])
+    wmax = max(v for k in copy for (_, v, _) in write[k]["WRITE_SIZE"])
+    gib_kib = 1 << 20
+    f_scale, w_scale = gib_kib / fmax, gib_kib / wmax
+    lines = ["# rocprofv3 counters: %s" % workload_tag, "",
+             "Commands (repo root on the GPU host; one counter pass per run):", "", cmd, "",
+             "Calibration: the 1 GiB device-to-device copy reads FETCH_SIZE %.0f KiB and "
+             "WRITE_SIZE %.0f KiB per dispatch, so the counters are scaled by %.4f (fetch) "
+             "and %.4f (write) to bytes moved." % (fmax, wmax, f_scale, w_scale), "",
+             "Per dispatch (mean over the dispatches of the kernel); queries = %d per "
+             "launch; VALU issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE/8 "
+             "XCDs):" % N, "",
+             "| kernel | VGPR | AGPR | scratch B/lane | LDS B | VALU lane-instr./query | "
+             "SALU instr./query (x64) | VALU issue | FETCH GB | WRITE GB |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    traffic = {}
+    mean = lambda xs: sum(xs) / len(xs)
+    for k in inst:
+        if "copy" in k.lower() or k not in fetch:
+            continue
+        g = mean([gs for (_, _, gs) in inst[k]["SQ_INSTS_VALU"]])
+        valu = mean([v for (_, v, _) in inst[k]["SQ_INSTS_VALU"]])
+        salu = mean([v for (_, v, _) in inst[k]["SQ_INSTS_SALU"]])
+        gui = mean([v for (_, v, _) in inst[k]["GRBM_GUI_ACTIVE"]])
+        nq = N if g < N else g
+        fb = mean([v for (_, v, _) in fetch[k]["FETCH_SIZE"]]) * 1024 * f_scale
+        wb = mean([v for (_, v, _) in write[k]["WRITE_SIZE"]]) * 1024 * w_scale
+        m = meta[k]
+        lines.append("| `%s` | %s | %s | %s | %s | %.0f | %.1f | %.2f | %.3f | %.3f |" % (
+            k, m["VGPR_Count"], m["Accum_VGPR_Count"], m["Scratch_Size"], m["LDS_Block_Size"],
+            valu * 64 / nq, salu * 64 / nq, valu * 4 / (1024 * gui / 8), fb / 1e9, wb / 1e9))
+        for st, pre in _STAGE_KERNEL.items():
+            if k.startswith(pre):
+                traffic[st] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb,
+                               "kernel": k}
+    lines += ["", "FLOP-class counters per query (counter total / queries):", "",
+              "| kernel | " + " | ".join(c.replace("SQ_INSTS_VALU_", "") for c in
+                                        sorted(next(iter(flops.values())))) + " |",
+              "|---|" + "---|" * len(next(iter(flops.values())))]
+    for k, cs in flops.items():
+        if "copy" in k.lower():
+            continue
+        lines.append("| `%s` | " % k + " | ".join(
+            "%.1f" % (mean([v for (_, v, _) in cs[c]]) / N) for c in sorted(cs)) + " |")
+    open(os.path.join(ROOT, "profiles", "bysdf_%s_counters.md" % tag), "w").write(
+        "\n".join(lines) + "\n")
+    json.dump({"src_hash": _src_hash(), "workload": workload_tag,
+               "unit": "bytes per launch",
+               "calibration": {"fetch_scale": f_scale, "write_scale": w_scale,
+                               "copy_bytes": 1 << 30},
+               "kernels": traffic},
+              open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    print("\n".join(lines))
 
 
 def _op_counts(bysdf, T, P, q, mode, n=4096):
@@ -176,7 +315,13 @@ def main():
                     help="also run a plain 1 GiB device copy (for PMC byte scaling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the heterogeneous-batch and adjoint measurements")
+    ap.add_argument("--summarize", metavar="PROF_DIR",
+                    help="no run: summarize rocprofv3 passes under PROF_DIR into profiles/")
     args = ap.parse_args()
+    if args.summarize:
+        _summarize(args.summarize, os.path.join(args.summarize, "bench.json"),
+                   "perblock 2e24")
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs single-GPU only "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -251,7 +396,7 @@ def main():
     if os.path.exists(tpath):
         tj = json.load(open(tpath))
         if tj.get("src_hash") == _src_hash() and dom in tj.get("kernels", {}):
-            traffic = tj["kernels"][dom]
+            traffic = tj["kernels"][dom]["bytes"]
     # algorithmic bytes per query of each kernel (SoA records, 4 B fields)
     bytes_q = {"eval": 40 + 52, "sample": 40 + 52, "eval_at_sample": 40 + 52,
                "furnace": 4 * 8 + 24.0 / 256}
@@ -276,6 +421,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a 1 GiB copy)",
+                     "algorithmic_bytes": bytes_q[dom] * N,
                      "ops_per_query": per_query[dom]},
         "kernels_ms": ktime,
         "kernel_gbs": {k: bytes_q[k] * N / (ktime[k] * 1e-3) / 1e9 for k in names},

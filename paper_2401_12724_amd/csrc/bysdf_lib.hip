@@ -248,12 +248,15 @@ struct OPtrs {
 };
 
 constexpr int kBlock = 256;
-// minimum wavefronts per SIMD (register budget) chosen by measurement
+// Minimum wavefronts per SIMD (the register budget), chosen by measurement:
+// at one wavefront the kernels keep 256 VGPRs plus accumulation registers
+// and never spill to scratch; at two the sampler spilled 360-600 B per lane
+// and wrote ~10x its output bytes to HBM.
 #ifndef BYSDF_EVAL_MIN_WAVES
 #define BYSDF_EVAL_MIN_WAVES 1
 #endif
 #ifndef BYSDF_SAMPLE_MIN_WAVES
-#define BYSDF_SAMPLE_MIN_WAVES 2
+#define BYSDF_SAMPLE_MIN_WAVES 1
 #endif
 
 // Lanes of a wavefront are served one distinct type at a time (a wavefront

@@ -440,103 +440,102 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
                                              const XState<G, S, MP>& X, int k, float s0, float s1,
                                              bool has_shift, Node<G, S>& nd)
 {
+    // The node is assembled in a local and stored once: partial stores on
+    // several return paths get merged by the optimiser into stores through a
+    // selected stack address, which pins the node in scratch memory.
     const PlyHit<G, MP>& ph = X.ph;
-    V3<G> xp = mk3<G>(ph.p2x, ph.p2y, ph.vhit);
-    if (!(val(X.mu_i) > 0.0f)) {
-        nd.T = S(0);
-        nd.att = S(1);
-        nd.wt = mk3<G>(G(0), G(0), G(0));
-        nd.fy.t = X.fx.t;
-        nd.fy.n = -X.fx.n;
-        nd.fy.b = cross(nd.fy.n, nd.fy.t);
-        nd.y = xp;
-        return;
-    }
-    const double phig = 0.61803398874989484820;
-    double a1 = (k + 0.5) / P.K, a2 = (k + 0.5) * phig;
-    if (has_shift) {
-        a1 += s0;
-        a2 += s1;
-    }
-    double xi1 = a1 - floor(a1), xi2 = a2 - floor(a2);
-    V3<G> wl = to_local(X.fx, X.wi_g);
-    V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, G(xi1), G(xi2));
-    V3<G> m = to_world(X.fx, ml);
-    G c = dot(X.wi_g, m);
-    c = val(c) > 0.0 ? c : G(0);
-    G ie = P.inv_eta_g;
-    G s2t = (G(1) - c * c) * ie * ie;
-    G ct = sqrt_(G(1) - s2t);
-    V3<G> wt = X.wi_g * (-ie) + m * (c * ie - ct);
-    nd.wt = wt;
-    S cs = Narrow<S>::from(c);
-    nd.T = fresnel_T<S>(cs, P.eta) *
-           smith_G1<S>(narrow3<S>(to_local(X.fx, wt)), narrow3<S>(ml), P.ax, P.ay);
-    // chord in the projected cross-section, starting at the ply hit
-    G le2 = wt.x * wt.x + wt.y * wt.y;
-    G il = val(le2) > 0.0 ? rsqrt_(le2) : G(0);
-    G le = le2 * il;
-    G en = wt.x * ph.n2x + wt.y * ph.n2y;
-    if (val(le) < 1e-6 || val(en) >= 0.0) {
-        nd.att = S(1);
-        nd.fy.t = X.fx.t;
-        nd.fy.n = -X.fx.n;
-        nd.fy.b = cross(nd.fy.n, nd.fy.t);
-        nd.y = xp;
-        return;
-    }
-    G ex = wt.x * il, ey = wt.y * il;
-    G bq = ph.p2x * ex + ph.p2y * ey;
-    G cq = ph.p2x * ph.p2x + ph.p2y * ph.p2y - G(1);
-    G dq = bq * bq - cq;
-    G syarn = -bq + (val(dq) > 0.0 ? sqrt_(dq) : G(0));
-    int N = 0, jl = -1;
-    G sbest = G(0), cxl = G(0), cyl = G(0), cthl = G(0), sthl = G(0);
+    Node<G, S> r;
+    // no refraction into the yarn, or a chord that leaves at once: the exit
+    // is the entry point x with the fiber frame flipped (thin-sheet exit)
+    r.T = S(0);
+    r.att = S(1);
+    r.wt = mk3<G>(G(0), G(0), G(0));
+    r.fy.t = X.fx.t;
+    r.fy.n = -X.fx.n;
+    r.fy.b = cross(r.fy.n, r.fy.t);
+    r.y = mk3<G>(ph.p2x, ph.p2y, ph.vhit);
+    if (val(X.mu_i) > 0.0f) {
+        const double phig = 0.61803398874989484820;
+        double a1 = (k + 0.5) / P.K, a2 = (k + 0.5) * phig;
+        if (has_shift) {
+            a1 += s0;
+            a2 += s1;
+        }
+        double xi1 = a1 - floor(a1), xi2 = a2 - floor(a2);
+        V3<G> wl = to_local(X.fx, X.wi_g);
+        V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, G(xi1), G(xi2));
+        V3<G> m = to_world(X.fx, ml);
+        G c = dot(X.wi_g, m);
+        c = val(c) > 0.0 ? c : G(0);
+        G ie = P.inv_eta_g;
+        G s2t = (G(1) - c * c) * ie * ie;
+        G ct = sqrt_(G(1) - s2t);
+        V3<G> wt = X.wi_g * (-ie) + m * (c * ie - ct);
+        r.wt = wt;
+        S cs = Narrow<S>::from(c);
+        r.T = fresnel_T<S>(cs, P.eta) *
+              smith_G1<S>(narrow3<S>(to_local(X.fx, wt)), narrow3<S>(ml), P.ax, P.ay);
+        // chord in the projected cross-section, starting at the ply hit
+        G le2 = wt.x * wt.x + wt.y * wt.y;
+        G il = val(le2) > 0.0 ? rsqrt_(le2) : G(0);
+        G le = le2 * il;
+        G en = wt.x * ph.n2x + wt.y * ph.n2y;
+        if (!(val(le) < 1e-6 || val(en) >= 0.0)) {
+            G ex = wt.x * il, ey = wt.y * il;
+            G bq = ph.p2x * ex + ph.p2y * ey;
+            G cq = ph.p2x * ph.p2x + ph.p2y * ph.p2y - G(1);
+            G dq = bq * bq - cq;
+            G syarn = -bq + (val(dq) > 0.0 ? sqrt_(dq) : G(0));
+            int N = 0, jl = -1;
+            G sbest = G(0), cxl = G(0), cyl = G(0), cthl = G(0), sthl = G(0);
 #pragma unroll
-    for (int j = 0; j < MP; ++j) {
-        if (j >= P.Np) break;
-        bool ent = false;
-        G so = G(0);
-        if (j == ph.ks) {
-            // the chord starts on this disc's rim and heads inside
-            G sx = G(-2) * P.rp * en * il;
-            so = val(sx) < val(syarn) ? sx : syarn;
-            ent = true;
-        } else {
-            G wx = ph.p2x - P.Rpc * ph.cth[j], wy = ph.p2y - P.Rpc * ph.sth[j];
-            G b = wx * ex + wy * ey;
-            G cc = wx * wx + wy * wy - P.rp * P.rp;
-            G disc = b * b - cc;
-            if (val(disc) > 0.0) {
-                G sq = sqrt_(disc);
-                G slo = -b - sq, shi = -b + sq;
-                if (val(shi) > 0.0 && val(slo) < val(syarn)) {
+            for (int j = 0; j < MP; ++j) {
+                if (j >= P.Np) break;
+                bool ent = false;
+                G so = G(0);
+                if (j == ph.ks) {
+                    // the chord starts on this disc's rim and heads inside
+                    G sx = G(-2) * P.rp * en * il;
+                    so = val(sx) < val(syarn) ? sx : syarn;
                     ent = true;
-                    so = val(shi) < val(syarn) ? shi : syarn;
+                } else {
+                    G wx = ph.p2x - P.Rpc * ph.cth[j], wy = ph.p2y - P.Rpc * ph.sth[j];
+                    G b = wx * ex + wy * ey;
+                    G cc = wx * wx + wy * wy - P.rp * P.rp;
+                    G disc = b * b - cc;
+                    if (val(disc) > 0.0) {
+                        G sq = sqrt_(disc);
+                        G slo = -b - sq, shi = -b + sq;
+                        if (val(shi) > 0.0 && val(slo) < val(syarn)) {
+                            ent = true;
+                            so = val(shi) < val(syarn) ? shi : syarn;
+                        }
+                    }
+                }
+                if (ent) {
+                    ++N;
+                    if (jl < 0 || val(so) > val(sbest)) {
+                        jl = j;
+                        sbest = so;
+                        cxl = P.Rpc * ph.cth[j];
+                        cyl = P.Rpc * ph.sth[j];
+                        cthl = ph.cth[j];
+                        sthl = ph.sth[j];
+                    }
                 }
             }
-        }
-        if (ent) {
-            ++N;
-            if (jl < 0 || val(so) > val(sbest)) {
-                jl = j;
-                sbest = so;
-                cxl = P.Rpc * ph.cth[j];
-                cyl = P.Rpc * ph.sth[j];
-                cthl = ph.cth[j];
-                sthl = ph.sth[j];
-            }
+            G y2x = ph.p2x + sbest * ex, y2y = ph.p2y + sbest * ey;
+            G ell = sbest * il;
+            G zy = ph.vhit + wt.z * ell;
+            G nyx = y2x - cxl, nyy = y2y - cyl;
+            G ninv = rsqrt_(nyx * nyx + nyy * nyy);
+            r.att = exp_(-P.sigma_t * Narrow<S>::from(ell) * S(float(N)));
+            r.fy = fiber_frame<G, S, Tab>(P, tab, cthl, sthl, nyx * ninv, nyy * ninv, zy, nullptr,
+                                          nullptr);
+            r.y = mk3<G>(y2x, y2y, zy);
         }
     }
-    G y2x = ph.p2x + sbest * ex, y2y = ph.p2y + sbest * ey;
-    G ell = sbest * il;
-    G zy = ph.vhit + wt.z * ell;
-    G nyx = y2x - cxl, nyy = y2y - cyl;
-    G ninv = rsqrt_(nyx * nyx + nyy * nyy);
-    nd.att = exp_(-P.sigma_t * Narrow<S>::from(ell) * S(float(N)));
-    nd.fy = fiber_frame<G, S, Tab>(P, tab, cthl, sthl, nyx * ninv, nyy * ninv, zy, nullptr,
-                                   nullptr);
-    nd.y = mk3<G>(y2x, y2y, zy);
+    nd = r;
 }
 
 // Exit refraction at y (Eq. 3): Walter's BTDF from inside (index eta) to
