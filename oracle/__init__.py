@@ -17,6 +17,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bysdf_oracle.c")
+_SOURCES = [_SRC, os.path.join(_HERE, "yarn_oracle.c")]
+_HEADERS = [os.path.join(_HERE, "bysdf_oracle.h"), os.path.join(_HERE, "yarn_oracle.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # flag bits (same numbering as the library's public flags)
@@ -50,10 +52,10 @@ class OrcParams(C.Structure):
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain C99, -O2, OpenMP, IEEE math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
-            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "bysdf_oracle.h"))):
+            os.path.getmtime(f) for f in _SOURCES + _HEADERS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp] + _SOURCES + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -101,6 +103,11 @@ def lib():
         L.orc_nodes.restype = C.c_uint32
         L.orc_frame_x.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_frame_x.restype = C.c_uint32
+        L.orc_scene_create.argtypes = [fp, C.POINTER(C.c_int64), C.c_int32]
+        L.orc_scene_create.restype = C.c_void_p
+        L.orc_scene_free.argtypes = [C.c_void_p]
+        L.orc_scene_frame.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, dp]
+        L.orc_intersect.argtypes = [C.c_void_p, C.c_int64, fp, fp, fp, C.c_double, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -321,3 +328,51 @@ def frame_x(d, tab, h, u, v, wi):
     fl = lib().orc_frame_x(C.byref(p), _ptr(t, C.c_double), float(h), float(u), float(v),
                            _ptr(w, C.c_double), _ptr(out, C.c_double))
     return out, fl
+
+
+# ---------------------------------------------------------------- yarn scenes
+
+HIT_MISS = 1 << 0
+HIT_CAP = 1 << 1
+HIT_EXCLUDED = 1 << 2
+HIT_GRAZING = 1 << 3
+HIT_TIE = 1 << 4
+HIT_ORIGIN_EDGE = 1 << 5
+HIT_MARGIN_MASK = HIT_GRAZING | HIT_TIE | HIT_ORIGIN_EDGE
+
+
+class Scene:
+    """Yarn scene for the intersection oracle: ctrl (n_cp, 4) float32 rows
+    (x, y, z, r), yarn_off (n_yarns + 1) int64 CSR offsets."""
+
+    def __init__(self, ctrl, yarn_off):
+        self.ctrl = np.ascontiguousarray(ctrl, np.float32)
+        self.off = np.ascontiguousarray(yarn_off, np.int64)
+        self._h = lib().orc_scene_create(_ptr(self.ctrl, C.c_float),
+                                         self.off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         len(self.off) - 1)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_scene_free(self._h)
+            self._h = None
+
+    def frame(self, yarn, seg, s):
+        """(T(3), N(3), v, position(3)) of the centreline at (yarn, seg, s)."""
+        out = np.zeros(10)
+        lib().orc_scene_frame(self._h, int(yarn), int(seg), float(s), _ptr(out, C.c_double))
+        return out
+
+
+def intersect(scene: Scene, o, d, t_max, t_min: float = 0.0, nthreads: int = 0):
+    """Rays (n, 3) float32 origins and directions, t_max (n,).  Returns
+    (n, 16) float64: t, yarn, seg, s, h, v, T(3), N(3), flags, depth, _,
+    second-best entry of another yarn."""
+    o = np.ascontiguousarray(o, np.float32)
+    d = np.ascontiguousarray(d, np.float32)
+    tm = np.ascontiguousarray(t_max, np.float32)
+    n = len(o)
+    out = np.zeros((n, 16))
+    lib().orc_intersect(scene._h, n, _ptr(o, C.c_float), _ptr(d, C.c_float), _ptr(tm, C.c_float),
+                        float(t_min), _ptr(out, C.c_double), nthreads)
+    return out

@@ -194,3 +194,99 @@ def with_theta(p: dict, th) -> dict:
     q["beta"], q["ply_twist"], q["fiber_twist"] = float(th[3]), float(th[4]), float(th[5])
     q["ply_density"], q["fiber_density"] = float(th[6]), float(th[7])
     return as_f32(q)
+
+
+# ---------------------------------------------------------------- yarn scenes
+
+def weave(n_warp: int = 256, n_weft: int = 256, pitch: float = 0.15, radius: float = 0.05,
+          cps_per_crossing: int = 4, seed: int = 2):
+    """Plain weave of yarn centrelines as uniform cubic B-spline control
+    points.  Warp yarn i runs along x at y_i, weft yarn j along y at x_j
+    (pitch apart, the fabric centred on the origin); their heights follow
+    +-radius/2 cos(pi (index coordinate) + pi (yarn index)), so the two
+    yarns of a crossing sit one radius apart with alternating over/under.
+    Control points are spaced pitch / cps_per_crossing along each yarn and
+    extend half a pitch past the outermost crossings (plus one point for
+    the spline's end spans).
+
+    Returns (ctrl (n_cp, 4) float32 rows x, y, z, r; yarn_off (n_yarns+1)
+    int64; yarn_type (n_yarns) int32; yarn_phase (n_yarns) float32, the
+    ply-helix phase of each yarn drawn uniformly in [0, 2 pi))."""
+    cw = (n_weft - 1) / 2.0
+    cp = (n_warp - 1) / 2.0
+    dx = pitch / cps_per_crossing
+    n_cp = n_weft * cps_per_crossing + 3
+    k = np.arange(n_cp, dtype=np.float64)
+    ctrl, off = [], [0]
+    # warp: along x
+    xs = (-cw - 0.5) * pitch - dx + k * dx
+    for i in range(n_warp):
+        y = (i - cp) * pitch
+        z = 0.5 * radius * np.cos(math.pi * (xs / pitch + cw) + math.pi * i)
+        ctrl.append(np.stack([xs, np.full(n_cp, y), z, np.full(n_cp, radius)], 1))
+        off.append(off[-1] + n_cp)
+    n_cp2 = n_warp * cps_per_crossing + 3
+    k2 = np.arange(n_cp2, dtype=np.float64)
+    ys = (-cp - 0.5) * pitch - dx + k2 * dx
+    for j in range(n_weft):
+        x = (j - cw) * pitch
+        z = -0.5 * radius * np.cos(math.pi * (ys / pitch + cp) + math.pi * j)
+        ctrl.append(np.stack([np.full(n_cp2, x), ys, z, np.full(n_cp2, radius)], 1))
+        off.append(off[-1] + n_cp2)
+    ctrl = np.concatenate(ctrl).astype(np.float32)
+    n_yarns = n_warp + n_weft
+    phase = (2.0 * math.pi * _rng(seed).random(n_yarns)).astype(np.float32)
+    return ctrl, np.array(off, np.int64), np.zeros(n_yarns, np.int32), phase
+
+
+def camera(eye, look_at, up=(0.0, 0.0, 1.0), vfov_deg: float = 30.0, width: int = 1920,
+           height: int = 1080):
+    """Pinhole camera record: eye, look-at, up, vertical field of view,
+    resolution (the renderer generates the rays from it)."""
+    return dict(eye=tuple(float(np.float32(e)) for e in eye),
+                look_at=tuple(float(np.float32(e)) for e in look_at),
+                up=tuple(float(np.float32(e)) for e in up), vfov=float(np.float32(vfov_deg * DEG)),
+                width=int(width), height=int(height))
+
+
+def weave_camera():
+    """Grazing view of the weave: eye 45 units back and 12 up from the
+    fabric centre, looking at the centre, 1920 x 1080, 30 degrees."""
+    return camera((0.0, -45.0, 12.0), (0.0, 0.0, 0.0))
+
+
+def pinhole_rays(cam: dict, px, py, jx=None, jy=None):
+    """Primary rays through pixels (px, py) (pixel centres, or offsets jx,
+    jy in [0, 1)); row 0 is the top of the image.  Returns (o (n, 3), d (n,
+    3)) float32 with unit directions.  The renderer's own camera code is
+    separate; this generator feeds intersection tests."""
+    eye = np.array(cam["eye"], np.float64)
+    f = np.array(cam["look_at"], np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.array(cam["up"], np.float64))
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    th = math.tan(0.5 * cam["vfov"])
+    W, H = cam["width"], cam["height"]
+    jx = 0.5 if jx is None else jx
+    jy = 0.5 if jy is None else jy
+    sx = (2.0 * (np.asarray(px, np.float64) + jx) / W - 1.0) * th * W / H
+    sy = (1.0 - 2.0 * (np.asarray(py, np.float64) + jy) / H) * th
+    d = f[None, :] + sx[:, None] * r[None, :] + sy[:, None] * u[None, :]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.repeat(eye[None, :], len(d), 0)
+    return o.astype(np.float32), d.astype(np.float32)
+
+
+def random_rays(n: int, seed: int, lo, hi, target_lo=None, target_hi=None):
+    """Rays from origins uniform in the box [lo, hi] towards points uniform
+    in [target_lo, target_hi] (default: the same box)."""
+    rng = _rng(seed)
+    lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
+    tl = lo if target_lo is None else np.asarray(target_lo, np.float64)
+    th = hi if target_hi is None else np.asarray(target_hi, np.float64)
+    o = lo + (hi - lo) * rng.random((n, 3))
+    t = tl + (th - tl) * rng.random((n, 3))
+    d = t - o
+    d /= np.maximum(np.linalg.norm(d, axis=1, keepdims=True), 1e-30)
+    return o.astype(np.float32), d.astype(np.float32)

@@ -1,0 +1,186 @@
+"""Pins of the ray / yarn-tube intersection oracle against closed forms and
+an independent brute force:
+
+* a straight yarn (collinear, evenly spaced control points) is a capsule:
+  entry parameter, h, arc length and frame in closed form;
+* coincident control points make a ball;
+* a march along the ray with the distance to the curve found by dense
+  sampling reproduces the entry parameter on a curved weave patch;
+* the transported frame stays orthonormal and does not spin about the
+  tangent (the defining property of a rotation-minimising frame), and a
+  planar yarn keeps the normal of its plane as binormal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_12724_amd import workloads as W
+
+
+def _straight(n_cp=10, R=0.2, x0=-2.0, dx=0.5):
+    x = x0 + dx * np.arange(n_cp)
+    ctrl = np.stack([x, np.zeros(n_cp), np.zeros(n_cp), np.full(n_cp, R)], 1).astype(np.float32)
+    return ctrl, np.array([0, n_cp], np.int64)
+
+
+def test_straight_yarn_is_a_capsule():
+    R, x0, dx, n_cp = float(np.float32(0.2)), -2.0, 0.5, 10
+    ctrl, off = _straight(n_cp, R, x0, dx)
+    S = oracle.Scene(ctrl, off)
+    rng = np.random.default_rng(0)
+    n = 300
+    # rays from above, aimed at points of the cylindrical part
+    xa = rng.uniform(x0 + 1.5 * dx, x0 + (n_cp - 2.5) * dx, n)
+    b = rng.uniform(-0.95, 0.95, n) * R          # signed offset from the axis
+    tilt = rng.uniform(-0.5, 0.5, n)              # component along the axis
+    d = np.stack([tilt, np.zeros(n), -np.ones(n)], 1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.stack([xa - 3.0 * d[:, 0] / -d[:, 2], b, np.full(n, 3.0)], 1)
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    out = oracle.intersect(S, o, d, np.full(n, 100.0, np.float32))
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    dd /= np.linalg.norm(dd, axis=1, keepdims=True)
+    # closed form: (o + t d) has y^2 + z^2 = R^2
+    A = dd[:, 1] ** 2 + dd[:, 2] ** 2
+    Bq = 2 * (od[:, 1] * dd[:, 1] + od[:, 2] * dd[:, 2])
+    Cq = od[:, 1] ** 2 + od[:, 2] ** 2 - R * R
+    t_ref = (-Bq - np.sqrt(Bq * Bq - 4 * A * Cq)) / (2 * A)
+    assert np.all(out[:, 12].astype(int) & oracle.HIT_MISS == 0)
+    np.testing.assert_allclose(out[:, 0], t_ref, rtol=1e-9, atol=1e-9)
+    p = od + t_ref[:, None] * dd
+    # the curve starts at x0 + dx (the B-spline of collinear even points is
+    # the line through them, starting at the second point)
+    np.testing.assert_allclose(out[:, 5], p[:, 0] - (x0 + dx), rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(out[:, 6:9], np.tile([1.0, 0, 0], (n, 1)), atol=1e-12)
+    # initial normal: +z projected off the tangent
+    np.testing.assert_allclose(out[:, 9:12], np.tile([0, 0, 1.0], (n, 1)), atol=1e-12)
+    # h: sine of (hit azimuth - incident azimuth) in the (N, B) = (z, -y)
+    # plane; for rays in the x-z plane the incident azimuth is 0
+    psi = np.arctan2(-p[:, 1], p[:, 2])
+    np.testing.assert_allclose(out[:, 4], np.sin(psi), atol=1e-9)
+
+
+def test_ball_from_coincident_points():
+    R = float(np.float32(0.3))
+    ctrl = np.tile(np.array([[1.0, 2.0, 3.0, R]], np.float32), (5, 1))
+    S = oracle.Scene(ctrl, np.array([0, 5], np.int64))
+    rng = np.random.default_rng(1)
+    n = 200
+    o = (np.array([1.0, 2.0, 3.0]) + W._sphere(rng, n).T * 2.0).astype(np.float32)
+    tgt = np.array([1.0, 2.0, 3.0]) + rng.uniform(-0.25, 0.25, (n, 3))
+    d = tgt - o
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    out = oracle.intersect(S, o, d, np.full(n, 10.0, np.float32))
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    dd /= np.linalg.norm(dd, axis=1, keepdims=True)
+    c = od - np.array([1.0, 2.0, 3.0])
+    bq = np.sum(c * dd, 1)
+    disc = bq * bq - (np.sum(c * c, 1) - R * R)
+    hit = disc > 0
+    t_ref = -bq - np.sqrt(np.maximum(disc, 0))
+    assert np.array_equal(out[:, 12].astype(int) & oracle.HIT_MISS == 0, hit)
+    np.testing.assert_allclose(out[hit, 0], t_ref[hit], rtol=1e-9, atol=1e-9)
+
+
+def _small_weave():
+    return W.weave(n_warp=4, n_weft=4, pitch=0.15, radius=0.05, cps_per_crossing=4)
+
+
+def _march(ctrl, off, o, d, t_max, step, dense=400):
+    """Independent brute force: march along the ray, distance to each yarn
+    by dense sampling of its whole curve, first t within R, then bisect."""
+    curves = []
+    for y in range(len(off) - 1):
+        P = ctrl[off[y]:off[y + 1], :3].astype(np.float64)
+        R = float(ctrl[off[y], 3])
+        pts = []
+        for j in range(len(P) - 3):
+            s = np.linspace(0, 1, dense)[:, None]
+            u = 1 - s
+            pts.append((u ** 3 * P[j] + (3 * s ** 3 - 6 * s ** 2 + 4) * P[j + 1] +
+                        (-3 * s ** 3 + 3 * s ** 2 + 3 * s + 1) * P[j + 2] + s ** 3 * P[j + 3]) / 6)
+        curves.append((np.concatenate(pts), R))
+    o, d = o.astype(np.float64), d.astype(np.float64) / np.linalg.norm(d)
+
+    def inside(t):
+        p = o + t * d
+        return any(np.min(np.sum((c - p) ** 2, 1)) <= R * R for c, R in curves)
+
+    t = step
+    while t < t_max:
+        if inside(t):
+            a, b = t - step, t
+            for _ in range(40):
+                m = 0.5 * (a + b)
+                if inside(m):
+                    b = m
+                else:
+                    a = m
+            return b
+        t += step
+    return np.inf
+
+
+def test_march_matches_on_weave_patch():
+    ctrl, off, _, _ = _small_weave()
+    S = oracle.Scene(ctrl, off)
+    o, d = W.random_rays(40, 7, (-0.4, -0.4, 0.3), (0.4, 0.4, 0.6), (-0.25, -0.25, -0.05),
+                         (0.25, 0.25, 0.05))
+    out = oracle.intersect(S, o, d, np.full(len(o), 5.0, np.float32))
+    n_hit = 0
+    for i in range(len(o)):
+        t_ref = _march(ctrl, off, o[i], d[i], 2.0, 2e-3)
+        fl = int(out[i, 12])
+        if fl & oracle.HIT_MARGIN_MASK:
+            continue
+        if np.isinf(t_ref):
+            assert fl & oracle.HIT_MISS
+        else:
+            n_hit += 1
+            # the dense curve sampling of the march resolves the tube
+            # surface to about 1e-5 R
+            assert abs(out[i, 0] - t_ref) < 2e-5, (i, out[i, 0], t_ref)
+    assert n_hit > 20
+
+
+def test_frame_is_rotation_minimising():
+    # a non-planar yarn: control points on a helix
+    k = np.arange(24)
+    ctrl = np.stack([np.cos(0.4 * k), np.sin(0.4 * k), 0.15 * k, np.full(24, 0.05)],
+                    1).astype(np.float32)
+    S = oracle.Scene(ctrl, np.array([0, 24], np.int64))
+    ss = np.linspace(0.05, 0.95, 7)
+    for seg in (0, 5, 17):
+        for s in ss:
+            f = S.frame(0, seg, s)
+            T, N = f[0:3], f[3:6]
+            assert abs(np.dot(T, N)) < 1e-12 and abs(np.linalg.norm(N) - 1) < 1e-12
+            # dN/ds has no component along B = T x N (no spin about T)
+            e = 1e-4
+            Np, Nm = S.frame(0, seg, s + e)[3:6], S.frame(0, seg, s - e)[3:6]
+            dN = (Np - Nm) / (2 * e)
+            dT = (S.frame(0, seg, s + e)[0:3] - S.frame(0, seg, s - e)[0:3]) / (2 * e)
+            B = np.cross(T, N)
+            assert abs(np.dot(dN, B)) < 1e-5 * max(1.0, np.linalg.norm(dT))
+    # a planar yarn keeps its plane normal as binormal
+    ctrl, off, _, _ = _small_weave()
+    S = oracle.Scene(ctrl, off)
+    for s in ss:
+        f = S.frame(1, 7, s)        # warp yarn: the x-z plane
+        assert abs(np.cross(f[0:3], f[3:6])[1]) > 1 - 1e-12
+        f = S.frame(5, 3, s)        # weft yarn: the y-z plane
+        assert abs(np.cross(f[0:3], f[3:6])[0]) > 1 - 1e-12
+
+
+def test_origin_inside_excludes_the_yarn():
+    ctrl, off = _straight()
+    S = oracle.Scene(ctrl, off)
+    # origin on the axis, ray leaving the tube: no hit (the tube holds the
+    # origin); origin just outside, ray towards the axis: hit
+    o = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.25]], np.float32)
+    d = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]], np.float32)
+    out = oracle.intersect(S, o, d, np.full(2, 10.0, np.float32))
+    assert int(out[0, 12]) & oracle.HIT_MISS and int(out[0, 12]) & oracle.HIT_EXCLUDED
+    assert abs(out[1, 0] - 0.05) < 1e-6
