@@ -286,29 +286,42 @@ static void scan_span(const scene_t* S, int y, int64_t g, d3 o, d3 d, double t_m
     double a = bi > 0 ? (double)(bi - 1) / SCAN : 0.0;
     double b = bi < SCAN ? (double)(bi + 1) / SCAN : 1.0;
     double bs = (double)bi / SCAN;
-    for (int it = 0; it < 100; ++it) {
-        double x1 = b - GOLD * (b - a), x2 = a + GOLD * (b - a);
-        double f1 = entry_at(p, o, d, R, t_min, x1, NULL), f2 = entry_at(p, o, d, R, t_min, x2, NULL);
-        if (f1 < f2) b = x2; else a = x1;
-    }
-    double sm = 0.5 * (a + b);
-    /* comparisons of T only locate a flat minimum to ~1e-8; finish with
-     * bisection on the sign of dT/ds, which is exact to rounding */
-    double lo = sm - 1e-6, hi = sm + 1e-6;
-    if (lo < 0.0) lo = 0.0;
-    if (hi > 1.0) hi = 1.0;
-    double glo = entry_slope(p, o, d, R, lo), ghi = entry_slope(p, o, d, R, hi);
-    if (glo < 0.0 && ghi > 0.0) {
-        for (int it = 0; it < 80; ++it) {
+    /* the minimum in [a, b] is where dT/ds changes sign (a ball that misses
+     * the ray counts as a steep wall: -inf on the left, +inf on the right);
+     * bisection on that sign is exact to rounding even where T is flat */
+    double sm = bs;
+    double ga = entry_slope(p, o, d, R, a), gb = entry_slope(p, o, d, R, b);
+    if (!(ga == ga)) ga = -INFINITY;
+    if (!(gb == gb)) gb = INFINITY;
+    if (ga < 0.0 && gb > 0.0) {
+        double lo = a, hi = b;
+        for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
             double m = 0.5 * (lo + hi);
+            if (m <= lo || m >= hi) break;
             double gm = entry_slope(p, o, d, R, m);
-            if (!(gm == gm)) break;
+            if (!(gm == gm)) {
+                /* a gap inside the bracket: fall back to golden section */
+                lo = hi = -1.0;
+                break;
+            }
             if (gm < 0.0) lo = m; else hi = m;
         }
-        sm = 0.5 * (lo + hi);
+        if (lo >= 0.0) {
+            sm = 0.5 * (lo + hi);
+        } else {
+            double aa = a, bb = b;
+            for (int it = 0; it < 100; ++it) {
+                double x1 = bb - GOLD * (bb - aa), x2 = aa + GOLD * (bb - aa);
+                double f1 = entry_at(p, o, d, R, t_min, x1, NULL), f2 = entry_at(p, o, d, R, t_min, x2, NULL);
+                if (f1 < f2) bb = x2; else aa = x1;
+            }
+            sm = 0.5 * (aa + bb);
+        }
     }
     double tm = entry_at(p, o, d, R, t_min, sm, NULL);
-    if (tm < bt) { bt = tm; bs = sm; }
+    /* where T is flat the refined value ties the best sample to rounding:
+     * keep the refined parameter */
+    if (tm <= bt + 1e-12 * (fabs(bt) > 1.0 ? fabs(bt) : 1.0)) { if (tm < bt) bt = tm; bs = sm; }
     /* the end points themselves (a minimum on the boundary) */
     for (int e = 0; e < 2; ++e) {
         double te = entry_at(p, o, d, R, t_min, (double)e, NULL);
@@ -378,6 +391,10 @@ static void intersect_one(const scene_t* S, d3 o, d3 d, double t_max, double t_m
     if ((seg == 0 && best.s <= 0.0) || (g == S->span_off[y + 1] - 1 && best.s >= 1.0))
         flags |= ORC_HIT_CAP;
     if (best.depth < 1e-3) flags |= ORC_HIT_GRAZING;
+    /* an entry right after t_min: the balls nearest the origin lie behind
+     * t_min, so the first ball ahead sits on the t_min level set and its
+     * parameter is not well defined */
+    if (best.t - t_min < 1e-2 * R) flags |= ORC_HIT_ORIGIN_EDGE;
     if (second - best.t < 1e-7 * (best.t > 1.0 ? best.t : 1.0)) flags |= ORC_HIT_TIE;
     double fr[10];
     orc_scene_frame(S, y, seg, best.s, fr);

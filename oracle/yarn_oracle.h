@@ -41,7 +41,8 @@ extern "C" {
 #define ORC_HIT_EXCLUDED     (1u << 2)  /* some yarn containing the origin was skipped */
 #define ORC_HIT_GRAZING      (1u << 3)  /* oracle only: the ray dips less than 1e-3 R into the tube */
 #define ORC_HIT_TIE          (1u << 4)  /* oracle only: another yarn's entry within the margin */
-#define ORC_HIT_ORIGIN_EDGE  (1u << 5)  /* oracle only: origin within the margin of an exclusion */
+#define ORC_HIT_ORIGIN_EDGE  (1u << 5)  /* oracle only: origin within the margin of an exclusion,
+                                           or the entry within 1e-2 R of t_min */
 #define ORC_HIT_MARGIN_MASK (ORC_HIT_GRAZING | ORC_HIT_TIE | ORC_HIT_ORIGIN_EDGE)
 
 /* Prepared scene: control points (x, y, z, r) as n_cp x 4 floats promoted
