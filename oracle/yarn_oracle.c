@@ -72,11 +72,14 @@ static d3 rmf_step(d3 x0, d3 t0, d3 n0, d3 x1, d3 t1)
 {
     d3 v1 = sub(x1, x0);
     double c1 = dot(v1, v1);
-    d3 nl = n0, tl = t0;
-    if (c1 > 0.0) {
-        nl = sub(n0, scl(v1, 2.0 * dot(v1, n0) / c1));
-        tl = sub(t0, scl(v1, 2.0 * dot(v1, t0) / c1));
+    /* a chord at rounding level has a random direction; its limit for a
+     * vanishing step is the tangent */
+    if (!(c1 > 1e-16 * (dot(x0, x0) + dot(x1, x1)))) {
+        v1 = t0;
+        c1 = 1.0;
     }
+    d3 nl = sub(n0, scl(v1, 2.0 * dot(v1, n0) / c1));
+    d3 tl = sub(t0, scl(v1, 2.0 * dot(v1, t0) / c1));
     d3 v2 = sub(t1, tl);
     double c2 = dot(v2, v2);
     if (c2 > 0.0) nl = sub(nl, scl(v2, 2.0 * dot(v2, nl) / c2));

@@ -184,3 +184,19 @@ def test_origin_inside_excludes_the_yarn():
     out = oracle.intersect(S, o, d, np.full(2, 10.0, np.float32))
     assert int(out[0, 12]) & oracle.HIT_MISS and int(out[0, 12]) & oracle.HIT_EXCLUDED
     assert abs(out[1, 0] - 0.05) < 1e-6
+
+
+def test_frame_continuous_at_tiny_steps():
+    """The frame a hair's breadth into a span equals the frame at the span
+    start, and the end of a span meets the start of the next (a chord at
+    rounding level must not pick a random reflection plane)."""
+    k = np.arange(24)
+    ctrl = np.stack([np.cos(0.4 * k), np.sin(0.4 * k), 0.15 * k, np.full(24, 0.05)],
+                    1).astype(np.float32)
+    S = oracle.Scene(ctrl, np.array([0, 24], np.int64))
+    for seg in (1, 9, 19):
+        f0 = S.frame(0, seg, 0.0)
+        for eps in (1e-15, 1e-13, 1e-11, 1e-9):
+            assert np.abs(S.frame(0, seg, eps)[3:6] - f0[3:6]).max() < 1e-8, (seg, eps)
+        prev = S.frame(0, seg - 1, 1.0 - 1e-14)
+        assert np.abs(prev[3:6] - f0[3:6]).max() < 1e-8, seg
