@@ -251,6 +251,74 @@ int bysdf_eval_backward(const bysdf_types_t* types, const bysdf_query_soa* q, in
                         const int64_t* type_offsets, const float* grad_E, float* grad_theta,
                         float* per_query, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------- yarn scenes */
+/* A scene of yarns given by their centrelines, uniform cubic B-splines
+ * (the explicit yarn curves of Sec. 3.3).  Yarn Y has control points
+ * ctrl_xyzr[yarn_offsets[Y] .. yarn_offsets[Y+1]-1] (at least 4; spans
+ * j = 0 .. n-4 use points j .. j+3, parameter s in [0, 1]) and radius R_Y =
+ * the r of its first control point.  Its tube is the set of points within
+ * R_Y of the centreline (the union of balls of radius R_Y on the curve). */
+typedef struct yarn_scene yarn_scene_t; /* opaque: curves, frames, BVH on the device */
+
+/* Build a scene from HOST arrays: ctrl_xyzr (n_cp x 4 floats, rows x y z
+ * r), yarn_offsets (n_yarns + 1, CSR, yarn_offsets[0] == 0), yarn_type
+ * (n_yarns BYSDF type indices, nullable: all 0) and yarn_phase (n_yarns
+ * ply-helix phases u in radians, nullable: all 0).  The library computes
+ * per span the rotation-minimising frame at its start (double reflection
+ * from +z projected off the yarn's first tangent, or +x when that tangent
+ * is within 25 degrees of z), the arc length from the yarn start, and a
+ * binned-SAH BVH over the spans (depth at most 64), then uploads them.
+ * Synchronises `stream`.  Errors: INVALID_ARG for NULL pointers or bad
+ * offsets, INVALID_PARAM for fewer than 4 points in a yarn or non-finite
+ * / non-positive values, OOM, UNSUPPORTED_DEVICE. */
+int yarn_scene_create(const float* ctrl_xyzr, const int64_t* yarn_offsets, int32_t n_yarns,
+                      const int32_t* yarn_type, const float* yarn_phase, yarn_scene_t** out,
+                      hipStream_t stream);
+
+/* Release a scene (NULL is accepted). */
+int yarn_scene_destroy(yarn_scene_t* scene);
+
+/* info[6] = n_yarns, control points, spans, BVH nodes, BVH depth, device
+ * bytes held by the scene. */
+int yarn_scene_info(const yarn_scene_t* scene, int64_t* info);
+
+/* Rays (DEVICE, n elements each): origins, directions (any non-zero
+ * length; normalised inside, t is measured along the unit direction in
+ * scene units) and the largest t of interest. */
+typedef struct {
+    const float *o_x, *o_y, *o_z;
+    const float *d_x, *d_y, *d_z;
+    const float* t_max;
+} yarn_ray_soa;
+
+/* Hits (DEVICE, n elements each).  t: entry parameter (INFINITY on a
+ * miss); yarn and seg: yarn index and span within the yarn (-1 on a miss);
+ * s: span parameter of the centreline point whose ball the ray enters;
+ * h, u, v: the BYSDF hit coordinates (h = sine of the hit azimuth minus the
+ * incident azimuth in the (N, B) plane, in [-1, 1]; u = the yarn's phase;
+ * v = arc length from the yarn start, scene units); tan / nrm: unit
+ * tangent T and reference normal N of the rotation-minimising frame (the
+ * binormal is T x N); flags: bit 0 miss, bit 1 entry through a yarn end,
+ * bit 2 a yarn holding the origin was skipped, bit 9 bad ray. */
+typedef struct {
+    float* t;
+    int32_t *yarn, *seg;
+    float *s, *h, *u, *v;
+    float *tan_x, *tan_y, *tan_z;
+    float *nrm_x, *nrm_y, *nrm_z;
+    uint32_t* flags;
+} yarn_hit_soa;
+
+/* First entry of each ray into a yarn tube with t_min < t <= t_max (Sec.
+ * 3.3: the explicit yarn curve is the only geometry traced).  A yarn whose
+ * tube contains the ray origin (distance to its centreline below
+ * R (1 - 1e-3)) is skipped for that ray, so rays leaving a yarn surface do
+ * not hit it again.  The search runs in double precision: BVH traversal,
+ * then per span a sampled scan of the ball entries and Newton on their
+ * slope.  n == 0 is a no-op. */
+int yarn_tube_intersect(const yarn_scene_t* scene, const yarn_ray_soa* rays, int64_t n, float t_min,
+                        const yarn_hit_soa* hits, hipStream_t stream);
+
 /* Host-only: algorithmic operation count of the kernels' formulation.
  * Runs the per-query model on the host with counting scalars over n
  * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type

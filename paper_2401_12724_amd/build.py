@@ -15,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbysdf.so")
-SOURCES = ["bysdf_lib.hip"]
-HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_opcount.hpp", "bysdf_dual.hpp"]
+SOURCES = ["bysdf_lib.hip", "yarn_scene.hip"]
+HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_opcount.hpp", "bysdf_dual.hpp",
+           "yarn_tube.hpp", "yarn_build.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

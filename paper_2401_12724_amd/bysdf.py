@@ -81,6 +81,18 @@ class SampleOutSoA(C.Structure):
 _lib = None
 
 
+class RaySoA(C.Structure):
+    _fields_ = [(k, _vp) for k in ("o_x", "o_y", "o_z", "d_x", "d_y", "d_z", "t_max")]
+
+
+HIT_FIELDS = ("t", "yarn", "seg", "s", "h", "u", "v", "tan_x", "tan_y", "tan_z", "nrm_x",
+              "nrm_y", "nrm_z", "flags")
+
+
+class HitSoA(C.Structure):
+    _fields_ = [(k, _vp) for k in HIT_FIELDS]
+
+
 def lib():
     """Load libbysdf.so; raises if it has not been built (no fallback)."""
     global _lib
@@ -110,6 +122,11 @@ def lib():
         L.bysdf_backward_workspace_size.restype = C.c_size_t
         L.bysdf_eval_backward.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, _vp, _vp, _vp, _vp,
                                           _vp, C.c_size_t, _vp]
+        L.yarn_scene_create.argtypes = [_vp, _vp, C.c_int32, _vp, _vp, C.POINTER(_vp), _vp]
+        L.yarn_scene_destroy.argtypes = [_vp]
+        L.yarn_scene_info.argtypes = [_vp, C.POINTER(C.c_int64)]
+        L.yarn_tube_intersect.argtypes = [_vp, C.POINTER(RaySoA), C.c_int64, C.c_float,
+                                          C.POINTER(HitSoA), _vp]
         _lib = L
     return _lib
 
@@ -364,3 +381,75 @@ def bysdf_eval_backward(types: Types, q: dict, offsets, grad_E, grad_theta=None,
                                      grad_E.data_ptr(), grad_theta.data_ptr(), _ptr(pq),
                                      aligned, ws, _stream(stream)), "bysdf_eval_backward")
     return grad_theta, pq
+
+
+# ---------------------------------------------------------------- yarn scenes
+
+HIT_MISS = 1 << 0
+HIT_CAP = 1 << 1
+HIT_EXCLUDED = 1 << 2
+HIT_BAD_INPUT = 1 << 9
+
+
+class Scene:
+    """Owner of a yarn_scene_t handle."""
+
+    def __init__(self, handle, n_yarns):
+        self.handle = handle
+        self.n_yarns = n_yarns
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                lib().yarn_scene_destroy(self.handle)
+            except TypeError:  # interpreter shutdown: the process releases the memory
+                pass
+            self.handle = None
+
+
+def yarn_scene_create(ctrl, yarn_off, yarn_type=None, yarn_phase=None, stream=None) -> Scene:
+    """ctrl (n_cp, 4) float32 host rows x y z r; yarn_off (n_yarns + 1)
+    int64; yarn_type (n_yarns) int32 and yarn_phase (n_yarns) float32,
+    optional.  All host arrays."""
+    ctrl = np.ascontiguousarray(ctrl, np.float32)
+    off = np.ascontiguousarray(yarn_off, np.int64)
+    n_y = len(off) - 1
+    ty = None if yarn_type is None else np.ascontiguousarray(yarn_type, np.int32)
+    ph = None if yarn_phase is None else np.ascontiguousarray(yarn_phase, np.float32)
+    h = _vp()
+    rc = lib().yarn_scene_create(ctrl.ctypes.data, off.ctypes.data, n_y,
+                                 None if ty is None else ty.ctypes.data,
+                                 None if ph is None else ph.ctypes.data, C.byref(h),
+                                 _stream(stream))
+    _check(rc, "yarn_scene_create")
+    return Scene(h.value, n_y)
+
+
+def yarn_scene_info(scene: Scene) -> dict:
+    info = (C.c_int64 * 6)()
+    _check(lib().yarn_scene_info(scene.handle, info), "yarn_scene_info")
+    return dict(zip(("n_yarns", "n_cp", "n_spans", "n_nodes", "depth", "bytes"), list(info)))
+
+
+def alloc_hits(n, device="cuda"):
+    import torch
+    out = {}
+    for k in HIT_FIELDS:
+        dt = torch.int32 if k in ("yarn", "seg", "flags") else torch.float32
+        out[k] = torch.empty(n, dtype=dt, device=device)
+    return out
+
+
+def yarn_tube_intersect(scene: Scene, o, d, t_max, t_min: float = 0.0, hits=None, stream=None):
+    """o, d: float32 device tensors [3, n]; t_max float32 [n].  Returns a
+    dict of device tensors keyed by the yarn_hit_soa field names."""
+    n = t_max.shape[0]
+    assert o.shape == (3, n) and d.shape == (3, n) and o.is_contiguous() and d.is_contiguous()
+    if hits is None:
+        hits = alloc_hits(n, device=t_max.device)
+    r = RaySoA(o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), d[0].data_ptr(),
+               d[1].data_ptr(), d[2].data_ptr(), t_max.data_ptr())
+    hs = HitSoA(*[hits[k].data_ptr() for k in HIT_FIELDS])
+    _check(lib().yarn_tube_intersect(scene.handle, C.byref(r), n, float(t_min), C.byref(hs),
+                                     _stream(stream)), "yarn_tube_intersect")
+    return hits

@@ -51,6 +51,13 @@ static int fail(int code, const char* fmt, ...)
                         "%s failed: %s", #expr, hipGetErrorString(e_));                   \
     } while (0)
 
+// shared with the other translation units of the library (scene, renderer)
+__attribute__((visibility("hidden"))) int bysdf_set_error(int code, const char* msg)
+{
+    g_err = msg;
+    return code;
+}
+
 extern "C" const char* bysdf_version(void) { return "bysdf-gfx950 0.1"; }
 extern "C" const char* bysdf_last_error(void) { return g_err.c_str(); }
 

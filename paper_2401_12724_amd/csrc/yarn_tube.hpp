@@ -1,0 +1,538 @@
+// yarn_tube.hpp -- device side of ray / yarn-tube intersection.
+//
+// A yarn is a uniform cubic B-spline centreline (the explicit yarn curves
+// of Sec. 3.3) with radius R; its tube is the union of the balls of radius
+// R centred on the curve.  Entering through the ball at C(s) happens at
+// ray parameter T(s) = z(s) - sqrt(R^2 - r^2(s)), with z the distance of
+// C(s) along the ray and r its distance from the ray, so the entry into a
+// span is the minimum of T over s (an interior minimum is where the ray
+// meets the tube surface, the closest-point condition).  Per span: T is
+// sampled at a few points, the best sample is bracketed and polished by
+// safeguarded Newton on dT/ds in double precision.
+//
+// The BVH is binary; a node holds both child boxes (64 bytes), children
+// are visited near first, and the per-thread stack lives in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "../../include/bysdf.h"
+
+namespace yarn {
+
+constexpr int kStack = 64;        // BVH depth bound enforced by the builder
+constexpr int kMaxExcluded = 4;   // yarns holding the ray origin
+constexpr double kExcludeFrac = 1e-3;
+
+// hit flags
+constexpr uint32_t HIT_MISS = 1u << 0;
+constexpr uint32_t HIT_CAP = 1u << 1;
+constexpr uint32_t HIT_EXCLUDED = 1u << 2;
+constexpr uint32_t HIT_BAD_INPUT = 1u << 9;
+
+struct BNode {
+    float4 a, b, c;  // child boxes: lo0 hi0 lo1 hi1 packed
+    int4 d;          // child codes: >= 0 node, < 0 leaf (-(first*4 + count-1) - 1)
+};
+
+// span record (leaf order): first control point, yarn, index in the
+// yarn, samples | first-span bit 16 | last-span bit 17
+struct SpanRec {
+    int cp0, yarn, seg, info;
+};
+
+struct SceneView {
+    const float4* cp;       // x y z R per control point
+    const SpanRec* span;    // leaf order
+    const float4* frame;    // per span (leaf order): RMF normal at s = 0, arc length at s = 0
+    const BNode* node;
+    const float* yarn_phase;
+    const int* yarn_type;
+    int n_nodes;
+};
+
+struct D3 {
+    double x, y, z;
+};
+__host__ __device__ inline D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+__host__ __device__ inline D3 operator+(D3 a, D3 b) { return d3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__host__ __device__ inline D3 operator-(D3 a, D3 b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__host__ __device__ inline D3 operator*(D3 a, double s) { return d3(a.x * s, a.y * s, a.z * s); }
+__host__ __device__ inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline D3 cross(D3 a, D3 b)
+{
+    return d3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline D3 unit(D3 a) { return a * (1.0 / sqrt(dot(a, a))); }
+
+// uniform cubic B-spline basis and its first two derivatives
+__host__ __device__ inline void basis(double s, double* b)
+{
+    double u = 1.0 - s, s2 = s * s, s3 = s2 * s;
+    b[0] = u * u * u * (1.0 / 6.0);
+    b[1] = (3.0 * s3 - 6.0 * s2 + 4.0) * (1.0 / 6.0);
+    b[2] = (-3.0 * s3 + 3.0 * s2 + 3.0 * s + 1.0) * (1.0 / 6.0);
+    b[3] = s3 * (1.0 / 6.0);
+}
+__host__ __device__ inline void basis1(double s, double* b)
+{
+    double u = 1.0 - s;
+    b[0] = -0.5 * u * u;
+    b[1] = 1.5 * s * s - 2.0 * s;
+    b[2] = -1.5 * s * s + s + 0.5;
+    b[3] = 0.5 * s * s;
+}
+__host__ __device__ inline void basis2(double s, double* b)
+{
+    b[0] = 1.0 - s;
+    b[1] = 3.0 * s - 2.0;
+    b[2] = -3.0 * s + 1.0;
+    b[3] = s;
+}
+__host__ __device__ inline D3 comb(const D3* c, const double* b)
+{
+    return d3(b[0] * c[0].x + b[1] * c[1].x + b[2] * c[2].x + b[3] * c[3].x,
+              b[0] * c[0].y + b[1] * c[1].y + b[2] * c[2].y + b[3] * c[3].y,
+              b[0] * c[0].z + b[1] * c[1].z + b[2] * c[2].z + b[3] * c[3].z);
+}
+
+// Ray-space view of one span: control points relative to the origin.
+struct SpanGeo {
+    D3 c[4];
+    double R;
+};
+
+__host__ __device__ inline double entry_at(const SpanGeo& g, D3 d, double s, double t_min)
+{
+    double b[4];
+    basis(s, b);
+    D3 p = comb(g.c, b);
+    double z = dot(p, d);
+    double r2 = dot(p, p) - z * z;
+    double q2 = g.R * g.R - r2;
+    if (!(q2 > 0.0)) return INFINITY;
+    double t = z - sqrt(q2);
+    return t > t_min ? t : INFINITY;
+}
+
+// dT/ds and d2T/ds2 at s; returns false where the ball misses the ray
+__host__ __device__ inline bool entry_slope(const SpanGeo& g, D3 d, double s, double* g1, double* g2)
+{
+    double b[4], b1[4], b2[4];
+    basis(s, b);
+    basis1(s, b1);
+    basis2(s, b2);
+    D3 p = comb(g.c, b), p1 = comb(g.c, b1), p2 = comb(g.c, b2);
+    double z = dot(p, d), z1 = dot(p1, d), z2 = dot(p2, d);
+    double r2 = dot(p, p) - z * z;
+    double q2 = g.R * g.R - r2;
+    if (!(q2 > 0.0)) return false;
+    double q = sqrt(q2);
+    double h = dot(p, p1) - z * z1;  // (r^2)' / 2
+    *g1 = z1 + h / q;
+    double hp = dot(p1, p1) + dot(p, p2) - z1 * z1 - z * z2;
+    *g2 = z2 + hp / q + h * h / (q2 * q);
+    return true;
+}
+
+// First entry of the ray (unit d, origin at 0 of the span view) into the
+// span's tube piece with t_min < t < t_best.  nsamp + 1 samples of T, then
+// safeguarded Newton on dT/ds inside the best sample's bracket.
+__host__ __device__ inline bool span_entry(const SpanGeo& g, D3 d, D3 e1, D3 e2, double t_min, double t_best,
+                                  int nsamp, double* t_out, double* s_out)
+{
+    // control-point hull outside the ray's R-slab: the curve is too
+    double R = g.R;
+    bool all_pu = true, all_nu = true, all_pw = true, all_nw = true, all_b = true, all_f = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double u = dot(g.c[k], e1), w = dot(g.c[k], e2), z = dot(g.c[k], d);
+        all_pu &= u > R;
+        all_nu &= u < -R;
+        all_pw &= w > R;
+        all_nw &= w < -R;
+        all_b &= z + R < t_min;
+        all_f &= z - R > t_best;
+    }
+    if (all_pu || all_nu || all_pw || all_nw || all_b || all_f) return false;
+    double inv = 1.0 / nsamp;
+    double bt = INFINITY;
+    int bi = -1;
+    for (int i = 0; i <= nsamp; ++i) {
+        double t = entry_at(g, d, i * inv, t_min);
+        if (t < bt) {
+            bt = t;
+            bi = i;
+        }
+    }
+    // a minimum between samples lies below the best sample by far less
+    // than R: refine unless the best sample is beyond t_best + R (two
+    // neighbouring spans share the ball at their joint, so a sample can
+    // tie the current best while the true minimum lies inside this span)
+    if (bi < 0 || bt > t_best + R) return false;
+    double lo = bi > 0 ? (bi - 1) * inv : 0.0, hi = bi < nsamp ? (bi + 1) * inv : 1.0;
+    double s = bi * inv, g1, g2;
+    // slope at the bracket ends (a ball that misses the ray reads as a
+    // steep wall: -inf on the left, +inf on the right)
+    double glo = entry_slope(g, d, lo, &g1, &g2) ? g1 : -INFINITY;
+    double ghi = entry_slope(g, d, hi, &g1, &g2) ? g1 : INFINITY;
+    double sb = s;
+    if (glo >= 0.0) {
+        sb = lo;
+    } else if (ghi <= 0.0) {
+        sb = hi;
+    } else {
+        for (int it = 0; it < 24; ++it) {
+            double sn;
+            if (entry_slope(g, d, s, &g1, &g2)) {
+                if (g1 < 0.0)
+                    lo = s;
+                else
+                    hi = s;
+                sn = s - g1 / g2;
+                if (!(g2 > 0.0) || !(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+            } else {
+                sn = 0.5 * (lo + hi);
+            }
+            bool done = fabs(sn - s) < 1e-15 || hi - lo < 1e-15;
+            s = sn;
+            if (done) break;
+        }
+        sb = s;
+    }
+    double t = entry_at(g, d, sb, t_min);
+    // where T is flat the refined value ties the best sample to rounding:
+    // keep the refined parameter
+    if (t <= bt + 1e-12 * fmax(1.0, fabs(bt))) {
+        *t_out = fmin(t, bt);
+        *s_out = sb;
+    } else {
+        *t_out = bt;
+        *s_out = bi * inv;
+    }
+    return true;
+}
+
+__host__ __device__ inline void load_span(const SceneView& S, const SpanRec& r, D3 o, SpanGeo* g)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float4 p = S.cp[r.cp0 + k];
+        g->c[k] = d3((double)p.x - o.x, (double)p.y - o.y, (double)p.z - o.z);
+        if (k == 0) g->R = (double)p.w;
+    }
+}
+
+// squared distance from the origin of the span view to the curve: samples,
+// then safeguarded Newton on the derivative of |C(s)|^2
+__host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
+{
+    double inv = 1.0 / nsamp, bv = INFINITY;
+    int bi = 0;
+    double b[4], b1[4], b2[4];
+    for (int i = 0; i <= nsamp; ++i) {
+        basis(i * inv, b);
+        D3 p = comb(g.c, b);
+        double v = dot(p, p);
+        if (v < bv) {
+            bv = v;
+            bi = i;
+        }
+    }
+    double lo = bi > 0 ? (bi - 1) * inv : 0.0, hi = bi < nsamp ? (bi + 1) * inv : 1.0, s = bi * inv;
+    for (int it = 0; it < 20; ++it) {
+        basis(s, b);
+        basis1(s, b1);
+        basis2(s, b2);
+        D3 p = comb(g.c, b), p1 = comb(g.c, b1), p2 = comb(g.c, b2);
+        double f1 = dot(p, p1), f2 = dot(p1, p1) + dot(p, p2);
+        double v = dot(p, p);
+        if (v < bv) bv = v;
+        if (f1 < 0.0)
+            lo = s;
+        else
+            hi = s;
+        double sn = s - f1 / f2;
+        if (!(f2 > 0.0) || !(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+        if (fabs(sn - s) < 1e-15) break;
+        s = sn;
+    }
+    basis(s, b);
+    D3 p = comb(g.c, b);
+    double v = dot(p, p);
+    return v < bv ? v : bv;
+}
+
+__host__ __device__ inline void decode_leaf(int code, int* first, int* count)
+{
+    int c = -code - 1;
+    *first = c >> 2;
+    *count = (c & 3) + 1;
+}
+
+__host__ __device__ inline void child_boxes(const BNode& n, float3* lo0, float3* hi0, float3* lo1, float3* hi1)
+{
+    *lo0 = make_float3(n.a.x, n.a.y, n.a.z);
+    *hi0 = make_float3(n.a.w, n.b.x, n.b.y);
+    *lo1 = make_float3(n.b.z, n.b.w, n.c.x);
+    *hi1 = make_float3(n.c.y, n.c.z, n.c.w);
+}
+
+__host__ __device__ inline bool box_ray(float3 lo, float3 hi, float3 o, float3 inv, float t0, float t1, float* tn)
+{
+    float ax = (lo.x - o.x) * inv.x, bx = (hi.x - o.x) * inv.x;
+    float ay = (lo.y - o.y) * inv.y, by = (hi.y - o.y) * inv.y;
+    float az = (lo.z - o.z) * inv.z, bz = (hi.z - o.z) * inv.z;
+    float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
+    float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t1));
+    // conservative against the rounding of the slab distances
+    tmax *= 1.0000004f;
+    *tn = tmin;
+    return tmin <= tmax;
+}
+
+__host__ __device__ inline bool box_point(float3 lo, float3 hi, float3 p)
+{
+    return p.x >= lo.x && p.x <= hi.x && p.y >= lo.y && p.y <= hi.y && p.z >= lo.z && p.z <= hi.z;
+}
+
+// Yarns whose tube holds the origin (distance to the centreline below
+// R (1 - 1e-3)).  Point query through the BVH; stack at stk[k * stride].
+__host__ __device__ inline int excluded_yarns(const SceneView& S, D3 o, int* stk, int stride, int* ex)
+{
+    float3 of = make_float3((float)o.x, (float)o.y, (float)o.z);
+    int nex = 0, sp = 0, code = 0;
+    while (true) {
+        if (code >= 0) {
+            BNode n = S.node[code];
+            float3 lo0, hi0, lo1, hi1;
+            child_boxes(n, &lo0, &hi0, &lo1, &hi1);
+            // the float origin may sit a rounding step outside a box that
+            // holds the double origin: grow the test box by a relative ulp
+            float3 e = make_float3(fabsf(of.x) * 2.4e-7f + 1e-30f, fabsf(of.y) * 2.4e-7f + 1e-30f,
+                                   fabsf(of.z) * 2.4e-7f + 1e-30f);
+            lo0 = make_float3(lo0.x - e.x, lo0.y - e.y, lo0.z - e.z);
+            hi0 = make_float3(hi0.x + e.x, hi0.y + e.y, hi0.z + e.z);
+            lo1 = make_float3(lo1.x - e.x, lo1.y - e.y, lo1.z - e.z);
+            hi1 = make_float3(hi1.x + e.x, hi1.y + e.y, hi1.z + e.z);
+            bool h0 = box_point(lo0, hi0, of), h1 = box_point(lo1, hi1, of);
+            if (h0 && h1) {
+                stk[sp++ * stride] = n.d.y;
+                code = n.d.x;
+                continue;
+            }
+            if (h0 || h1) {
+                code = h0 ? n.d.x : n.d.y;
+                continue;
+            }
+        } else {
+            int first, count;
+            decode_leaf(code, &first, &count);
+            for (int k = 0; k < count; ++k) {
+                SpanRec r = S.span[first + k];
+                bool seen = false;
+                for (int j = 0; j < nex; ++j) seen |= ex[j] == r.yarn;
+                if (seen || nex >= kMaxExcluded) continue;
+                SpanGeo g;
+                load_span(S, r, o, &g);
+                double lim = g.R * (1.0 - kExcludeFrac);
+                if (span_dist2(g, r.info & 0xffff) < lim * lim) ex[nex++] = r.yarn;
+            }
+        }
+        if (sp == 0) break;
+        code = stk[--sp * stride];
+    }
+    return nex;
+}
+
+struct RayHit {
+    double t, s;
+    int span;  // leaf-order span index, -1 for a miss
+};
+
+// Closest entering hit with t_min < t <= t_max.
+__host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, double t_min, double t_max,
+                                     const int* ex, int nex, int* stk, int stride)
+{
+    RayHit best{t_max, 0.0, -1};
+    float3 of = make_float3((float)o.x, (float)o.y, (float)o.z);
+    float3 inv = make_float3(1.0f / (fabs(d.x) > 1e-30 ? (float)d.x : 1e-30f),
+                             1.0f / (fabs(d.y) > 1e-30 ? (float)d.y : 1e-30f),
+                             1.0f / (fabs(d.z) > 1e-30 ? (float)d.z : 1e-30f));
+    // the float origin is within a relative ulp of the double one: widen
+    // the slab interval by that much along the ray
+    float slack = 2.4e-7f * (fabsf(of.x) + fabsf(of.y) + fabsf(of.z)) + 1e-30f;
+    // basis of the plane across the ray (for the span hull test)
+    D3 a = fabs(d.x) < 0.9 ? d3(1, 0, 0) : d3(0, 1, 0);
+    D3 e1 = unit(cross(d, a)), e2 = cross(d, e1);
+    int sp = 0, code = 0;
+    float t0 = (float)t_min - slack;
+    while (true) {
+        float t1 = (float)best.t + slack;
+        if (code >= 0) {
+            BNode n = S.node[code];
+            float3 lo0, hi0, lo1, hi1;
+            child_boxes(n, &lo0, &hi0, &lo1, &hi1);
+            float tn0, tn1;
+            bool h0 = box_ray(lo0, hi0, of, inv, t0, t1, &tn0);
+            bool h1 = box_ray(lo1, hi1, of, inv, t0, t1, &tn1);
+            if (h0 && h1) {
+                bool first0 = tn0 <= tn1;
+                stk[sp++ * stride] = first0 ? n.d.y : n.d.x;
+                code = first0 ? n.d.x : n.d.y;
+                continue;
+            }
+            if (h0 || h1) {
+                code = h0 ? n.d.x : n.d.y;
+                continue;
+            }
+        } else {
+            int first, count;
+            decode_leaf(code, &first, &count);
+            for (int k = 0; k < count; ++k) {
+                SpanRec r = S.span[first + k];
+                bool skip = false;
+                for (int j = 0; j < nex; ++j) skip |= ex[j] == r.yarn;
+                if (skip) continue;
+                SpanGeo g;
+                load_span(S, r, o, &g);
+                double t, s;
+                if (span_entry(g, d, e1, e2, t_min, best.t, r.info & 0xffff, &t, &s) && t < best.t) {
+                    best.t = t;
+                    best.s = s;
+                    best.span = first + k;
+                }
+            }
+        }
+        if (sp == 0) break;
+        code = stk[--sp * stride];
+    }
+    return best;
+}
+
+// Frame, h and arc length at a hit.
+struct HitFrame {
+    D3 T, N, B, c;  // tangent, reference normal, binormal, centreline point
+    double v;       // arc length from the yarn start
+};
+
+__host__ __device__ inline HitFrame hit_frame(const SceneView& S, int span, double s)
+{
+    SpanRec r = S.span[span];
+    D3 c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float4 p = S.cp[r.cp0 + k];
+        c[k] = d3(p.x, p.y, p.z);
+    }
+    double b[4];
+    basis(0.0, b);
+    D3 x0 = comb(c, b);
+    basis1(0.0, b);
+    D3 t0 = unit(comb(c, b));
+    basis(s, b);
+    D3 x1 = comb(c, b);
+    basis1(s, b);
+    D3 t1 = unit(comb(c, b));
+    float4 f = S.frame[span];
+    D3 n0 = d3(f.x, f.y, f.z);
+    // one double-reflection step of the rotation-minimising frame
+    // (Wang, Juettler, Zheng and Liu 2008) from the span start to s
+    // a chord at rounding level has a random direction; its limit for a
+    // vanishing step is the tangent
+    D3 v1 = x1 - x0;
+    double c1 = dot(v1, v1);
+    if (!(c1 > 1e-16 * (dot(x0, x0) + dot(x1, x1)))) {
+        v1 = t0;
+        c1 = 1.0;
+    }
+    D3 nl = n0 - v1 * (2.0 * dot(v1, n0) / c1);
+    D3 tl = t0 - v1 * (2.0 * dot(v1, t0) / c1);
+    D3 v2 = t1 - tl;
+    double c2 = dot(v2, v2);
+    if (c2 > 0.0) nl = nl - v2 * (2.0 * dot(v2, nl) / c2);
+    HitFrame h;
+    h.T = t1;
+    h.N = unit(nl - t1 * dot(nl, t1));
+    h.B = cross(h.T, h.N);
+    h.c = x1;
+    // arc length inside the span: 5-point Gauss-Legendre on [0, s]
+    const double gx[5] = {0.0, -0.5384693101056831, 0.5384693101056831, -0.9061798459386640,
+                          0.9061798459386640};
+    const double gw[5] = {0.5688888888888889, 0.4786286704993665, 0.4786286704993665,
+                          0.2369268850561891, 0.2369268850561891};
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        basis1(0.5 * s * (1.0 + gx[k]), b);
+        D3 dd = comb(c, b);
+        acc += gw[k] * sqrt(dot(dd, dd));
+    }
+    h.v = (double)f.w + 0.5 * s * acc;
+    return h;
+}
+
+// One ray: exclusion point query, closest entering hit, hit frame, h, v.
+// stk: this lane's stack entries at stk[k * stride].
+__host__ __device__ inline void intersect_ray(const SceneView& S, int64_t i, const yarn_ray_soa& R,
+                                              double t_min, const yarn_hit_soa& H, int* stk, int stride)
+{
+    D3 o = d3(R.o_x[i], R.o_y[i], R.o_z[i]);
+    D3 dr = d3(R.d_x[i], R.d_y[i], R.d_z[i]);
+    double tm = R.t_max[i];
+    double l2 = dot(dr, dr);
+    uint32_t flags = 0;
+    bool ok = __builtin_isfinite(o.x) && __builtin_isfinite(o.y) && __builtin_isfinite(o.z) &&
+              __builtin_isfinite(l2) && l2 > 0.0 && !__builtin_isnan(tm);
+    if (ok) {
+        D3 d = dr * (1.0 / sqrt(l2));
+        int ex[kMaxExcluded];
+        int nex = excluded_yarns(S, o, stk, stride, ex);
+        if (nex) flags |= HIT_EXCLUDED;
+        RayHit hit = closest_hit(S, o, d, t_min, tm, ex, nex, stk, stride);
+        if (hit.span >= 0) {
+            SpanRec r = S.span[hit.span];
+            HitFrame f = hit_frame(S, hit.span, hit.s);
+            D3 p = o + d * hit.t;
+            D3 q = p - f.c;
+            double qn = dot(q, f.N), qb = dot(q, f.B);
+            double wn = -dot(d, f.N), wb = -dot(d, f.B);
+            double ql = sqrt(qn * qn + qb * qb), wl = sqrt(wn * wn + wb * wb);
+            double h = (ql > 0.0 && wl > 0.0) ? (qb * wn - qn * wb) / (ql * wl) : 0.0;
+            h = fmin(1.0, fmax(-1.0, h));
+            if (((r.info >> 16) & 1) && hit.s <= 0.0) flags |= HIT_CAP;
+            if (((r.info >> 17) & 1) && hit.s >= 1.0) flags |= HIT_CAP;
+            H.t[i] = (float)hit.t;
+            H.yarn[i] = r.yarn;
+            H.seg[i] = r.seg;
+            H.s[i] = (float)hit.s;
+            H.h[i] = (float)h;
+            H.u[i] = S.yarn_phase[r.yarn];
+            H.v[i] = (float)f.v;
+            H.tan_x[i] = (float)f.T.x;
+            H.tan_y[i] = (float)f.T.y;
+            H.tan_z[i] = (float)f.T.z;
+            H.nrm_x[i] = (float)f.N.x;
+            H.nrm_y[i] = (float)f.N.y;
+            H.nrm_z[i] = (float)f.N.z;
+            H.flags[i] = flags;
+            return;
+        }
+    } else {
+        flags |= HIT_BAD_INPUT;
+    }
+    H.t[i] = INFINITY;
+    H.yarn[i] = -1;
+    H.seg[i] = -1;
+    H.s[i] = 0.f;
+    H.h[i] = 0.f;
+    H.u[i] = 0.f;
+    H.v[i] = 0.f;
+    H.tan_x[i] = H.tan_y[i] = H.tan_z[i] = 0.f;
+    H.nrm_x[i] = H.nrm_y[i] = H.nrm_z[i] = 0.f;
+    H.flags[i] = flags | HIT_MISS;
+}
+
+}  // namespace yarn

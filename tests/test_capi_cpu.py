@@ -71,3 +71,30 @@ def test_null_arguments_rejected(L):
     assert L.bysdf_sample_pdf(None, None, 0, None, None) == bysdf.ERR_INVALID_ARG
     assert L.bysdf_types_destroy(None) == bysdf.OK
     assert L.bysdf_types_count(None) == bysdf.ERR_INVALID_ARG
+
+
+def test_scene_arguments_rejected_on_host(L):
+    """yarn_scene_create validates its host arrays before any device call."""
+    import numpy as np
+    h = C.c_void_p()
+    ctrl, off, _, _ = workloads.weave(2, 2, 0.15, 0.05, 4)
+    cp = lambda a: a.ctypes.data
+    assert L.yarn_scene_create(None, cp(off), 4, None, None, C.byref(h), None) == bysdf.ERR_INVALID_ARG
+    assert L.yarn_scene_create(cp(ctrl), cp(off), 0, None, None, C.byref(h), None) == bysdf.ERR_INVALID_ARG
+    assert L.yarn_scene_create(cp(ctrl), cp(off), 4, None, None, None, None) == bysdf.ERR_INVALID_ARG
+    bad_off = off.copy()
+    bad_off[1] = 3                     # a yarn of 3 control points
+    assert L.yarn_scene_create(cp(ctrl), cp(bad_off), 4, None, None, C.byref(h),
+                               None) == bysdf.ERR_INVALID_PARAM
+    assert "control points" in L.bysdf_last_error().decode()
+    bad = ctrl.copy()
+    bad[5, 1] = np.nan
+    assert L.yarn_scene_create(cp(bad), cp(off), 4, None, None, C.byref(h), None) == bysdf.ERR_INVALID_PARAM
+    bad = ctrl.copy()
+    bad[off[2], 3] = 0.0               # radius of yarn 2
+    assert L.yarn_scene_create(cp(bad), cp(off), 4, None, None, C.byref(h), None) == bysdf.ERR_INVALID_PARAM
+    assert h.value is None
+    assert L.yarn_scene_destroy(None) == bysdf.OK
+    info = (C.c_int64 * 6)()
+    assert L.yarn_scene_info(None, info) == bysdf.ERR_INVALID_ARG
+    assert L.yarn_tube_intersect(None, None, 0, C.c_float(0.0), None, None) == bysdf.ERR_INVALID_ARG
