@@ -17,8 +17,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bysdf_oracle.c")
-_SOURCES = [_SRC, os.path.join(_HERE, "yarn_oracle.c")]
-_HEADERS = [os.path.join(_HERE, "bysdf_oracle.h"), os.path.join(_HERE, "yarn_oracle.h")]
+_SOURCES = [_SRC, os.path.join(_HERE, "yarn_oracle.c"), os.path.join(_HERE, "render_oracle.c")]
+_HEADERS = [os.path.join(_HERE, "bysdf_oracle.h"), os.path.join(_HERE, "yarn_oracle.h"),
+            os.path.join(_HERE, "render_oracle.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # flag bits (same numbering as the library's public flags)
@@ -47,6 +48,31 @@ class OrcParams(C.Structure):
         ("ply_density", C.c_double), ("fiber_density", C.c_double),
         ("shadow_halfwidth", C.c_double),
     ]
+
+
+class RenderSettings(C.Structure):
+    _fields_ = [
+        ("eye", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+        ("vfov", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+        ("crop_x", C.c_int32), ("crop_y", C.c_int32), ("crop_w", C.c_int32), ("crop_h", C.c_int32),
+        ("light_corner", C.c_float * 3), ("light_u", C.c_float * 3), ("light_v", C.c_float * 3),
+        ("light_radiance", C.c_float * 3), ("env_radiance", C.c_float * 3),
+        ("spp", C.c_int32), ("max_depth", C.c_int32), ("lod_px", C.c_float), ("n_h", C.c_int32),
+        ("seed", C.c_uint64), ("ray_eps", C.c_float), ("nee", C.c_int32),
+    ]
+
+
+def render_settings_struct(rs: dict) -> RenderSettings:
+    s = RenderSettings()
+    rs = dict(rs)
+    rs.setdefault("nee", 1)
+    for k, _ in RenderSettings._fields_:
+        v = rs[k]
+        if isinstance(v, (tuple, list)):
+            getattr(s, k)[:] = [float(x) for x in v]
+        else:
+            setattr(s, k, v)
+    return s
 
 
 def build(force: bool = False) -> str:
@@ -108,6 +134,8 @@ def lib():
         L.orc_scene_free.argtypes = [C.c_void_p]
         L.orc_scene_frame.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, dp]
         L.orc_intersect.argtypes = [C.c_void_p, C.c_int64, fp, fp, fp, C.c_double, dp, C.c_int]
+        L.orc_render.argtypes = [C.c_void_p, pp, tp, C.c_int32, ip, fp, C.POINTER(RenderSettings),
+                                 dp, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -376,3 +404,19 @@ def intersect(scene: Scene, o, d, t_max, t_min: float = 0.0, nthreads: int = 0):
     lib().orc_intersect(scene._h, n, _ptr(o, C.c_float), _ptr(d, C.c_float), _ptr(tm, C.c_float),
                         float(t_min), _ptr(out, C.c_double), nthreads)
     return out
+
+
+def render(scene: Scene, ts, yarn_type, yarn_phase, rs: dict, nthreads: int = 0):
+    """Crop of the image by the CPU path tracer (render_oracle.c).  ts: a
+    TypeSet (or parameter dicts) indexed by yarn_type.  Returns (mean
+    (crop_h, crop_w, 3), mean of squares (crop_h, crop_w, 3))."""
+    ts = _types(ts)
+    yt = np.ascontiguousarray(yarn_type, np.int32)
+    ph = np.ascontiguousarray(yarn_phase, np.float32)
+    st = render_settings_struct(rs)
+    fb = np.zeros((rs["crop_h"], rs["crop_w"], 3))
+    sq = np.zeros_like(fb)
+    lib().orc_render(scene._h, ts.structs, ts._tp, len(ts), _ptr(yt, C.c_int32),
+                     _ptr(ph, C.c_float), C.byref(st), _ptr(fb, C.c_double), _ptr(sq, C.c_double),
+                     nthreads)
+    return fb, sq

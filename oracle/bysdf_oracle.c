@@ -801,6 +801,15 @@ int orc_eval(const orc_params* types, const double* const* tables, int32_t n_typ
 }
 
 
+/* One query of eval (single type, its table): out[13] as orc_eval. */
+uint32_t orc_eval_query(const orc_params* p, const double* tab, double h, double u, double v,
+                        const double wi[3], const double wo[3], double out[13])
+{
+    uint32_t f;
+    eval_one(p, tab, h, u, v, mk(wi[0], wi[1], wi[2]), mk(wo[0], wo[1], wo[2]), NULL, out, &f);
+    return f;
+}
+
 /* Draw one direction (Sec. 4.1.5): pick a lobe with the energy weights,
  * then GGX visible normals for the specular lobes and a cosine lobe for
  * the body lobes; the forward lobes also pick one quadrature node.
@@ -905,6 +914,15 @@ static void sample_one(const orc_params* p, const double* tab, double h, double 
     for (int c = 0; c < 3; ++c) out[3 + c] = e[c] / pdf;
     out[6] = pdf;
     *fl = f;
+}
+
+/* One query of the sampler (single type, its table): out[12] as orc_sample. */
+uint32_t orc_sample_query(const orc_params* p, const double* tab, double h, double u, double v,
+                          const double wi[3], const double xi[3], double out[12])
+{
+    uint32_t f;
+    sample_one(p, tab, h, u, v, mk(wi[0], wi[1], wi[2]), xi, NULL, out, &f);
+    return f;
 }
 
 int orc_sample(const orc_params* types, const double* const* tables, int32_t n_types,

@@ -133,6 +133,12 @@ uint32_t orc_frame_x(const orc_params* p, const double* tab, double h, double u,
                      const double wi[3], double* out);
 void orc_set_margins(double geo, double shade, double amplify, double tir, double xi);
 
+/* Single queries (one type and its table from orc_table). */
+uint32_t orc_eval_query(const orc_params* p, const double* tab, double h, double u, double v,
+                        const double wi[3], const double wo[3], double out[13]);
+uint32_t orc_sample_query(const orc_params* p, const double* tab, double h, double u, double v,
+                          const double wi[3], const double xi[3], double out[12]);
+
 #ifdef __cplusplus
 }
 #endif

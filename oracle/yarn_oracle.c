@@ -339,12 +339,13 @@ static void scan_span(const scene_t* S, int y, int64_t g, d3 o, d3 d, double t_m
     }
 }
 
-static void intersect_one(const scene_t* S, d3 o, d3 d, double t_max, double t_min, double* out)
+static void intersect_one(const scene_t* S, d3 o, d3 d, double t_max, double t_min, int skip, double* out)
 {
     unsigned flags = 0;
     cand_t best = {INFINITY, 0.0, -INFINITY, -1, -1};
     double second = INFINITY; /* best entry of any other yarn */
     for (int y = 0; y < S->n_yarns; ++y) {
+        if (y == skip) continue;
         const double* yb = S->ybox + 6 * y;
         double R = S->R[y];
         /* exclusion: the origin lies inside this yarn's tube */
@@ -437,6 +438,15 @@ void orc_intersect(const void* scene, int64_t n, const float* o, const float* d,
     for (int64_t i = 0; i < n; ++i) {
         d3 oo = mk(o[3 * i], o[3 * i + 1], o[3 * i + 2]);
         d3 dd = unit(mk(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
-        intersect_one(S, oo, dd, (double)t_max[i], t_min, out + 16 * i);
+        intersect_one(S, oo, dd, (double)t_max[i], t_min, -1, out + 16 * i);
     }
 }
+
+void orc_intersect_one(const void* scene, const double o[3], const double d[3], double t_min,
+                       double t_max, int32_t skip_yarn, double out[16])
+{
+    intersect_one((const scene_t*)scene, mk(o[0], o[1], o[2]), unit(mk(d[0], d[1], d[2])), t_max,
+                  t_min, skip_yarn, out);
+}
+
+double orc_scene_radius(const void* scene, int32_t yarn) { return ((const scene_t*)scene)->R[yarn]; }

@@ -62,6 +62,14 @@ void orc_scene_frame(const void* scene, int32_t yarn, int32_t seg, double s, dou
 void orc_intersect(const void* scene, int64_t n, const float* o, const float* d,
                    const float* t_max, double t_min, double* out, int nthreads);
 
+/* One ray (double origin and direction) with yarn `skip_yarn` left out
+ * (-1: none); out[16] as orc_intersect. */
+void orc_intersect_one(const void* scene, const double o[3], const double d[3], double t_min,
+                       double t_max, int32_t skip_yarn, double out[16]);
+
+/* Radius of a yarn. */
+double orc_scene_radius(const void* scene, int32_t yarn);
+
 #ifdef __cplusplus
 }
 #endif
