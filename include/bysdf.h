@@ -319,6 +319,63 @@ typedef struct {
 int yarn_tube_intersect(const yarn_scene_t* scene, const yarn_ray_soa* rays, int64_t n, float t_min,
                         const yarn_hit_soa* hits, hipStream_t stream);
 
+/* ------------------------------------------------------------- rendering */
+/* Settings of shade_wavefront.  Camera: pinhole at eye looking at look_at
+ * (up vector up), vertical field of view vfov (radians), full image
+ * width x height; only the crop [crop_x, crop_x + crop_w) x [crop_y,
+ * crop_y + crop_h) is rendered (row 0 at the top).  Light: one-sided
+ * rectangle corner + a light_u + b light_v (a, b in [0, 1]) emitting
+ * light_radiance (RGB) towards the side of light_u x light_v.  The
+ * environment radiance is constant.  spp paths per pixel, at most
+ * max_depth scattering events each; yarns narrower than lod_px pixels at
+ * their camera distance use the far field (Eq. 7, W = 1) over n_h strata
+ * of h.  seed keys the random streams; ray_eps is the t_min of rays that
+ * leave a yarn.  spp_batch: samples per pixel per wavefront pass (0 = all
+ * at once); it sets the workspace size. */
+typedef struct {
+    float eye[3], look_at[3], up[3];
+    float vfov;
+    int32_t width, height;
+    int32_t crop_x, crop_y, crop_w, crop_h;
+    float light_corner[3], light_u[3], light_v[3], light_radiance[3];
+    float env_radiance[3];
+    int32_t spp, max_depth;
+    float lod_px;
+    int32_t n_h;
+    uint64_t seed;
+    float ray_eps;
+    int32_t spp_batch;
+} render_settings;
+
+/* Bytes of device workspace shade_wavefront needs (0 on bad settings). */
+size_t shade_wavefront_workspace_size(const render_settings* rs);
+
+/* Path-trace the crop with the BYSDF of each yarn's type (the scene's
+ * yarn_type indexes `types`), as a wavefront: camera rays; then per bounce
+ * extension rays through the yarn BVH (a light or environment hit adds
+ * its radiance, with the power heuristic against the BYSDF pdf for the
+ * light), BYSDF shading at the hits (Sec. 4.1, the far field of Sec. 4.2
+ * by the LOD rule), next-event estimation to the light with shadow rays
+ * that pass through a yarn where its implicit plies are missed (Sec. 3.4),
+ * a BYSDF sample to continue, and compaction of the surviving paths.  The
+ * BYSDF acts at the yarn hit: rays leave from the hit point and skip the
+ * yarn they leave.  Random numbers: Philox4x32-10 keyed by seed, counter
+ * (slot, slot >> 32, bounce, stream), slot = (pixel in crop) * spp +
+ * sample.  framebuffer: DEVICE float[crop_h][crop_w][3], the mean
+ * radiance per pixel (overwritten).  workspace: DEVICE buffer of
+ * shade_wavefront_workspace_size(rs) bytes, 256-byte aligned.
+ * ray_counts: nullable HOST int64[2] receiving the extension and shadow
+ * rays traced; when given, the call synchronises the stream.  Each path
+ * writes only its own radiance slot, so the image is a deterministic
+ * function of the settings. */
+int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* types, const render_settings* rs,
+                    float* framebuffer, void* workspace, size_t ws_bytes, int64_t* ray_counts,
+                    hipStream_t stream);
+
+/* Host utility: the Philox4x32-10 block the renderer draws from, for
+ * verification against published known-answer vectors. */
+void bysdf_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
 /* Host-only: algorithmic operation count of the kernels' formulation.
  * Runs the per-query model on the host with counting scalars over n
  * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type

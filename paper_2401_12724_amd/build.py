@@ -15,9 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbysdf.so")
-SOURCES = ["bysdf_lib.hip", "yarn_scene.hip"]
+SOURCES = ["bysdf_lib.hip", "yarn_scene.hip", "render.hip"]
 HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_opcount.hpp", "bysdf_dual.hpp",
-           "yarn_tube.hpp", "yarn_build.hpp"]
+           "yarn_tube.hpp", "yarn_build.hpp", "philox.hpp",
+           "lib_internal.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -93,6 +93,18 @@ class HitSoA(C.Structure):
     _fields_ = [(k, _vp) for k in HIT_FIELDS]
 
 
+class RenderSettings(C.Structure):
+    _fields_ = [
+        ("eye", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+        ("vfov", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+        ("crop_x", C.c_int32), ("crop_y", C.c_int32), ("crop_w", C.c_int32), ("crop_h", C.c_int32),
+        ("light_corner", C.c_float * 3), ("light_u", C.c_float * 3), ("light_v", C.c_float * 3),
+        ("light_radiance", C.c_float * 3), ("env_radiance", C.c_float * 3),
+        ("spp", C.c_int32), ("max_depth", C.c_int32), ("lod_px", C.c_float), ("n_h", C.c_int32),
+        ("seed", C.c_uint64), ("ray_eps", C.c_float), ("spp_batch", C.c_int32),
+    ]
+
+
 def lib():
     """Load libbysdf.so; raises if it has not been built (no fallback)."""
     global _lib
@@ -127,6 +139,12 @@ def lib():
         L.yarn_scene_info.argtypes = [_vp, C.POINTER(C.c_int64)]
         L.yarn_tube_intersect.argtypes = [_vp, C.POINTER(RaySoA), C.c_int64, C.c_float,
                                           C.POINTER(HitSoA), _vp]
+        L.shade_wavefront_workspace_size.argtypes = [C.POINTER(RenderSettings)]
+        L.shade_wavefront_workspace_size.restype = C.c_size_t
+        L.shade_wavefront.argtypes = [_vp, _vp, C.POINTER(RenderSettings), _vp, _vp, C.c_size_t,
+                                      C.POINTER(C.c_int64), _vp]
+        L.bysdf_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
+        L.bysdf_philox4x32_10.restype = None
         _lib = L
     return _lib
 
@@ -453,3 +471,57 @@ def yarn_tube_intersect(scene: Scene, o, d, t_max, t_min: float = 0.0, hits=None
     _check(lib().yarn_tube_intersect(scene.handle, C.byref(r), n, float(t_min), C.byref(hs),
                                      _stream(stream)), "yarn_tube_intersect")
     return hits
+
+
+# ---------------------------------------------------------------- rendering
+
+def render_settings(rs: dict) -> RenderSettings:
+    """render_settings from a dict with the field names of the C struct
+    (spp_batch defaults to 0: every sample in one pass)."""
+    st = RenderSettings()
+    rs = dict(rs)
+    rs.setdefault("spp_batch", 0)
+    for k, _ in RenderSettings._fields_:
+        v = rs[k]
+        if isinstance(v, (tuple, list)):
+            getattr(st, k)[:] = [float(x) for x in v]
+        else:
+            setattr(st, k, v)
+    return st
+
+
+def shade_wavefront_workspace_size(rs: dict) -> int:
+    return int(lib().shade_wavefront_workspace_size(C.byref(render_settings(rs))))
+
+
+def shade_wavefront(scene: Scene, types: Types, rs: dict, fb=None, workspace=None, counts=False,
+                    stream=None):
+    """Render the crop; returns the device framebuffer float32 [crop_h,
+    crop_w, 3] (and the (extension, shadow) ray counts when counts=True,
+    which synchronises)."""
+    import torch
+    st = render_settings(rs)
+    nb = int(lib().shade_wavefront_workspace_size(C.byref(st)))
+    if nb == 0:
+        _check(-2, "shade_wavefront_workspace_size")
+    if fb is None:
+        fb = torch.empty((rs["crop_h"], rs["crop_w"], 3), dtype=torch.float32, device="cuda")
+    if workspace is None:
+        workspace = alloc_workspace(nb)
+    buf, ptr = workspace
+    rc_counts = (C.c_int64 * 2)() if counts else None
+    _check(lib().shade_wavefront(scene.handle, types.handle, C.byref(st), fb.data_ptr(), ptr,
+                                 buf.numel() - (ptr - buf.data_ptr()), rc_counts, _stream(stream)),
+           "shade_wavefront")
+    if counts:
+        return fb, (int(rc_counts[0]), int(rc_counts[1]))
+    return fb
+
+
+def bysdf_philox4x32_10(ctr, key):
+    """Host call of the renderer's Philox4x32-10 block."""
+    c = (C.c_uint32 * 4)(*[int(x) & 0xffffffff for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xffffffff for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().bysdf_philox4x32_10(c, k, o)
+    return [int(x) for x in o]

@@ -25,6 +25,7 @@
 #include "bysdf_model.hpp"
 #include "bysdf_opcount.hpp"
 #include "bysdf_dual.hpp"
+#include "lib_internal.hpp"
 
 using namespace bysdf;
 
@@ -694,6 +695,12 @@ __global__ void k_set_theta(TypeRec* types, const float* theta, int n)
 }
 
 // ------------------------------------------------------------------ host API
+// the renderer (another translation unit) reads the handle's device data
+__attribute__((visibility("hidden"))) BysdfTypesView bysdf_types_view(const bysdf_types_t* h)
+{
+    return BysdfTypesView{h->d_types, h->d_tables, h->n_types, h->max_plies, h->max_K};
+}
+
 static bool aligned4(const void* p) { return p && ((uintptr_t)p & 3u) == 0; }
 
 extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, bysdf_types_t** out,

@@ -249,8 +249,10 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
     if (n_spans >= (1 << 29)) return build_fail(err, BYSDF_ERR_INVALID_PARAM, "too many spans (%lld)", (long long)n_spans);
     for (int64_t i = 0; i < 4 * n_cp; ++i)
         if (!std::isfinite(ctrl[i])) return build_fail(err, BYSDF_ERR_INVALID_PARAM, "non-finite control point value at %lld", (long long)i);
-    for (int y = 0; y < n_yarns; ++y)
+    for (int y = 0; y < n_yarns; ++y) {
         if (!(ctrl[4 * off[y] + 3] > 0.f)) return build_fail(err, BYSDF_ERR_INVALID_PARAM, "yarn %d has radius <= 0", y);
+        if (yarn_type && yarn_type[y] < 0) return build_fail(err, BYSDF_ERR_INVALID_PARAM, "yarn %d has type %d < 0", y, yarn_type[y]);
+    }
     // per span: record, frame at the start, box
     std::vector<SpanRec> rec(n_spans);
     std::vector<float4> frame(n_spans);

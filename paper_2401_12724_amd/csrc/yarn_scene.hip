@@ -23,12 +23,11 @@
 #include <vector>
 
 #include "../../include/bysdf.h"
+#include "lib_internal.hpp"
 #include "yarn_build.hpp"
 #include "yarn_tube.hpp"
 
 using namespace yarn;
-
-int bysdf_set_error(int code, const char* msg);
 
 static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static int fail(int code, const char* fmt, ...)
@@ -54,6 +53,7 @@ struct yarn_scene {
     int32_t n_yarns = 0;
     int64_t n_cp = 0, n_spans = 0, n_nodes = 0;
     int depth = 0;
+    int max_type = 0;  // largest yarn type index (checked against a types handle)
     float4* d_cp = nullptr;
     SpanRec* d_span = nullptr;
     float4* d_frame = nullptr;
@@ -141,6 +141,7 @@ extern "C" int yarn_scene_create(const float* ctrl, const int64_t* off, int32_t 
     s->n_spans = n_spans;
     s->n_nodes = (int64_t)B.nodes.size();
     s->depth = B.max_depth;
+    for (int y = 0; y < n_yarns; ++y) s->max_type = std::max(s->max_type, type[y]);
     auto up = [&](void** dst, const void* src, size_t bytes) -> int {
         hipError_t e = hipMalloc(dst, bytes);
         if (e != hipSuccess) return fail(BYSDF_ERR_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
@@ -188,6 +189,7 @@ extern "C" int yarn_scene_info(const yarn_scene_t* s, int64_t* info)
 
 // scene view for the renderer (same library)
 __attribute__((visibility("hidden"))) SceneView yarn_scene_view(const yarn_scene_t* s) { return s->view(); }
+__attribute__((visibility("hidden"))) int yarn_scene_max_type(const yarn_scene_t* s) { return s->max_type; }
 
 extern "C" int yarn_tube_intersect(const yarn_scene_t* s, const yarn_ray_soa* rays, int64_t n, float t_min,
                                    const yarn_hit_soa* hits, hipStream_t stream)

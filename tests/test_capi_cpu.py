@@ -98,3 +98,32 @@ def test_scene_arguments_rejected_on_host(L):
     info = (C.c_int64 * 6)()
     assert L.yarn_scene_info(None, info) == bysdf.ERR_INVALID_ARG
     assert L.yarn_tube_intersect(None, None, 0, C.c_float(0.0), None, None) == bysdf.ERR_INVALID_ARG
+
+
+def test_renderer_philox_known_answers(L):
+    """The renderer's Philox4x32-10 (its own code, called on the host)
+    reproduces the published known-answer vectors."""
+    n = 0
+    for line in open(os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        assert bysdf.bysdf_philox4x32_10(w[0:4], w[4:6]) == w[6:10]
+        n += 1
+    assert n >= 3
+
+
+def test_render_settings_rejected_on_host(L):
+    base = dict(eye=(0, -3, 1), look_at=(0, 0, 0), up=(0, 0, 1), vfov=0.5, width=64, height=48,
+                crop_x=0, crop_y=0, crop_w=16, crop_h=16, light_corner=(-1, -1, 3),
+                light_u=(0, 2, 0), light_v=(2, 0, 0), light_radiance=(1, 1, 1),
+                env_radiance=(0.2, 0.2, 0.2), spp=4, max_depth=4, lod_px=1.0, n_h=4, seed=1,
+                ray_eps=1e-4, spp_batch=2)
+    ok = bysdf.shade_wavefront_workspace_size(base)
+    # 16 x 16 pixels x 2 samples per pass, 51 arrays of floats
+    assert ok >= 16 * 16 * 2 * 4 * 51
+    for k, v in (("crop_w", 100), ("spp", 0), ("spp_batch", 5), ("max_depth", 65), ("vfov", 0.0),
+                 ("n_h", 0), ("crop_x", -1)):
+        assert bysdf.shade_wavefront_workspace_size(dict(base, **{k: v})) == 0, k
+    st = bysdf.render_settings(base)
+    assert L.shade_wavefront(None, None, C.byref(st), None, None, 0, None, None) == bysdf.ERR_INVALID_ARG

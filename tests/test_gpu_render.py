@@ -1,0 +1,144 @@
+"""GPU wavefront renderer (shade_wavefront) against the CPU path tracer of
+the oracle, on the same random streams: crop means within sampling error and, at
+one path per pixel, most paths equal to their oracle twin (a path departs
+where the model's fiber-scale detail amplifies a last-bit difference),
+the far field, the white furnace, two crops
+of the full 512-yarn weave, determinism and independence of the batching.
+
+Reading of the large-weave view: a yarn of radius 0.05 at most ~65 units
+from the camera spans at least ~3 pixels of the 1920 x 1080 image, so the
+one-pixel LOD switch never fires there; the crop near the far edge uses a
+4-pixel switch to exercise the far field."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_12724_amd import bysdf, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _settings(cam, crop, **kw):
+    rs = dict(eye=cam["eye"], look_at=cam["look_at"], up=cam["up"], vfov=cam["vfov"],
+              width=cam["width"], height=cam["height"], crop_x=crop[0], crop_y=crop[1],
+              crop_w=crop[2], crop_h=crop[3], light_corner=(-5.0, -5.0, 30.0),
+              light_u=(0.0, 10.0, 0.0), light_v=(10.0, 0.0, 0.0), light_radiance=(5.0, 5.0, 5.0),
+              env_radiance=(0.2, 0.2, 0.2), spp=16, max_depth=8, lod_px=1.0, n_h=4, seed=7,
+              ray_eps=1e-4, spp_batch=0)
+    rs.update(kw)
+    return rs
+
+
+def _render_both(torch, scene_args, P, rs):
+    ctrl, off, ty, ph = scene_args
+    Sg = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    Tg = bysdf.bysdf_types_create(P)
+    fb, counts = bysdf.shade_wavefront(Sg, Tg, rs, counts=True)
+    torch.cuda.synchronize()
+    g = fb.cpu().numpy().astype(np.float64)
+    o, sq = oracle.render(oracle.Scene(ctrl, off), P, ty, ph, rs)
+    return g, o, sq, counts
+
+
+def _check(g, o, sq, spp, label):
+    """Crop means within sampling error (the two images share their random
+    numbers, so this bound is loose unless some path is treated
+    differently)."""
+    var = np.maximum(sq - o * o, 0.0)
+    sigma = np.sqrt(var.sum() / spp) / o.size
+    d = g.mean() - o.mean()
+    print(label, "gpu", g.mean(), "oracle", o.mean(), "z", d / max(sigma, 1e-12))
+    assert abs(d) <= 4 * sigma + 1e-6, label
+
+
+def _paths_equal(torch, scene_args, P, rs, label, frac):
+    """One path per pixel: the share of paths whose radiance equals the
+    oracle's to 1e-2.  The model carries fiber-scale detail -- the normal
+    perturbation of the fiber table is steep between some texels, and the
+    ply fixed point is ill-conditioned for rays running along a yarn -- so
+    a difference in the last bit of a hit point can move a path's value by
+    a few percent or flip a later decision; the share is measured on the
+    same paths with the library's model run on the host (0.92 on the small
+    weave, 0.86 on the large one)."""
+    g, o, _, _ = _render_both(torch, scene_args, P, dict(rs, spp=1))
+    rel = np.abs(g - o).max(2) / np.maximum(np.abs(o).max(2), 1e-3)
+    eq = (rel < 1e-2).mean()
+    print(label, "paths equal to 1e-2:", eq, "to 1e-3:", (rel < 1e-3).mean())
+    assert eq >= frac, label
+
+
+def test_small_weave_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    scene = W.weave(12, 12, 0.15, 0.05, 4)
+    P = [W.default_params()]
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=96, height=72)
+    rs = _settings(cam, (36, 24, 24, 24))
+    g, o, sq, counts = _render_both(torch, scene, P, rs)
+    print("rays", counts)
+    assert counts[0] >= 24 * 24 * 16 and counts[1] > 0
+    _check(g, o, sq, rs["spp"], "small weave")
+    _paths_equal(torch, scene, P, _settings(cam, (24, 12, 48, 48)), "small weave", 0.85)
+
+
+def test_far_field_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    scene = W.weave(12, 12, 0.15, 0.05, 4)
+    P = [W.default_params()]
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=96, height=72)
+    rs = _settings(cam, (36, 24, 24, 24), lod_px=1e4)   # every yarn in the far field
+    g, o, sq, _ = _render_both(torch, scene, P, rs)
+    _check(g, o, sq, rs["spp"], "far field")
+    _paths_equal(torch, scene, P, _settings(cam, (24, 12, 48, 48), lod_px=1e4), "far field", 0.8)
+
+
+def test_white_furnace(torch_cuda):
+    torch = torch_cuda
+    ctrl, off, ty, ph = W.weave(8, 8, 0.15, 0.05, 4)
+    P = [W.default_params(B=1.0, albedo=(1.0, 1.0, 1.0), ply_density=0.0, fiber_density=0.0)]
+    cam = W.camera((0.0, -1.5, 0.8), (0.0, 0.0, 0.0), width=48, height=48)
+    rs = _settings(cam, (8, 8, 32, 32), light_radiance=(0.0, 0.0, 0.0), env_radiance=(1.0, 1.0, 1.0),
+                   light_corner=(-5.0, -5.0, -30.0), spp=64, max_depth=32)
+    fb = bysdf.shade_wavefront(bysdf.yarn_scene_create(ctrl, off, ty, ph), bysdf.bysdf_types_create(P),
+                               rs)
+    torch.cuda.synchronize()
+    g = fb.cpu().numpy()
+    print("furnace", g.mean(), g.min(), g.max())
+    assert abs(g.mean() - 1.0) < 4e-3
+
+
+def test_weave_crops(torch_cuda):
+    """The 256 + 256 yarn weave seen from the grazing 1920 x 1080 camera:
+    a crop at the image centre and one near the far edge (far field)."""
+    torch = torch_cuda
+    scene = W.weave()
+    P = [W.default_params()]
+    cam = W.weave_camera()
+    for crop, lod, label in (((936, 516, 40, 40), 1.0, "centre"), ((936, 392, 40, 40), 4.0,
+                                                                      "far edge, far field")):
+        rs = _settings(cam, crop, spp=8, lod_px=lod)
+        g, o, sq, _ = _render_both(torch, scene, P, rs)
+        _check(g, o, sq, rs["spp"], label)
+        _paths_equal(torch, scene, P, rs, label, 0.75)
+
+
+def test_deterministic_and_batching(torch_cuda):
+    torch = torch_cuda
+    ctrl, off, ty, ph = W.weave(8, 8, 0.15, 0.05, 4)
+    S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    T = bysdf.bysdf_types_create([W.default_params()])
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=64, height=48)
+    rs = _settings(cam, (16, 12, 32, 24), spp=8)
+    a = bysdf.shade_wavefront(S, T, rs).clone()
+    b = bysdf.shade_wavefront(S, T, rs).clone()
+    c = bysdf.shade_wavefront(S, T, dict(rs, spp_batch=2)).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # the same paths: only the order of the per-pixel sums differs
+    assert torch.allclose(a, c, rtol=1e-5, atol=1e-7)
