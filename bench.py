@@ -303,6 +303,53 @@ def _fwd_bwd(torch, bysdf, W):
             "fwd_bwd_over_fwd_time": b_ms / f_ms}
 
 
+def _weave_render(torch, bysdf, W, spp=4):
+    """The plain weave (256 + 256 B-spline yarns, 524,288 spans) seen by the
+    grazing 1920 x 1080 camera: primary-ray intersection of every pixel
+    centre, and a full-frame render at spp samples per pixel (depth <= 8,
+    next-event estimation with MIS, 1-pixel LOD)."""
+    ctrl, off, ty, ph = W.weave()
+    t0 = time.perf_counter()
+    S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    build_s = time.perf_counter() - t0
+    info = bysdf.yarn_scene_info(S)
+    cam = W.weave_camera()
+    py, px = np.meshgrid(np.arange(cam["height"]), np.arange(cam["width"]), indexing="ij")
+    o, d = W.pinhole_rays(cam, px.ravel(), py.ravel())
+    n = len(o)
+    od = torch.from_numpy(np.ascontiguousarray(o.T)).cuda()
+    dd = torch.from_numpy(np.ascontiguousarray(d.T)).cuda()
+    tm = torch.full((n,), 1e3, dtype=torch.float32, device="cuda")
+    hits = bysdf.alloc_hits(n)
+    isect = lambda: bysdf.yarn_tube_intersect(S, od, dd, tm, 1e-4, hits)
+    isect()
+    torch.cuda.synchronize()
+    ims = _timed(torch, isect, 5)
+    hit_frac = float((hits["flags"] & 1).eq(0).float().mean())
+    T = bysdf.bysdf_types_create([W.default_params()])
+    rs = dict(eye=cam["eye"], look_at=cam["look_at"], up=cam["up"], vfov=cam["vfov"],
+              width=cam["width"], height=cam["height"], crop_x=0, crop_y=0,
+              crop_w=cam["width"], crop_h=cam["height"], light_corner=(-5.0, -5.0, 30.0),
+              light_u=(0.0, 10.0, 0.0), light_v=(10.0, 0.0, 0.0), light_radiance=(5.0, 5.0, 5.0),
+              env_radiance=(0.2, 0.2, 0.2), spp=spp, max_depth=8, lod_px=1.0, n_h=4, seed=2,
+              ray_eps=1e-4, spp_batch=1)
+    ws = bysdf.alloc_workspace(bysdf.shade_wavefront_workspace_size(rs))
+    fb = torch.empty((cam["height"], cam["width"], 3), dtype=torch.float32, device="cuda")
+    _, counts = bysdf.shade_wavefront(S, T, rs, fb, ws, counts=True)
+    rms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rs, fb, ws), 3)
+    rays = counts[0] + counts[1]
+    return {"scene": {"yarns": info["n_yarns"], "spans": info["n_spans"],
+                      "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"],
+                      "device_bytes": info["bytes"], "build_s": build_s},
+            "intersect": {"rays": n, "ms": ims, "rays_per_s": n / (ims * 1e-3),
+                          "hit_fraction": hit_frac},
+            "render": {"width": cam["width"], "height": cam["height"], "spp": spp, "ms": rms,
+                       "extension_rays": counts[0], "shadow_rays": counts[1],
+                       "rays_per_s": rays / (rms * 1e-3),
+                       "paths_per_s": cam["width"] * cam["height"] * spp / (rms * 1e-3),
+                       "mean_radiance": float(fb.mean())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,6 +484,7 @@ def main():
         del ev, sv, ev2, q2
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
         out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
+        out["weave"] = _weave_render(torch, bysdf, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(P, q, args.cpu_seconds)
     print(json.dumps(out), flush=True)

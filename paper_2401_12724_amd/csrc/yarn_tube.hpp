@@ -137,14 +137,13 @@ __host__ __device__ inline bool entry_slope(const SpanGeo& g, D3 d, double s, do
     return true;
 }
 
-// First entry of the ray (unit d, origin at 0 of the span view) into the
-// span's tube piece with t_min < t < t_best.  nsamp + 1 samples of T, then
-// safeguarded Newton on dT/ds inside the best sample's bracket.
-__host__ __device__ inline bool span_entry(const SpanGeo& g, D3 d, D3 e1, D3 e2, double t_min, double t_best,
-                                  int nsamp, double* t_out, double* s_out)
+// Sampled scan of one span: the smallest entry T(s_i) > t_min over the
+// nsamp + 1 samples, if it is at most t_lim (and the control-point hull
+// reaches the ray's R-slab within [t_min, t_lim + R]).
+__host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, double t_min, double t_lim,
+                                          int nsamp, double* t_out, int* i_out)
 {
-    // control-point hull outside the ray's R-slab: the curve is too
-    double R = g.R;
+    const double R = g.R;
     bool all_pu = true, all_nu = true, all_pw = true, all_nw = true, all_b = true, all_f = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -154,10 +153,10 @@ __host__ __device__ inline bool span_entry(const SpanGeo& g, D3 d, D3 e1, D3 e2,
         all_pw &= w > R;
         all_nw &= w < -R;
         all_b &= z + R < t_min;
-        all_f &= z - R > t_best;
+        all_f &= z - R > t_lim;
     }
     if (all_pu || all_nu || all_pw || all_nw || all_b || all_f) return false;
-    double inv = 1.0 / nsamp;
+    const double inv = 1.0 / nsamp;
     double bt = INFINITY;
     int bi = -1;
     for (int i = 0; i <= nsamp; ++i) {
@@ -167,11 +166,18 @@ __host__ __device__ inline bool span_entry(const SpanGeo& g, D3 d, D3 e1, D3 e2,
             bi = i;
         }
     }
-    // a minimum between samples lies below the best sample by far less
-    // than R: refine unless the best sample is beyond t_best + R (two
-    // neighbouring spans share the ball at their joint, so a sample can
-    // tie the current best while the true minimum lies inside this span)
-    if (bi < 0 || bt > t_best + R) return false;
+    if (bi < 0 || bt > t_lim) return false;
+    *t_out = bt;
+    *i_out = bi;
+    return true;
+}
+
+// Minimum of T in the bracket of sample bi (best sampled value bt):
+// safeguarded Newton on dT/ds in double precision.
+__host__ __device__ inline void span_refine(const SpanGeo& g, D3 d, double t_min, int nsamp, int bi, double bt,
+                                            double* t_out, double* s_out)
+{
+    const double inv = 1.0 / nsamp;
     double lo = bi > 0 ? (bi - 1) * inv : 0.0, hi = bi < nsamp ? (bi + 1) * inv : 1.0;
     double s = bi * inv, g1, g2;
     // slope at the bracket ends (a ball that misses the ray reads as a
@@ -212,7 +218,6 @@ __host__ __device__ inline bool span_entry(const SpanGeo& g, D3 d, D3 e1, D3 e2,
         *t_out = bt;
         *s_out = bi * inv;
     }
-    return true;
 }
 
 __host__ __device__ inline void load_span(const SceneView& S, const SpanRec& r, D3 o, SpanGeo* g)
@@ -352,11 +357,20 @@ struct RayHit {
     int span;  // leaf-order span index, -1 for a miss
 };
 
-// Closest entering hit with t_min < t <= t_max.
+// Candidates kept for refinement: spans whose best sample lies within
+// kCandMargin R of the best sample so far.  A minimum between samples
+// undershoots its bracket's best sample by far less than that unless the
+// ray only grazes the tube (samples are at most 0.05 R apart along the
+// curve), so the true first entry is among them.
+constexpr int kCand = 6;
+constexpr double kCandMargin = 0.1;
+
+// Closest entering hit with t_min < t <= t_max.  Traversal ranks spans by
+// their sampled entries (an upper bound of the true entry, so it is safe
+// for culling); only the candidates are refined, once, at the end.
 __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, double t_min, double t_max,
-                                     const int* ex, int nex, int* stk, int stride)
+                                              const int* ex, int nex, int* stk, int stride)
 {
-    RayHit best{t_max, 0.0, -1};
     float3 of = make_float3((float)o.x, (float)o.y, (float)o.z);
     float3 inv = make_float3(1.0f / (fabs(d.x) > 1e-30 ? (float)d.x : 1e-30f),
                              1.0f / (fabs(d.y) > 1e-30 ? (float)d.y : 1e-30f),
@@ -367,10 +381,20 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
     // basis of the plane across the ray (for the span hull test)
     D3 a = fabs(d.x) < 0.9 ? d3(1, 0, 0) : d3(0, 1, 0);
     D3 e1 = unit(cross(d, a)), e2 = cross(d, e1);
+    // candidates sorted by sampled entry (static indices: registers)
+    double ct[kCand];
+    int cs[kCand], ci[kCand];
+#pragma unroll
+    for (int k = 0; k < kCand; ++k) {
+        ct[k] = INFINITY;
+        cs[k] = -1;
+        ci[k] = 0;
+    }
+    double tb = t_max;  // best sampled entry (bounds the true first entry)
     int sp = 0, code = 0;
     float t0 = (float)t_min - slack;
     while (true) {
-        float t1 = (float)best.t + slack;
+        float t1 = (float)tb + slack;
         if (code >= 0) {
             BNode n = S.node[code];
             float3 lo0, hi0, lo1, hi1;
@@ -398,17 +422,49 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
                 if (skip) continue;
                 SpanGeo g;
                 load_span(S, r, o, &g);
-                double t, s;
-                if (span_entry(g, d, e1, e2, t_min, best.t, r.info & 0xffff, &t, &s) && t < best.t) {
-                    best.t = t;
-                    best.s = s;
-                    best.span = first + k;
+                double t;
+                int bi;
+                double lim = fmin(t_max, tb + kCandMargin * g.R);
+                if (span_scan(g, d, e1, e2, t_min, lim, r.info & 0xffff, &t, &bi)) {
+                    tb = fmin(tb, t);
+                    double nt = t;
+                    int nsp = first + k, nbi = bi;
+#pragma unroll
+                    for (int q = 0; q < kCand; ++q) {
+                        if (nt < ct[q]) {
+                            double tt = ct[q];
+                            int ts = cs[q], tq = ci[q];
+                            ct[q] = nt;
+                            cs[q] = nsp;
+                            ci[q] = nbi;
+                            nt = tt;
+                            nsp = ts;
+                            nbi = tq;
+                        }
+                    }
                 }
             }
         }
         if (sp == 0) break;
         code = stk[--sp * stride];
     }
+    RayHit best{t_max, 0.0, -1};
+#pragma unroll
+    for (int q = 0; q < kCand; ++q) {
+        if (cs[q] < 0) continue;
+        SpanRec r = S.span[cs[q]];
+        SpanGeo g;
+        load_span(S, r, o, &g);
+        if (ct[q] > tb + kCandMargin * g.R) continue;
+        double t, s;
+        span_refine(g, d, t_min, r.info & 0xffff, ci[q], ct[q], &t, &s);
+        if (t < best.t || (t == best.t && best.span < 0)) {
+            best.t = t;
+            best.s = s;
+            best.span = cs[q];
+        }
+    }
+    if (!(best.t <= t_max)) best.span = -1;
     return best;
 }
 
