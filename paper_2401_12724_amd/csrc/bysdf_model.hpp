@@ -742,47 +742,49 @@ __host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const 
     bool ok = false;
     V3<G> ex = mk3<G>(X.ph.p2x, X.ph.p2y, X.ph.vhit);
     const G gx1 = G((double)xi1), gx2 = G((double)xi2);
-    if (lobe == 0) {
-        V3<G> wl = to_local(X.fx, X.wi_g);
-        if (val(wl.z) > 0.0) {
-            V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, gx1, gx2);
-            V3<G> mw = to_world(X.fx, ml);
-            wo = mw * (G(2) * dot(X.wi_g, mw)) - X.wi_g;
-            ok = val(dot(wo, X.fx.n)) > 0.0;
-        }
-    } else if (lobe == 1) {
-        // refraction out of the yarn at the node's exit point
-        Node<G, S> nd;
+    // Each step below runs once per wavefront whatever mix of lobes its
+    // lanes drew: the chosen node (forward lobes), one visible-normal
+    // sample (specular lobes), one cosine sample (body lobes).
+    Node<G, S> nd;
+    if (lobe == 1 || lobe == 3) {
         node_of(node, nd);
         ex = nd.y;
-        V3<G> wip = -nd.wt;
-        Frame<G> fi;
-        fi.t = nd.fy.t;
-        fi.n = -nd.fy.n;
-        fi.b = cross(fi.n, fi.t);
-        V3<G> wl = to_local(fi, wip);
-        if (val(wl.z) > 0.0 && val(X.mu_i) > 0.0f) {
+    }
+    if (lobe <= 1) {
+        // reflection at x, or refraction out of the yarn at the node's
+        // exit point (visible normals seen from inside, up = -n_y)
+        Frame<G> F;
+        V3<G> w;
+        if (lobe == 0) {
+            F = X.fx;
+            w = X.wi_g;
+        } else {
+            F.t = nd.fy.t;
+            F.n = -nd.fy.n;
+            F.b = cross(F.n, F.t);
+            w = -nd.wt;
+        }
+        V3<G> wl = to_local(F, w);
+        if (val(wl.z) > 0.0 && (lobe == 0 || val(X.mu_i) > 0.0f)) {
             V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, gx1, gx2);
-            V3<G> mw = to_world(fi, ml);
-            G c = dot(wip, mw);
-            c = val(c) > 0.0 ? c : G(0);
-            G s2t = P.eta_g * P.eta_g * (G(1) - c * c);
-            if (val(s2t) < 1.0) {
-                G ct = sqrt_(G(1) - s2t);
-                wo = wip * (-P.eta_g) + mw * (P.eta_g * c - ct);
-                ok = val(dot(wo, nd.fy.n)) > 0.0;
+            V3<G> mw = to_world(F, ml);
+            if (lobe == 0) {
+                wo = mw * (G(2) * dot(X.wi_g, mw)) - X.wi_g;
+                ok = val(dot(wo, X.fx.n)) > 0.0;
+            } else {
+                G c = dot(w, mw);
+                c = val(c) > 0.0 ? c : G(0);
+                G s2t = P.eta_g * P.eta_g * (G(1) - c * c);
+                if (val(s2t) < 1.0) {
+                    G ct = sqrt_(G(1) - s2t);
+                    wo = w * (-P.eta_g) + mw * (P.eta_g * c - ct);
+                    ok = val(dot(wo, nd.fy.n)) > 0.0;
+                }
             }
         }
     } else {
-        Frame<G> fr;
-        if (lobe == 2) {
-            fr = X.fx;
-        } else {
-            Node<G, S> nd;
-            node_of(node, nd);
-            fr = nd.fy;
-            ex = nd.y;
-        }
+        // cosine lobe about the fiber normal at x or at the node's exit
+        Frame<G> fr = lobe == 2 ? X.fx : nd.fy;
         G rad = sqrt_(gx1);
         G su, cu;
         sincos_turns_g(gx2, &su, &cu);
