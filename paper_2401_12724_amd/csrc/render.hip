@@ -191,8 +191,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_r_extend(RView V, PathQ Q, cons
         const double tmin = depth == 0 ? 0.0 : V.eps;
         const int lid = Q.lid[i], skip = Q.skip[i];
         int ex[yarn::kMaxExcluded + 1];
-        int nex = yarn::excluded_yarns(V.S, o, my, kTraceBlock, ex);
-        if (skip >= 0) ex[nex++] = skip;
+        int nex = yarn::excluded_yarns(V.S, o, my, kTraceBlock, ex, skip);
         yarn::RayHit hit = yarn::closest_hit(V.S, o, d, tmin, 1e30, ex, nex, my, kTraceBlock);
         // the light: one-sided rectangle
         D3 ln = dv(V.ln);
@@ -454,8 +453,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_r_shadow(RView V, ShadowQ SQ, c
         bool visible = false;
         for (int k = 0; k < kMaxPassThrough; ++k) {
             int ex[yarn::kMaxExcluded + 1];
-            int nex = yarn::excluded_yarns(V.S, o, my, kTraceBlock, ex);
-            if (skip >= 0) ex[nex++] = skip;
+            int nex = yarn::excluded_yarns(V.S, o, my, kTraceBlock, ex, skip);
             yarn::RayHit hit = yarn::closest_hit(V.S, o, d, V.eps, tmax, ex, nex, my, kTraceBlock);
             if (hit.span < 0) {
                 visible = true;

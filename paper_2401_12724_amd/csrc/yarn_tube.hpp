@@ -145,9 +145,12 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
 {
     const double R = g.R;
     bool all_pu = true, all_nu = true, all_pw = true, all_nw = true, all_b = true, all_f = true;
+    double pu[4], pw[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         double u = dot(g.c[k], e1), w = dot(g.c[k], e2), z = dot(g.c[k], d);
+        pu[k] = u;
+        pw[k] = w;
         all_pu &= u > R;
         all_nu &= u < -R;
         all_pw &= w > R;
@@ -156,6 +159,24 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
         all_f &= z - R > t_lim;
     }
     if (all_pu || all_nu || all_pw || all_nw || all_b || all_f) return false;
+    // the curve lies in the hull of its control points: in the plane across
+    // the ray, a hull entirely more than R to one side of the line through
+    // the outer two points' direction (the span's chord) misses the ray
+    {
+        double cx = pu[3] - pu[0], cy = pw[3] - pw[0];
+        double cl = sqrt(cx * cx + cy * cy);
+        if (cl > 1e-12 * R) {
+            double nx = -cy / cl, ny = cx / cl;
+            bool all_p = true, all_n = true;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double sd = nx * pu[k] + ny * pw[k];
+                all_p &= sd > R;
+                all_n &= sd < -R;
+            }
+            if (all_p || all_n) return false;
+        }
+    }
     const double inv = 1.0 / nsamp;
     double bt = INFINITY;
     int bi = -1;
@@ -270,6 +291,33 @@ __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
     return v < bv ? v : bv;
 }
 
+// True when the span is certainly farther than lim from the origin of the
+// span view: the curve lies in the hull of its control points, which lies
+// within the slab of the chord direction they span and within the
+// cylinder around the chord line that holds them.
+__host__ __device__ inline bool span_far(const SpanGeo& g, double lim)
+{
+    D3 ch = g.c[3] - g.c[0];
+    double cl2 = dot(ch, ch);
+    if (!(cl2 > 0.0)) return false;
+    D3 t = ch * (1.0 / sqrt(cl2));
+    bool all_p = true, all_n = true;
+    double rho2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double a = dot(g.c[k], t);
+        all_p &= a > lim;
+        all_n &= a < -lim;
+        D3 q = g.c[k] - g.c[0];
+        D3 pq = q - t * dot(q, t);
+        rho2 = fmax(rho2, dot(pq, pq));
+    }
+    if (all_p || all_n) return true;
+    D3 p0 = g.c[0] - t * dot(g.c[0], t);  // origin to the chord line
+    double dl = sqrt(dot(p0, p0)) - sqrt(rho2);
+    return dl > lim;
+}
+
 __host__ __device__ inline void decode_leaf(int code, int* first, int* count)
 {
     int c = -code - 1;
@@ -305,10 +353,14 @@ __host__ __device__ inline bool box_point(float3 lo, float3 hi, float3 p)
 
 // Yarns whose tube holds the origin (distance to the centreline below
 // R (1 - 1e-3)).  Point query through the BVH; stack at stk[k * stride].
-__host__ __device__ inline int excluded_yarns(const SceneView& S, D3 o, int* stk, int stride, int* ex)
+// Yarn `skip` (-1: none) is left out of the query and comes first in ex:
+// a ray leaving a yarn skips that yarn whatever its origin.
+__host__ __device__ inline int excluded_yarns(const SceneView& S, D3 o, int* stk, int stride, int* ex,
+                                              int skip = -1)
 {
     float3 of = make_float3((float)o.x, (float)o.y, (float)o.z);
     int nex = 0, sp = 0, code = 0;
+    if (skip >= 0) ex[nex++] = skip;
     while (true) {
         if (code >= 0) {
             BNode n = S.node[code];
@@ -339,10 +391,11 @@ __host__ __device__ inline int excluded_yarns(const SceneView& S, D3 o, int* stk
                 SpanRec r = S.span[first + k];
                 bool seen = false;
                 for (int j = 0; j < nex; ++j) seen |= ex[j] == r.yarn;
-                if (seen || nex >= kMaxExcluded) continue;
+                if (seen || nex >= kMaxExcluded + (skip >= 0 ? 1 : 0)) continue;
                 SpanGeo g;
                 load_span(S, r, o, &g);
                 double lim = g.R * (1.0 - kExcludeFrac);
+                if (span_far(g, lim)) continue;
                 if (span_dist2(g, r.info & 0xffff) < lim * lim) ex[nex++] = r.yarn;
             }
         }
