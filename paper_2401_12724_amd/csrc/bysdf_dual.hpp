@@ -112,6 +112,50 @@ template <> struct Narrow<DF> {
     __host__ __device__ static DF from(float x) { return DF::make(x, 0.0f); }
 };
 
+// Plain values as duals with zero tangents (parts of the model that do not
+// depend on the seeded parameter are computed in plain arithmetic).
+__host__ __device__ inline V3<DD> promote(const V3<double>& a) { return mk3<DD>(DD(a.x), DD(a.y), DD(a.z)); }
+__host__ __device__ inline V3<DF> promote(const V3<float>& a) { return mk3<DF>(DF(a.x), DF(a.y), DF(a.z)); }
+template <class T> __host__ __device__ inline Frame<Dual<T>> promote(const Frame<T>& f)
+{
+    Frame<Dual<T>> g;
+    g.t = promote(f.t);
+    g.b = promote(f.b);
+    g.n = promote(f.n);
+    return g;
+}
+template <int MP> __host__ __device__ inline void promote(const PlyHit<double, MP>& a, PlyHit<DD, MP>& b)
+{
+    b.pass = a.pass;
+    b.flags = a.flags;
+    b.x2x = DD(a.x2x); b.x2y = DD(a.x2y); b.dhx = DD(a.dhx); b.dhy = DD(a.dhy);
+    b.kappa = DD(a.kappa);
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        b.cth[k] = DD(a.cth[k]);
+        b.sth[k] = DD(a.sth[k]);
+    }
+    b.ks = a.ks;
+    b.p2x = DD(a.p2x); b.p2y = DD(a.p2y); b.n2x = DD(a.n2x); b.n2y = DD(a.n2y);
+    b.vhit = DD(a.vhit);
+}
+template <int MP>
+__host__ __device__ inline void promote(const XState<double, float, MP>& a, XState<DD, DF, MP>& b)
+{
+    promote(a.ph, b.ph);
+    b.fx = promote(a.fx);
+    b.fxs = promote(a.fxs);
+    b.wi_g = promote(a.wi_g);
+    b.wi_s = promote(a.wi_s);
+    b.Gp = DF(a.Gp);
+    b.Gf = DF(a.Gf);
+    b.mu_i = DF(a.mu_i);
+    for (int k = 0; k < 4; ++k) b.w[k] = DF(a.w[k]);
+    b.a = DD(a.a);
+    b.rawp = DD(a.rawp);
+    b.rawf = DD(a.rawf);
+}
+
 // Scalars of one type with the tangent seeded on one differentiable
 // parameter: 0 beta, 1 ply twist, 2 fiber twist.
 __host__ __device__ inline Derived<DD, DF> derive_dual(const TypeRec& t, int seed)

@@ -525,7 +525,13 @@ __device__ inline bool locate_tile(int tile, const int32_t* __restrict__ tile_fi
 // tangents of E with grad_E, and adds the closed-form derivatives of the
 // linear parameters (albedo, densities).  The tile's lanes reduce in a
 // fixed tree order to one partial per tile.
-template <int MP>
+// One pass of the adjoint per launch, so that each pass gets the register
+// allocation of its own code: pass 0 differentiates beta (and writes the
+// closed forms of the albedo and the densities), pass 1 the ply twist,
+// pass 2 the fiber twist.  Parts of the model that do not depend on the
+// seeded parameter run in plain arithmetic and are promoted to duals with
+// zero tangents: everything at x for beta, the ply hit for the fiber twist.
+template <int MP, int PASS>
 __global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__ types,
                                                      const float4* __restrict__ tables, QPtrs q,
                                                      const int64_t* __restrict__ off, int n_types,
@@ -534,7 +540,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__
                                                      float* __restrict__ partials,
                                                      float* __restrict__ per_query)
 {
-    __shared__ float s_red[8][kBlock];
+    constexpr int NS = PASS == 0 ? 6 : 1;
+    // theta slots written by this pass
+    constexpr int kSlot0[6] = {0, 1, 2, 3, 6, 7};
+    __shared__ float s_red[NS][kBlock];
     int t = 0, count = 0;
     int64_t start = 0;
     if (!locate_tile(blockIdx.x, tile_first, n_types, off, &t, &start, &count)) return;
@@ -543,8 +552,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__
     const TypeRec& rec = types[t];
     TabPtr tab;
     tab.p = tables + rec.table_off;
-    float g[8];
-    for (int k = 0; k < 8; ++k) g[k] = 0.0f;
+    float g[NS];
+    for (int k = 0; k < NS; ++k) g[k] = 0.0f;
     if (tid < count) {
         const int64_t i = start + tid;
         V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
@@ -555,15 +564,25 @@ __global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__
             const float ge[3] = {gE[3 * i], gE[3 * i + 1], gE[3 * i + 2]};
             const float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
             V3<DD> wo_d = mk3<DD>(DD((double)wo.x), DD((double)wo.y), DD((double)wo.z));
-            for (int p = 0; p < 3; ++p) {
-                Derived<DD, DF> P = derive_dual(rec, p);
-                XState<DD, DF, MP> X;
+            Derived<DD, DF> P = derive_dual(rec, PASS);
+            XState<DD, DF, MP> X;
+            if (PASS == 0) {
+                XState<double, float, MP> Xp;
+                state_at_x(rec.d, tab, h, u, v, wi, Xp);
+                promote(Xp, X);
+            } else if (PASS == 2) {
+                PlyHit<double, MP> ph;
+                trace_plies(rec.d, h, u, v, wi, ph);
+                promote(ph, X.ph);
+                state_after_plies(P, tab, wi, X);
+            } else {
                 state_at_x(P, tab, h, u, v, wi, X);
-                if (X.ph.pass) break;
+            }
+            if (!X.ph.pass) {
                 EvalOut<DF> e;
                 lobes(P, tab, X, wo_d, s0, s1, q.s0 != nullptr, e);
-                g[3 + p] = ge[0] * e.E[0].d + ge[1] * e.E[1].d + ge[2] * e.E[2].d;
-                if (p == 0) {
+                const float dE = ge[0] * e.E[0].d + ge[1] * e.E[1].d + ge[2] * e.E[2].d;
+                if (PASS == 0) {
                     const float b0 = e.body0.v, Gp = X.Gp.v, Gf = X.Gf.v;
                     const float op = 1.0f - (float)X.rawp.v, of = 1.0f - (float)X.rawf.v;
                     float sa = 0.0f;
@@ -571,22 +590,25 @@ __global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__
                         g[c] = ge[c] * b0 * Gp * Gf;
                         sa += ge[c] * rec.d.alb[c];
                     }
-                    g[6] = -sa * b0 * Gf * op;
-                    g[7] = -sa * b0 * Gp * of;
+                    g[3] = dE;
+                    g[4] = -sa * b0 * Gf * op;
+                    g[5] = -sa * b0 * Gp * of;
+                } else {
+                    g[0] = dE;
                 }
             }
         }
         if (per_query)
-            for (int k = 0; k < 8; ++k) per_query[8 * i + k] = g[k];
+            for (int k = 0; k < NS; ++k) per_query[8 * i + (PASS == 0 ? kSlot0[k] : 3 + PASS)] = g[k];
     }
-    for (int k = 0; k < 8; ++k) s_red[k][tid] = g[k];
+    for (int k = 0; k < NS; ++k) s_red[k][tid] = g[k];
     __syncthreads();
     for (int st = kBlock / 2; st > 0; st >>= 1) {
         if (tid < st)
-            for (int k = 0; k < 8; ++k) s_red[k][tid] += s_red[k][tid + st];
+            for (int k = 0; k < NS; ++k) s_red[k][tid] += s_red[k][tid + st];
         __syncthreads();
     }
-    if (tid < 8) partials[8 * (int64_t)blockIdx.x + tid] = s_red[tid][0];
+    if (tid < NS) partials[8 * (int64_t)blockIdx.x + (PASS == 0 ? kSlot0[tid] : 3 + PASS)] = s_red[tid][0];
 }
 
 // grad[t] = sum of the partials of type t's tiles, in tile order
@@ -1007,10 +1029,15 @@ extern "C" int bysdf_eval_backward(const bysdf_types_t* h, const bysdf_query_soa
     HIP_TRY(hipGetLastError());
     int64_t tiles = max_tiles(n, h->n_types);
     if (tiles > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many tiles");
-    auto kern = h->max_plies <= 4 ? k_backward<4> : k_backward<8>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(kBlock), 0, stream, h->d_types, h->d_tables, qp,
-                       type_offsets, h->n_types, tile_first, grad_E, partials, per_query);
-    HIP_TRY(hipGetLastError());
+    const bool mp4 = h->max_plies <= 4;
+    decltype(&k_backward<4, 0>) passes[3] = {mp4 ? k_backward<4, 0> : k_backward<8, 0>,
+                                             mp4 ? k_backward<4, 1> : k_backward<8, 1>,
+                                             mp4 ? k_backward<4, 2> : k_backward<8, 2>};
+    for (auto kern : passes) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(kBlock), 0, stream, h->d_types, h->d_tables, qp,
+                           type_offsets, h->n_types, tile_first, grad_E, partials, per_query);
+        HIP_TRY(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_backward_sum, dim3((h->n_types + 255) / 256), dim3(256), 0, stream, tile_first,
                        h->n_types, partials, grad_theta);
     HIP_TRY(hipGetLastError());

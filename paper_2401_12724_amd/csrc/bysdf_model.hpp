@@ -392,10 +392,9 @@ template <class G, class S, int MP> struct XState {
 };
 
 template <class G, class S, int MP, class Tab>
-__host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& tab, float h, float u,
-                                           float v, const V3<float>& wi, XState<G, S, MP>& X)
+__host__ __device__ inline void state_after_plies(const Derived<G, S>& P, const Tab& tab, const V3<float>& wi,
+                                                  XState<G, S, MP>& X)
 {
-    trace_plies(P, h, u, v, wi, X.ph);
     X.wi_g = mk3<G>(G((double)wi.x), G((double)wi.y), G((double)wi.z));
     X.wi_s = mk3<S>(S(wi.x), S(wi.y), S(wi.z));
     if (X.ph.pass) return;
@@ -420,6 +419,16 @@ __host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& ta
     X.w[1] = (S(1) - P.B) * (S(1) - PR);
     X.w[2] = P.B * P.r;
     X.w[3] = P.B * (S(1) - P.r);
+}
+
+// Everything at x that does not depend on wo: ply hit, fiber frame,
+// shadowing, lobe weights.
+template <class G, class S, int MP, class Tab>
+__host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& tab, float h, float u,
+                                           float v, const V3<float>& wi, XState<G, S, MP>& X)
+{
+    trace_plies(P, h, u, v, wi, X.ph);
+    state_after_plies(P, tab, wi, X);
 }
 
 // ---------------------------------------------------------------- forward nodes
