@@ -4,11 +4,14 @@
 One step = one pass of the path over the per-block workload: 2^24 queries in
 65,536 parameter blocks of 256 (one 3-ply yarn geometry; beta and albedo
 drawn per block), inputs resident in HBM:
-    bysdf_eval            value, lobes and pdf at (wi, wo)
-    bysdf_sample_pdf      one importance-sampled direction per query
-    bysdf_eval            value and pdf at the sampled directions
+    bysdf_eval_sample     per query: value, lobes and pdf at (wi, wo), and one
+                          importance-sampled direction with its weight and pdf
+                          (state at the hit and forward nodes shared)
     bysdf_furnace_blocks  per-block white-furnace mean/variance (256 draws)
-value = queries per second (2^24 queries per step / step time).
+value = queries per second (2^24 queries per step / step time).  The same
+work through the separate entry points (bysdf_eval, bysdf_sample_pdf, and
+bysdf_eval again at the sampled directions) is timed after the steps and
+reported under "unfused".
 
 Prints ONE JSON line.  `roofline` is for the kernel with the largest time
 per step, priced with the algorithmic operation count of the kernels'
@@ -53,8 +56,7 @@ def _src_hash():
 
 
 # bench stage -> kernel name prefix in rocprofv3 output
-_STAGE_KERNEL = {"eval": "k_eval<", "sample": "k_sample<", "eval_at_sample": "k_eval<",
-                 "furnace": "k_furnace<"}
+_STAGE_KERNEL = {"eval_sample": "k_eval_sample<", "furnace": "k_furnace<"}
 
 
 def _kname(full):
@@ -99,8 +101,7 @@ def _summarize(prof_dir, bench_json, workload_tag):
     for k, (c, a, mn, mx, pc) in sorted(stats.items(), key=lambda kv: -kv[1][4]):
         lines.append("| `%s` | %d | %.1f | %.1f | %.1f | %.2f |" % (k, c, a, mn, mx, pc))
     # per-dispatch durations of the step's launches: in dispatch order the
-    # bench issues eval, sample, eval (at the sampled directions), furnace,
-    # step after step, before any other work
+    # bench issues eval_sample, furnace, step after step, before any other work
     trace = sorted(csv.DictReader(open(os.path.join(prof_dir, "stats", "run_kernel_trace.csv"))),
                    key=lambda r: int(r["Dispatch_Id"]))
     stages = list(bj["kernels_ms"])
@@ -202,7 +203,8 @@ def _op_counts(bysdf, T, P, q, mode, n=4096):
 
 
 def _cpu_baseline(P, q, target_s):
-    """FP64 oracle on the first blocks of the workload, same four stages."""
+    """FP64 oracle on the first blocks of the workload, same stages (eval at
+    wo, one sampled direction with its pdf, furnace per block)."""
     import oracle
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
@@ -214,10 +216,7 @@ def _cpu_baseline(P, q, target_s):
         ts = oracle.TypeSet(P[:nb])
         t0 = time.perf_counter()
         oracle.eval(ts, sub, nthreads=cores)
-        so, _ = oracle.sample(ts, sub, nthreads=cores)
-        s2 = dict(sub)
-        s2["wo"] = np.ascontiguousarray(so[:, :3].T.astype(np.float32))
-        oracle.eval(ts, s2, nthreads=cores)
+        oracle.sample(ts, sub, nthreads=cores)
         oracle.furnace(ts, sub, 256, nthreads=cores)
         return time.perf_counter() - t0
 
@@ -227,8 +226,8 @@ def _cpu_baseline(P, q, target_s):
     dt = run(nb)
     n = nb * 256
     return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d blocks (%d queries) of the per-block workload, same four "
-                      "stages (eval, sample, eval at sampled wo, furnace), %.1f s" % (nb, n, dt)}
+            "sample": "first %d blocks (%d queries) of the per-block workload, same "
+                      "stages (eval, sample with pdf, furnace), %.1f s" % (nb, n, dt)}
 
 
 def _timed(torch, fn, reps):
@@ -387,20 +386,15 @@ def main():
     qd = bysdf.to_device(q)
     ev = bysdf.alloc_eval_out(N)
     sv = bysdf.alloc_sample_out(N)
-    ev2 = bysdf.alloc_eval_out(N)
     fm = torch.empty((N // 256, 3), dtype=torch.float32, device="cuda")
     fv = torch.empty_like(fm)
-    q2 = dict(qd)
-    q2["wo"] = sv[0][0:3]  # sampled directions, rows of the sample output
     torch.cuda.synchronize()
 
-    names = ("eval", "sample", "eval_at_sample", "furnace")
+    names = ("eval_sample", "furnace")
     stream = torch.cuda.current_stream()
 
     def step(events=None):
-        calls = (lambda: bysdf.bysdf_eval(T, qd, ev),
-                 lambda: bysdf.bysdf_sample_pdf(T, qd, sv),
-                 lambda: bysdf.bysdf_eval(T, q2, ev2),
+        calls = (lambda: bysdf.bysdf_eval_sample(T, qd, (ev, sv)),
                  lambda: bysdf.bysdf_furnace_blocks(T, qd, 256, fm, fv))
         for k, c in enumerate(calls):
             if events is not None:
@@ -425,6 +419,19 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
 
+    # the same work through the separate entry points, for comparison
+    ev2 = bysdf.alloc_eval_out(N)
+    sv2 = bysdf.alloc_sample_out(N)
+    q2 = dict(qd)
+    q2["wo"] = sv2[0][0:3]  # sampled directions, rows of the sample output
+    sep = {"eval": lambda: bysdf.bysdf_eval(T, qd, ev2),
+           "sample": lambda: bysdf.bysdf_sample_pdf(T, qd, sv2),
+           "eval_at_sample": lambda: bysdf.bysdf_eval(T, q2, ev2)}
+    for f in sep.values():
+        f()
+    unfused = {k: _timed(torch, f, max(3, args.steps)) for k, f in sep.items()}
+    del ev2, sv2, q2
+
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -434,8 +441,8 @@ def main():
     # algorithmic operations per query (kernels' own formulation)
     ops_eval = _op_counts(bysdf, T, P, q, 0)
     ops_samp = _op_counts(bysdf, T, P, q, 1)
-    per_query = {"eval": ops_eval.sum(), "sample": ops_samp.sum(),
-                 "eval_at_sample": ops_eval.sum(), "furnace": ops_samp.sum()}
+    ops_both = _op_counts(bysdf, T, P, q, 2)
+    per_query = {"eval_sample": ops_both.sum(), "furnace": ops_samp.sum()}
     dom = max(ktime, key=ktime.get)
     achieved = per_query[dom] * N / (ktime[dom] * 1e-3) / 1e12
     traffic = None
@@ -445,8 +452,9 @@ def main():
         if tj.get("src_hash") == _src_hash() and dom in tj.get("kernels", {}):
             traffic = tj["kernels"][dom]["bytes"]
     # algorithmic bytes per query of each kernel (SoA records, 4 B fields)
-    bytes_q = {"eval": 40 + 52, "sample": 40 + 52, "eval_at_sample": 40 + 52,
-               "furnace": 4 * 8 + 24.0 / 256}
+    # eval_sample: type, h, u, v, wi, wo, xi in (52 B); eval out 12 floats +
+    # flags, sample out 10 floats + lobe + node + flags (104 B)
+    bytes_q = {"eval_sample": 52 + 104, "furnace": 4 * 8 + 24.0 / 256}
     out = {
         "metric": "BYSDF queries/s (eval+sample, fp32), % VALU peak; fwd+bwd vs plain fwd",
         "value": value,
@@ -462,8 +470,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "per-block: %d queries in %d blocks of 256, 3-ply yarn "
                                "(64 fibers/ply, twist 28/15 deg, r_p 0.45, eta 1.55), beta "
-                               "U[0.05,0.3] and albedo U[0.3,0.95]^3 per block; step = eval, "
-                               "sample, eval at sampled wo, furnace per block" % (N, N // 256),
+                               "U[0.05,0.3] and albedo U[0.3,0.95]^3 per block; step = eval "
+                               "at (wi, wo) and one sampled wo with its weight and pdf (one "
+                               "kernel), furnace per block" % (N, N // 256),
                    "queries": N, "blocks": N // 256, "K": 4, "n_iter": 5},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
@@ -474,14 +483,23 @@ def main():
                      "ops_per_query": per_query[dom]},
         "kernels_ms": ktime,
         "kernel_gbs": {k: bytes_q[k] * N / (ktime[k] * 1e-3) / 1e9 for k in names},
-        "ops_per_query": {"eval": {"fp64": ops_eval[:5].tolist(), "fp32": ops_eval[5:].tolist()},
+        "ops_per_query": {"eval_sample": {"fp64": ops_both[:5].tolist(),
+                                          "fp32": ops_both[5:].tolist()},
+                          "eval": {"fp64": ops_eval[:5].tolist(), "fp32": ops_eval[5:].tolist()},
                           "sample": {"fp64": ops_samp[:5].tolist(), "fp32": ops_samp[5:].tolist()},
                           "order": "add mul div sqrt transcendental"},
+        "unfused": {"kernels_ms": unfused,
+                    "step_ms": unfused["eval"] + unfused["sample"] + unfused["eval_at_sample"]
+                    + ktime["furnace"],
+                    "eval_queries_per_s": N / (unfused["eval"] * 1e-3),
+                    "sample_queries_per_s": N / (unfused["sample"] * 1e-3),
+                    "note": "bysdf_eval, bysdf_sample_pdf and bysdf_eval at the sampled "
+                            "directions as separate launches, plus the furnace"},
         "src_hash": _src_hash(),
     }
     if not args.no_extras:
-        eval_qps = N / (ktime["eval"] * 1e-3)
-        del ev, sv, ev2, q2
+        eval_qps = N / (unfused["eval"] * 1e-3)
+        del ev, sv
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
         out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
         out["weave"] = _weave_render(torch, bysdf, W)

@@ -185,6 +185,19 @@ int bysdf_eval(const bysdf_types_t* types, const bysdf_query_soa* q, int64_t n,
 int bysdf_sample_pdf(const bysdf_types_t* types, const bysdf_sample_soa* q, int64_t n,
                      const bysdf_sample_out_soa* out, hipStream_t stream);
 
+/* Both of the above on the same hits in one pass: per query, the value and
+ * pdf at q's wo (as bysdf_eval) and one direction drawn with xi0..xi2 (as
+ * bysdf_sample_pdf with the same hit and xi).  The state at the hit point and
+ * the K forward quadrature nodes (Sec. 4.1.1) depend on wi only, so they are
+ * computed once and serve both directions -- the pattern of a path tracer
+ * that evaluates a light direction and draws the next bounce at each hit.
+ * xi*: device arrays of n uniforms in [0, 1).  Outputs as for the two calls;
+ * a bad wo flags only the eval output.  n == 0 is a no-op. */
+int bysdf_eval_sample(const bysdf_types_t* types, const bysdf_query_soa* q, const float* xi0,
+                      const float* xi1, const float* xi2, int64_t n,
+                      const bysdf_eval_out_soa* eval_out, const bysdf_sample_out_soa* sample_out,
+                      hipStream_t stream);
+
 /* White-furnace integral per block (Sec. 4.3): block b (n / block blocks)
  * draws `block` directions for the hit of query b*block (type, h, u, v, wi,
  * shift) with the xi of queries b*block .. b*block+block-1, and writes the
@@ -381,7 +394,7 @@ void bysdf_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t 
  * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type
  * *p, whose fiber table (tex_size x 3 floats: dn, rho_hat, G_f) is given in
  * host memory.  mode 0 counts bysdf_eval (wo needed), mode 1
- * bysdf_sample_pdf (xi needed).  counts[10] receives the mean per query of
+ * bysdf_sample_pdf (xi needed), mode 2 bysdf_eval_sample (both).  counts[10] receives the mean per query of
  * (add, mul, div, sqrt, transcendental) for the FP64 geometry scalar,
  * then the same five for the FP32 shading scalar.  Touches no device. */
 int bysdf_count_ops(const bysdf_type_params* p, const float* table, int64_t n, const float* h,

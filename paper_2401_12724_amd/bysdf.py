@@ -123,6 +123,8 @@ def lib():
         L.bysdf_eval.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, C.POINTER(EvalOutSoA), _vp]
         L.bysdf_sample_pdf.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64,
                                        C.POINTER(SampleOutSoA), _vp]
+        L.bysdf_eval_sample.argtypes = [_vp, C.POINTER(QuerySoA), _vp, _vp, _vp, C.c_int64,
+                                        C.POINTER(EvalOutSoA), C.POINTER(SampleOutSoA), _vp]
         L.bysdf_furnace_blocks.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64, C.c_int32, _vp,
                                            _vp, _vp]
         L.bysdf_batched_workspace_size.argtypes = [C.c_int32]
@@ -351,6 +353,29 @@ def bysdf_sample_pdf(types: Types, q: dict, out=None, stream=None):
     _check(lib().bysdf_sample_pdf(types.handle, C.byref(qs), n, C.byref(o), _stream(stream)),
            "bysdf_sample_pdf")
     return vals, lobe, node, flags
+
+
+def bysdf_eval_sample(types: Types, q: dict, out=None, stream=None):
+    """Value and pdf at q["wo"] and one direction drawn with q["xi"], per
+    query, in one pass.  out: (eval_out, sample_out) as allocated by
+    alloc_eval_out / alloc_sample_out.  Returns (eval_vals float32[12, n],
+    eval_flags int32[n], sample_vals float32[10, n], lobe, node, sample_flags)."""
+    n = int(q["h"].numel())
+    eo, so = out if out is not None else (alloc_eval_out(n, q["h"].device),
+                                          alloc_sample_out(n, q["h"].device))
+    ev, ef = eo
+    sv, lobe, node, sf = so
+    o = _eval_out_soa(ev, ef)
+    s = SampleOutSoA()
+    names = ("wo_x", "wo_y", "wo_z", "w_r", "w_g", "w_b", "pdf", "exit_x", "exit_y", "exit_z")
+    for i, nm in enumerate(names):
+        setattr(s, nm, _ptr(sv[i]))
+    s.lobe, s.node, s.flags = _ptr(lobe), _ptr(node), _ptr(sf)
+    qs = _qsoa(q)
+    xi = q["xi"]
+    _check(lib().bysdf_eval_sample(types.handle, C.byref(qs), _ptr(xi[0]), _ptr(xi[1]), _ptr(xi[2]),
+                                   n, C.byref(o), C.byref(s), _stream(stream)), "bysdf_eval_sample")
+    return ev, ef, sv, lobe, node, sf
 
 
 def bysdf_furnace_blocks(types: Types, q: dict, block: int = 256, mean=None, var=None,

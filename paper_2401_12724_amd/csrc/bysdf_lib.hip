@@ -380,6 +380,71 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
     }
 }
 
+// ------------------------------------------------------------------ eval + sample
+// Both calls on one hit: the value and pdf at the query's wo, and one drawn
+// direction.  The state at x and the K forward nodes are computed once and
+// serve both directions, so a query costs about one evaluation plus the
+// draw instead of an evaluation and a sample.
+template <bool kLds, int MP>
+__global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_eval_sample(
+    const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
+    QPtrs q, const float* __restrict__ xi0, const float* __restrict__ xi1,
+    const float* __restrict__ xi2, OPtrs o, SOPtrs so_p, int64_t n)
+{
+    extern __shared__ float4 s_tab[];
+    if (kLds) {
+        for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int t = q.type[i];
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+        float h = q.h[i], u = q.u[i], v = q.v[i], x0 = xi0[i], x1 = xi1[i], x2 = xi2[i];
+        const uint32_t bad_t = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+        const uint32_t bad_hit = bad_t | check_inputs(h, u, v, wi);
+        const uint32_t bad_wo = check_dir(wo);
+        uint32_t fe = bad_hit | bad_wo, fs = bad_hit;
+        EvalOut<float> e;
+        for (int c = 0; c < 3; ++c) e.E[c] = e.ExB[c] = e.EyB[c] = 0.0f;
+        e.ExS = e.EyS = e.pdf = 0.0f;
+        SampleOut<float> so;
+        for (int c = 0; c < 3; ++c) so.wo[c] = so.wgt[c] = so.ex[c] = 0.0f;
+        so.pdf = 0.0f;
+        so.lobe = -1;
+        so.node = 0;
+        for_each_wave_type(t, bad_hit == 0u, [&](int tu) {
+            const Derived<double, float>& P = types[tu].d;
+            TabPtr tab;
+            tab.p = kLds ? s_tab : tables + types[tu].table_off;
+            XState<double, float, MP> X;
+            state_at_x(P, tab, h, u, v, wi, X);
+            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+            NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, s0, s1, q.s0 != nullptr};
+            V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
+            fs = eval_sample_from_x(P, X, wi, wo_g, bad_wo == 0u, x0, x1, x2, nf, e, so);
+            if (bad_wo == 0u) {
+                fe = X.ph.flags;
+                if (!X.ph.pass && !(X.mu_i > 0.0f)) fe |= F_BACKFACING;
+            }
+        });
+        o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
+        o.ExS[i] = e.ExS; o.EyS[i] = e.EyS;
+        o.ExBr[i] = e.ExB[0]; o.ExBg[i] = e.ExB[1]; o.ExBb[i] = e.ExB[2];
+        o.EyBr[i] = e.EyB[0]; o.EyBg[i] = e.EyB[1]; o.EyBb[i] = e.EyB[2];
+        o.pdf[i] = e.pdf;
+        o.flags[i] = fe;
+        so_p.wox[i] = so.wo[0]; so_p.woy[i] = so.wo[1]; so_p.woz[i] = so.wo[2];
+        so_p.wr[i] = so.wgt[0]; so_p.wg[i] = so.wgt[1]; so_p.wb[i] = so.wgt[2];
+        so_p.pdf[i] = so.pdf;
+        so_p.exx[i] = so.ex[0]; so_p.exy[i] = so.ex[1]; so_p.exz[i] = so.ex[2];
+        so_p.lobe[i] = so.lobe;
+        so_p.node[i] = so.node;
+        so_p.flags[i] = fs;
+    }
+}
+
 // ------------------------------------------------------------------ furnace
 // One workgroup per furnace block.  Every draw shares the block's hit, so
 // the state at x is computed per lane (identical values) while the K
@@ -915,6 +980,41 @@ extern "C" int bysdf_sample_pdf(const bysdf_types_t* h, const bysdf_sample_soa* 
     return BYSDF_OK;
 }
 
+extern "C" int bysdf_eval_sample(const bysdf_types_t* h, const bysdf_query_soa* q, const float* xi0,
+                                 const float* xi1, const float* xi2, int64_t n,
+                                 const bysdf_eval_out_soa* o, const bysdf_sample_out_soa* so,
+                                 hipStream_t stream)
+{
+    if (!h || !q || !o || !so) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return BYSDF_OK;
+    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y,
+                          q->wo_z, xi0, xi1, xi2, o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS,
+                          o->E_xB_r, o->E_xB_g, o->E_xB_b, o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf,
+                          o->flags, so->wo_x, so->wo_y, so->wo_z, so->w_r, so->w_g, so->w_b, so->pdf,
+                          so->exit_x, so->exit_y, so->exit_z, so->lobe, so->node, so->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query/output pointer is NULL or misaligned");
+    if ((q->shift0 == nullptr) != (q->shift1 == nullptr) ||
+        (q->shift0 && (!aligned4(q->shift0) || !aligned4(q->shift1))))
+        return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
+    QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
+             q->shift0, q->shift1};
+    OPtrs op{o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
+             o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    SOPtrs sop{so->wo_x, so->wo_y, so->wo_z, so->w_r, so->w_g, so->w_b, so->pdf, so->exit_x,
+               so->exit_y, so->exit_z, so->lobe, so->node, so->flags};
+    int grid = grid_for(n);
+    size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
+    int tx = h->single_table ? h->table_texels : 0;
+    auto kern = h->max_plies <= 4 ? (h->single_table ? k_eval_sample<true, 4> : k_eval_sample<false, 4>)
+                                   : (h->single_table ? k_eval_sample<true, 8> : k_eval_sample<false, 8>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                       h->d_tables, tx, qp, xi0, xi1, xi2, op, sop, n);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
 extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_soa* q, int64_t n,
                                     int32_t block, float* mean, float* var, hipStream_t stream)
 {
@@ -950,10 +1050,10 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
                                const float* h, const float* u, const float* v, const float* wi,
                                const float* wo, const float* xi, int32_t mode, double* counts)
 {
-    if (!p || !table || !h || !u || !v || !wi || !counts || n < 1 || (mode != 0 && mode != 1))
+    if (!p || !table || !h || !u || !v || !wi || !counts || n < 1 || mode < 0 || mode > 2)
         return fail(BYSDF_ERR_INVALID_ARG, "bad argument");
-    if (mode == 0 && !wo) return fail(BYSDF_ERR_INVALID_ARG, "mode 0 needs wo");
-    if (mode == 1 && !xi) return fail(BYSDF_ERR_INVALID_ARG, "mode 1 needs xi");
+    if (mode != 1 && !wo) return fail(BYSDF_ERR_INVALID_ARG, "modes 0 and 2 need wo");
+    if (mode != 0 && !xi) return fail(BYSDF_ERR_INVALID_ARG, "modes 1 and 2 need xi");
     if (int rc = validate(*p, 0)) return rc;
     TypeRec rec = make_rec(*p);
     std::vector<float4> tb(p->tex_size);
@@ -974,6 +1074,14 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
             V3<CD> b = mk3<CD>(CD((double)wo[i]), CD((double)wo[n + i]), CD((double)wo[2 * n + i]));
             EvalOut<CF> e;
             lobes(P, tab, X, b, 0.0f, 0.0f, false, e);
+        } else if (mode == 2) {
+            XState<CD, CF, kMaxPlies> X;
+            state_at_x(P, tab, h[i], u[i], v[i], a, X);
+            V3<CD> b = mk3<CD>(CD((double)wo[i]), CD((double)wo[n + i]), CD((double)wo[2 * n + i]));
+            NodesComputed<CD, CF, kMaxPlies, HostTab> nf{P, tab, X, 0.0f, 0.0f, false};
+            EvalOut<CF> e;
+            SampleOut<CF> so;
+            eval_sample_from_x(P, X, a, b, true, xi[i], xi[n + i], xi[2 * n + i], nf, e, so);
         } else {
             SampleOut<CF> so;
             sample_query<CD, CF, kMaxPlies>(P, tab, h[i], u[i], v[i], a, xi[i], xi[n + i],

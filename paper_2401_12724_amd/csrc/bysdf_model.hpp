@@ -588,13 +588,21 @@ template <class S> struct EvalOut {
     S body0;  // body lobes per unit albedo without G_p G_f (closed-form derivatives)
 };
 
-// The four lobes of Eq. 1 and the mixture pdf of Sec. 4.1.5 at wo.  Dot
-// products, the half vector and local coordinates are formed in the
+// Running sums of the lobes at one direction wo: the terms at x and the
+// sums over the forward nodes.
+template <class S> struct LobeAcc {
+    S ExS, pxS, bxu, pxB;  // specular and body at x (body per unit albedo, before G_p G_f)
+    S EyS, pyS, by, pyB;   // sums over the nodes
+};
+
+// The four lobes of Eq. 1 and the mixture pdf of Sec. 4.1.5 at wo, in three
+// steps: the terms at x, one step per forward node, and the combination.
+// Dot products, the half vector and local coordinates are formed in the
 // geometry scalar (a grazing cosine or a near-opposite pair cancels), the
 // lobe formulas then run in the shading scalar.
-template <class G, class S, int MP, class NodeFn>
-__host__ __device__ inline void lobes_nodes(const Derived<G, S>& P, const XState<G, S, MP>& X,
-                                            const V3<G>& wo_g, const NodeFn& node_of, EvalOut<S>& o)
+template <class G, class S, int MP>
+__host__ __device__ inline void lobes_at_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                           const V3<G>& wo_g, LobeAcc<S>& a)
 {
     S mu_i = X.mu_i;
     G mu_o_g = dot(wo_g, X.fx.n);
@@ -619,40 +627,93 @@ __host__ __device__ inline void lobes_nodes(const Derived<G, S>& P, const XState
         bxu = P.B * P.r * (fls + S(float(1.0 / kPi))) * mu_o / (S(1) + ls_albedo<S>(mp));
         pxB = mu_o * S(float(1.0 / kPi));
     }
-    S EyS = S(0), pyS = S(0), by = S(0), pyB = S(0);
-    for (int k = 0; k < P.K; ++k) {
-        Node<G, S> nd;
-        node_of(k, nd);
-        G cyg = dot(wo_g, nd.fy.n);
-        if (val(cyg) > 0.0) {
-            S c = Narrow<S>::from(cyg) * S(float(1.0 / kPi));
-            by = by + c;
-            pyB = pyB + c;
-        }
-        if (front_i) {
-            S vv, pd;
-            exit_btdf(P, nd.wt, nd.fy, wo_g, &vv, &pd);
-            EyS = EyS + nd.T * nd.att * vv;
-            pyS = pyS + pd;
-        }
+    a.ExS = ExS;
+    a.pxS = pxS;
+    a.bxu = bxu;
+    a.pxB = pxB;
+    a.EyS = a.pyS = a.by = a.pyB = S(0);
+}
+
+template <class G, class S>
+__host__ __device__ inline void lobes_node_step(const Derived<G, S>& P, bool front_i, const Node<G, S>& nd,
+                                                const V3<G>& wo_g, LobeAcc<S>& a)
+{
+    G cyg = dot(wo_g, nd.fy.n);
+    if (val(cyg) > 0.0) {
+        S c = Narrow<S>::from(cyg) * S(float(1.0 / kPi));
+        a.by = a.by + c;
+        a.pyB = a.pyB + c;
     }
+    if (front_i) {
+        S vv, pd;
+        exit_btdf(P, nd.wt, nd.fy, wo_g, &vv, &pd);
+        a.EyS = a.EyS + nd.T * nd.att * vv;
+        a.pyS = a.pyS + pd;
+    }
+}
+
+template <class G, class S, int MP>
+__host__ __device__ inline void lobes_finish(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                             const LobeAcc<S>& a, EvalOut<S>& o)
+{
     S invK = S(1) / S(float(P.K));
-    EyS = EyS * (S(1) - P.B) * P.kS * invK;
-    pyS = pyS * invK;
-    S byu = by * P.B * (S(1) - P.r) * invK;
-    pyB = pyB * invK;
+    S EyS = a.EyS * (S(1) - P.B) * P.kS * invK;
+    S pyS = a.pyS * invK;
+    S byu = a.by * P.B * (S(1) - P.r) * invK;
+    S pyB = a.pyB * invK;
     S gg = X.Gp * X.Gf;
-    S bx = bxu * gg, byg = byu * gg;
-    o.body0 = bxu + byu;
-    o.ExS = ExS;
+    S bx = a.bxu * gg, byg = byu * gg;
+    o.body0 = a.bxu + byu;
+    o.ExS = a.ExS;
     o.EyS = EyS;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         o.ExB[c] = bx * P.alb[c];
         o.EyB[c] = byg * P.alb[c];
-        o.E[c] = ExS + EyS + o.ExB[c] + o.EyB[c];
+        o.E[c] = a.ExS + EyS + o.ExB[c] + o.EyB[c];
     }
-    o.pdf = X.w[0] * pxS + X.w[1] * pyS + X.w[2] * pxB + X.w[3] * pyB;
+    o.pdf = X.w[0] * a.pxS + X.w[1] * pyS + X.w[2] * a.pxB + X.w[3] * pyB;
+}
+
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline void lobes_nodes(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                            const V3<G>& wo_g, const NodeFn& node_of, EvalOut<S>& o)
+{
+    LobeAcc<S> a;
+    lobes_at_x(P, X, wo_g, a);
+    const bool front_i = val(X.mu_i) > 0.0f;
+    for (int k = 0; k < P.K; ++k) {
+        Node<G, S> nd;
+        node_of(k, nd);
+        lobes_node_step(P, front_i, nd, wo_g, a);
+    }
+    lobes_finish(P, X, a, o);
+}
+
+// The lobes at two directions of one hit (a given direction and a sampled
+// one, say): the forward nodes depend on wi only, so each is computed once
+// and serves both.  A direction whose flag is false is skipped and its
+// output left untouched.
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline void lobes_nodes2(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                             const V3<G>& wo_a, bool use_a, const V3<G>& wo_b,
+                                             bool use_b, const NodeFn& node_of, EvalOut<S>& oa,
+                                             EvalOut<S>& ob)
+{
+    LobeAcc<S> a, b;
+    if (use_a) lobes_at_x(P, X, wo_a, a);
+    if (use_b) lobes_at_x(P, X, wo_b, b);
+    const bool front_i = val(X.mu_i) > 0.0f;
+    if (use_a || use_b) {
+        for (int k = 0; k < P.K; ++k) {
+            Node<G, S> nd;
+            node_of(k, nd);
+            if (use_a) lobes_node_step(P, front_i, nd, wo_a, a);
+            if (use_b) lobes_node_step(P, front_i, nd, wo_b, b);
+        }
+    }
+    if (use_a) lobes_finish(P, X, a, oa);
+    if (use_b) lobes_finish(P, X, b, ob);
 }
 
 // node providers: compute node k from the state at x, or read it from an
@@ -715,10 +776,10 @@ template <class S> struct SampleOut {
 // mixture pdf at the drawn direction.  Lobes: 0 x-specular, 1 y-specular,
 // 2 x-body, 3 y-body, 4 pass-through.
 template <class G, class S, int MP, class NodeFn>
-__host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
-                                                  const V3<float>& wi, float xi0, float xi1,
-                                                  float xi2, const NodeFn& node_of,
-                                                  SampleOut<S>& so)
+__host__ __device__ inline uint32_t sample_draw(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                const V3<float>& wi, float xi0, float xi1, float xi2,
+                                                const NodeFn& node_of, SampleOut<S>& so, V3<G>& wo,
+                                                bool& ok)
 {
     for (int c = 0; c < 3; ++c) {
         so.wo[c] = S(0); so.wgt[c] = S(0); so.ex[c] = S(0);
@@ -726,6 +787,8 @@ __host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const 
     so.pdf = S(0);
     so.lobe = -1;
     so.node = 0;
+    wo = mk3<G>(G(0), G(0), G(0));
+    ok = false;
     uint32_t flags = X.ph.flags;
     if (X.ph.pass) {
         so.wo[0] = S(-wi.x); so.wo[1] = S(-wi.y); so.wo[2] = S(-wi.z);
@@ -747,8 +810,6 @@ __host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const 
     }
     so.lobe = lobe;
     so.node = node;
-    V3<G> wo = mk3<G>(G(0), G(0), G(0));
-    bool ok = false;
     V3<G> ex = mk3<G>(X.ph.p2x, X.ph.p2y, X.ph.vhit);
     const G gx1 = G((double)xi1), gx2 = G((double)xi2);
     // Each step below runs once per wavefront whatever mix of lobes its
@@ -806,8 +867,15 @@ __host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const 
     so.ex[2] = Narrow<S>::from(ex.z);
     if (!ok) return flags | F_SAMPLE_FAIL;
     wo = normalize(wo);
-    EvalOut<S> e;
-    lobes_nodes(P, X, wo, node_of, e);
+    return flags;
+}
+
+// Last step of the sampler: weight and pdf from the lobes at the drawn
+// direction; a direction of zero density counts as a failed draw.
+template <class G, class S>
+__host__ __device__ inline uint32_t sample_finish(const EvalOut<S>& e, const V3<G>& wo, uint32_t flags,
+                                                  SampleOut<S>& so)
+{
     if (!(val(e.pdf) > 0.0f)) return flags | F_SAMPLE_FAIL;
     so.wo[0] = Narrow<S>::from(wo.x);
     so.wo[1] = Narrow<S>::from(wo.y);
@@ -816,6 +884,42 @@ __host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const 
     for (int c = 0; c < 3; ++c) so.wgt[c] = e.E[c] * ip;
     so.pdf = e.pdf;
     return flags;
+}
+
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                  const V3<float>& wi, float xi0, float xi1,
+                                                  float xi2, const NodeFn& node_of,
+                                                  SampleOut<S>& so)
+{
+    V3<G> wo;
+    bool ok;
+    const uint32_t flags = sample_draw(P, X, wi, xi0, xi1, xi2, node_of, so, wo, ok);
+    if (!ok) return flags;
+    EvalOut<S> e;
+    lobes_nodes(P, X, wo, node_of, e);
+    return sample_finish(e, wo, flags, so);
+}
+
+// Evaluation at a given direction wo_q and one sampled direction for the
+// same hit, sharing the state at x and the forward nodes.  The eval output
+// is written only when eval_ok (the given direction is valid) and the hit is
+// not a pass-through; returns the sampler's flags.
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline uint32_t eval_sample_from_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                       const V3<float>& wi, const V3<G>& wo_q,
+                                                       bool eval_ok, float xi0, float xi1, float xi2,
+                                                       const NodeFn& node_of, EvalOut<S>& eo,
+                                                       SampleOut<S>& so)
+{
+    V3<G> ws;
+    bool ok;
+    const uint32_t flags = sample_draw(P, X, wi, xi0, xi1, xi2, node_of, so, ws, ok);
+    if (X.ph.pass) return flags;
+    EvalOut<S> es;
+    lobes_nodes2(P, X, wo_q, eval_ok, ws, ok, node_of, eo, es);
+    if (!ok) return flags;
+    return sample_finish(es, ws, flags, so);
 }
 
 template <class G, class S, int MP, class Tab>

@@ -342,16 +342,20 @@ __global__ __launch_bounds__(kShadeBlock, 1) void k_r_shade(RView V, PathQ Q, co
             SampleOut<float> so;
             uint32_t sf = 0;
             if (!far) {
+                // the light direction and the drawn one share the state at x
+                // and the forward nodes
                 XState<double, float, MP> X;
                 bysdf::state_at_x(P, tab, hq, uq, vl, wi, X);
+                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false};
+                EvalOut<float> e;
+                for (int c = 0; c < 3; ++c) e.E[c] = 0.0f;
+                e.pdf = 0.0f;
+                sf = bysdf::eval_sample_from_x(P, X, wi, bysdf::mk3<double>(wol.x, wol.y, wol.z),
+                                               cosl > 0.0, u1[2], u1[3], u2[0], nf, e, so);
                 if (!X.ph.pass && cosl > 0.0) {
-                    EvalOut<float> e;
-                    bysdf::lobes(P, tab, X, bysdf::mk3<double>(wol.x, wol.y, wol.z), 0.0f, 0.0f, false, e);
                     for (int c = 0; c < 3; ++c) En[c] = e.E[c];
                     pb = e.pdf;
                 }
-                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false};
-                sf = bysdf::sample_from_x(P, X, wi, u1[2], u1[3], u2[0], nf, so);
             } else {
                 if (cosl > 0.0) far_eval<MP>(P, tab, uq, vl, wi, wol, V.n_h, u2[2], En, &pb);
                 int js = (int)floorf(u2[1] * V.n_h);

@@ -112,6 +112,78 @@ def test_sample_single_type(torch_cuda):
     assert np.array_equal(node[fw], o[fw, 11].astype(np.int32))
 
 
+def _hetero_types(seed, n_types=24):
+    rng = np.random.default_rng(seed)
+    P = []
+    for t in range(n_types):
+        npl = int(rng.integers(1, 9))
+        rp = W.packed_ply_radius(npl)
+        P.append(W.default_params(
+            n_plies=npl, ply_radius=rp, ply_center_radius=1 - rp if npl > 1 else 0.0,
+            fibers_per_ply=int(rng.integers(8, 160)), K=int(rng.integers(1, 17)),
+            n_iter=int(rng.integers(0, 8)), tex_size=int(rng.choice([64, 256, 512, 1024])),
+            beta=float(rng.uniform(0.05, 0.5)), aniso=float(rng.uniform(0.5, 2.0)),
+            B=float(rng.uniform(0, 1)), r=float(rng.uniform(0, 1)),
+            sigma_t=float(rng.uniform(0, 2)), eta=float(rng.uniform(1.2, 1.8))))
+    return P
+
+
+@pytest.mark.parametrize("case", ["single", "hetero"])
+def test_eval_sample_fused(torch_cuda, case):
+    """bysdf_eval_sample: the eval half against the oracle's eval and the
+    sample half against the oracle's sampler on the same queries, and both
+    against the separate entry points (same model code, so equal up to the
+    compiler's operation order).  Some wo are made invalid: only the eval
+    half may flag them."""
+    torch = torch_cuda
+    if case == "single":
+        P = [W.default_params()]
+        _, q = W.single_type(65536 + 41, 13, with_xi=True)
+    else:
+        P = _hetero_types(43)
+        n = 2 * 65536 + 77
+        q = W.queries(n, 17, n_types=len(P), v_max=40.0)
+        rng = np.random.default_rng(18)
+        q["xi"] = np.minimum(rng.random((3, n)).astype(np.float32), np.float32(1.0 - 2.0 ** -24))
+        q["shift"] = rng.random((2, n)).astype(np.float32)
+    n = len(q["h"])
+    q["wo"] = np.array(q["wo"], dtype=np.float32, copy=True)
+    q["wo"][:, 5:n:997] = np.nan
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef, sv, lobe, node, sf = bysdf.bysdf_eval_sample(T, qd)
+    ev2, ef2 = bysdf.bysdf_eval(T, qd)
+    sv2, lobe2, node2, sf2 = bysdf.bysdf_sample_pdf(T, qd)
+    torch.cuda.synchronize()
+    ev, ef, sv, sf = ev.cpu().numpy().T, ef.cpu().numpy().view(np.uint32), sv.cpu().numpy().T, \
+        sf.cpu().numpy().view(np.uint32)
+    lobe, node = lobe.cpu().numpy(), node.cpu().numpy()
+    bad_wo = np.zeros(n, bool)
+    bad_wo[5:n:997] = True
+    assert np.all(ef[bad_wo] & oracle.BAD_INPUT)
+    assert not np.any(sf[bad_wo] & oracle.BAD_INPUT)
+    # against the separate entry points
+    ev2, ef2 = ev2.cpu().numpy().T, ef2.cpu().numpy().view(np.uint32)
+    sv2, sf2 = sv2.cpu().numpy().T, sf2.cpu().numpy().view(np.uint32)
+    assert np.array_equal(ef, ef2) and np.array_equal(sf, sf2)
+    assert np.array_equal(lobe, lobe2.cpu().numpy()) and np.array_equal(node, node2.cpu().numpy())
+    for a, b, label in ((ev, ev2, "eval"), (sv, sv2, "sample")):
+        rel = np.abs(a - b) / (np.abs(b) + 1e-6)
+        print(case, label, "equal share", np.mean(a == b), "max rel", rel.max())
+        assert rel.max() <= 1e-5, label
+    # against the oracle
+    o, of = oracle.eval(P, q)
+    rep = compare(ev, ef, o[:, :12], of)
+    print(case, "eval", {k: v for k, v in rep.items() if k != "bad_idx"})
+    assert_parity(rep, max_flagged=0.05)
+    so, sof = oracle.sample(P, q)
+    rep = compare(sv, sf, so[:, :10], sof)
+    print(case, "sample", {k: v for k, v in rep.items() if k != "bad_idx"})
+    assert_parity(rep, max_flagged=0.05)
+    ok = (sof & oracle.MARGIN_MASK) == 0
+    assert np.array_equal(lobe[ok], so[ok, 10].astype(np.int32))
+
+
 def test_furnace_blocks(torch_cuda):
     """Per-block white-furnace mean and variance (Sec. 4.3) against the
     oracle; blocks whose hit or any draw sits on a margin are skipped."""
