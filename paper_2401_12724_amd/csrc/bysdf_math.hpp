@@ -20,7 +20,28 @@ __host__ __device__ inline float val(float x) { return x; }
 __host__ __device__ inline double val(double x) { return x; }
 
 __host__ __device__ inline float sqrt_(float x) { return sqrtf(x); }
-__host__ __device__ inline double sqrt_(double x) { return sqrt(x); }
+// Double-precision square root.  The device path takes the hardware
+// reciprocal-root estimate, one Goldschmidt step that refines the root and
+// half its reciprocal together, and one Newton correction of the root,
+// which leaves it within an ulp of the rounded root.  It skips the
+// library's rescaling of arguments below 2^-767 and its infinity fix-up:
+// the model only forms arguments that are 0 (returned exactly), negative
+// (NaN, as the library), or far above that range.
+__host__ __device__ inline double sqrt_(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, hy = 0.5 * y;
+    const double r = fma(-hy, g, 0.5);
+    g = fma(g, r, g);
+    hy = fma(hy, r, hy);
+    const double d = fma(-g, g, x);
+    g = fma(d, hy, g);
+    return x == 0.0 ? 0.0 : g;
+#else
+    return sqrt(x);
+#endif
+}
 // reciprocal square root (the device uses the hardware estimate refined by
 // the math library; the host path only serves host-side tools)
 __host__ __device__ inline float rsqrt_(float x)
@@ -31,10 +52,16 @@ __host__ __device__ inline float rsqrt_(float x)
     return 1.0f / sqrtf(x);
 #endif
 }
+// Double-precision reciprocal square root: hardware estimate y and one
+// third-order correction y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.  Without
+// the library's fix-up for 0 and infinity (the model guards zero lengths
+// itself).
 __host__ __device__ inline double rsqrt_(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return rsqrt(x);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 #else
     return 1.0 / sqrt(x);
 #endif
@@ -45,19 +72,37 @@ __host__ __device__ inline float cos_(float x) { return cosf(x); }
 __host__ __device__ inline double cos_(double x) { return cos(x); }
 __host__ __device__ inline float atan2_(float y, float x) { return atan2f(y, x); }
 
+// Quotient a / b in double precision from the hardware reciprocal estimate:
+// two Newton steps on 1/b, the product, and one residual correction (within
+// an ulp).  For b of ordinary magnitude (no overflow or denormal handling).
+__host__ __device__ inline double div_ordinary(double a, double b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(r, fma(-b, r, 1.0), r);
+    r = fma(r, fma(-b, r, 1.0), r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+#else
+    return a / b;
+#endif
+}
+
 // atan2 in double precision: fold to the first octant (t = min/max in
 // [0, 1]), reduce once more with atan t = pi/6 + atan((sqrt3 t - 1)/(sqrt3 +
 // t)) to |t| <= tan(pi/12), then sum the odd Taylor series of atan to t^27
-// (remainder below 1e-18) and unfold.
+// (remainder below 1e-18) and unfold.  Both reductions share one quotient:
+// (sqrt3 t - 1)/(sqrt3 + t) = (sqrt3 mn - mx)/(sqrt3 mx + mn).
 __host__ __device__ inline double atan2_(double y, double x)
 {
     const double ax = fabs(x), ay = fabs(y);
     const double mx = fmax(ax, ay), mn = fmin(ax, ay);
-    const double t = mx > 0.0 ? mn / mx : 0.0;
     const double k3 = 1.73205080756887729353;   // sqrt(3)
     const double t12 = 0.26794919243112270647;  // tan(pi/12)
-    const bool big = t > t12;
-    const double tr = big ? (k3 * t - 1.0) / (k3 + t) : t;
+    const bool big = mn > t12 * mx;
+    const double num = big ? fma(k3, mn, -mx) : mn;
+    const double den = big ? fma(k3, mx, mn) : mx;
+    const double tr = mx > 0.0 ? div_ordinary(num, den) : 0.0;
     const double z = tr * tr;
     double p = -1.0 / 27.0;
     p = fma(p, z, 1.0 / 25.0);
