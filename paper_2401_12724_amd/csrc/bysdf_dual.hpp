@@ -59,6 +59,11 @@ template <class T> __host__ __device__ inline Dual<T> sqrt_(Dual<T> x)
     T s = sqrt_(x.v);
     return Dual<T>::make(s, s > (T)0 ? x.d / ((T)2 * s) : (T)0);
 }
+template <class T> __host__ __device__ inline Dual<T> rcp_(Dual<T> x)
+{
+    T r = rcp_(x.v);
+    return Dual<T>::make(r, -x.d * r * r);
+}
 template <class T> __host__ __device__ inline Dual<T> rsqrt_(Dual<T> x)
 {
     T r = rsqrt_(x.v);

@@ -256,6 +256,7 @@ struct OPtrs {
 };
 
 constexpr int kBlock = 256;
+constexpr int kWave = 64;  // wavefront width of gfx950
 // Minimum wavefronts per SIMD (the register budget), chosen by measurement:
 // at one wavefront the kernels keep 256 VGPRs plus accumulation registers
 // and never spill to scratch; at two the sampler spilled 360-600 B per lane
@@ -460,6 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
                                                     int block, float* mean, float* var)
 {
     __shared__ Node<double, float> s_nodes[kMaxNodes];
+    __shared__ XState<double, float, MP> s_X;
     __shared__ float s_red[3][kBlock];
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x;
@@ -474,16 +476,21 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
     const float h = q.h[q0], u = q.u[q0], v = q.v[q0];
     const float s0 = q.s0 ? q.s0[q0] : 0.0f, s1 = q.s1 ? q.s1[q0] : 0.0f;
     const bool bad = !valid || check_inputs(h, u, v, wi) != 0u;
-    XState<double, float, MP> X;
-    if (!bad) {
-        state_at_x(P, tab, h, u, v, wi, X);
-        if (!X.ph.pass && tid < P.K) {
+    // the first wavefront computes the state at the shared hit (every lane
+    // the same values) and the K nodes (lane k node k); all draws read both
+    // from LDS
+    if (!bad && tid < kWave) {
+        XState<double, float, MP> X0;
+        state_at_x(P, tab, h, u, v, wi, X0);
+        if (tid == 0) s_X = X0;
+        if (!X0.ph.pass && tid < P.K) {
             Node<double, float> nd;
-            forward_node(P, tab, X, tid, s0, s1, q.s0 != nullptr, nd);
+            forward_node(P, tab, X0, tid, s0, s1, q.s0 != nullptr, nd);
             s_nodes[tid] = nd;
         }
     }
     __syncthreads();
+    const XState<double, float, MP>& X = s_X;
     NodesStored<double, float> nodes{s_nodes};
     float w[kMaxDrawsPerLane][3];
     float sum[3] = {0.0f, 0.0f, 0.0f};

@@ -19,7 +19,27 @@ constexpr double kInvTwoPi = 0.15915494309189533577;
 __host__ __device__ inline float val(float x) { return x; }
 __host__ __device__ inline double val(double x) { return x; }
 
-__host__ __device__ inline float sqrt_(float x) { return sqrtf(x); }
+// Single-precision square root, reciprocal, exp and log for the lobe
+// formulas: on the device the hardware instructions (about 1 ulp; the
+// library's rescaling of denormal arguments is skipped -- the lobes never
+// form them), exp and log through exp2 / log2 with one multiply.
+__host__ __device__ inline float sqrt_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+__host__ __device__ inline float rcp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ inline double rcp_(double x) { return 1.0 / x; }
 // Double-precision square root.  The device path takes the hardware
 // reciprocal-root estimate, one Goldschmidt step that refines the root and
 // half its reciprocal together, and one Newton correction of the root,
@@ -126,9 +146,23 @@ __host__ __device__ inline double atan2_(double y, double x)
 }
 __host__ __device__ inline float asin_(float x) { return asinf(x); }
 __host__ __device__ inline double asin_(double x) { return asin(x); }
-__host__ __device__ inline float exp_(float x) { return expf(x); }
+__host__ __device__ inline float exp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f);
+#else
+    return expf(x);
+#endif
+}
 __host__ __device__ inline double exp_(double x) { return exp(x); }
-__host__ __device__ inline float log_(float x) { return logf(x); }
+__host__ __device__ inline float log_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x) * 0.69314718055994530942f;
+#else
+    return logf(x);
+#endif
+}
 __host__ __device__ inline double log_(double x) { return log(x); }
 __host__ __device__ inline float abs_(float x) { return fabsf(x); }
 __host__ __device__ inline double abs_(double x) { return fabs(x); }

@@ -93,11 +93,11 @@ template <> __host__ __device__ inline void sincos_turns_g<double>(const double&
 // of relative index e; total internal reflection returns 1.
 template <class S> __host__ __device__ inline S fresnel(S c, S e)
 {
-    S s2t = (S(1) - c * c) / (e * e);
+    S s2t = (S(1) - c * c) * rcp_(e * e);
     if (val(s2t) >= 1.0f) return S(1);
     S ct = sqrt_(S(1) - s2t);
-    S rs = (c - e * ct) / (c + e * ct);
-    S rpp = (e * c - ct) / (e * c + ct);
+    S rs = (c - e * ct) * rcp_(c + e * ct);
+    S rpp = (e * c - ct) * rcp_(e * c + ct);
     return S(0.5f) * (rs * rs + rpp * rpp);
 }
 
@@ -106,19 +106,19 @@ template <class S> __host__ __device__ inline S fresnel(S c, S e)
 // polarisation.
 template <class S> __host__ __device__ inline S fresnel_T(S c, S e)
 {
-    S s2t = (S(1) - c * c) / (e * e);
+    S s2t = (S(1) - c * c) * rcp_(e * e);
     if (val(s2t) >= 1.0f) return S(0);
     S ct = sqrt_(S(1) - s2t);
     S a = c + e * ct, b = e * c + ct;
-    return S(2) * e * c * ct * (S(1) / (a * a) + S(1) / (b * b));
+    return S(2) * e * c * ct * (rcp_(a * a) + rcp_(b * b));
 }
 
 template <class S> __host__ __device__ inline S ggx_D(const V3<S>& m, S ax, S ay)
 {
     if (!(val(m.z) > 0.0f)) return S(0);
-    S qx = m.x / ax, qy = m.y / ay;
+    S qx = m.x * rcp_(ax), qy = m.y * rcp_(ay);
     S t = qx * qx + qy * qy + m.z * m.z;
-    return S(1) / (S(float(kPi)) * ax * ay * t * t);
+    return rcp_(S(float(kPi)) * ax * ay * t * t);
 }
 
 template <class S> __host__ __device__ inline S smith_G1(const V3<S>& w, const V3<S>& m, S ax, S ay)
@@ -126,8 +126,8 @@ template <class S> __host__ __device__ inline S smith_G1(const V3<S>& w, const V
     S wm = dot(w, m);
     if (!(val(wm) * val(w.z) > 0.0f)) return S(0);
     S tx = ax * w.x, ty = ay * w.y;
-    S a2t2 = (tx * tx + ty * ty) / (w.z * w.z);
-    return S(2) / (S(1) + sqrt_(S(1) + a2t2));
+    S a2t2 = (tx * tx + ty * ty) * rcp_(w.z * w.z);
+    return S(2) * rcp_(S(1) + sqrt_(S(1) + a2t2));
 }
 
 // Visible-normal sampling of GGX (Heitz 2018): stretch the view to unit
@@ -159,7 +159,7 @@ template <class T> __host__ __device__ inline V3<T> sample_vndf(const V3<T>& w, 
 template <class S> __host__ __device__ inline S ls_albedo(S mu)
 {
     if (!(val(mu) > 0.0f)) return S(0.5f);
-    return S(0.5f) * (S(1) - mu * log_(S(1) + S(1) / mu));
+    return S(0.5f) * (S(1) - mu * log_(S(1) + rcp_(mu)));
 }
 
 // ---------------------------------------------------------------- ply hit
@@ -576,7 +576,7 @@ __host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& w
     S g1o = smith_G1<S>(narrow3<S>(to_local(fy, wo)), ml, P.ax, P.ay);
     // |wi'.m| |wo.m| / (|wi'.n| |wo.n|) * Jacobian / (eta wi'.m + wo.m)^2,
     // times |wo.n| for the returned value
-    S geo = Narrow<S>::from(-im / -ci * om / (den * den));
+    S geo = Narrow<S>::from((im * om) / (ci * (den * den)));
     *val_out = geo * Narrow<S>::from(Ft) * g1i * g1o * D;
     *pdf_out = geo * g1i * D;
 }
@@ -617,14 +617,15 @@ __host__ __device__ inline void lobes_at_x(const Derived<G, S>& P, const XState<
         S g1o = smith_G1<S>(narrow3<S>(to_local(X.fx, wo_g)), hl, P.ax, P.ay);
         S ih = Narrow<S>::from(dot(X.wi_g, hv)), oh = Narrow<S>::from(dot(wo_g, hv));
         S ihp = val(ih) > 0.0f ? ih : S(0);
-        ExS = (S(1) - P.B) * P.kS * fresnel<S>(ihp, P.eta) * g1i * g1o * D / (S(4) * mu_i);
-        if (val(oh) > 0.0f) pxS = g1i * ihp * D / mu_i / (S(4) * oh);
+        const S q4 = rcp_(S(4) * mu_i);
+        ExS = (S(1) - P.B) * P.kS * fresnel<S>(ihp, P.eta) * g1i * g1o * D * q4;
+        if (val(oh) > 0.0f) pxS = g1i * ihp * D * q4 * rcp_(oh);
     }
     S bxu = S(0), pxB = S(0);
     if (val(mu_o_g) > 0.0) {
         S mp = front_i ? mu_i : S(0);
-        S fls = S(1) / (S(float(4.0 * kPi)) * (mp + mu_o));
-        bxu = P.B * P.r * (fls + S(float(1.0 / kPi))) * mu_o / (S(1) + ls_albedo<S>(mp));
+        S fls = rcp_(S(float(4.0 * kPi)) * (mp + mu_o));
+        bxu = P.B * P.r * (fls + S(float(1.0 / kPi))) * mu_o * rcp_(S(1) + ls_albedo<S>(mp));
         pxB = mu_o * S(float(1.0 / kPi));
     }
     a.ExS = ExS;
@@ -656,7 +657,7 @@ template <class G, class S, int MP>
 __host__ __device__ inline void lobes_finish(const Derived<G, S>& P, const XState<G, S, MP>& X,
                                              const LobeAcc<S>& a, EvalOut<S>& o)
 {
-    S invK = S(1) / S(float(P.K));
+    S invK = rcp_(S(float(P.K)));
     S EyS = a.EyS * (S(1) - P.B) * P.kS * invK;
     S pyS = a.pyS * invK;
     S byu = a.by * P.B * (S(1) - P.r) * invK;
@@ -880,7 +881,7 @@ __host__ __device__ inline uint32_t sample_finish(const EvalOut<S>& e, const V3<
     so.wo[0] = Narrow<S>::from(wo.x);
     so.wo[1] = Narrow<S>::from(wo.y);
     so.wo[2] = Narrow<S>::from(wo.z);
-    S ip = S(1) / e.pdf;
+    S ip = rcp_(e.pdf);
     for (int c = 0; c < 3; ++c) so.wgt[c] = e.E[c] * ip;
     so.pdf = e.pdf;
     return flags;

@@ -46,6 +46,8 @@ BYSDF_CNT_FN1(asin_, std::asin, trans)
 BYSDF_CNT_FN1(exp_, std::exp, trans)
 BYSDF_CNT_FN1(log_, std::log, trans)
 #undef BYSDF_CNT_FN1
+inline CD rcp_(CD x) { if (g_tally) g_tally->div[0] += 1; return mkc<double, 0>(1.0 / x.v); }
+inline CF rcp_(CF x) { if (g_tally) g_tally->div[1] += 1; return mkc<float, 1>(1.0f / x.v); }
 inline CD rsqrt_(CD x) { if (g_tally) g_tally->sqrt[0] += 1; return mkc<double, 0>(1.0 / std::sqrt(x.v)); }
 inline CF rsqrt_(CF x) { if (g_tally) g_tally->sqrt[1] += 1; return mkc<float, 1>(1.0f / std::sqrt(x.v)); }
 inline CD atan2_(CD y, CD x) { if (g_tally) g_tally->trans[0] += 1; return mkc<double, 0>(std::atan2(y.v, x.v)); }
