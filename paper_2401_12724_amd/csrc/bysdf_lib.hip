@@ -257,15 +257,28 @@ struct OPtrs {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;  // wavefront width of gfx950
-// Minimum wavefronts per SIMD (the register budget), chosen by measurement:
-// at one wavefront the kernels keep 256 VGPRs plus accumulation registers
-// and never spill to scratch; at two the sampler spilled 360-600 B per lane
-// and wrote ~10x its output bytes to HBM.
+// Minimum wavefronts per SIMD (the register budget), chosen by measurement
+// on 2^24 queries.  At one wavefront a kernel keeps 256 VGPRs plus
+// accumulation registers and never spills, but a lone wavefront stalls on
+// the latency of its FP64 dependency chains; at two the kernels spill
+// 200-350 B per lane.  Two wavefronts win for the plain eval (4.55 -> 4.40
+// ms), the fused eval + sample (6.69 -> 5.33 ms) and the batched eval
+// (20.2 -> 14.7 ms on 2^26 queries); one wins for the sampler alone
+// (5.46 vs 6.40 ms) and the adjoint passes.
 #ifndef BYSDF_EVAL_MIN_WAVES
-#define BYSDF_EVAL_MIN_WAVES 1
+#define BYSDF_EVAL_MIN_WAVES 2
 #endif
 #ifndef BYSDF_SAMPLE_MIN_WAVES
 #define BYSDF_SAMPLE_MIN_WAVES 1
+#endif
+#ifndef BYSDF_EVAL_SAMPLE_MIN_WAVES
+#define BYSDF_EVAL_SAMPLE_MIN_WAVES 2
+#endif
+#ifndef BYSDF_BATCHED_MIN_WAVES
+#define BYSDF_BATCHED_MIN_WAVES 2
+#endif
+#ifndef BYSDF_BACKWARD_MIN_WAVES
+#define BYSDF_BACKWARD_MIN_WAVES 1
 #endif
 
 // Lanes of a wavefront are served one distinct type at a time (a wavefront
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
 // serve both directions, so a query costs about one evaluation plus the
 // draw instead of an evaluation and a sample.
 template <bool kLds, int MP>
-__global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_eval_sample(
+__global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sample(
     const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
     QPtrs q, const float* __restrict__ xi0, const float* __restrict__ xi1,
     const float* __restrict__ xi2, OPtrs o, SOPtrs so_p, int64_t n)
@@ -604,7 +617,7 @@ __device__ inline bool locate_tile(int tile, const int32_t* __restrict__ tile_fi
 // seeded parameter run in plain arithmetic and are promoted to duals with
 // zero tangents: everything at x for beta, the ply hit for the fiber twist.
 template <int MP, int PASS>
-__global__ __launch_bounds__(kBlock) void k_backward(const TypeRec* __restrict__ types,
+__global__ __launch_bounds__(kBlock, BYSDF_BACKWARD_MIN_WAVES) void k_backward(const TypeRec* __restrict__ types,
                                                      const float4* __restrict__ tables, QPtrs q,
                                                      const int64_t* __restrict__ off, int n_types,
                                                      const int32_t* __restrict__ tile_first,
@@ -706,7 +719,7 @@ __global__ void k_backward_sum(const int32_t* __restrict__ tile_first, int n_typ
 __global__ void k_reset_counter(int* counter) { *counter = 0; }
 
 template <int MP, bool kLds>
-__global__ __launch_bounds__(kBlock) void k_eval_batched(
+__global__ __launch_bounds__(kBlock, BYSDF_BATCHED_MIN_WAVES) void k_eval_batched(
     const TypeRec* __restrict__ types, const float4* __restrict__ tables,
     const int64_t* __restrict__ off, int n_types, const int32_t* __restrict__ tile_first,
     int* counter, QPtrs q, OPtrs o, int chunk)

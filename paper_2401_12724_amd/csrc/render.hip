@@ -282,7 +282,10 @@ __device__ inline void far_eval(const Derived<double, float>& P, const TabPtr& t
 }
 
 template <int MP>
-__global__ __launch_bounds__(kShadeBlock, 1) void k_r_shade(RView V, PathQ Q, const int* cnt_in, HitQ H, PathQ O,
+#ifndef RENDER_SHADE_MIN_WAVES
+#define RENDER_SHADE_MIN_WAVES 1
+#endif
+__global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade(RView V, PathQ Q, const int* cnt_in, HitQ H, PathQ O,
                                                             int* cnt_out, ShadowQ SQ, int* cnt_sh, int cap,
                                                             int depth, int j0, int spp_batch)
 {
