@@ -220,10 +220,15 @@ def _cpu_baseline(P, q, target_s):
         oracle.furnace(ts, sub, 256, nthreads=cores)
         return time.perf_counter() - t0
 
+    # grow the sample until it takes about target_s (a small first run is
+    # dominated by fixed costs, so one extrapolation undershoots)
     nb = 16
     dt = run(nb)
-    nb = int(min(len(P), max(16, nb * target_s / max(dt, 1e-3))))
-    dt = run(nb)
+    for _ in range(4):
+        if dt >= 0.5 * target_s or nb >= len(P):
+            break
+        nb = int(min(len(P), max(nb + 1, nb * target_s / max(dt, 1e-3))))
+        dt = run(nb)
     n = nb * 256
     return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
             "sample": "first %d blocks (%d queries) of the per-block workload, same "
