@@ -6,8 +6,9 @@
 //   k_r_extend  one ray per lane (LDS traversal stack): yarn BVH, the light
 //               rectangle, the environment; light / environment hits add
 //               their radiance to the path's slot and end it
-//   k_r_shade   BYSDF at the hit (wave-uniform type): one state at x serves
-//               the next-event evaluation and the sample; far field by the
+//   k_r_shade   BYSDF at the hit (wave-uniform type): one state at x and one
+//               set of forward nodes serve the next-event evaluation and
+//               the sample; far field by the
 //               LOD rule; appends a shadow ray and the continued path
 //               (wave-aggregated atomics: compaction)
 //   k_r_shadow  shadow rays; a yarn whose implicit plies are missed is
@@ -179,10 +180,14 @@ __global__ __launch_bounds__(256) void k_r_camera(RView V, PathQ A, float* L, in
     }
 }
 
-__global__ __launch_bounds__(kTraceBlock) void k_r_extend(RView V, PathQ Q, const int* cnt_in, HitQ H, float* L,
-                                                          int cap, int depth)
+#ifndef RENDER_TRACE_MIN_WAVES
+#define RENDER_TRACE_MIN_WAVES 3
+#endif
+__global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_extend(RView V, PathQ Q,
+                                                                                  const int* cnt_in, HitQ H,
+                                                                                  float* L, int cap, int depth)
 {
-    __shared__ int stk[yarn::kStack * kTraceBlock];
+    extern __shared__ int stk[];  // yarn::stack_entries(BVH depth) x kTraceBlock
     int* my = stk + threadIdx.x;
     const int n = *cnt_in;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -447,9 +452,11 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
 }
 
 template <int MP>
-__global__ __launch_bounds__(kTraceBlock) void k_r_shadow(RView V, ShadowQ SQ, const int* cnt, float* L, int cap)
+__global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_shadow(RView V, ShadowQ SQ,
+                                                                                  const int* cnt, float* L,
+                                                                                  int cap)
 {
-    __shared__ int stk[yarn::kStack * kTraceBlock];
+    extern __shared__ int stk[];  // yarn::stack_entries(BVH depth) x kTraceBlock
     int* my = stk + threadIdx.x;
     const int n = *cnt;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -687,6 +694,9 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
                        3 * (int64_t)npix);
     hipLaunchKernelGGL(k_r_fill, dim3(1), dim3(256), 0, stream, (float*)stats, (int64_t)4);
     const bool mp4 = tv.max_plies <= 4;
+    int64_t sinfo[6];
+    if (int rc = yarn_scene_info(scene, sinfo)) return rc;
+    const size_t stk_bytes = sizeof(int) * yarn::stack_entries((int)sinfo[4]) * kTraceBlock;
     for (int j0 = 0; j0 < rs->spp; j0 += spp_batch) {
         const int nb = std::min(spp_batch, rs->spp - j0);
         const int n = npix * nb;
@@ -695,8 +705,8 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
         for (int depth = 0; depth <= rs->max_depth; ++depth) {
             const int a = depth & 1, b = a ^ 1;
             hipLaunchKernelGGL(k_r_tally, dim3(1), dim3(64), 0, stream, cnt, a, stats, 0);
-            hipLaunchKernelGGL(k_r_extend, dim3(grid_for(n, kTraceBlock, 16384)), dim3(kTraceBlock), 0, stream, V,
-                               Qs[a], cnt + a, Hh, L, n, depth);
+            hipLaunchKernelGGL(k_r_extend, dim3(grid_for(n, kTraceBlock, 16384)), dim3(kTraceBlock), stk_bytes,
+                               stream, V, Qs[a], cnt + a, Hh, L, n, depth);
             if (depth == rs->max_depth) break;
             hipLaunchKernelGGL(k_r_counters, dim3(1), dim3(64), 0, stream, cnt, b, 2, -1);
             if (mp4)
@@ -706,12 +716,8 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
                 hipLaunchKernelGGL(k_r_shade<8>, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream,
                                    V, Qs[a], cnt + a, Hh, Qs[b], cnt + b, SQ, cnt + 2, n, depth, j0, nb);
             hipLaunchKernelGGL(k_r_tally, dim3(1), dim3(64), 0, stream, cnt, 2, stats, 1);
-            if (mp4)
-                hipLaunchKernelGGL(k_r_shadow<4>, dim3(grid_for(n, kTraceBlock, 16384)), dim3(kTraceBlock), 0, stream,
-                                   V, SQ, cnt + 2, L, n);
-            else
-                hipLaunchKernelGGL(k_r_shadow<8>, dim3(grid_for(n, kTraceBlock, 16384)), dim3(kTraceBlock), 0, stream,
-                                   V, SQ, cnt + 2, L, n);
+            hipLaunchKernelGGL(mp4 ? k_r_shadow<4> : k_r_shadow<8>, dim3(grid_for(n, kTraceBlock, 16384)),
+                               dim3(kTraceBlock), stk_bytes, stream, V, SQ, cnt + 2, L, n);
         }
         hipLaunchKernelGGL(k_r_accum, dim3(grid_for(npix, 256, 4096)), dim3(256), 0, stream, L, fb, npix, nb, n,
                            1.0f / rs->spp);

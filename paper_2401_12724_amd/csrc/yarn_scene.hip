@@ -8,8 +8,8 @@
 // median splits below depth 40 so the depth stays within the traversal
 // stack.  Spans are stored in leaf order next to their records.
 //
-// Kernel k_intersect: one ray per lane, 128-lane workgroups, a 64-entry
-// LDS stack per lane ([entry][lane], no bank conflicts).  A point query
+// Kernel k_intersect: one ray per lane, 128-lane workgroups, an LDS stack
+// per lane ([entry][lane], no bank conflicts) of depth + 1 entries.  A point query
 // first collects the yarns whose tube holds the origin, then the closest
 // entering hit is searched; hit frame, h and v are formed for the winner.
 #include <hip/hip_runtime.h>
@@ -78,10 +78,14 @@ struct yarn_scene {
 // ------------------------------------------------------------ kernel
 constexpr int kIsectBlock = 128;
 
-__global__ __launch_bounds__(kIsectBlock) void k_intersect(SceneView S, yarn_ray_soa R, int64_t n,
-                                                           double t_min, yarn_hit_soa H)
+#ifndef YARN_ISECT_MIN_WAVES
+#define YARN_ISECT_MIN_WAVES 3
+#endif
+__global__ __launch_bounds__(kIsectBlock, YARN_ISECT_MIN_WAVES) void k_intersect(SceneView S, yarn_ray_soa R,
+                                                                                 int64_t n, double t_min,
+                                                                                 yarn_hit_soa H)
 {
-    __shared__ int stk[kStack * kIsectBlock];
+    extern __shared__ int stk[];  // stack_entries(depth) x kIsectBlock
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         intersect_ray(S, i, R, t_min, H, stk + threadIdx.x, kIsectBlock);
@@ -207,7 +211,8 @@ extern "C" int yarn_tube_intersect(const yarn_scene_t* s, const yarn_ray_soa* ra
     if (!std::isfinite(t_min)) return fail(BYSDF_ERR_INVALID_ARG, "t_min must be finite");
     int64_t blocks = (n + kIsectBlock - 1) / kIsectBlock;
     if (blocks > 65536 * 8) blocks = 65536 * 8;
-    hipLaunchKernelGGL(k_intersect, dim3((unsigned)blocks), dim3(kIsectBlock), 0, stream, s->view(), *rays, n,
+    hipLaunchKernelGGL(k_intersect, dim3((unsigned)blocks), dim3(kIsectBlock),
+                       sizeof(int) * stack_entries(s->depth) * kIsectBlock, stream, s->view(), *rays, n,
                        (double)t_min, *hits);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(BYSDF_ERR_LAUNCH, "k_intersect: %s", hipGetErrorString(e));

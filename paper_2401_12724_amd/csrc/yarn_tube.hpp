@@ -23,6 +23,12 @@
 namespace yarn {
 
 constexpr int kStack = 64;        // BVH depth bound enforced by the builder
+// Entries of a lane's traversal stack for a BVH of the given depth: a push
+// happens at most once per level above the current node, so depth + 1
+// entries never overflow.  The traversal kernels size their LDS stacks
+// with this at launch, which leaves LDS for more wavefronts per CU on
+// shallow trees.
+inline int stack_entries(int depth) { return depth + 1; }
 constexpr int kMaxExcluded = 4;   // yarns holding the ray origin
 constexpr double kExcludeFrac = 1e-3;
 
