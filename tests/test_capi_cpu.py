@@ -127,3 +127,42 @@ def test_render_settings_rejected_on_host(L):
         assert bysdf.shade_wavefront_workspace_size(dict(base, **{k: v})) == 0, k
     st = bysdf.render_settings(base)
     assert L.shade_wavefront(None, None, C.byref(st), None, None, 0, None, None) == bysdf.ERR_INVALID_ARG
+
+
+def test_null_arguments_rejected_eval_sample(L):
+    assert L.bysdf_eval_sample(None, None, None, None, None, 0, None, None, None) == bysdf.ERR_INVALID_ARG
+
+
+def test_op_counts_of_the_kernels_formulation(L):
+    """bysdf_count_ops runs the kernels' per-query model on the host with
+    counting scalars (host only, for the roofline).  The fused count shares
+    the state at x and the forward nodes, so it lies between one evaluation
+    and an evaluation plus a sample; a bad mode is rejected."""
+    import numpy as np
+    import oracle
+    P = workloads.default_params()
+    _, q = workloads.single_type(512, 3, with_xi=True)
+    tab = np.ascontiguousarray(oracle.table(P), np.float32)
+    L.bysdf_count_ops.argtypes = ([C.POINTER(bysdf.TypeParams), C.c_void_p, C.c_int64]
+                                  + [C.c_void_p] * 6 + [C.c_int32, C.c_void_p])
+    f = lambda a: np.ascontiguousarray(a, np.float32).ctypes.data_as(C.c_void_p)
+    arr = bysdf.params_array([P])
+    keep = [np.ascontiguousarray(q[k], np.float32) for k in ("h", "u", "v", "wi", "wo", "xi")]
+    ptrs = [a.ctypes.data_as(C.c_void_p) for a in keep]
+
+    def count(mode):
+        c = np.zeros(10)
+        rc = L.bysdf_count_ops(arr, tab.ctypes.data_as(C.c_void_p), 512, *ptrs, mode,
+                               c.ctypes.data_as(C.c_void_p))
+        assert rc == bysdf.OK
+        return c
+
+    ev, sm, both = count(0), count(1), count(2)
+    assert np.all(ev >= 0) and ev[:2].sum() > 500  # FP64 adds and muls per query
+    assert ev.sum() < both.sum() < ev.sum() + sm.sum()
+    c = np.zeros(10)
+    assert L.bysdf_count_ops(arr, tab.ctypes.data_as(C.c_void_p), 512, *ptrs, 3,
+                             c.ctypes.data_as(C.c_void_p)) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_count_ops(arr, tab.ctypes.data_as(C.c_void_p), 512, ptrs[0], ptrs[1], ptrs[2],
+                             ptrs[3], None, ptrs[5], 2, c.ctypes.data_as(C.c_void_p)) \
+        == bysdf.ERR_INVALID_ARG
