@@ -374,7 +374,7 @@ def main():
                    "perblock 2e24")
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs single-GPU only "
+        print("bench.py measures one GPU: the path runs on a single GPU "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
