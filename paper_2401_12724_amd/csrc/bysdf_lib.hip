@@ -261,15 +261,15 @@ constexpr int kWave = 64;  // wavefront width of gfx950
 // on 2^24 queries.  At one wavefront a kernel keeps 256 VGPRs plus
 // accumulation registers and never spills, but a lone wavefront stalls on
 // the latency of its FP64 dependency chains; at two the kernels spill
-// 200-350 B per lane.  Two wavefronts win for the plain eval (4.55 -> 4.40
-// ms), the fused eval + sample (6.69 -> 5.33 ms) and the batched eval
-// (20.2 -> 14.7 ms on 2^26 queries); one wins for the sampler alone
-// (5.46 vs 6.40 ms) and the adjoint passes.
+// 200-350 B per lane.  With the single-type path of the type waterfall, two
+// wavefronts win for the eval (4.09 ms), the sampler (5.47 -> 4.88 ms), the
+// fused eval + sample (4.43 ms) and the batched eval (20.2 -> 14.7 ms on
+// 2^26 queries); one wins for the adjoint passes.
 #ifndef BYSDF_EVAL_MIN_WAVES
 #define BYSDF_EVAL_MIN_WAVES 2
 #endif
 #ifndef BYSDF_SAMPLE_MIN_WAVES
-#define BYSDF_SAMPLE_MIN_WAVES 1
+#define BYSDF_SAMPLE_MIN_WAVES 2
 #endif
 #ifndef BYSDF_EVAL_SAMPLE_MIN_WAVES
 #define BYSDF_EVAL_SAMPLE_MIN_WAVES 2
@@ -280,23 +280,6 @@ constexpr int kWave = 64;  // wavefront width of gfx950
 #ifndef BYSDF_BACKWARD_MIN_WAVES
 #define BYSDF_BACKWARD_MIN_WAVES 1
 #endif
-
-// Lanes of a wavefront are served one distinct type at a time (a wavefront
-// of one type -- sorted or per-block input -- takes a single pass): the
-// type index is made wavefront-uniform, so its record is read with scalar
-// loads and its scalars stay out of the vector registers.
-template <class F>
-__device__ inline void for_each_wave_type(int t, bool need, F&& body)
-{
-    unsigned long long pending = __ballot(need);
-    while (pending) {
-        const int lead = __ffsll(pending) - 1;
-        const int tu = __builtin_amdgcn_readlane(t, lead);
-        const bool mine = need && t == tu;
-        if (mine) body(tu);
-        pending &= ~__ballot(mine);
-    }
-}
 
 template <bool kLds, int MP>
 __global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const TypeRec* __restrict__ types, int n_types,

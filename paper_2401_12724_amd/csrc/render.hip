@@ -117,19 +117,6 @@ __device__ inline V3<float> to_loc(D3 T, D3 N, D3 w)
     return bysdf::mk3<float>((float)yarn::dot(w, N), (float)yarn::dot(w, B), (float)yarn::dot(w, T));
 }
 
-template <class F>
-__device__ inline void for_each_wave_type(int t, bool need, F&& body)
-{
-    unsigned long long pending = __ballot(need);
-    while (pending) {
-        const int lead = __ffsll((long long)pending) - 1;
-        const int tu = __builtin_amdgcn_readlane(t, lead);
-        const bool mine = need && t == tu;
-        if (mine) body(tu);
-        pending &= ~__ballot(mine);
-    }
-}
-
 // ------------------------------------------------------------ kernels
 
 __global__ __launch_bounds__(256) void k_r_fill(float* p, int64_t n)
