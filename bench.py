@@ -175,6 +175,27 @@ def _summarize(prof_dir, bench_json, workload_tag):
             continue
         lines.append("| `%s` | " % k + " | ".join(
             "%.1f" % (mean([v for (_, v, _) in cs[c]]) / N) for c in sorted(cs)) + " |")
+    # executed floating-point work from the FLOPS counters (per wavefront
+    # instruction, an FMA counting 2; x 64 lanes), priced at the kernel's
+    # HIP-event time in the traced bench run
+    kms = dict(bj.get("unfused", {}).get("kernels_ms", {}))
+    kms.update(bj["kernels_ms"])
+    stage_of = {"k_eval_sample<": "eval_sample", "k_furnace<": "furnace", "k_eval<": "eval",
+                "k_sample<": "sample"}
+    lines += ["", "Executed FLOPs from the counters, (FLOPS_FP64 + FLOPS_FP64_TRANS + FLOPS_FP32 + "
+              "FLOPS_FP32_TRANS) x 64 lanes per query (per draw for the furnace), at the kernel's "
+              "HIP-event time in this run, against the 78.6 TFLOP/s FP64 / unpacked FP32 vector "
+              "peak (and the 157.3 TFLOP/s packed FP32 figure):", "",
+              "| kernel | executed FLOP/query | ms | executed TFLOP/s | of 78.6 | of 157.3 |",
+              "|---|---|---|---|---|---|"]
+    for k, cs in flops.items():
+        st = next((v for pre, v in stage_of.items() if k.startswith(pre)), None)
+        if st is None or st not in kms:
+            continue
+        fq = 64 * sum(mean([v for (_, v, _) in cs[c]]) for c in cs if "FLOPS" in c) / N
+        rate = fq * N / (kms[st] * 1e-3) / 1e12
+        lines.append("| `%s` | %.0f | %.3f | %.1f | %.1f %% | %.1f %% |" % (
+            k, fq, kms[st], rate, 100 * rate / PEAK_VALU_TFLOPS, 100 * rate / 157.3))
     open(os.path.join(ROOT, "profiles", "bysdf_%s_counters.md" % tag), "w").write(
         "\n".join(lines) + "\n")
     json.dump({"src_hash": _src_hash(), "workload": workload_tag,
