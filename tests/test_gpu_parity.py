@@ -260,15 +260,17 @@ def test_deterministic(torch_cuda):
 
 
 def test_full_size_per_block_sampled(torch_cuda):
-    """The benchmark workload: 2^24 queries in 65,536 parameter blocks of
-    256 (beta and albedo per block), eval, sample and pdf at the sampled
-    direction, checked on a random sample of 12,000 queries."""
+    """The benchmark workload in the benchmark's launches: 2^24 queries in
+    65,536 parameter blocks of 256 (beta and albedo per block) through
+    bysdf_eval_sample (value at wo, one sampled direction with weight and
+    pdf) and bysdf_furnace_blocks, checked on a random sample of 12,000
+    queries and 64 furnace blocks."""
     torch = torch_cuda
     P, q = W.per_block(65536, 256, seed=1)
     T = bysdf.bysdf_types_create(P)
     qd = bysdf.to_device(q)
-    ev, ef = bysdf.bysdf_eval(T, qd)
-    sv, lobe, node, sf = bysdf.bysdf_sample_pdf(T, qd)
+    ev, ef, sv, lobe, node, sf = bysdf.bysdf_eval_sample(T, qd)
+    mean, var = bysdf.bysdf_furnace_blocks(T, qd, 256)
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(0).choice(len(q["h"]), 12000, replace=False))
     sub = {k: (v[..., idx] if v is not None else None) for k, v in q.items()}
@@ -281,3 +283,18 @@ def test_full_size_per_block_sampled(torch_cuda):
     rep = compare(sv[:, idx].cpu().numpy().T, sf[idx].cpu().numpy(), so[:, :10], sof)
     print("sample", {k: v for k, v in rep.items() if k != "bad_idx"})
     assert_parity(rep, max_flagged=0.03)
+    # furnace blocks: the oracle on whole blocks gathered from the workload
+    blocks = np.sort(np.random.default_rng(1).choice(65536, 64, replace=False))
+    rows = (blocks[:, None] * 256 + np.arange(256)[None, :]).ravel()
+    qb = {k: (v[..., rows] if v is not None else None) for k, v in q.items()}
+    om, ov = oracle.furnace(ts, qb, 256)
+    qq = dict(qb)
+    for k in ("type", "h", "u", "v"):
+        qq[k] = np.repeat(qb[k][::256], 256)
+    qq["wi"] = np.repeat(qb["wi"][:, ::256], 256, axis=1)
+    _, bsf = oracle.sample(ts, qq)
+    blk_ok = ((bsf & oracle.MARGIN_MASK) == 0).reshape(len(blocks), 256).all(1)
+    assert blk_ok.sum() >= 32  # blocks whose hit or any draw sits on a margin are skipped
+    gm, gv = mean.cpu().numpy()[blocks], var.cpu().numpy()[blocks]
+    assert np.all((np.abs(gm - om) <= 1e-4 * np.abs(om) + 1e-6)[blk_ok])
+    assert np.all((np.abs(gv - ov) <= 1e-3 * np.abs(ov) + 1e-6)[blk_ok])
