@@ -39,7 +39,7 @@ __host__ __device__ inline float rcp_(float x)
     return 1.0f / x;
 #endif
 }
-__host__ __device__ inline double rcp_(double x) { return 1.0 / x; }
+__host__ __device__ inline double rcp_(double x);  // after div_ordinary below
 // Double-precision square root.  The device path takes the hardware
 // reciprocal-root estimate, one Goldschmidt step that refines the root and
 // half its reciprocal together, and one Newton correction of the root,
@@ -105,6 +105,19 @@ __host__ __device__ inline double div_ordinary(double a, double b)
     return fma(fma(-b, q, a), r, q);
 #else
     return a / b;
+#endif
+}
+
+// Double-precision reciprocal of an argument of ordinary magnitude: the
+// hardware estimate and two Newton steps (within an ulp).
+__host__ __device__ inline double rcp_(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
 #endif
 }
 

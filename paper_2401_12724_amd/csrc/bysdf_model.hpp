@@ -576,7 +576,7 @@ __host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& w
     S g1o = smith_G1<S>(narrow3<S>(to_local(fy, wo)), ml, P.ax, P.ay);
     // |wi'.m| |wo.m| / (|wi'.n| |wo.n|) * Jacobian / (eta wi'.m + wo.m)^2,
     // times |wo.n| for the returned value
-    S geo = Narrow<S>::from((im * om) / (ci * (den * den)));
+    S geo = Narrow<S>::from((im * om) * rcp_(ci * (den * den)));
     *val_out = geo * Narrow<S>::from(Ft) * g1i * g1o * D;
     *pdf_out = geo * g1i * D;
 }
