@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include "../../include/bysdf.h"
+#include "bysdf_math.hpp"
 
 namespace yarn {
 
@@ -119,7 +120,7 @@ __host__ __device__ inline double entry_at(const SpanGeo& g, D3 d, double s, dou
     double r2 = dot(p, p) - z * z;
     double q2 = g.R * g.R - r2;
     if (!(q2 > 0.0)) return INFINITY;
-    double t = z - sqrt(q2);
+    double t = z - bysdf::sqrt_(q2);
     return t > t_min ? t : INFINITY;
 }
 
@@ -135,11 +136,11 @@ __host__ __device__ inline bool entry_slope(const SpanGeo& g, D3 d, double s, do
     double r2 = dot(p, p) - z * z;
     double q2 = g.R * g.R - r2;
     if (!(q2 > 0.0)) return false;
-    double q = sqrt(q2);
+    double q = bysdf::sqrt_(q2), iq = bysdf::rcp_(q);
     double h = dot(p, p1) - z * z1;  // (r^2)' / 2
-    *g1 = z1 + h / q;
+    *g1 = z1 + h * iq;
     double hp = dot(p1, p1) + dot(p, p2) - z1 * z1 - z * z2;
-    *g2 = z2 + hp / q + h * h / (q2 * q);
+    *g2 = z2 + (hp + h * h / q2) * iq;
     return true;
 }
 
