@@ -72,7 +72,7 @@ __host__ __device__ inline D3 cross(D3 a, D3 b)
 {
     return d3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
-__host__ __device__ inline D3 unit(D3 a) { return a * (1.0 / sqrt(dot(a, a))); }
+__host__ __device__ inline D3 unit(D3 a) { return a * bysdf::rsqrt_(dot(a, a)); }
 
 // uniform cubic B-spline basis and its first two derivatives
 __host__ __device__ inline void basis(double s, double* b)
@@ -171,9 +171,10 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
     // the outer two points' direction (the span's chord) misses the ray
     {
         double cx = pu[3] - pu[0], cy = pw[3] - pw[0];
-        double cl = sqrt(cx * cx + cy * cy);
+        double cl = bysdf::sqrt_(cx * cx + cy * cy);
         if (cl > 1e-12 * R) {
-            double nx = -cy / cl, ny = cx / cl;
+            const double icl = bysdf::rcp_(cl);
+            double nx = -cy * icl, ny = cx * icl;
             bool all_p = true, all_n = true;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -225,7 +226,7 @@ __host__ __device__ inline void span_refine(const SpanGeo& g, D3 d, double t_min
                     lo = s;
                 else
                     hi = s;
-                sn = s - g1 / g2;
+                sn = s - g1 * bysdf::rcp_(g2);
                 if (!(g2 > 0.0) || !(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
             } else {
                 sn = 0.5 * (lo + hi);
@@ -287,7 +288,7 @@ __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
             lo = s;
         else
             hi = s;
-        double sn = s - f1 / f2;
+        double sn = s - f1 * bysdf::rcp_(f2);
         if (!(f2 > 0.0) || !(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
         if (fabs(sn - s) < 1e-15) break;
         s = sn;
@@ -307,7 +308,7 @@ __host__ __device__ inline bool span_far(const SpanGeo& g, double lim)
     D3 ch = g.c[3] - g.c[0];
     double cl2 = dot(ch, ch);
     if (!(cl2 > 0.0)) return false;
-    D3 t = ch * (1.0 / sqrt(cl2));
+    D3 t = ch * bysdf::rsqrt_(cl2);
     bool all_p = true, all_n = true;
     double rho2 = 0.0;
 #pragma unroll
@@ -321,7 +322,7 @@ __host__ __device__ inline bool span_far(const SpanGeo& g, double lim)
     }
     if (all_p || all_n) return true;
     D3 p0 = g.c[0] - t * dot(g.c[0], t);  // origin to the chord line
-    double dl = sqrt(dot(p0, p0)) - sqrt(rho2);
+    double dl = bysdf::sqrt_(dot(p0, p0)) - bysdf::sqrt_(rho2);
     return dl > lim;
 }
 
@@ -584,7 +585,7 @@ __host__ __device__ inline HitFrame hit_frame(const SceneView& S, int span, doub
     for (int k = 0; k < 5; ++k) {
         basis1(0.5 * s * (1.0 + gx[k]), b);
         D3 dd = comb(c, b);
-        acc += gw[k] * sqrt(dot(dd, dd));
+        acc += gw[k] * bysdf::sqrt_(dot(dd, dd));
     }
     h.v = (double)f.w + 0.5 * s * acc;
     return h;
