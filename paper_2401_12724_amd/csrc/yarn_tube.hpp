@@ -144,6 +144,16 @@ __host__ __device__ inline bool entry_slope(const SpanGeo& g, D3 d, double s, do
     return true;
 }
 
+// Power-form coefficients a0 + a1 s + a2 s^2 + a3 s^3 of a uniform cubic
+// B-spline coordinate with control values c0..c3 (the basis above, expanded).
+__host__ __device__ inline void spline_power(const double* c, double* a)
+{
+    a[0] = (c[0] + 4.0 * c[1] + c[2]) * (1.0 / 6.0);
+    a[1] = (c[2] - c[0]) * 0.5;
+    a[2] = (c[0] - 2.0 * c[1] + c[2]) * 0.5;
+    a[3] = (c[3] - c[0] + 3.0 * (c[1] - c[2])) * (1.0 / 6.0);
+}
+
 // Sampled scan of one span: the smallest entry T(s_i) > t_min over the
 // nsamp + 1 samples, if it is at most t_lim (and the control-point hull
 // reaches the ray's R-slab within [t_min, t_lim + R]).
@@ -152,12 +162,13 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
 {
     const double R = g.R;
     bool all_pu = true, all_nu = true, all_pw = true, all_nw = true, all_b = true, all_f = true;
-    double pu[4], pw[4];
+    double pu[4], pw[4], pz[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         double u = dot(g.c[k], e1), w = dot(g.c[k], e2), z = dot(g.c[k], d);
         pu[k] = u;
         pw[k] = w;
+        pz[k] = z;
         all_pu &= u > R;
         all_nu &= u < -R;
         all_pw &= w > R;
@@ -185,12 +196,26 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
             if (all_p || all_n) return false;
         }
     }
-    const double inv = 1.0 / nsamp;
+    // the samples in the ray's frame (e1, e2, d): the centreline's offset
+    // (u, w) from the ray and its position z along it are cubics in s, in
+    // power form from the projected control points, so a sample costs three
+    // Horner steps per coordinate and r^2 = u^2 + w^2 has no cancellation
+    double au[4], aw[4], az[4];
+    spline_power(pu, au);
+    spline_power(pw, aw);
+    spline_power(pz, az);
+    const double inv = 1.0 / nsamp, R2 = R * R;
     double bt = INFINITY;
     int bi = -1;
     for (int i = 0; i <= nsamp; ++i) {
-        double t = entry_at(g, d, i * inv, t_min);
-        if (t < bt) {
+        const double sv = i * inv;
+        const double u = fma(fma(fma(au[3], sv, au[2]), sv, au[1]), sv, au[0]);
+        const double w = fma(fma(fma(aw[3], sv, aw[2]), sv, aw[1]), sv, aw[0]);
+        const double q2 = R2 - (u * u + w * w);
+        if (!(q2 > 0.0)) continue;
+        const double z = fma(fma(fma(az[3], sv, az[2]), sv, az[1]), sv, az[0]);
+        const double t = z - bysdf::sqrt_(q2);
+        if (t > t_min && t < bt) {
             bt = t;
             bi = i;
         }
