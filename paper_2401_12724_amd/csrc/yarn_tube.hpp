@@ -111,39 +111,6 @@ struct SpanGeo {
     double R;
 };
 
-__host__ __device__ inline double entry_at(const SpanGeo& g, D3 d, double s, double t_min)
-{
-    double b[4];
-    basis(s, b);
-    D3 p = comb(g.c, b);
-    double z = dot(p, d);
-    double r2 = dot(p, p) - z * z;
-    double q2 = g.R * g.R - r2;
-    if (!(q2 > 0.0)) return INFINITY;
-    double t = z - bysdf::sqrt_(q2);
-    return t > t_min ? t : INFINITY;
-}
-
-// dT/ds and d2T/ds2 at s; returns false where the ball misses the ray
-__host__ __device__ inline bool entry_slope(const SpanGeo& g, D3 d, double s, double* g1, double* g2)
-{
-    double b[4], b1[4], b2[4];
-    basis(s, b);
-    basis1(s, b1);
-    basis2(s, b2);
-    D3 p = comb(g.c, b), p1 = comb(g.c, b1), p2 = comb(g.c, b2);
-    double z = dot(p, d), z1 = dot(p1, d), z2 = dot(p2, d);
-    double r2 = dot(p, p) - z * z;
-    double q2 = g.R * g.R - r2;
-    if (!(q2 > 0.0)) return false;
-    double q = bysdf::sqrt_(q2), iq = bysdf::rcp_(q);
-    double h = dot(p, p1) - z * z1;  // (r^2)' / 2
-    *g1 = z1 + h * iq;
-    double hp = dot(p1, p1) + dot(p, p2) - z1 * z1 - z * z2;
-    *g2 = z2 + (hp + h * h / q2) * iq;
-    return true;
-}
-
 // Power-form coefficients a0 + a1 s + a2 s^2 + a3 s^3 of a uniform cubic
 // B-spline coordinate with control values c0..c3 (the basis above, expanded).
 __host__ __device__ inline void spline_power(const double* c, double* a)
@@ -152,6 +119,46 @@ __host__ __device__ inline void spline_power(const double* c, double* a)
     a[1] = (c[2] - c[0]) * 0.5;
     a[2] = (c[0] - 2.0 * c[1] + c[2]) * 0.5;
     a[3] = (c[3] - c[0] + 3.0 * (c[1] - c[2])) * (1.0 / 6.0);
+}
+
+// A span seen from the ray: the centreline's offset (u, w) from the ray
+// and its position z along it, each a cubic in s in power form.
+struct RayCubic {
+    double u[4], w[4], z[4];
+};
+
+__host__ __device__ inline double horner3(const double* a, double s)
+{
+    return fma(fma(fma(a[3], s, a[2]), s, a[1]), s, a[0]);
+}
+
+// entry T(s) = z - sqrt(R^2 - u^2 - w^2) if above t_min, else +inf
+__host__ __device__ inline double entry_at(const RayCubic& rc, double R, double s, double t_min)
+{
+    const double u = horner3(rc.u, s), w = horner3(rc.w, s);
+    const double q2 = R * R - (u * u + w * w);
+    if (!(q2 > 0.0)) return INFINITY;
+    const double t = horner3(rc.z, s) - bysdf::sqrt_(q2);
+    return t > t_min ? t : INFINITY;
+}
+
+// dT/ds and d2T/ds2 at s; returns false where the ball misses the ray
+__host__ __device__ inline bool entry_slope(const RayCubic& rc, double R, double s, double* g1, double* g2)
+{
+    double u = horner3(rc.u, s), w = horner3(rc.w, s);
+    double q2 = R * R - (u * u + w * w);
+    if (!(q2 > 0.0)) return false;
+    // first and second derivatives of the three cubics
+    auto d1 = [s](const double* a) { return fma(fma(3.0 * a[3], s, 2.0 * a[2]), s, a[1]); };
+    auto d2 = [s](const double* a) { return fma(6.0 * a[3], s, 2.0 * a[2]); };
+    const double u1 = d1(rc.u), w1 = d1(rc.w), z1 = d1(rc.z);
+    const double u2 = d2(rc.u), w2 = d2(rc.w), z2 = d2(rc.z);
+    const double q = bysdf::sqrt_(q2), iq = bysdf::rcp_(q);
+    const double h = u * u1 + w * w1;  // (r^2)' / 2
+    *g1 = z1 + h * iq;
+    const double hp = u1 * u1 + w1 * w1 + u * u2 + w * w2;
+    *g2 = z2 + (hp + h * h / q2) * iq;
+    return true;
 }
 
 // Sampled scan of one span: the smallest entry T(s_i) > t_min over the
@@ -200,22 +207,16 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
     // (u, w) from the ray and its position z along it are cubics in s, in
     // power form from the projected control points, so a sample costs three
     // Horner steps per coordinate and r^2 = u^2 + w^2 has no cancellation
-    double au[4], aw[4], az[4];
-    spline_power(pu, au);
-    spline_power(pw, aw);
-    spline_power(pz, az);
-    const double inv = 1.0 / nsamp, R2 = R * R;
+    RayCubic rc;
+    spline_power(pu, rc.u);
+    spline_power(pw, rc.w);
+    spline_power(pz, rc.z);
+    const double inv = 1.0 / nsamp;
     double bt = INFINITY;
     int bi = -1;
     for (int i = 0; i <= nsamp; ++i) {
-        const double sv = i * inv;
-        const double u = fma(fma(fma(au[3], sv, au[2]), sv, au[1]), sv, au[0]);
-        const double w = fma(fma(fma(aw[3], sv, aw[2]), sv, aw[1]), sv, aw[0]);
-        const double q2 = R2 - (u * u + w * w);
-        if (!(q2 > 0.0)) continue;
-        const double z = fma(fma(fma(az[3], sv, az[2]), sv, az[1]), sv, az[0]);
-        const double t = z - bysdf::sqrt_(q2);
-        if (t > t_min && t < bt) {
+        const double t = entry_at(rc, R, i * inv, t_min);
+        if (t < bt) {
             bt = t;
             bi = i;
         }
@@ -228,16 +229,30 @@ __host__ __device__ inline bool span_scan(const SpanGeo& g, D3 d, D3 e1, D3 e2, 
 
 // Minimum of T in the bracket of sample bi (best sampled value bt):
 // safeguarded Newton on dT/ds in double precision.
-__host__ __device__ inline void span_refine(const SpanGeo& g, D3 d, double t_min, int nsamp, int bi, double bt,
-                                            double* t_out, double* s_out)
+__host__ __device__ inline void span_refine(const SpanGeo& g, D3 d, D3 e1, D3 e2, double t_min, int nsamp, int bi,
+                                            double bt, double* t_out, double* s_out)
 {
+    RayCubic rc;
+    {
+        double pu[4], pw[4], pz[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pu[k] = dot(g.c[k], e1);
+            pw[k] = dot(g.c[k], e2);
+            pz[k] = dot(g.c[k], d);
+        }
+        spline_power(pu, rc.u);
+        spline_power(pw, rc.w);
+        spline_power(pz, rc.z);
+    }
+    const double R = g.R;
     const double inv = 1.0 / nsamp;
     double lo = bi > 0 ? (bi - 1) * inv : 0.0, hi = bi < nsamp ? (bi + 1) * inv : 1.0;
     double s = bi * inv, g1, g2;
     // slope at the bracket ends (a ball that misses the ray reads as a
     // steep wall: -inf on the left, +inf on the right)
-    double glo = entry_slope(g, d, lo, &g1, &g2) ? g1 : -INFINITY;
-    double ghi = entry_slope(g, d, hi, &g1, &g2) ? g1 : INFINITY;
+    double glo = entry_slope(rc, R, lo, &g1, &g2) ? g1 : -INFINITY;
+    double ghi = entry_slope(rc, R, hi, &g1, &g2) ? g1 : INFINITY;
     double sb = s;
     if (glo >= 0.0) {
         sb = lo;
@@ -246,7 +261,7 @@ __host__ __device__ inline void span_refine(const SpanGeo& g, D3 d, double t_min
     } else {
         for (int it = 0; it < 24; ++it) {
             double sn;
-            if (entry_slope(g, d, s, &g1, &g2)) {
+            if (entry_slope(rc, R, s, &g1, &g2)) {
                 if (g1 < 0.0)
                     lo = s;
                 else
@@ -262,7 +277,7 @@ __host__ __device__ inline void span_refine(const SpanGeo& g, D3 d, double t_min
         }
         sb = s;
     }
-    double t = entry_at(g, d, sb, t_min);
+    double t = entry_at(rc, R, sb, t_min);
     // where T is flat the refined value ties the best sample to rounding:
     // keep the refined parameter
     if (t <= bt + 1e-12 * fmax(1.0, fabs(bt))) {
@@ -288,12 +303,22 @@ __host__ __device__ inline void load_span(const SceneView& S, const SpanRec& r, 
 // then safeguarded Newton on the derivative of |C(s)|^2
 __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
 {
+    // the centreline relative to the point, a cubic per coordinate
+    double cx[4], cy[4], cz[4], ax[4], ay[4], az[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cx[k] = g.c[k].x;
+        cy[k] = g.c[k].y;
+        cz[k] = g.c[k].z;
+    }
+    spline_power(cx, ax);
+    spline_power(cy, ay);
+    spline_power(cz, az);
+    auto at = [&](double s) { return d3(horner3(ax, s), horner3(ay, s), horner3(az, s)); };
     double inv = 1.0 / nsamp, bv = INFINITY;
     int bi = 0;
-    double b[4], b1[4], b2[4];
     for (int i = 0; i <= nsamp; ++i) {
-        basis(i * inv, b);
-        D3 p = comb(g.c, b);
+        D3 p = at(i * inv);
         double v = dot(p, p);
         if (v < bv) {
             bv = v;
@@ -302,10 +327,10 @@ __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
     }
     double lo = bi > 0 ? (bi - 1) * inv : 0.0, hi = bi < nsamp ? (bi + 1) * inv : 1.0, s = bi * inv;
     for (int it = 0; it < 20; ++it) {
-        basis(s, b);
-        basis1(s, b1);
-        basis2(s, b2);
-        D3 p = comb(g.c, b), p1 = comb(g.c, b1), p2 = comb(g.c, b2);
+        D3 p = at(s);
+        auto d1 = [s](const double* a) { return fma(fma(3.0 * a[3], s, 2.0 * a[2]), s, a[1]); };
+        auto d2 = [s](const double* a) { return fma(6.0 * a[3], s, 2.0 * a[2]); };
+        D3 p1 = d3(d1(ax), d1(ay), d1(az)), p2 = d3(d2(ax), d2(ay), d2(az));
         double f1 = dot(p, p1), f2 = dot(p1, p1) + dot(p, p2);
         double v = dot(p, p);
         if (v < bv) bv = v;
@@ -318,12 +343,10 @@ __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
         if (fabs(sn - s) < 1e-15) break;
         s = sn;
     }
-    basis(s, b);
-    D3 p = comb(g.c, b);
+    D3 p = at(s);
     double v = dot(p, p);
     return v < bv ? v : bv;
 }
-
 // True when the span is certainly farther than lim from the origin of the
 // span view: the curve lies in the hull of its control points, which lies
 // within the slab of the chord direction they span and within the
@@ -543,7 +566,7 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
         load_span(S, r, o, &g);
         if (ct[q] > tb + kCandMargin * g.R) continue;
         double t, s;
-        span_refine(g, d, t_min, r.info & 0xffff, ci[q], ct[q], &t, &s);
+        span_refine(g, d, e1, e2, t_min, r.info & 0xffff, ci[q], ct[q], &t, &s);
         if (t < best.t || (t == best.t && best.span < 0)) {
             best.t = t;
             best.s = s;
