@@ -47,6 +47,8 @@ class OrcParams(C.Structure):
         ("B", C.c_double), ("r", C.c_double), ("sigma_t", C.c_double),
         ("ply_density", C.c_double), ("fiber_density", C.c_double),
         ("shadow_halfwidth", C.c_double),
+        ("mig_tables", C.c_int32), ("mig_period", C.c_double), ("mig_blend", C.c_double),
+        ("mig_spread", C.c_double), ("mig_seed", C.c_uint32),
     ]
 
 
@@ -100,6 +102,10 @@ def lib():
         pp = C.POINTER(OrcParams)
         tp = C.POINTER(dp)
         L.orc_table.argtypes = [pp, dp]
+        L.orc_mig_table.argtypes = [pp, C.c_int64, C.c_int32]
+        L.orc_mig_table.restype = C.c_int32
+        L.orc_fiber_lookup.argtypes = [pp, dp, C.c_double, C.c_double, C.c_int32, dp]
+        L.orc_fiber_lookup.restype = None
         L.orc_eval.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp, up,
                                C.c_int]
         L.orc_sample.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp,
@@ -169,7 +175,8 @@ class TypeSet:
         self.tables = []
         cache = {}
         for i, d in enumerate(self.dicts):
-            key = (d["fibers_per_ply"], float(d["fiber_radius"]), d["tex_size"])
+            key = (d["fibers_per_ply"], float(d["fiber_radius"]), d["tex_size"],
+                   max(1, d["mig_tables"]), float(d["mig_spread"]), d["mig_seed"])
             if key not in cache:
                 cache[key] = table(d)
             self.tables.append(cache[key])
@@ -180,13 +187,29 @@ class TypeSet:
 
 
 def table(d: dict) -> np.ndarray:
-    """Fiber table (N_u x 3: dn, rho_hat, G_f) of one parameter record."""
-    tab = np.zeros((d["tex_size"], 3), dtype=np.float64)
+    """Fiber tables of one parameter record: max(1, mig_tables) tables of
+    N_u texels, stacked ((tables x N_u) x 3: dn, rho_hat, G_f)."""
+    tab = np.zeros((max(1, d["mig_tables"]) * d["tex_size"], 3), dtype=np.float64)
     p = params_struct(d)
     rc = lib().orc_table(C.byref(p), _ptr(tab, C.c_double))
     if rc != 0:
         raise ValueError("invalid fiber-table parameters")
     return tab
+
+
+def mig_table(d: dict, q: int, k: int) -> int:
+    """Fiber-migration table index of ply k in period q."""
+    return int(lib().orc_mig_table(C.byref(params_struct(d)), q, k))
+
+
+def fiber_lookup(d: dict, tab: np.ndarray, uf: float, vply: float, k: int) -> np.ndarray:
+    """Fiber-table values (dn, rho_hat, G_f) at fiber phase uf, ply arc
+    length vply, on ply k (tab from table(d))."""
+    out = np.zeros(3)
+    t = np.ascontiguousarray(tab, np.float64)
+    lib().orc_fiber_lookup(C.byref(params_struct(d)), _ptr(t, C.c_double), uf, vply, k,
+                           _ptr(out, C.c_double))
+    return out
 
 
 def _types(ts):

@@ -195,20 +195,70 @@ static double union_cos_measure(ival* iv, int n)
     return 0.5 * tot;
 }
 
+/* Number of fiber tables of a type (fiber migration off: one). */
+static int mig_count(const orc_params* p) { return p->mig_tables > 1 ? p->mig_tables : 1; }
+
+/* Uniform in [0, 1) from the top 24 bits of a Philox output word. */
+static double u01_24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+/* Fiber migration draws: Philox4x32-10 with key (mig_seed, "FIBR"). */
+static void mig_philox(const orc_params* p, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                       uint32_t out[4])
+{
+    const uint32_t ctr[4] = {c0, c1, c2, c3};
+    const uint32_t key[2] = {p->mig_seed, 0x46494252u};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Fiber centres of table m: the regular layout for m = 0; for m > 0 every
+ * fiber j moves towards the ply centre by the factor
+ * min(1, 1 + spread (2 xi_j - 1)), xi_j from the counter (j, m, "MIGR", 0). */
+static void fiber_centres_m(const orc_params* p, int m, double* fx, double* fy)
+{
+    int M = p->fibers_per_ply;
+    fiber_centres(M, p->fiber_radius, fx, fy);
+    if (m == 0) return;
+    for (int j = 0; j < M; ++j) {
+        uint32_t o[4];
+        mig_philox(p, (uint32_t)j, (uint32_t)m, 0x4d494752u, 0u, o);
+        double f = 1.0 + p->mig_spread * (2.0 * u01_24(o[0]) - 1.0);
+        if (f > 1.0) f = 1.0;
+        fx[j] *= f;
+        fy[j] *= f;
+    }
+}
+
 /* Texel i looks radially inwards from the ply boundary at angle
  * zeta_i = 2 pi (i + 1/2) / N_u.  The first fiber hit gives the normal
  * perturbation dn (signed angle from the ply's radial normal to the fiber
  * normal), the normalised radius of that fiber, and the cosine-weighted
  * unoccluded fraction of the fiber hemisphere at the hit point. */
+static void table_of_centres(const orc_params* p, const double* fx, const double* fy, ival* iv,
+                             double* tab);
+
 int orc_table(const orc_params* p, double* tab)
 {
     int M = p->fibers_per_ply, Nu = p->tex_size;
     double rho = p->fiber_radius;
     if (M < 1 || Nu < 2 || !(rho > 0.0 && rho < 1.0)) return -1;
+    if (p->mig_tables > 1 && !(p->mig_spread >= 0.0 && p->mig_spread < 1.0)) return -1;
     double* fx = (double*)malloc(sizeof(double) * M);
     double* fy = (double*)malloc(sizeof(double) * M);
     ival* iv = (ival*)malloc(sizeof(ival) * (M > 1 ? M : 1));
-    fiber_centres(M, rho, fx, fy);
+    for (int m = 0; m < mig_count(p); ++m) {
+        fiber_centres_m(p, m, fx, fy);
+        table_of_centres(p, fx, fy, iv, tab + (size_t)3 * Nu * m);
+    }
+    free(fx); free(fy); free(iv);
+    return 0;
+}
+
+/* One table from the fiber centres fx, fy (ply radii). */
+static void table_of_centres(const orc_params* p, const double* fx, const double* fy, ival* iv,
+                             double* tab)
+{
+    int M = p->fibers_per_ply, Nu = p->tex_size;
+    double rho = p->fiber_radius;
     for (int i = 0; i < Nu; ++i) {
         double zeta = TWO_PI * (i + 0.5) / Nu;
         double ex = cos(zeta), ey = sin(zeta);
@@ -256,8 +306,6 @@ int orc_table(const orc_params* p, double* tab)
         tab[3 * i + 1] = (double)(float)rh;
         tab[3 * i + 2] = (double)(float)(blocked < 1.0 ? 1.0 - blocked : 0.0);
     }
-    free(fx); free(fy); free(iv);
-    return 0;
 }
 
 /* Periodic linear interpolation between texel centres. */
@@ -270,6 +318,47 @@ static void tab_lookup(const double* tab, int Nu, double uf, double out[3])
     if (i0 < 0) i0 += Nu;
     long i1 = (i0 + 1) % Nu;
     for (int c = 0; c < 3; ++c) out[c] = (1.0 - f) * tab[3 * i0 + c] + f * tab[3 * i1 + c];
+}
+
+/* Table of ply k in migration period q: Philox counter (q low, q high,
+ * k, "SELT"), first word modulo the table count. */
+static int mig_table(const orc_params* p, int64_t q, int k)
+{
+    uint32_t o[4];
+    uint64_t uq = (uint64_t)q;
+    mig_philox(p, (uint32_t)(uq & 0xffffffffu), (uint32_t)(uq >> 32), (uint32_t)k, 0x53454c54u, o);
+    return (int)(o[0] % (uint32_t)mig_count(p));
+}
+
+/* Fiber-table values at fiber phase uf on ply k at ply arc length vply
+ * (Sec. 3.5.1; with migration, Sec. 3.5.2: the period's table, blended
+ * linearly into the next period's over the period's last mig_blend share,
+ * so the values are continuous along the ply). */
+static void fiber_lookup(const orc_params* p, const double* tab, double uf, double vply, int k,
+                         double out[3])
+{
+    int Nu = p->tex_size;
+    if (mig_count(p) == 1) {
+        tab_lookup(tab, Nu, uf, out);
+        return;
+    }
+    double t = vply / p->mig_period;
+    double fl = floor(t), ph = t - fl;
+    int64_t q = (int64_t)fl;
+    double b = p->mig_blend;
+    double w = (b > 0.0 && ph > 1.0 - b) ? (ph - (1.0 - b)) / b : 0.0;
+    double o0[3], o1[3];
+    tab_lookup(tab + (size_t)3 * Nu * mig_table(p, q, k), Nu, uf, o0);
+    tab_lookup(tab + (size_t)3 * Nu * mig_table(p, q + 1, k), Nu, uf, o1);
+    for (int c = 0; c < 3; ++c) out[c] = (1.0 - w) * o0[c] + w * o1[c];
+}
+
+int orc_mig_table(const orc_params* p, int64_t q, int k) { return mig_table(p, q, k); }
+
+void orc_fiber_lookup(const orc_params* p, const double* tab, double uf, double vply, int k,
+                      double out[3])
+{
+    fiber_lookup(p, tab, uf, vply, k, out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -442,7 +531,7 @@ static void trace_plies(const orc_params* p, double h, double u, double v, v3 wi
 
 /* Ply frame and fiber frame on disc k at 2D outward normal n2 and
  * yarn-axis height z (Sec. 3.4 last paragraph, Sec. 3.5.1). */
-static void fiber_frame(const orc_params* p, const double* tab, double th, double n2x,
+static void fiber_frame(const orc_params* p, const double* tab, double th, int k, double n2x,
                         double n2y, double z, frame* f, double* gf_tab, double* a_out)
 {
     double wp = helix_rate(p);
@@ -456,7 +545,7 @@ static void fiber_frame(const orc_params* p, const double* tab, double th, doubl
     double rho = p->fiber_radius;
     double wf = tan(p->fiber_twist) / ((1.0 - rho) * p->ply_radius);
     double tv[3];
-    tab_lookup(tab, p->tex_size, a + wf * vply, tv);
+    fiber_lookup(p, tab, a + wf * vply, vply, k, tv);
     v3 bp = vcross(tp, np);
     v3 npr = vadd(vscl(np, cos(tv[0])), vscl(bp, sin(tv[0])));
     double tfa = tv[1] * tan(p->fiber_twist);
@@ -526,7 +615,7 @@ static void geom_x(const orc_params* p, const double* tab, double h, double u, d
     plyhit* ph = &g->ph;
     int ks = ph->kstar;
     double gft, a;
-    fiber_frame(p, tab, ph->th[ks], ph->n2[0], ph->n2[1], ph->vhit, &g->fx, &gft, &a);
+    fiber_frame(p, tab, ph->th[ks], ks, ph->n2[0], ph->n2[1], ph->vhit, &g->fx, &gft, &a);
     ph->a = a;
     g->x3 = mk(ph->p2[0], ph->p2[1], ph->vhit);
 
@@ -647,7 +736,7 @@ static void geom_x(const orc_params* p, const double* tab, double h, double u, d
         nd->N = N;
         nd->ell = ell;
         nd->att = exp(-p->sigma_t * ell * N);
-        fiber_frame(p, tab, ph->th[jL], nyx / nyl, nyy / nyl, zy, &nd->fy, NULL, NULL);
+        fiber_frame(p, tab, ph->th[jL], jL, nyx / nyl, nyy / nyl, zy, &nd->fy, NULL, NULL);
         nd->y = mk(y2x, y2y, zy);
     }
 }

@@ -65,10 +65,28 @@ typedef struct {
     double ply_density;      /* rho_p, scales ply occlusion */
     double fiber_density;    /* rho_f, scales fiber occlusion */
     double shadow_halfwidth; /* Delta_p, angular box filter of G_p */
+    /* fiber migration (Sec. 3.5.2): mig_tables > 1 switches between that
+     * many fiber tables along the ply, one per period of mig_period yarn
+     * radii of ply arc length, blending into the next period's table over
+     * its last mig_blend share; table 0 is the regular layout, table m > 0
+     * pulls each fiber inwards by a factor min(1, 1 + mig_spread (2 xi - 1));
+     * the draws come from Philox4x32-10 keyed by mig_seed */
+    int32_t mig_tables;
+    double mig_period;
+    double mig_blend;
+    double mig_spread;
+    uint32_t mig_seed;
 } orc_params;
 
-/* Fiber table of one type: N_u texels x 3 channels (dn, rho_hat, G_f). */
+/* Fiber tables of one type: max(1, mig_tables) tables of N_u texels x 3
+ * channels (dn, rho_hat, G_f), one after the other. */
 int orc_table(const orc_params* p, double* tab);
+
+/* Fiber migration, exposed for tests: the table index of ply k in period q,
+ * and the fiber-table values at fiber phase uf and ply arc length vply. */
+int orc_mig_table(const orc_params* p, int64_t q, int k);
+void orc_fiber_lookup(const orc_params* p, const double* tab, double uf, double vply, int k,
+                      double out[3]);
 
 /* Query arrays: type[n], h[n], u[n], v[n], wi[3][n] (SoA x,y,z), wo[3][n],
  * shift[2][n] (nullable).  out_eval is n x 13 doubles:

@@ -35,6 +35,8 @@ def default_params(**over) -> dict:
         albedo=(0.8, 0.6, 0.4), beta=0.15, aniso=1.0, k_spec=1.0,
         B=0.5, r=0.5, sigma_t=0.5, ply_density=1.0, fiber_density=1.0,
         shadow_halfwidth=0.1,
+        # fiber migration (off with one table)
+        mig_tables=1, mig_period=4.0, mig_blend=0.25, mig_spread=0.3, mig_seed=0,
     )
     p.update(over)
     if "ply_radius" in over and "ply_center_radius" not in over:
@@ -42,7 +44,7 @@ def default_params(**over) -> dict:
     return as_f32(p)
 
 
-INT_FIELDS = ("n_plies", "fibers_per_ply", "K", "n_iter", "tex_size")
+INT_FIELDS = ("n_plies", "fibers_per_ply", "K", "n_iter", "tex_size", "mig_tables", "mig_seed")
 
 
 def as_f32(p: dict) -> dict:
