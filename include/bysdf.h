@@ -86,6 +86,18 @@ typedef struct {
     float ply_density;        /* rho_p in [0, 1]: G_p = 1 - rho_p (1 - G_raw) */
     float fiber_density;      /* rho_f in [0, 1]: G_f = 1 - rho_f (1 - G_raw) */
     float shadow_halfwidth;   /* half width of the G_p window, (0, pi/2]      */
+    /* Fiber migration (Sec. 3.5.2): with mig_tables > 1 the fiber table
+     * switches along the ply between that many tables -- table 0 the
+     * regular arrangement, table m > 0 with every fiber pulled inwards by
+     * min(1, 1 + mig_spread (2 xi - 1)) -- one drawn per ply and period of
+     * mig_period yarn radii of ply arc length, blended linearly into the
+     * next period's over the period's last mig_blend share.  The draws are
+     * Philox4x32-10 keyed by mig_seed.  0 or 1 table: no migration. */
+    int32_t mig_tables;       /* 0..8                                          */
+    float mig_period;         /* > 0 when mig_tables > 1                       */
+    float mig_blend;          /* [0, 1]                                        */
+    float mig_spread;         /* [0, 1)                                        */
+    uint32_t mig_seed;
 } bysdf_type_params;
 
 typedef struct bysdf_types bysdf_types_t; /* opaque: params + fiber tables */
@@ -161,9 +173,9 @@ int bysdf_types_destroy(bysdf_types_t* types);
 /* Number of types in a handle, or a negative error. */
 int32_t bysdf_types_count(const bysdf_types_t* types);
 
-/* Copy the fiber table of type `type_index` to host memory: tex_size x 3
- * floats (dn, rho_hat, G_f) into `host_out` (capacity `cap` floats).
- * Synchronous. */
+/* Copy the fiber tables of type `type_index` to host memory:
+ * max(1, mig_tables) x tex_size x 3 floats (dn, rho_hat, G_f; the tables one
+ * after the other) into `host_out` (capacity `cap` floats).  Synchronous. */
 int bysdf_types_table(const bysdf_types_t* types, int32_t type_index, float* host_out,
                       int64_t cap);
 
@@ -392,9 +404,10 @@ void bysdf_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t 
 /* Host-only: algorithmic operation count of the kernels' formulation.
  * Runs the per-query model on the host with counting scalars over n
  * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type
- * *p, whose fiber table (tex_size x 3 floats: dn, rho_hat, G_f) is given in
- * host memory.  mode 0 counts bysdf_eval (wo needed), mode 1
- * bysdf_sample_pdf (xi needed), mode 2 bysdf_eval_sample (both).  counts[10] receives the mean per query of
+ * *p, whose fiber tables (max(1, mig_tables) x tex_size x 3 floats: dn,
+ * rho_hat, G_f, as bysdf_types_table returns them) are given in host memory.
+ * mode 0 counts bysdf_eval (wo needed), mode 1 bysdf_sample_pdf (xi
+ * needed), mode 2 bysdf_eval_sample (both).  counts[10] receives the mean per query of
  * (add, mul, div, sqrt, transcendental) for the FP64 geometry scalar,
  * then the same five for the FP32 shading scalar.  Touches no device. */
 int bysdf_count_ops(const bysdf_type_params* p, const float* table, int64_t n, const float* h,

@@ -50,6 +50,8 @@ class TypeParams(C.Structure):
         ("aniso", C.c_float), ("k_spec", C.c_float), ("B", C.c_float), ("r", C.c_float),
         ("sigma_t", C.c_float), ("ply_density", C.c_float), ("fiber_density", C.c_float),
         ("shadow_halfwidth", C.c_float),
+        ("mig_tables", C.c_int32), ("mig_period", C.c_float), ("mig_blend", C.c_float),
+        ("mig_spread", C.c_float), ("mig_seed", C.c_uint32),
     ]
 
 
@@ -216,7 +218,9 @@ def bysdf_types_destroy(types: Types):
 
 
 def bysdf_types_table(types: Types, type_index: int) -> np.ndarray:
-    nu = types.dicts[type_index]["tex_size"]
+    """Fiber tables of a type: ((tables x tex_size) x 3) float32."""
+    d = types.dicts[type_index]
+    nu = max(1, d.get("mig_tables", 1)) * d["tex_size"]
     out = np.zeros((nu, 3), dtype=np.float32)
     _check(lib().bysdf_types_table(types.handle, type_index,
                                    out.ctypes.data_as(C.POINTER(C.c_float)), out.size),

@@ -193,6 +193,7 @@ __host__ __device__ inline Derived<DD, DF> derive_dual(const TypeRec& t, int see
     for (int c = 0; c < 3; ++c) d.alb[c] = DF(f.alb[c]);
     d.rp_s = DF(f.rp_s);
     d.Rpc_s = DF(f.Rpc_s);
+    d.n_mig = f.n_mig; d.mig_seed = f.mig_seed; d.mig_period = f.mig_period; d.mig_blend = f.mig_blend;
     return d;
 }
 

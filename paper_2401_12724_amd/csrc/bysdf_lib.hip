@@ -70,6 +70,7 @@ struct bysdf_types {
     int32_t n_tables = 0;
     int32_t max_plies = 0, max_K = 0;
     int32_t single_table = 0;   // every type uses table 0
+    int32_t any_mig = 0;        // some type has fiber migration
     int32_t table_texels = 0;   // texels of table 0 (LDS staging size)
     int device = 0;
     TypeRec* d_types = nullptr;
@@ -80,10 +81,6 @@ struct bysdf_types {
     std::vector<int32_t> h_type_table;
 };
 
-struct TabPtr {
-    const float4* p;
-    __host__ __device__ float4 operator()(int i) const { return p[i]; }
-};
 
 static int validate(const bysdf_type_params& p, int i)
 {
@@ -116,6 +113,13 @@ static int validate(const bysdf_type_params& p, int i)
     if (!(p.fiber_density >= 0.0f && p.fiber_density <= 1.0f)) return bad("fiber_density must be in [0, 1]");
     if (!(p.shadow_halfwidth > 0.0f && p.shadow_halfwidth <= 1.5707964f))
         return bad("shadow_halfwidth must be in (0, pi/2]");
+    if (p.mig_tables < 0 || p.mig_tables > kMaxMigTables) return bad("mig_tables must be in 0..8");
+    if (p.mig_tables > 1) {
+        if (!(p.mig_period > 0.0f && p.mig_period < 1e6f)) return bad("mig_period must be in (0, 1e6)");
+        if (!(p.mig_blend >= 0.0f && p.mig_blend <= 1.0f)) return bad("mig_blend must be in [0, 1]");
+        if (!(p.mig_spread >= 0.0f && p.mig_spread < 1.0f)) return bad("mig_spread must be in [0, 1)");
+        if ((int64_t)p.mig_tables * p.tex_size > 16384) return bad("mig_tables x tex_size must be <= 16384");
+    }
     return 0;
 }
 
@@ -143,6 +147,12 @@ static TypeRec make_rec(const bysdf_type_params& p)
     t.ply_density = p.ply_density;
     t.fiber_density = p.fiber_density;
     t.shadow_hw = p.shadow_halfwidth;
+    t.mig_tables = p.mig_tables > 1 ? p.mig_tables : 1;
+    t.mig_seed = p.mig_seed;
+    t.mig_period = p.mig_tables > 1 ? p.mig_period : 1.0;
+    t.mig_blend = p.mig_blend;
+    t.mig_spread = p.mig_spread;
+    t.table_texels = t.mig_tables * p.tex_size;
     fill_derived(t);
     return t;
 }
@@ -151,7 +161,21 @@ static TypeRec make_rec(const bysdf_type_params& p)
 // One workgroup per texel (Sec. 3.5.1).  Fiber centres: Vogel spiral of M
 // centres within radius 1 - rho (ply radii).  The texel looks radially
 // inwards from the ply rim; lane j tests fiber j.
-__global__ __launch_bounds__(256) void k_fiber_table(int M, double rho, int Nu, float4* out)
+// Fiber migration (Sec. 3.5.2): table m > 0 pulls fiber j inwards by
+// min(1, 1 + spread (2 xi - 1)), xi from Philox4x32-10 with counter
+// (j, m, "MIGR", 0) and key (seed, "FIBR").
+__device__ inline double mig_scale(int j, int m, double spread, uint32_t seed)
+{
+    if (m == 0) return 1.0;
+    uint32_t o[4];
+    rng::philox4x32_10((uint32_t)j, (uint32_t)m, 0x4d494752u, 0u, seed, 0x46494252u, o);
+    const double xi = (double)(o[0] >> 8) * (1.0 / 16777216.0);
+    const double f = 1.0 + spread * (2.0 * xi - 1.0);
+    return f > 1.0 ? 1.0 : f;
+}
+
+__global__ __launch_bounds__(256) void k_fiber_table(int M, double rho, int Nu, float4* out, int m,
+                                                      double spread, uint32_t seed)
 {
     __shared__ double s_val[256];
     __shared__ int s_idx[256];
@@ -165,8 +189,9 @@ __global__ __launch_bounds__(256) void k_fiber_table(int M, double rho, int Nu, 
     double fx = 0.0, fy = 0.0, s = INFINITY;
     if (tid < M) {
         double rj = (1.0 - rho) * sqrt((tid + 0.5) / M);
-        fx = rj * cos(tid * gold);
-        fy = rj * sin(tid * gold);
+        const double f = mig_scale(tid, m, spread, seed);
+        fx = rj * cos(tid * gold) * f;
+        fy = rj * sin(tid * gold) * f;
         double wx = ox - fx, wy = oy - fy;
         double b = -(wx * ex + wy * ey);
         double c = wx * wx + wy * wy - rho * rho;
@@ -196,7 +221,8 @@ __global__ __launch_bounds__(256) void k_fiber_table(int M, double rho, int Nu, 
         return;
     }
     double rb = (1.0 - rho) * sqrt((jb + 0.5) / M);
-    double bx = rb * cos(jb * gold), by = rb * sin(jb * gold);
+    const double fb = mig_scale(jb, m, spread, seed);
+    double bx = rb * cos(jb * gold) * fb, by = rb * sin(jb * gold) * fb;
     double qx = ox - sb * ex, qy = oy - sb * ey;
     double nx = (qx - bx) / rho, ny = (qy - by) / rho;
     bool ok = false;
@@ -281,7 +307,7 @@ constexpr int kWave = 64;  // wavefront width of gfx950
 #define BYSDF_BACKWARD_MIN_WAVES 1
 #endif
 
-template <bool kLds, int MP>
+template <bool kLds, int MP, bool MIG>
 __global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const TypeRec* __restrict__ types, int n_types,
                                                  const float4* __restrict__ tables, int lds_texels,
                                                  QPtrs q, OPtrs o, int64_t n)
@@ -305,7 +331,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const Typ
         const bool need = fl == 0u;
         for_each_wave_type(t, need, [&](int tu) {
             const Derived<double, float>& P = types[tu].d;
-            TabPtr tab;
+            TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + types[tu].table_off;
             XState<double, float, MP> X;
             state_at_x(P, tab, h, u, v, wi, X);
@@ -337,7 +363,7 @@ struct SOPtrs {
     uint32_t* flags;
 };
 
-template <bool kLds, int MP>
+template <bool kLds, int MP, bool MIG>
 __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const TypeRec* __restrict__ types, int n_types,
                                                    const float4* __restrict__ tables,
                                                    int lds_texels, SPtrs q, SOPtrs o, int64_t n)
@@ -362,7 +388,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
         float h = q.h[i], u = q.u[i], v = q.v[i], x0 = q.xi0[i], x1 = q.xi1[i], x2 = q.xi2[i];
         for_each_wave_type(t, need, [&](int tu) {
             const Derived<double, float>& P = types[tu].d;
-            TabPtr tab;
+            TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + types[tu].table_off;
             fl = sample_query<double, float, MP>(P, tab, h, u, v, wi, x0, x1, x2, s0, s1,
                                                  q.s0 != nullptr, so);
@@ -382,7 +408,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
 // direction.  The state at x and the K forward nodes are computed once and
 // serve both directions, so a query costs about one evaluation plus the
 // draw instead of an evaluation and a sample.
-template <bool kLds, int MP>
+template <bool kLds, int MP, bool MIG>
 __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sample(
     const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
     QPtrs q, const float* __restrict__ xi0, const float* __restrict__ xi1,
@@ -413,12 +439,12 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sa
         so.node = 0;
         for_each_wave_type(t, bad_hit == 0u, [&](int tu) {
             const Derived<double, float>& P = types[tu].d;
-            TabPtr tab;
+            TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + types[tu].table_off;
             XState<double, float, MP> X;
             state_at_x(P, tab, h, u, v, wi, X);
             float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
-            NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, s0, s1, q.s0 != nullptr};
+            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{P, tab, X, s0, s1, q.s0 != nullptr};
             V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
             fs = eval_sample_from_x(P, X, wi, wo_g, bad_wo == 0u, x0, x1, x2, nf, e, so);
             if (bad_wo == 0u) {
@@ -451,7 +477,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sa
 // tree order (bitwise reproducible).
 constexpr int kMaxDrawsPerLane = 4;  // block <= 1024 = 4 x 256
 
-template <int MP>
+template <int MP, bool MIG>
 __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ types, int n_types,
                                                     const float4* __restrict__ tables, SPtrs q,
                                                     int block, float* mean, float* var)
@@ -466,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
     const bool valid = t >= 0 && t < n_types;
     const TypeRec& rec = types[valid ? t : 0];
     const Derived<double, float>& P = rec.d;
-    TabPtr tab;
+    TabPtrT<MIG> tab;
     tab.p = tables + rec.table_off;
     V3<float> wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
     const float h = q.h[q0], u = q.u[q0], v = q.v[q0];
@@ -728,7 +754,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_BATCHED_MIN_WAVES) void k_eval_batche
             if (kLds) {
                 if (type != staged) {
                     __syncthreads();
-                    for (int k = tid; k < rec.tex_size; k += kBlock) s_tab[k] = tables[rec.table_off + k];
+                    for (int k = tid; k < rec.table_texels; k += kBlock) s_tab[k] = tables[rec.table_off + k];
                     __syncthreads();
                     staged = type;
                 }
@@ -813,20 +839,33 @@ extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, b
     bysdf_types* h = new bysdf_types();
     h->n_types = n_types;
     h->device = dev;
-    std::map<std::tuple<int, float, int>, int> uniq;
+    // one table set per distinct (M, rho, N_u, migration tables, spread,
+    // seed): its tables one after the other
+    std::map<std::tuple<int, float, int, int, float, uint32_t>, int> uniq;
     int32_t texels = 0;
-    std::vector<std::tuple<int, double, int>> jobs;
+    struct Job {
+        int M;
+        double rho;
+        int Nu, tables;
+        double spread;
+        uint32_t seed;
+    };
+    std::vector<Job> jobs;
     for (int i = 0; i < n_types; ++i) {
-        auto key = std::make_tuple(p[i].fibers_per_ply, p[i].fiber_radius, p[i].tex_size);
+        const int nt = p[i].mig_tables > 1 ? p[i].mig_tables : 1;
+        const float spread = nt > 1 ? p[i].mig_spread : 0.0f;
+        const uint32_t seed = nt > 1 ? p[i].mig_seed : 0u;
+        auto key = std::make_tuple(p[i].fibers_per_ply, p[i].fiber_radius, p[i].tex_size, nt, spread, seed);
         auto it = uniq.find(key);
         int ti;
         if (it == uniq.end()) {
             ti = (int)h->h_table_size.size();
             uniq[key] = ti;
-            h->h_table_size.push_back(p[i].tex_size);
+            h->h_table_size.push_back(nt * p[i].tex_size);
             h->h_table_off.push_back(texels);
-            texels += p[i].tex_size;
-            jobs.emplace_back(p[i].fibers_per_ply, (double)p[i].fiber_radius, p[i].tex_size);
+            texels += nt * p[i].tex_size;
+            jobs.push_back(Job{p[i].fibers_per_ply, (double)p[i].fiber_radius, p[i].tex_size, nt,
+                               (double)spread, seed});
         } else {
             ti = it->second;
         }
@@ -835,6 +874,7 @@ extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, b
         h->h_types.push_back(r);
         h->h_type_table.push_back(ti);
         h->max_plies = std::max(h->max_plies, p[i].n_plies);
+        if (p[i].mig_tables > 1) h->any_mig = 1;
         h->max_K = std::max(h->max_K, p[i].K);
     }
     h->n_tables = (int32_t)h->h_table_size.size();
@@ -855,12 +895,14 @@ extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, b
                        stream);
     if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_LAUNCH, "upload: %s", hipGetErrorString(e)));
     for (size_t j = 0; j < jobs.size(); ++j) {
-        int M = std::get<0>(jobs[j]), Nu = std::get<2>(jobs[j]);
-        double rho = std::get<1>(jobs[j]);
-        hipLaunchKernelGGL(k_fiber_table, dim3(Nu), dim3(256), 0, stream, M, rho, Nu,
-                           h->d_tables + h->h_table_off[j]);
-        e = hipGetLastError();
-        if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_LAUNCH, "k_fiber_table: %s", hipGetErrorString(e)));
+        const Job& jb = jobs[j];
+        for (int m = 0; m < jb.tables; ++m) {
+            hipLaunchKernelGGL(k_fiber_table, dim3(jb.Nu), dim3(256), 0, stream, jb.M, jb.rho, jb.Nu,
+                               h->d_tables + h->h_table_off[j] + (int64_t)m * jb.Nu, m, jb.spread, jb.seed);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return cleanup(fail(BYSDF_ERR_LAUNCH, "k_fiber_table: %s", hipGetErrorString(e)));
+        }
     }
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return cleanup(fail(BYSDF_ERR_LAUNCH, "table build: %s", hipGetErrorString(e)));
@@ -910,6 +952,13 @@ extern "C" int bysdf_types_set_theta(bysdf_types_t* h, const float* theta, hipSt
     return BYSDF_OK;
 }
 
+// kernel instance for a handle: ply bound, LDS-staged table, migration
+#define BYSDF_PICK(K, h)                                                                               \
+    ((h)->any_mig ? ((h)->max_plies <= 4 ? ((h)->single_table ? K<true, 4, true> : K<false, 4, true>)  \
+                                         : ((h)->single_table ? K<true, 8, true> : K<false, 8, true>)) \
+                  : ((h)->max_plies <= 4 ? ((h)->single_table ? K<true, 4, false> : K<false, 4, false>) \
+                                         : ((h)->single_table ? K<true, 8, false> : K<false, 8, false>)))
+
 static int grid_for(int64_t n)
 {
     int64_t g = (n + kBlock - 1) / kBlock;
@@ -938,8 +987,7 @@ extern "C" int bysdf_eval(const bysdf_types_t* h, const bysdf_query_soa* q, int6
     int grid = grid_for(n);
     size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
     int tx = h->single_table ? h->table_texels : 0;
-    auto kern = h->max_plies <= 4 ? (h->single_table ? k_eval<true, 4> : k_eval<false, 4>)
-                                   : (h->single_table ? k_eval<true, 8> : k_eval<false, 8>);
+    auto kern = BYSDF_PICK(k_eval, h);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
                        h->d_tables, tx, qp, op, n);
     HIP_TRY(hipGetLastError());
@@ -975,8 +1023,7 @@ extern "C" int bysdf_sample_pdf(const bysdf_types_t* h, const bysdf_sample_soa* 
     int grid = grid_for(n);
     size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
     int tx = h->single_table ? h->table_texels : 0;
-    auto kern = h->max_plies <= 4 ? (h->single_table ? k_sample<true, 4> : k_sample<false, 4>)
-                                   : (h->single_table ? k_sample<true, 8> : k_sample<false, 8>);
+    auto kern = BYSDF_PICK(k_sample, h);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
                        h->d_tables, tx, sp, op, n);
     HIP_TRY(hipGetLastError());
@@ -1010,8 +1057,7 @@ extern "C" int bysdf_eval_sample(const bysdf_types_t* h, const bysdf_query_soa* 
     int grid = grid_for(n);
     size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
     int tx = h->single_table ? h->table_texels : 0;
-    auto kern = h->max_plies <= 4 ? (h->single_table ? k_eval_sample<true, 4> : k_eval_sample<false, 4>)
-                                   : (h->single_table ? k_eval_sample<true, 8> : k_eval_sample<false, 8>);
+    auto kern = BYSDF_PICK(k_eval_sample, h);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
                        h->d_tables, tx, qp, xi0, xi1, xi2, op, sop, n);
     HIP_TRY(hipGetLastError());
@@ -1032,7 +1078,8 @@ extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_s
     if (nb > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many blocks");
     SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
              q->shift0, q->shift1};
-    auto kern = h->max_plies <= 4 ? k_furnace<4> : k_furnace<8>;
+    auto kern = h->any_mig ? (h->max_plies <= 4 ? k_furnace<4, true> : k_furnace<8, true>)
+                           : (h->max_plies <= 4 ? k_furnace<4, false> : k_furnace<8, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, stream, h->d_types, h->n_types,
                        h->d_tables, sp, block, mean, var);
     HIP_TRY(hipGetLastError());
@@ -1045,6 +1092,7 @@ thread_local OpTally* g_tally = nullptr;
 }
 
 struct HostTab {
+    static constexpr bool kMigration = true;
     const float4* p;
     float4 operator()(int i) const { return p[i]; }
 };
@@ -1059,8 +1107,8 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
     if (mode != 0 && !xi) return fail(BYSDF_ERR_INVALID_ARG, "modes 1 and 2 need xi");
     if (int rc = validate(*p, 0)) return rc;
     TypeRec rec = make_rec(*p);
-    std::vector<float4> tb(p->tex_size);
-    for (int i = 0; i < p->tex_size; ++i)
+    std::vector<float4> tb(rec.table_texels);
+    for (int i = 0; i < rec.table_texels; ++i)
         tb[i] = make_float4(table[3 * i], table[3 * i + 1], table[3 * i + 2], 0.0f);
     HostTab tab{tb.data()};
     Derived<CD, CF> P = derive_counted(rec);

@@ -12,11 +12,13 @@
 #pragma once
 
 #include "bysdf_math.hpp"
+#include "philox.hpp"
 
 namespace bysdf {
 
 constexpr int kMaxPlies = 8;
 constexpr int kMaxNodes = 16;
+constexpr int kMaxMigTables = 8;  // fiber tables of one type with migration
 
 // flag bits (public numbering; see include/bysdf.h)
 constexpr uint32_t F_PASS_THROUGH = 1u << 0;
@@ -34,17 +36,25 @@ template <class G, class S> struct Derived {
     S ax, ay, eta, kS, B, r, sigma_t, rho_p, rho_f, dP;
     S alb[3];
     S rp_s, Rpc_s;
+    // fiber migration (Sec. 3.5.2): n_mig tables switched per period of
+    // mig_period along the ply, blended over the period's last mig_blend
+    int n_mig;
+    uint32_t mig_seed;
+    double mig_period, mig_blend;
 };
 
 // Per-type record resident in device memory: the primary parameters and
 // everything derived from them, ready to be read with scalar loads when a
 // wavefront serves one type.
 struct TypeRec {
-    int32_t n_plies, K, n_iter, tex_size, table_off, pad0;
+    int32_t n_plies, K, n_iter, tex_size, table_off, table_texels;  // table_texels: all migration tables
     // primary parameters
     double rp, Rpc, ply_twist, fiber_twist, rho_f_geom;  // rho_f_geom = r_f / r_p
     double beta, aniso, eta;
     float albedo[3], k_spec, B, r, sigma_t, ply_density, fiber_density, shadow_hw;
+    int32_t mig_tables;
+    uint32_t mig_seed;
+    double mig_period, mig_blend, mig_spread;
     Derived<double, float> d;
 };
 
@@ -76,6 +86,10 @@ __host__ __device__ inline void fill_derived(TypeRec& t)
     for (int c = 0; c < 3; ++c) d.alb[c] = t.albedo[c];
     d.rp_s = (float)t.rp;
     d.Rpc_s = (float)t.Rpc;
+    d.n_mig = t.mig_tables > 1 ? t.mig_tables : 1;
+    d.mig_seed = t.mig_seed;
+    d.mig_period = t.mig_period;
+    d.mig_blend = t.mig_blend;
 }
 
 __host__ __device__ inline Derived<double, float> derive(const TypeRec& t) { return t.d; }
@@ -258,34 +272,76 @@ __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, flo
 template <class G> __host__ __device__ inline G floor_g(const G& x);
 template <> __host__ __device__ inline double floor_g<double>(const double& x) { return floor(x); }
 
-// Ply frame on the disc with phase (cth, sth) at 2D outward normal (n2x,
+// Fiber-migration draws (Sec. 3.5.2): Philox4x32-10 with key (seed, "FIBR").
+// Table of ply k in period q: counter (q low, q high, k, "SELT"), first word
+// modulo the number of tables.
+__host__ __device__ inline int mig_table(uint32_t seed, int n_mig, int64_t q, int k)
+{
+    uint32_t o[4];
+    const uint64_t uq = (uint64_t)q;
+    rng::philox4x32_10((uint32_t)(uq & 0xffffffffu), (uint32_t)(uq >> 32), (uint32_t)k, 0x53454c54u, seed,
+                       0x46494252u, o);
+    return (int)(o[0] % (uint32_t)n_mig);
+}
+
+// Periodic linear interpolation between the texel centres of the table at
+// texel offset base, at a phase given in turns.
+template <class G, class Tab>
+__host__ __device__ inline void table_at(const Tab& tab, int Nu, int base, const G& turns, G& dn, G& rh,
+                                         G& gf)
+{
+    G fl = floor_g(turns);
+    G x = (turns - fl) * G((double)Nu) - G(0.5);
+    G xf = floor_g(x);
+    G f = x - xf;
+    // texel index in [0, Nu): x lies in [-1/2, Nu - 1/2) for a finite phase;
+    // anything else (a non-finite phase) reads texel 0
+    double xi0 = val(xf) < 0.0 ? val(xf) + Nu : val(xf);
+    int i0 = (xi0 >= 0.0 && xi0 < (double)Nu) ? (int)xi0 : 0;
+    int i1 = i0 + 1 == Nu ? 0 : i0 + 1;
+    float4 t0 = tab(base + i0), t1 = tab(base + i1);
+    G omf = G(1) - f;
+    dn = omf * G((double)t0.x) + f * G((double)t1.x);
+    rh = omf * G((double)t0.y) + f * G((double)t1.y);
+    gf = omf * G((double)t0.z) + f * G((double)t1.z);
+}
+
+// Ply frame on the disc k with phase (cth, sth) at 2D outward normal (n2x,
 // n2y) and yarn height z, then the fiber frame from the 1D fiber table
 // (Sec. 3.5.1): normal rotated about the ply tangent by dn, tangent tilted
-// against the ply twist by atan(rho_hat tan(alpha_f)).
+// against the ply twist by atan(rho_hat tan(alpha_f)).  With fiber
+// migration (Sec. 3.5.2) the table is the one drawn for ply k in the
+// current period of the ply arc length, blended linearly into the next
+// period's table over the period's last mig_blend share.
 template <class G, class S, class Tab>
-__host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Tab& tab, G cth, G sth,
+__host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Tab& tab, G cth, G sth, int k,
                                                 G n2x, G n2y, G z, G* gf_out, G* a_out)
 {
     V3<G> tp = mk3<G>(-P.slope * sth * P.tnorm_inv, P.slope * cth * P.tnorm_inv, P.tnorm_inv);
     V3<G> n23 = mk3<G>(n2x, n2y, G(0));
     V3<G> np = normalize(n23 - tp * dot(n23, tp));
     G a = atan2_(cth * n2y - sth * n2x, cth * n2x + sth * n2y);
-    G turns = a * G(kInvTwoPi) + P.wf_turns * (z * P.vply_scale);
-    // periodic linear interpolation between texel centres
-    G fl = floor_g(turns);
-    G x = (turns - fl) * G((double)P.Nu) - G(0.5);
-    G xf = floor_g(x);
-    G f = x - xf;
-    // texel index in [0, Nu): x lies in [-1/2, Nu - 1/2) for a finite phase;
-    // anything else (a non-finite phase) reads texel 0
-    double xi0 = val(xf) < 0.0 ? val(xf) + P.Nu : val(xf);
-    int i0 = (xi0 >= 0.0 && xi0 < (double)P.Nu) ? (int)xi0 : 0;
-    int i1 = i0 + 1 == P.Nu ? 0 : i0 + 1;
-    float4 t0 = tab(i0), t1 = tab(i1);
-    G omf = G(1) - f;
-    G dn = omf * G((double)t0.x) + f * G((double)t1.x);
-    G rh = omf * G((double)t0.y) + f * G((double)t1.y);
-    G gfv = omf * G((double)t0.z) + f * G((double)t1.z);
+    const G vply = z * P.vply_scale;
+    G turns = a * G(kInvTwoPi) + P.wf_turns * vply;
+    G dn, rh, gfv;
+    if (Tab::kMigration && P.n_mig > 1) {
+        G t = vply / G(P.mig_period);
+        G fq = floor_g(t);
+        G ph = t - fq;
+        const int64_t q = (int64_t)val(fq);
+        const double b = P.mig_blend;
+        G w = (b > 0.0 && val(ph) > 1.0 - b) ? (ph - G(1.0 - b)) / G(b) : G(0);
+        const int m0 = mig_table(P.mig_seed, P.n_mig, q, k), m1 = mig_table(P.mig_seed, P.n_mig, q + 1, k);
+        G d0, r0, g0, d1, r1, g1;
+        table_at(tab, P.Nu, m0 * P.Nu, turns, d0, r0, g0);
+        table_at(tab, P.Nu, m1 * P.Nu, turns, d1, r1, g1);
+        G omw = G(1) - w;
+        dn = omw * d0 + w * d1;
+        rh = omw * r0 + w * r1;
+        gfv = omw * g0 + w * g1;
+    } else {
+        table_at(tab, P.Nu, 0, turns, dn, rh, gfv);
+    }
     V3<G> bp = cross(tp, np);
     G sdn, cdn;
     sincos_turns_g(dn * G(kInvTwoPi), &sdn, &cdn);
@@ -403,7 +459,7 @@ __host__ __device__ inline void state_after_plies(const Derived<G, S>& P, const 
     for (int k = 0; k < MP; ++k)
         if (k == X.ph.ks) { cth = X.ph.cth[k]; sth = X.ph.sth[k]; }
     G gft;
-    X.fx = fiber_frame(P, tab, cth, sth, X.ph.n2x, X.ph.n2y, X.ph.vhit, &gft, &X.a);
+    X.fx = fiber_frame(P, tab, cth, sth, X.ph.ks, X.ph.n2x, X.ph.n2y, X.ph.vhit, &gft, &X.a);
     X.fxs = narrowf<S>(X.fx);
     // shadowing in the geometry scalar: a mostly occluded window leaves a
     // small visible share that single precision cannot resolve
@@ -539,7 +595,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
             G nyx = y2x - cxl, nyy = y2y - cyl;
             G ninv = rsqrt_(nyx * nyx + nyy * nyy);
             r.att = exp_(-P.sigma_t * Narrow<S>::from(ell) * S(float(N)));
-            r.fy = fiber_frame<G, S, Tab>(P, tab, cthl, sthl, nyx * ninv, nyy * ninv, zy, nullptr,
+            r.fy = fiber_frame<G, S, Tab>(P, tab, cthl, sthl, jl, nyx * ninv, nyy * ninv, zy, nullptr,
                                           nullptr);
             r.y = mk3<G>(y2x, y2y, zy);
         }

@@ -80,6 +80,7 @@ inline Derived<CD, CF> derive_counted(const TypeRec& t)
     d.sigma_t = f.sigma_t; d.rho_p = f.rho_p; d.rho_f = f.rho_f; d.dP = f.dP;
     for (int c = 0; c < 3; ++c) d.alb[c] = f.alb[c];
     d.rp_s = f.rp_s; d.Rpc_s = f.Rpc_s;
+    d.n_mig = f.n_mig; d.mig_seed = f.mig_seed; d.mig_period = f.mig_period; d.mig_blend = f.mig_blend;
     return d;
 }
 

@@ -6,6 +6,16 @@
 #include "bysdf_model.hpp"
 #include "yarn_tube.hpp"
 
+// Fiber tables in device memory (or LDS).  MIG: the kernel may serve types
+// with fiber migration (several tables per type); kernels instantiated
+// without it skip that code, which keeps their register allocation.
+template <bool MIG> struct TabPtrT {
+    static constexpr bool kMigration = MIG;
+    const float4* p;
+    __host__ __device__ float4 operator()(int i) const { return p[i]; }
+};
+using TabPtr = TabPtrT<true>;
+
 // record a thread-local error message and return `code`
 int bysdf_set_error(int code, const char* msg);
 

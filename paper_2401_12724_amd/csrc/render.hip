@@ -245,10 +245,6 @@ __global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_exten
     }
 }
 
-struct TabPtr {
-    const float4* p;
-    __host__ __device__ float4 operator()(int i) const { return p[i]; }
-};
 
 // far field (Eq. 7, W = 1): mean value and mean pdf over n_h strata of h
 template <int MP>

@@ -166,3 +166,17 @@ def test_op_counts_of_the_kernels_formulation(L):
     assert L.bysdf_count_ops(arr, tab.ctypes.data_as(C.c_void_p), 512, ptrs[0], ptrs[1], ptrs[2],
                              ptrs[3], None, ptrs[5], 2, c.ctypes.data_as(C.c_void_p)) \
         == bysdf.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("field,value", [
+    ("mig_tables", 9), ("mig_tables", -1), ("mig_period", 0.0), ("mig_blend", 1.5),
+    ("mig_spread", 1.0), ("mig_spread", -0.1), ("tex_size", 4096),
+])
+def test_invalid_migration_params_rejected(L, field, value):
+    p = workloads.default_params(mig_tables=8)
+    p[field] = value
+    arr = bysdf.params_array([p])
+    h = C.c_void_p()
+    assert L.bysdf_types_create(arr, 1, C.byref(h), None) == bysdf.ERR_INVALID_PARAM
+    assert h.value is None
+    assert "mig" in L.bysdf_last_error().decode()
