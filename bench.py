@@ -328,6 +328,25 @@ def _fwd_bwd(torch, bysdf, W):
             "fwd_bwd_over_fwd_time": b_ms / f_ms}
 
 
+def _migration(torch, bysdf, W, P, qd, q, base_ms):
+    """The per-block workload with fiber migration on every type (4 tables,
+    period 3 yarn radii, blend 0.25, spread 0.4): the fused eval + sample."""
+    Pm = [dict(p, mig_tables=4, mig_period=3.0, mig_blend=0.25, mig_spread=0.4, mig_seed=11)
+          for p in P]
+    T = bysdf.bysdf_types_create(Pm)
+    n = int(qd["h"].numel())
+    out = (bysdf.alloc_eval_out(n), bysdf.alloc_sample_out(n))
+    f = lambda: bysdf.bysdf_eval_sample(T, qd, out)
+    f()
+    torch.cuda.synchronize()
+    ms = _timed(torch, f, 5)
+    ops = _op_counts(bysdf, T, Pm, q, 2).sum()
+    return {"queries": n, "tables_per_type": 4, "eval_sample_ms": ms,
+            "queries_per_s": n / (ms * 1e-3), "vs_without": base_ms / ms,
+            "ops_per_query": ops,
+            "valu_frac": ops * n / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS}
+
+
 def _weave_render(torch, bysdf, W, spp=4):
     """The plain weave (256 + 256 B-spline yarns, 524,288 spans) seen by the
     grazing 1920 x 1080 camera: primary-ray intersection of every pixel
@@ -526,6 +545,7 @@ def main():
     if not args.no_extras:
         eval_qps = N / (unfused["eval"] * 1e-3)
         del ev, sv
+        out["migration"] = _migration(torch, bysdf, W, P, qd, q, ktime["eval_sample"])
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
         out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
         out["weave"] = _weave_render(torch, bysdf, W)

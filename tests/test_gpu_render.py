@@ -142,3 +142,16 @@ def test_deterministic_and_batching(torch_cuda):
     assert torch.equal(a, b)
     # the same paths: only the order of the per-pixel sums differs
     assert torch.allclose(a, c, rtol=1e-5, atol=1e-7)
+
+
+def test_small_weave_with_fiber_migration(torch_cuda):
+    """Yarns whose fiber tables switch and blend along the ply (Sec. 3.5.2)."""
+    torch = torch_cuda
+    scene = W.weave(12, 12, 0.15, 0.05, 4)
+    P = [W.default_params(mig_tables=4, mig_period=3.0, mig_blend=0.25, mig_spread=0.4,
+                          mig_seed=11)]
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=96, height=72)
+    rs = _settings(cam, (36, 24, 24, 24))
+    g, o, sq, _ = _render_both(torch, scene, P, rs)
+    _check(g, o, sq, rs["spp"], "migration")
+    _paths_equal(torch, scene, P, _settings(cam, (24, 12, 48, 48)), "migration", 0.85)
