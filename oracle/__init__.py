@@ -114,6 +114,13 @@ def lib():
                                   fp, fp, dp, dp, C.c_int]
         L.orc_eval_far.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, C.c_double, ip, fp,
                                    fp, fp, fp, dp, C.c_int]
+        L.orc_eval_multi.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp, fp,
+                                     fp, fp, fp, fp, fp, dp, up, C.c_int]
+        L.orc_sample_multi.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp,
+                                       fp, fp, fp, fp, fp, fp, fp, dp, up, C.c_int]
+        L.orc_footprint.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                    dp, dp]
+        L.orc_footprint.restype = C.c_int32
         L.orc_grad_fd.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp,
                                   C.c_double, dp, dp, C.c_int]
         L.orc_philox4x32_10.argtypes = [up, up, up]
@@ -285,6 +292,55 @@ def eval_far(ts, q: dict, n_h: int = 4, zeta: float = 0.5, nthreads: int = 0):
                        _ptr(u, C.c_float), _ptr(v, C.c_float), _ptr(wi, C.c_float),
                        _ptr(wo, C.c_float), _ptr(out, C.c_double), nthreads)
     return out
+
+
+def eval_multi(ts, q: dict, n_max: int = 4, nthreads: int = 0):
+    """Multi-scale BYSDF (Sec. 4.2, Eq. 8-11) at wo over the footprint
+    (h1, h, h2) with strata offset zeta.  Returns (out[n,13], flags[n])
+    laid out as eval."""
+    ts = _types(ts)
+    n = len(q["h"])
+    out = np.zeros((n, 13), dtype=np.float64)
+    flags = np.zeros(n, dtype=np.uint32)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    a = [_f32(q[k]) for k in ("h", "h1", "h2", "zeta", "u", "v", "wi", "wo")]
+    sh = _f32(q["shift"]) if q.get("shift") is not None else None
+    rc = lib().orc_eval_multi(ts.structs, ts._tp, len(ts), n, n_max, _ptr(tpe, C.c_int32),
+                              *[_ptr(x, C.c_float) for x in a], _ptr(sh, C.c_float),
+                              _ptr(out, C.c_double), _ptr(flags, C.c_uint32), nthreads)
+    if rc != 0:
+        raise ValueError("n_max out of range")
+    return out, flags
+
+
+def sample_multi(ts, q: dict, n_max: int = 4, nthreads: int = 0):
+    """Multi-scale sampler: xi_s picks a stratum with probability W / sum W.
+    Returns (out[n,13], flags[n]): wo(3) weight(3) pdf exit(3) lobe node
+    stratum."""
+    ts = _types(ts)
+    n = len(q["h"])
+    out = np.zeros((n, 13), dtype=np.float64)
+    flags = np.zeros(n, dtype=np.uint32)
+    tpe = np.ascontiguousarray(q["type"], dtype=np.int32)
+    a = [_f32(q[k]) for k in ("h", "h1", "h2", "zeta", "xi_s", "u", "v", "wi", "xi")]
+    sh = _f32(q["shift"]) if q.get("shift") is not None else None
+    rc = lib().orc_sample_multi(ts.structs, ts._tp, len(ts), n, n_max, _ptr(tpe, C.c_int32),
+                                *[_ptr(x, C.c_float) for x in a], _ptr(sh, C.c_float),
+                                _ptr(out, C.c_double), _ptr(flags, C.c_uint32), nthreads)
+    if rc != 0:
+        raise ValueError("n_max out of range")
+    return out, flags
+
+
+def footprint(h0, h1, h2, zeta, n_max: int = 4):
+    """Strata of one footprint: (offsets, weights)."""
+    hs = np.zeros(16)
+    ws = np.zeros(16)
+    k = lib().orc_footprint(float(h0), float(h1), float(h2), float(zeta), n_max,
+                            _ptr(hs, C.c_double), _ptr(ws, C.c_double))
+    if k < 0:
+        raise ValueError("invalid footprint")
+    return hs[:k], ws[:k]
 
 
 def grad_fd(ts, q: dict, gE, rel_step: float = 1e-6, nthreads: int = 0):

@@ -606,8 +606,9 @@ typedef struct {
 
 static double frac(double x) { return x - floor(x); }
 
-static void geom_x(const orc_params* p, const double* tab, double h, double u, double v,
-                   v3 wi, const double* shift, xgeom* g)
+/* The hit at x: ply hit, fiber frame and the two shadowing terms. */
+static void geom_hit(const orc_params* p, const double* tab, double h, double u, double v, v3 wi,
+                     xgeom* g)
 {
     memset(g, 0, sizeof(*g));
     trace_plies(p, h, u, v, wi, &g->ph);
@@ -624,7 +625,16 @@ static void geom_x(const orc_params* p, const double* tab, double h, double u, d
     double gpr = orc_ply_shadow_raw(p, a, phi);
     g->Gp = 1.0 - p->ply_density * (1.0 - gpr);
     g->Gf = 1.0 - p->fiber_density * (1.0 - gft);
+}
 
+/* Everything else that depends on wi only, from the frame at x: lobe
+ * weights and the forward quadrature nodes. */
+static void geom_shade(const orc_params* p, const double* tab, v3 wi, const double* shift,
+                       xgeom* g)
+{
+    if (g->ph.pass) return;
+    plyhit* ph = &g->ph;
+    int ks = ph->kstar;
     double ax = p->beta, ay = p->beta * p->aniso, eta = p->eta;
     g->mu_i = vdot(wi, g->fx.n);
     if (fabs(g->mu_i) < g_margin_shade) ph->flags |= ORC_NEARTIE;
@@ -739,6 +749,13 @@ static void geom_x(const orc_params* p, const double* tab, double h, double u, d
         fiber_frame(p, tab, ph->th[jL], jL, nyx / nyl, nyy / nyl, zy, &nd->fy, NULL, NULL);
         nd->y = mk(y2x, y2y, zy);
     }
+}
+
+static void geom_x(const orc_params* p, const double* tab, double h, double u, double v,
+                   v3 wi, const double* shift, xgeom* g)
+{
+    geom_hit(p, tab, h, u, v, wi, g);
+    geom_shade(p, tab, wi, shift, g);
 }
 
 /* ------------------------------------------------------------------ */
@@ -904,6 +921,9 @@ uint32_t orc_eval_query(const orc_params* p, const double* tab, double h, double
  * the body lobes; the forward lobes also pick one quadrature node.
  * out: wo(3) weight(3) pdf exit(3) lobe node.  Lobes: 0 x-specular,
  * 1 y-specular, 2 x-body, 3 y-body, 4 pass-through. */
+static int draw_from(const orc_params* p, const xgeom* gp, v3 wi, const double xi[3], v3* wo_out,
+                     double out[12], uint32_t* fl);
+
 static void sample_one(const orc_params* p, const double* tab, double h, double u, double v,
                        v3 wi, const double xi[3], const double* shift, double out[12],
                        uint32_t* fl)
@@ -923,6 +943,27 @@ static void sample_one(const orc_params* p, const double* tab, double h, double 
         *fl = f;
         return;
     }
+    v3 wo;
+    if (!draw_from(p, &g, wi, xi, &wo, out, &f)) { *fl = f | ORC_SAMPLE_FAIL; return; }
+    double e[13];
+    lobes(p, &g, wi, wo, e, &f);
+    double pdf = e[11];
+    if (!(pdf > 0.0)) { *fl = f | ORC_SAMPLE_FAIL; return; }
+    out[0] = wo.x; out[1] = wo.y; out[2] = wo.z;
+    for (int c = 0; c < 3; ++c) out[3 + c] = e[c] / pdf;
+    out[6] = pdf;
+    *fl = f;
+}
+
+/* The draw of sample_one from the state at x of a hit (not a
+ * pass-through): lobe and node from xi[0], the direction from xi[1],
+ * xi[2].  Sets the exit point, lobe and node in out[7..11] and returns 1
+ * with the unit direction in *wo_out, or 0 when no valid direction. */
+static int draw_from(const orc_params* p, const xgeom* gp, v3 wi, const double xi[3], v3* wo_out,
+                     double out[12], uint32_t* fl)
+{
+    const xgeom g = *gp;
+    uint32_t f = *fl;
     double ax = p->beta, ay = p->beta * p->aniso, eta = p->eta;
     double cum[3];
     cum[0] = g.w[0];
@@ -993,16 +1034,10 @@ static void sample_one(const orc_params* p, const double* tab, double h, double 
     out[7] = ex.x; out[8] = ex.y; out[9] = ex.z;
     out[10] = lobe;
     out[11] = node;
-    if (!ok) { *fl = f | ORC_SAMPLE_FAIL; return; }
-    wo = vnorm(wo);
-    double e[13];
-    lobes(p, &g, wi, wo, e, &f);
-    double pdf = e[11];
-    if (!(pdf > 0.0)) { *fl = f | ORC_SAMPLE_FAIL; return; }
-    out[0] = wo.x; out[1] = wo.y; out[2] = wo.z;
-    for (int c = 0; c < 3; ++c) out[3 + c] = e[c] / pdf;
-    out[6] = pdf;
     *fl = f;
+    if (!ok) return 0;
+    *wo_out = vnorm(wo);
+    return 1;
 }
 
 /* One query of the sampler (single type, its table): out[12] as orc_sample. */
@@ -1115,6 +1150,285 @@ int orc_eval_far(const orc_params* types, const double* const* tables, int32_t n
         for (int c = 0; c < 3; ++c) out_E[3 * i + c] = acc[c] / n_h;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* multi-scale BYSDF (Sec. 4.2, Eq. 8-11; footprint as in Sec. 5.3)    */
+/* ------------------------------------------------------------------ */
+
+/* The pixel footprint on the yarn: offsets h1 <= h0 <= h2 from the ray
+ * differentials, n strata of [h1, h2] at the shared offset zeta, each with
+ * the weight W of a tent that is 1 at h0 and 0 at h1 and h2 (the weight
+ * falls with the distance to h0).  The number of strata grows with the
+ * covered share of the yarn, n = ceil(n_max (h2 - h1) / 2) in [1, n_max];
+ * a single stratum carries weight 1.  Stratum offsets are rounded to FP32,
+ * the precision of a query's h. */
+typedef struct {
+    int n;
+    double h[ORC_MAX_STRATA], w[ORC_MAX_STRATA];
+    double wsum;
+} footprint;
+
+static int footprint_make(double h0, double h1, double h2, double zeta, int n_max, footprint* fp)
+{
+    if (!(h1 >= -1.0 && h1 <= h0 && h0 <= h2 && h2 <= 1.0) || !(zeta >= 0.0 && zeta < 1.0))
+        return -1;
+    int n = (int)ceil(n_max * (h2 - h1) * 0.5);
+    n = n < 1 ? 1 : (n > n_max ? n_max : n);
+    fp->n = n;
+    fp->wsum = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double hj = (double)(float)fma(h2 - h1, (j + zeta) / n, h1);
+        double w = 1.0;
+        if (n > 1) {
+            if (hj < h0)
+                w = 1.0 - (h0 - hj) / (h0 - h1);
+            else if (h2 > h0)
+                w = 1.0 - (hj - h0) / (h2 - h0);
+        }
+        fp->h[j] = hj;
+        fp->w[j] = w;
+        fp->wsum += w;
+    }
+    return 0;
+}
+
+/* Aggregated geometry of the footprint (Eq. 9-11): the W-weighted means of
+ * the fiber normal, the fiber tangent and the fiber shadowing G_f over the
+ * strata that hit a ply.  The mean normal is normalised, the mean tangent
+ * made orthogonal to it and normalised; a single contributing stratum
+ * keeps its own frame.  Returns 0 when no stratum of positive weight hits
+ * a ply. */
+static int footprint_geometry(const orc_params* p, const double* tab, double u, double v, v3 wi,
+                              const footprint* fp, frame* F, double* Gm, uint32_t* flags)
+{
+    v3 sn = mk(0, 0, 0), st = mk(0, 0, 0);
+    double sg = 0.0, sw = 0.0;
+    frame first;
+    int have = 0;
+    double g1 = 0.0;
+    for (int j = 0; j < fp->n; ++j) {
+        xgeom g;
+        geom_hit(p, tab, fp->h[j], u, v, wi, &g);
+        *flags |= g.ph.flags & ~ORC_PASS_THROUGH;
+        if (g.ph.pass || !(fp->w[j] > 0.0)) continue;
+        sn = vadd(sn, vscl(g.fx.n, fp->w[j]));
+        st = vadd(st, vscl(g.fx.t, fp->w[j]));
+        sg += fp->w[j] * g.Gf;
+        sw += fp->w[j];
+        if (!have) { first = g.fx; g1 = g.Gf; }
+        ++have;
+    }
+    if (!have) return 0;
+    if (have == 1) {
+        /* one stratum: its own frame and shadowing, unrounded */
+        *F = first;
+        *Gm = g1;
+        return 1;
+    }
+    *Gm = sg / sw;
+    double ln = vlen(sn);
+    if (ln < 1e-6 * sw) *flags |= ORC_ILLCOND;
+    if (!(ln > 1e-12 * sw)) {
+        *F = first;
+        return 1;
+    }
+    v3 n = vscl(sn, 1.0 / ln);
+    v3 t = vsub(st, vscl(n, vdot(st, n)));
+    double lt = vlen(t);
+    if (lt < 1e-6 * sw) *flags |= ORC_ILLCOND;
+    if (!(lt > 1e-12 * sw)) {
+        *F = first;
+        return 1;
+    }
+    F->n = n;
+    F->t = vscl(t, 1.0 / lt);
+    F->b = vcross(F->n, F->t);
+    return 1;
+}
+
+/* The near-field model at one stratum with the footprint's aggregated
+ * frame, shadowing and roughness (Eq. 8 integrand): the ply hit and the
+ * chords through the plies are the stratum's own. */
+static int stratum_state(const orc_params* pm, const double* tab, double hj, double u, double v,
+                         v3 wi, const frame* F, double Gm, const double* shift, xgeom* g,
+                         uint32_t* flags)
+{
+    geom_hit(pm, tab, hj, u, v, wi, g);
+    if (g->ph.pass) return 0;
+    g->fx = *F;
+    g->Gf = Gm;
+    geom_shade(pm, tab, wi, shift, g);
+    *flags |= g->ph.flags & ~ORC_PASS_THROUGH;
+    return 1;
+}
+
+static int footprint_inputs_ok(double h0, double h1, double h2, double zeta)
+{
+    return isfinite(h1) && isfinite(h2) && isfinite(zeta) && h1 >= -1.0 && h1 <= h0 && h0 <= h2 &&
+           h2 <= 1.0 && zeta >= 0.0 && zeta < 1.0;
+}
+
+/* f_multi of Eq. 8 at wo with the tent weights: out[13] as eval_one, each
+ * entry the W-weighted mean over the strata (pass-through strata count
+ * with value 0).  The specular roughness is beta_multi = beta + (h2 - h1)/2
+ * along the fiber (the linear widening of Sec. 4.2 normalised by the
+ * full-range C = 2 of the far field). */
+static void eval_multi_one(const orc_params* p, const double* tab, double h0, double h1,
+                           double h2, double zeta, int n_max, double u, double v, v3 wi, v3 wo,
+                           const double* shift, double out[13], uint32_t* fl)
+{
+    for (int i = 0; i < 13; ++i) out[i] = 0.0;
+    uint32_t bad = check_dir(wi) | check_dir(wo);
+    if (!isfinite(h0) || !isfinite(u) || !isfinite(v) || !footprint_inputs_ok(h0, h1, h2, zeta))
+        bad |= ORC_BAD_INPUT;
+    if (bad) { *fl = bad; return; }
+    footprint fp;
+    footprint_make(h0, h1, h2, zeta, n_max, &fp);
+    orc_params pm = *p;
+    pm.beta = p->beta + (h2 - h1) * 0.5;
+    uint32_t f = 0;
+    frame F;
+    double Gm;
+    if (!footprint_geometry(&pm, tab, u, v, wi, &fp, &F, &Gm, &f)) {
+        *fl = f | ORC_PASS_THROUGH;
+        return;
+    }
+    for (int j = 0; j < fp.n; ++j) {
+        xgeom g;
+        if (!stratum_state(&pm, tab, fp.h[j], u, v, wi, &F, Gm, shift, &g, &f)) continue;
+        double e[13];
+        lobes(&pm, &g, wi, wo, e, &f);
+        for (int i = 0; i < 12; ++i) out[i] += fp.w[j] * e[i];
+    }
+    for (int i = 0; i < 12; ++i) out[i] /= fp.wsum;
+    *fl = f;
+}
+
+/* The multi-scale sampler: a stratum drawn with probability W / sum W from
+ * xi_s, a pass-through stratum passes the ray through (lobe 4), otherwise
+ * the stratum's aggregated state draws the direction as sample_one does,
+ * and the weight and pdf are those of f_multi at it.  out[13]: wo(3)
+ * weight(3) pdf exit(3) lobe node stratum. */
+static void sample_multi_one(const orc_params* p, const double* tab, double h0, double h1,
+                             double h2, double zeta, double xis, int n_max, double u, double v,
+                             v3 wi, const double xi[3], const double* shift, double out[13],
+                             uint32_t* fl)
+{
+    for (int i = 0; i < 13; ++i) out[i] = 0.0;
+    uint32_t bad = check_dir(wi);
+    if (!isfinite(h0) || !isfinite(u) || !isfinite(v) || !footprint_inputs_ok(h0, h1, h2, zeta) ||
+        !(xis >= 0.0 && xis < 1.0))
+        bad |= ORC_BAD_INPUT;
+    if (bad) { *fl = bad; out[10] = -1; return; }
+    footprint fp;
+    footprint_make(h0, h1, h2, zeta, n_max, &fp);
+    orc_params pm = *p;
+    pm.beta = p->beta + (h2 - h1) * 0.5;
+    uint32_t f = 0;
+    /* the stratum */
+    int s = fp.n - 1;
+    double cum = 0.0, xw = xis * fp.wsum;
+    for (int j = 0; j < fp.n; ++j) {
+        cum += fp.w[j];
+        if (j < fp.n - 1 && fabs(xw - cum) < g_margin_xi * fp.wsum) f |= ORC_NEAR_LOBE_BOUNDARY;
+        if (xw < cum) { s = j; break; }
+    }
+    out[12] = s;
+    frame F;
+    double Gm;
+    int any = footprint_geometry(&pm, tab, u, v, wi, &fp, &F, &Gm, &f);
+    xgeom g;
+    if (!any || !stratum_state(&pm, tab, fp.h[s], u, v, wi, &F, Gm, shift, &g, &f)) {
+        out[0] = -wi.x; out[1] = -wi.y; out[2] = -wi.z;
+        out[3] = out[4] = out[5] = 1.0;
+        out[10] = 4;
+        *fl = f | ORC_PASS_THROUGH;
+        return;
+    }
+    v3 wo;
+    if (!draw_from(&pm, &g, wi, xi, &wo, out, &f)) { *fl = f | ORC_SAMPLE_FAIL; return; }
+    double E[3] = {0, 0, 0}, pdf = 0.0;
+    for (int j = 0; j < fp.n; ++j) {
+        xgeom gj;
+        if (!stratum_state(&pm, tab, fp.h[j], u, v, wi, &F, Gm, shift, &gj, &f)) continue;
+        double e[13];
+        lobes(&pm, &gj, wi, wo, e, &f);
+        for (int c = 0; c < 3; ++c) E[c] += fp.w[j] * e[c];
+        pdf += fp.w[j] * e[11];
+    }
+    for (int c = 0; c < 3; ++c) E[c] /= fp.wsum;
+    pdf /= fp.wsum;
+    if (!(pdf > 0.0)) { *fl = f | ORC_SAMPLE_FAIL; return; }
+    out[0] = wo.x; out[1] = wo.y; out[2] = wo.z;
+    for (int c = 0; c < 3; ++c) out[3 + c] = E[c] / pdf;
+    out[6] = pdf;
+    *fl = f;
+}
+
+int orc_eval_multi(const orc_params* types, const double* const* tables, int32_t n_types,
+                   int64_t n, int32_t n_max, const int32_t* type, const float* h, const float* h1,
+                   const float* h2, const float* zeta, const float* u, const float* v,
+                   const float* wi, const float* wo, const float* shift, double* out,
+                   uint32_t* flags, int nthreads)
+{
+    if (n_max < 1 || n_max > ORC_MAX_STRATA) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t t = type[i];
+        if (!valid_type(t, n_types)) {
+            for (int c = 0; c < 13; ++c) out[13 * i + c] = 0.0;
+            flags[i] = ORC_BAD_INPUT;
+            continue;
+        }
+        double sh[2];
+        if (shift) { sh[0] = shift[i]; sh[1] = shift[n + i]; }
+        eval_multi_one(&types[t], tables[t], h[i], h1[i], h2[i], zeta[i], n_max, u[i], v[i], Q_WI(i),
+                       Q_WO(i), shift ? sh : NULL, &out[13 * i], &flags[i]);
+    }
+    return 0;
+}
+
+int orc_sample_multi(const orc_params* types, const double* const* tables, int32_t n_types,
+                     int64_t n, int32_t n_max, const int32_t* type, const float* h,
+                     const float* h1, const float* h2, const float* zeta, const float* xi_s,
+                     const float* u, const float* v, const float* wi, const float* xi,
+                     const float* shift, double* out, uint32_t* flags, int nthreads)
+{
+    if (n_max < 1 || n_max > ORC_MAX_STRATA) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t t = type[i];
+        if (!valid_type(t, n_types)) {
+            for (int c = 0; c < 13; ++c) out[13 * i + c] = 0.0;
+            out[13 * i + 10] = -1;
+            flags[i] = ORC_BAD_INPUT;
+            continue;
+        }
+        double x3[3] = {xi[i], xi[n + i], xi[2 * n + i]};
+        double sh[2];
+        if (shift) { sh[0] = shift[i]; sh[1] = shift[n + i]; }
+        sample_multi_one(&types[t], tables[t], h[i], h1[i], h2[i], zeta[i], xi_s[i], n_max, u[i],
+                         v[i], Q_WI(i), x3, shift ? sh : NULL, &out[13 * i], &flags[i]);
+    }
+    return 0;
+}
+
+/* Strata of one footprint (test access): offsets and weights, returns n. */
+int orc_footprint(double h0, double h1, double h2, double zeta, int32_t n_max, double* hs,
+                  double* ws)
+{
+    if (n_max < 1 || n_max > ORC_MAX_STRATA) return -1;
+    footprint fp;
+    if (footprint_make(h0, h1, h2, zeta, n_max, &fp)) return -1;
+    for (int j = 0; j < fp.n; ++j) { hs[j] = fp.h[j]; ws[j] = fp.w[j]; }
+    return fp.n;
 }
 
 /* theta index -> parameter slot */

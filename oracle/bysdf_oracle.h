@@ -25,6 +25,7 @@ extern "C" {
 
 #define ORC_MAX_PLIES 8
 #define ORC_MAX_NODES 16
+#define ORC_MAX_STRATA 16
 
 /* Per-query flag bits (same numbering as the library's public flags). */
 #define ORC_PASS_THROUGH      (1u << 0)  /* ray misses every implicit ply (Sec. 3.4) */
@@ -115,6 +116,26 @@ int orc_eval_far(const orc_params* types, const double* const* tables, int32_t n
                  int64_t n, int32_t n_h, double zeta, const int32_t* type,
                  const float* u, const float* v, const float* wi, const float* wo,
                  double* out_E, int nthreads);
+
+/* Multi-scale BYSDF (Sec. 4.2, Eq. 8-11): per query the footprint
+ * h1 <= h <= h2 in [-1, 1] and the strata offset zeta in [0, 1); up to
+ * n_max (1..ORC_MAX_STRATA) strata with tent weights around h.  Eval: out
+ * n x 13 as orc_eval.  Sampler: xi_s picks the stratum; out n x 13 =
+ * orc_sample's 12 values and the stratum. */
+int orc_eval_multi(const orc_params* types, const double* const* tables, int32_t n_types,
+                   int64_t n, int32_t n_max, const int32_t* type, const float* h, const float* h1,
+                   const float* h2, const float* zeta, const float* u, const float* v,
+                   const float* wi, const float* wo, const float* shift, double* out,
+                   uint32_t* flags, int nthreads);
+int orc_sample_multi(const orc_params* types, const double* const* tables, int32_t n_types,
+                     int64_t n, int32_t n_max, const int32_t* type, const float* h,
+                     const float* h1, const float* h2, const float* zeta, const float* xi_s,
+                     const float* u, const float* v, const float* wi, const float* xi,
+                     const float* shift, double* out, uint32_t* flags, int nthreads);
+/* The strata of one footprint: offsets hs[] and weights ws[] (n_max
+ * entries), returns their number or -1 for an invalid footprint. */
+int orc_footprint(double h0, double h1, double h2, double zeta, int32_t n_max, double* hs,
+                  double* ws);
 
 /* Central finite differences of sum_q sum_c gE[q][c] E_c(q) with respect to
  * theta = (albedo r g b, beta, ply_twist, fiber_twist, ply_density,

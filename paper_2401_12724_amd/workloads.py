@@ -82,6 +82,32 @@ def _sphere(rng, n):
     return np.stack([s * np.cos(phi), s * np.sin(phi), z]).astype(np.float32)
 
 
+def sphere(n: int, rng) -> np.ndarray:
+    """n directions uniform on S^2 from a numpy Generator, (3, n) float32."""
+    return _sphere(rng, n)
+
+
+def footprints(q: dict, seed: int, w_min: float = 2.0 ** -6, w_max: float = 2.0) -> dict:
+    """Pixel footprints for the multi-scale model around each query's h: a
+    width log-uniform in [w_min, w_max] (2 = a pixel covering the whole
+    yarn), split at a uniform share to either side of h and cut at +-1;
+    the strata offset zeta and the stratum draw xi_s uniform in [0, 1)."""
+    rng = _rng(seed + 3000)
+    n = len(q["h"])
+    w = np.exp(rng.uniform(math.log(w_min), math.log(w_max), n))
+    a = rng.random(n)
+    h = q["h"].astype(np.float64)
+    q["h1"] = np.maximum(h - a * w, -1.0).astype(np.float32)
+    q["h2"] = np.minimum(h + (1.0 - a) * w, 1.0).astype(np.float32)
+    # FP32 rounding keeps h1 <= h <= h2: both ends round towards h
+    q["h1"] = np.minimum(q["h1"], q["h"])
+    q["h2"] = np.maximum(q["h2"], q["h"])
+    top = np.float32(1.0 - 2.0 ** -24)
+    q["zeta"] = np.minimum(rng.random(n).astype(np.float32), top)
+    q["xi_s"] = np.minimum(rng.random(n).astype(np.float32), top)
+    return q
+
+
 def queries(n: int, seed: int, n_types: int = 1, type_ids=None, with_xi: bool = False,
             v_max: float = 10.0) -> dict:
     """n queries: h~U[-1,1], u~U[0,2pi), v~U[0,v_max), wi, wo uniform on S^2."""
