@@ -347,6 +347,33 @@ def _migration(torch, bysdf, W, P, qd, q, base_ms):
             "valu_frac": ops * n / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS}
 
 
+def _multiscale(torch, bysdf, W, P, q, qd, near_ms, n_max=4):
+    """The per-block workload with a pixel footprint per query (widths
+    log-uniform in [2^-6, 2] yarn half-widths, so from a point to the whole
+    yarn): the multi-scale evaluation and sampler with up to n_max strata."""
+    qf = W.footprints(dict(q), 1)
+    qm = dict(qd)
+    qm.update(bysdf.to_device({k: qf[k] for k in ("h1", "h2", "zeta", "xi_s")}))
+    n = int(qd["h"].numel())
+    w = qf["h2"].astype(np.float64) - qf["h1"]
+    strata = np.clip(np.ceil(n_max * w / 2), 1, n_max)
+    T = bysdf.bysdf_types_create(P)
+    eo, so = bysdf.alloc_eval_out(n), bysdf.alloc_sample_out(n)
+    fe = lambda: bysdf.bysdf_eval_multi(T, qm, n_max, eo)
+    fs = lambda: bysdf.bysdf_sample_multi(T, qm, n_max, so)
+    fe()
+    fs()
+    torch.cuda.synchronize()
+    e_ms, s_ms = _timed(torch, fe, 5), _timed(torch, fs, 5)
+    return {"queries": n, "n_max": n_max, "strata_per_query": float(strata.mean()),
+            "eval_multi_ms": e_ms, "sample_multi_ms": s_ms,
+            "eval_queries_per_s": n / (e_ms * 1e-3), "sample_queries_per_s": n / (s_ms * 1e-3),
+            "eval_time_vs_near": e_ms / near_ms["eval"],
+            "sample_time_vs_near": s_ms / near_ms["sample"],
+            "note": "strata_per_query near-field states per query enter the aggregated "
+                    "geometry and as many again the lobes; the sampler adds its draw"}
+
+
 def _weave_render(torch, bysdf, W, spp=4):
     """The plain weave (256 + 256 B-spline yarns, 524,288 spans) seen by the
     grazing 1920 x 1080 camera: primary-ray intersection of every pixel
@@ -382,6 +409,12 @@ def _weave_render(torch, bysdf, W, spp=4):
     _, counts = bysdf.shade_wavefront(S, T, rs, fb, ws, counts=True)
     rms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rs, fb, ws), 3)
     rays = counts[0] + counts[1]
+    # the same frame in multi-scale mode: camera hits over their pixel
+    # footprint (up to 8 strata), later bounces near field
+    rm = dict(rs, multiscale=1, n_h=8)
+    fbm = torch.empty_like(fb)
+    _, mcounts = bysdf.shade_wavefront(S, T, rm, fbm, ws, counts=True)
+    mms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rm, fbm, ws), 3)
     return {"scene": {"yarns": info["n_yarns"], "spans": info["n_spans"],
                       "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"],
                       "device_bytes": info["bytes"], "build_s": build_s},
@@ -391,7 +424,11 @@ def _weave_render(torch, bysdf, W, spp=4):
                        "extension_rays": counts[0], "shadow_rays": counts[1],
                        "rays_per_s": rays / (rms * 1e-3),
                        "paths_per_s": cam["width"] * cam["height"] * spp / (rms * 1e-3),
-                       "mean_radiance": float(fb.mean())}}
+                       "mean_radiance": float(fb.mean())},
+            "render_multiscale": {"spp": spp, "n_max": 8, "ms": mms,
+                                  "extension_rays": mcounts[0], "shadow_rays": mcounts[1],
+                                  "paths_per_s": cam["width"] * cam["height"] * spp / (mms * 1e-3),
+                                  "mean_radiance": float(fbm.mean())}}
 
 
 def main():
@@ -546,6 +583,7 @@ def main():
         eval_qps = N / (unfused["eval"] * 1e-3)
         del ev, sv
         out["migration"] = _migration(torch, bysdf, W, P, qd, q, ktime["eval_sample"])
+        out["multiscale"] = _multiscale(torch, bysdf, W, P, q, qd, unfused)
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
         out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
         out["weave"] = _weave_render(torch, bysdf, W)

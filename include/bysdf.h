@@ -210,6 +210,47 @@ int bysdf_eval_sample(const bysdf_types_t* types, const bysdf_query_soa* q, cons
                       const bysdf_eval_out_soa* eval_out, const bysdf_sample_out_soa* sample_out,
                       hipStream_t stream);
 
+/* ------------------------------------------------------------ multi-scale */
+/* The pixel footprint of a multi-scale query (Sec. 4.2 and 5.3): device
+ * arrays of n elements.  h1 <= h <= h2 (q's h) in [-1, 1] are the
+ * azimuthal offsets of the two ray differentials and of the hit itself;
+ * zeta in [0, 1) is the offset of the footprint's strata; xi_s in [0, 1)
+ * draws the stratum (sampler only; bysdf_eval_multi ignores it and it may
+ * be NULL there).  A query whose footprint breaks these bounds gets
+ * BYSDF_FLAG_BAD_INPUT and zero outputs. */
+typedef struct {
+    const float *h1, *h2;
+    const float* zeta;
+    const float* xi_s;
+} bysdf_footprint_soa;
+
+/* Multi-scale BYSDF f_multi (Sec. 4.2, Eq. 8-11) at q's wo: the footprint
+ * [h1, h2] is cut into n = ceil(n_max (h2 - h1) / 2) strata
+ * h_j = h1 + (h2 - h1)(j + zeta)/n (FP32), weighted by a tent W that is 1
+ * at h and 0 at h1 and h2 (one stratum weighs 1).  Over the strata that hit
+ * a ply, the fiber normal and tangent at x (Eq. 9-10, the mean normal
+ * normalised, the mean tangent made orthogonal to it) and the fiber
+ * shadowing (Eq. 11) are W-weighted means; the roughness along and across
+ * the fiber widens to (beta + (h2 - h1)/2)(1, aniso).  Outputs as
+ * bysdf_eval, each the W-weighted mean over all strata of the near-field
+ * model at that stratum's ply hit with the aggregated frame and shadowing
+ * (a stratum between the plies counts 0); BYSDF_FLAG_PASS_THROUGH when no
+ * stratum hits.  n_max in 1..16 (BYSDF_ERR_INVALID_ARG otherwise); h1 = h2
+ * gives bysdf_eval exactly.  n == 0 is a no-op. */
+int bysdf_eval_multi(const bysdf_types_t* types, const bysdf_query_soa* q,
+                     const bysdf_footprint_soa* footprint, int64_t n, int32_t n_max,
+                     const bysdf_eval_out_soa* out, hipStream_t stream);
+
+/* Importance sampling of f_multi: xi_s picks stratum j with probability
+ * W_j / sum W; a stratum between the plies passes the ray through (lobe 4,
+ * as bysdf_sample_pdf); otherwise xi0..xi2 draw from that stratum's
+ * aggregated state as in bysdf_sample_pdf, and the weight and pdf are those
+ * of f_multi at the drawn direction.  Outputs as bysdf_sample_pdf, except
+ * node = forward node + 16 x stratum. */
+int bysdf_sample_multi(const bysdf_types_t* types, const bysdf_sample_soa* q,
+                       const bysdf_footprint_soa* footprint, int64_t n, int32_t n_max,
+                       const bysdf_sample_out_soa* out, hipStream_t stream);
+
 /* White-furnace integral per block (Sec. 4.3): block b (n / block blocks)
  * draws `block` directions for the hit of query b*block (type, h, u, v, wi,
  * shift) with the xi of queries b*block .. b*block+block-1, and writes the
@@ -356,7 +397,13 @@ int yarn_tube_intersect(const yarn_scene_t* scene, const yarn_ray_soa* rays, int
  * their camera distance use the far field (Eq. 7, W = 1) over n_h strata
  * of h.  seed keys the random streams; ray_eps is the t_min of rays that
  * leave a yarn.  spp_batch: samples per pixel per wavefront pass (0 = all
- * at once); it sets the workspace size. */
+ * at once); it sets the workspace size.  multiscale = 1 replaces the LOD
+ * switch by the multi-scale model (Sec. 4.2, as bysdf_eval_multi /
+ * bysdf_sample_multi with n_max = n_h <= 16) at camera hits: the footprint
+ * [h1, h2] comes from custom ray differentials (Sec. 5.3) -- the offsets,
+ * from the hit's local straight yarn axis, of the camera rays one pixel
+ * along and against the screen-space gradient of h, cut at +-1 -- and
+ * later bounces use the near field. */
 typedef struct {
     float eye[3], look_at[3], up[3];
     float vfov;
@@ -370,6 +417,7 @@ typedef struct {
     uint64_t seed;
     float ray_eps;
     int32_t spp_batch;
+    int32_t multiscale;
 } render_settings;
 
 /* Bytes of device workspace shade_wavefront needs (0 on bad settings). */

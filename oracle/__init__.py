@@ -61,6 +61,7 @@ class RenderSettings(C.Structure):
         ("light_radiance", C.c_float * 3), ("env_radiance", C.c_float * 3),
         ("spp", C.c_int32), ("max_depth", C.c_int32), ("lod_px", C.c_float), ("n_h", C.c_int32),
         ("seed", C.c_uint64), ("ray_eps", C.c_float), ("nee", C.c_int32),
+        ("multiscale", C.c_int32),
     ]
 
 
@@ -68,6 +69,7 @@ def render_settings_struct(rs: dict) -> RenderSettings:
     s = RenderSettings()
     rs = dict(rs)
     rs.setdefault("nee", 1)
+    rs.setdefault("multiscale", 0)
     for k, _ in RenderSettings._fields_:
         v = rs[k]
         if isinstance(v, (tuple, list)):
@@ -142,6 +144,9 @@ def lib():
         L.orc_nodes.restype = C.c_uint32
         L.orc_frame_x.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_frame_x.restype = C.c_uint32
+        L.orc_camera_footprint.argtypes = [C.c_void_p, C.POINTER(RenderSettings), C.c_double,
+                                           C.c_double, dp]
+        L.orc_camera_footprint.restype = C.c_int32
         L.orc_scene_create.argtypes = [fp, C.POINTER(C.c_int64), C.c_int32]
         L.orc_scene_create.restype = C.c_void_p
         L.orc_scene_free.argtypes = [C.c_void_p]
@@ -483,6 +488,15 @@ def intersect(scene: Scene, o, d, t_max, t_min: float = 0.0, nthreads: int = 0):
     lib().orc_intersect(scene._h, n, _ptr(o, C.c_float), _ptr(d, C.c_float), _ptr(tm, C.c_float),
                         float(t_min), _ptr(out, C.c_double), nthreads)
     return out
+
+
+def camera_footprint(scene: Scene, rs: dict, px: float, py: float):
+    """(yarn, h0, h1, h2) of the camera ray through pixel position (px, py)."""
+    st = render_settings_struct(rs)
+    out = np.zeros(3)
+    y = lib().orc_camera_footprint(scene._h, C.byref(st), float(px), float(py),
+                                   _ptr(out, C.c_double))
+    return int(y), out[0], out[1], out[2]
 
 
 def render(scene: Scene, ts, yarn_type, yarn_phase, rs: dict, nthreads: int = 0):

@@ -1420,6 +1420,28 @@ int orc_sample_multi(const orc_params* types, const double* const* tables, int32
     return 0;
 }
 
+/* One multi-scale query (single type, its table): out[13] as orc_eval_multi. */
+uint32_t orc_eval_multi_query(const orc_params* p, const double* tab, double h0, double h1,
+                              double h2, double zeta, int32_t n_max, double u, double v,
+                              const double wi[3], const double wo[3], double out[13])
+{
+    uint32_t f;
+    eval_multi_one(p, tab, h0, h1, h2, zeta, n_max, u, v, mk(wi[0], wi[1], wi[2]),
+                   mk(wo[0], wo[1], wo[2]), NULL, out, &f);
+    return f;
+}
+
+/* One multi-scale draw (single type, its table): out[13] as orc_sample_multi. */
+uint32_t orc_sample_multi_query(const orc_params* p, const double* tab, double h0, double h1,
+                                double h2, double zeta, double xi_s, int32_t n_max, double u,
+                                double v, const double wi[3], const double xi[3], double out[13])
+{
+    uint32_t f;
+    sample_multi_one(p, tab, h0, h1, h2, zeta, xi_s, n_max, u, v, mk(wi[0], wi[1], wi[2]), xi, NULL,
+                     out, &f);
+    return f;
+}
+
 /* Strata of one footprint (test access): offsets and weights, returns n. */
 int orc_footprint(double h0, double h1, double h2, double zeta, int32_t n_max, double* hs,
                   double* ws)

@@ -132,6 +132,12 @@ int orc_sample_multi(const orc_params* types, const double* const* tables, int32
                      const float* h1, const float* h2, const float* zeta, const float* xi_s,
                      const float* u, const float* v, const float* wi, const float* xi,
                      const float* shift, double* out, uint32_t* flags, int nthreads);
+uint32_t orc_eval_multi_query(const orc_params* p, const double* tab, double h0, double h1,
+                              double h2, double zeta, int32_t n_max, double u, double v,
+                              const double wi[3], const double wo[3], double out[13]);
+uint32_t orc_sample_multi_query(const orc_params* p, const double* tab, double h0, double h1,
+                                double h2, double zeta, double xi_s, int32_t n_max, double u,
+                                double v, const double wi[3], const double xi[3], double out[13]);
 /* The strata of one footprint: offsets hs[] and weights ws[] (n_max
  * entries), returns their number or -1 for an invalid footprint. */
 int orc_footprint(double h0, double h1, double h2, double zeta, int32_t n_max, double* hs,

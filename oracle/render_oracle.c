@@ -128,6 +128,78 @@ static void far_eval(const ctx_t* C, const orc_params* P, const double* tab, dou
     (void)C;
 }
 
+/* Pixel footprint of a camera hit in azimuthal offsets (custom ray
+ * differentials, Sec. 5.3).  Locally the yarn is the straight tube of radius
+ * R about the axis through c along T, where c lies R from the hit p against
+ * the surface normal at azimuth atan2(wi) + asin h in the (N, T x N) plane;
+ * a camera ray through screen point (sx, sy) then has offset
+ * cross(o - c, d) / (|d| R) in that plane.  One-pixel steps right and up
+ * give the gradient of h on the screen; the rays one pixel along and
+ * against it give the ends h1 <= h2, cut at -1 and 1 and widened to contain
+ * h0.  FP32 results, as the query's h. */
+static void camera_footprint(r3 o, r3 f, r3 rr, r3 uu, double th, double aspect, int width,
+                             int height, r3 du, double t, const hitrec* hr, double R, double* h1,
+                             double* h2)
+{
+    double h0 = hr->h;
+    r3 B = rcross(hr->T, hr->N);
+    r3 p = radd(o, rscl(du, t));
+    double ang = atan2(-rdot(du, B), -rdot(du, hr->N)) + asin(h0);
+    r3 c = rsub(p, rscl(radd(rscl(hr->N, cos(ang)), rscl(B, sin(ang))), R));
+    r3 e = rsub(o, c);
+    double e1 = rdot(e, hr->N), e2 = rdot(e, B);
+    double fd = rdot(du, f);
+    double sx = rdot(du, rr) / fd, sy = rdot(du, uu) / fd;
+    double stepx = 2.0 * th * aspect / width, stepy = 2.0 * th / height;
+    double hx[4];
+    double dirs[4][2] = {{1, 0}, {0, 1}, {0, 0}, {0, 0}};
+    for (int k = 0; k < 4; ++k) {
+        if (k == 2) {
+            double gx = hx[0] - h0, gy = hx[1] - h0, gl = sqrt(gx * gx + gy * gy);
+            if (!(gl > 0.0)) {
+                *h1 = *h2 = h0;
+                return;
+            }
+            dirs[2][0] = gx / gl; dirs[2][1] = gy / gl;
+            dirs[3][0] = -gx / gl; dirs[3][1] = -gy / gl;
+        }
+        r3 dd = runit(radd(f, radd(rscl(rr, sx + dirs[k][0] * stepx), rscl(uu, sy + dirs[k][1] * stepy))));
+        double a = rdot(dd, hr->N), b = rdot(dd, B), l = sqrt(a * a + b * b);
+        hx[k] = l > 1e-12 ? (e1 * b - e2 * a) / (l * R) : h0;
+    }
+    double lo = hx[2] < hx[3] ? hx[2] : hx[3], hi = hx[2] < hx[3] ? hx[3] : hx[2];
+    lo = lo < -1.0 ? -1.0 : lo;
+    hi = hi > 1.0 ? 1.0 : hi;
+    *h1 = f32(lo < h0 ? lo : h0);
+    *h2 = f32(hi > h0 ? hi : h0);
+}
+
+/* The footprint of the camera ray through continuous pixel position (px, py)
+ * (test access): out = h0, h1, h2 of its first yarn hit; returns the yarn or
+ * -1 on a miss. */
+int orc_camera_footprint(const void* scene, const orc_render_settings* rs, double px, double py,
+                         double out[3])
+{
+    r3 eye = r3v(rs->eye);
+    r3 f = runit(rsub(r3v(rs->look_at), eye));
+    r3 rr = runit(rcross(f, r3v(rs->up)));
+    r3 uu = rcross(rr, f);
+    double th = tan(0.5 * rs->vfov);
+    double aspect = (double)rs->width / rs->height;
+    double sx = (2.0 * px / rs->width - 1.0) * th * aspect;
+    double sy = (1.0 - 2.0 * py / rs->height) * th;
+    r3 o = r3f(eye);
+    r3 du = runit(r3f(runit(radd(f, radd(rscl(rr, sx), rscl(uu, sy))))));
+    hitrec hr;
+    trace(scene, o, du, 0.0, 1e30, -1, &hr);
+    if (hr.miss) return -1;
+    double R = orc_scene_radius(scene, hr.yarn);
+    out[0] = hr.h;
+    camera_footprint(o, f, rr, uu, th, aspect, rs->width, rs->height, du, hr.t, &hr, f32(R), &out[1],
+                     &out[2]);
+    return hr.yarn;
+}
+
 int orc_render(const void* scene, const orc_params* types, const double* const* tables,
                int32_t n_types, const int32_t* yarn_type, const float* yarn_phase,
                const orc_render_settings* rs, double* fb, double* sq, int nthreads)
@@ -212,7 +284,14 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                 double uq = (double)yarn_phase[y];
                 double vl = f32(hr.v / R);
                 double dist_cam = sqrt(rdot(rsub(p, eye), rsub(p, eye)));
-                int far = 2.0 * R / (dist_cam * pix_angle) < rs->lod_px;
+                /* multi-scale: camera hits over their pixel footprint, later
+                 * bounces near field; otherwise the LOD rule picks the far field */
+                int ms = rs->multiscale && depth == 0;
+                int far = !rs->multiscale && 2.0 * R / (dist_cam * pix_angle) < rs->lod_px;
+                double fh1 = hr.h, fh2 = hr.h;
+                if (ms)
+                    camera_footprint(o, f, rr, uu, th, aspect, rs->width, rs->height, du, hr.t, &hr,
+                                     f32(R), &fh1, &fh2);
                 double u1[4], u2[4];
                 rnd(rs->seed, slot, (uint32_t)depth, 1, u1);
                 rnd(rs->seed, slot, (uint32_t)depth, 2, u2);
@@ -226,7 +305,13 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                     double wo[3];
                     to_loc(&hr, wl, wo);
                     double E[3], pb;
-                    if (far) {
+                    if (ms) {
+                        double out[13];
+                        orc_eval_multi_query(P, tab, hr.h, fh1, fh2, u2[2], rs->n_h, uq, vl, wi, wo,
+                                             out);
+                        for (int c = 0; c < 3; ++c) E[c] = f32(out[c]);
+                        pb = f32(out[11]);
+                    } else if (far) {
                         far_eval(&C, P, tab, uq, vl, wi, wo, rs->n_h, u2[2], E, &pb);
                     } else {
                         double out[13];
@@ -256,7 +341,14 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                     if (js > rs->n_h - 1) js = rs->n_h - 1;
                     hq = f32(-1.0 + 2.0 * (js + u2[2]) / rs->n_h);
                 }
-                sf = orc_sample_query(P, tab, hq, uq, vl, wi, xi, so);
+                if (ms) {
+                    double sm[13];
+                    sf = orc_sample_multi_query(P, tab, hr.h, fh1, fh2, u2[2], u2[1], rs->n_h, uq, vl,
+                                                wi, xi, sm);
+                    memcpy(so, sm, sizeof(so));
+                } else {
+                    sf = orc_sample_query(P, tab, hq, uq, vl, wi, xi, so);
+                }
                 int lobe = (int)so[10];
                 r3 dnew;
                 if (lobe == 4) {

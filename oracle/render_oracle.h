@@ -16,7 +16,8 @@
  *   at a yarn hit: BYSDF query in the rotation-minimising frame (x = N,
  *   y = T x N, z = T; v in yarn radii); far field (Eq. 7, W = 1, N_h
  *   strata with one random offset) when the yarn is narrower than lod_px
- *   pixels at its camera distance; next-event estimation to a uniform
+ *   pixels at its camera distance, or, in multi-scale mode, the
+ *   multi-scale model over the pixel footprint of a camera hit; next-event estimation to a uniform
  *   point of the light with a shadow ray that passes through a yarn where
  *   the implicit plies are missed (Sec. 3.4), weighted by the power
  *   heuristic; then a BYSDF sample continues the path.  At this scale the
@@ -55,7 +56,15 @@ typedef struct {
     int32_t nee;   /* oracle-only switch: 0 = no next-event estimation (light
                       reached by BYSDF samples alone, weight 1), for the pin
                       that both estimators agree */
+    int32_t multiscale; /* 1: camera hits use the multi-scale model over their
+                           pixel footprint (Sec. 4.2, 5.3), later bounces the
+                           near field, no LOD switch */
 } orc_render_settings;
+
+/* Footprint probe: h0, h1, h2 of the camera ray through pixel position
+ * (px, py); returns the yarn hit or -1. */
+int orc_camera_footprint(const void* scene, const orc_render_settings* rs, double px, double py,
+                         double out[3]);
 
 /* fb[crop_h][crop_w][3] receives the mean radiance over spp; if sq is not
  * NULL it receives the mean of the squared per-sample radiance (for the

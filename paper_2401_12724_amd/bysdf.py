@@ -70,6 +70,10 @@ class SampleSoA(C.Structure):
                                    "xi0", "xi1", "xi2", "shift0", "shift1")]
 
 
+class FootprintSoA(C.Structure):
+    _fields_ = [(n, _vp) for n in ("h1", "h2", "zeta", "xi_s")]
+
+
 class Schedule(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("grid", C.c_int32), ("use_lds", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -104,6 +108,7 @@ class RenderSettings(C.Structure):
         ("light_radiance", C.c_float * 3), ("env_radiance", C.c_float * 3),
         ("spp", C.c_int32), ("max_depth", C.c_int32), ("lod_px", C.c_float), ("n_h", C.c_int32),
         ("seed", C.c_uint64), ("ray_eps", C.c_float), ("spp_batch", C.c_int32),
+        ("multiscale", C.c_int32),
     ]
 
 
@@ -127,6 +132,10 @@ def lib():
                                        C.POINTER(SampleOutSoA), _vp]
         L.bysdf_eval_sample.argtypes = [_vp, C.POINTER(QuerySoA), _vp, _vp, _vp, C.c_int64,
                                         C.POINTER(EvalOutSoA), C.POINTER(SampleOutSoA), _vp]
+        L.bysdf_eval_multi.argtypes = [_vp, C.POINTER(QuerySoA), C.POINTER(FootprintSoA),
+                                       C.c_int64, C.c_int32, C.POINTER(EvalOutSoA), _vp]
+        L.bysdf_sample_multi.argtypes = [_vp, C.POINTER(SampleSoA), C.POINTER(FootprintSoA),
+                                         C.c_int64, C.c_int32, C.POINTER(SampleOutSoA), _vp]
         L.bysdf_furnace_blocks.argtypes = [_vp, C.POINTER(SampleSoA), C.c_int64, C.c_int32, _vp,
                                            _vp, _vp]
         L.bysdf_batched_workspace_size.argtypes = [C.c_int32]
@@ -382,6 +391,43 @@ def bysdf_eval_sample(types: Types, q: dict, out=None, stream=None):
     return ev, ef, sv, lobe, node, sf
 
 
+def _fsoa(q, sampler):
+    f = FootprintSoA()
+    f.h1, f.h2, f.zeta = _ptr(q["h1"]), _ptr(q["h2"]), _ptr(q["zeta"])
+    f.xi_s = _ptr(q["xi_s"]) if sampler else None
+    return f
+
+
+def bysdf_eval_multi(types: Types, q: dict, n_max: int = 4, out=None, stream=None):
+    """Multi-scale value and pdf at q["wo"] over the footprint (q["h1"],
+    q["h"], q["h2"]) with strata offset q["zeta"].  Returns (vals
+    float32[12, n], flags int32[n]) as bysdf_eval."""
+    n = int(q["h"].numel())
+    vals, flags = out if out is not None else alloc_eval_out(n, q["h"].device)
+    o = _eval_out_soa(vals, flags)
+    qs, fs = _qsoa(q), _fsoa(q, False)
+    _check(lib().bysdf_eval_multi(types.handle, C.byref(qs), C.byref(fs), n, n_max, C.byref(o),
+                                  _stream(stream)), "bysdf_eval_multi")
+    return vals, flags
+
+
+def bysdf_sample_multi(types: Types, q: dict, n_max: int = 4, out=None, stream=None):
+    """Multi-scale sampler (q["xi_s"] draws the stratum).  Returns (vals
+    float32[10, n], lobe, node, flags) as bysdf_sample_pdf, with node =
+    forward node + 16 x stratum."""
+    n = int(q["h"].numel())
+    vals, lobe, node, flags = out if out is not None else alloc_sample_out(n, q["h"].device)
+    o = SampleOutSoA()
+    names = ("wo_x", "wo_y", "wo_z", "w_r", "w_g", "w_b", "pdf", "exit_x", "exit_y", "exit_z")
+    for i, nm in enumerate(names):
+        setattr(o, nm, _ptr(vals[i]))
+    o.lobe, o.node, o.flags = _ptr(lobe), _ptr(node), _ptr(flags)
+    qs, fs = _ssoa(q), _fsoa(q, True)
+    _check(lib().bysdf_sample_multi(types.handle, C.byref(qs), C.byref(fs), n, n_max, C.byref(o),
+                                    _stream(stream)), "bysdf_sample_multi")
+    return vals, lobe, node, flags
+
+
 def bysdf_furnace_blocks(types: Types, q: dict, block: int = 256, mean=None, var=None,
                          stream=None):
     """Returns (mean float32[nb, 3], var float32[nb, 3])."""
@@ -506,10 +552,11 @@ def yarn_tube_intersect(scene: Scene, o, d, t_max, t_min: float = 0.0, hits=None
 
 def render_settings(rs: dict) -> RenderSettings:
     """render_settings from a dict with the field names of the C struct
-    (spp_batch defaults to 0: every sample in one pass)."""
+    (spp_batch defaults to 0: every sample in one pass; multiscale to 0)."""
     st = RenderSettings()
     rs = dict(rs)
     rs.setdefault("spp_batch", 0)
+    rs.setdefault("multiscale", 0)
     for k, _ in RenderSettings._fields_:
         v = rs[k]
         if isinstance(v, (tuple, list)):

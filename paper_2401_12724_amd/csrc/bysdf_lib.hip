@@ -23,6 +23,7 @@
 
 #include "../../include/bysdf.h"
 #include "bysdf_model.hpp"
+#include "bysdf_multi.hpp"
 #include "bysdf_opcount.hpp"
 #include "bysdf_dual.hpp"
 #include "lib_internal.hpp"
@@ -465,6 +466,105 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sa
         so_p.lobe[i] = so.lobe;
         so_p.node[i] = so.node;
         so_p.flags[i] = fs;
+    }
+}
+
+// ------------------------------------------------------------------ multi-scale
+// The multi-scale model (Sec. 4.2, Eq. 8-11): one query per lane, its
+// footprint's strata in a loop (first the aggregated geometry, then the
+// near-field lobes of every stratum with it).  Lanes of a wavefront with
+// fewer strata idle while the widest footprint finishes.
+struct FPtrs {
+    const float *h1, *h2, *zeta, *xi_s;
+};
+
+#ifndef BYSDF_MULTI_MIN_WAVES
+#define BYSDF_MULTI_MIN_WAVES 2
+#endif
+
+template <bool kLds, int MP, bool MIG>
+__global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
+    const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
+    QPtrs q, FPtrs fp, int n_max, OPtrs o, int64_t n)
+{
+    extern __shared__ float4 s_tab[];
+    if (kLds) {
+        for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int t = q.type[i];
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+        float h = q.h[i], u = q.u[i], v = q.v[i];
+        float h1 = fp.h1[i], h2 = fp.h2[i], zeta = fp.zeta[i];
+        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+        fl |= check_inputs(h, u, v, wi) | check_dir(wo) | check_footprint(h, h1, h2, zeta);
+        EvalOut<float> e;
+        for (int c = 0; c < 3; ++c) e.E[c] = e.ExB[c] = e.EyB[c] = 0.0f;
+        e.ExS = e.EyS = e.pdf = 0.0f;
+        for_each_wave_type(t, fl == 0u, [&](int tu) {
+            const TypeRec& R = types[tu];
+            TabPtrT<MIG> tab;
+            tab.p = kLds ? s_tab : tables + R.table_off;
+            Footprint f;
+            make_footprint(h, h1, h2, zeta, n_max, f);
+            const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, f);
+            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+            fl = eval_multi<double, float, MP>(Pm, tab, f, u, v, wi, wo, s0, s1, q.s0 != nullptr, e);
+        });
+        o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
+        o.ExS[i] = e.ExS; o.EyS[i] = e.EyS;
+        o.ExBr[i] = e.ExB[0]; o.ExBg[i] = e.ExB[1]; o.ExBb[i] = e.ExB[2];
+        o.EyBr[i] = e.EyB[0]; o.EyBg[i] = e.EyB[1]; o.EyBb[i] = e.EyB[2];
+        o.pdf[i] = e.pdf;
+        o.flags[i] = fl;
+    }
+}
+
+template <bool kLds, int MP, bool MIG>
+__global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
+    const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
+    SPtrs q, FPtrs fp, int n_max, SOPtrs o, int64_t n)
+{
+    extern __shared__ float4 s_tab[];
+    if (kLds) {
+        for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int t = q.type[i];
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        float h = q.h[i], u = q.u[i], v = q.v[i], x0 = q.xi0[i], x1 = q.xi1[i], x2 = q.xi2[i];
+        float h1 = fp.h1[i], h2 = fp.h2[i], zeta = fp.zeta[i], xs = fp.xi_s[i];
+        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+        fl |= check_inputs(h, u, v, wi) | check_footprint(h, h1, h2, zeta);
+        if (!(xs >= 0.0f && xs < 1.0f)) fl |= F_BAD_INPUT;
+        SampleOut<float> so;
+        for (int c = 0; c < 3; ++c) so.wo[c] = so.wgt[c] = so.ex[c] = 0.0f;
+        so.pdf = 0.0f;
+        so.lobe = -1;
+        so.node = 0;
+        for_each_wave_type(t, fl == 0u, [&](int tu) {
+            const TypeRec& R = types[tu];
+            TabPtrT<MIG> tab;
+            tab.p = kLds ? s_tab : tables + R.table_off;
+            Footprint f;
+            make_footprint(h, h1, h2, zeta, n_max, f);
+            const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, f);
+            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
+            fl = sample_multi<double, float, MP>(Pm, tab, f, xs, u, v, wi, x0, x1, x2, s0, s1,
+                                                 q.s0 != nullptr, so);
+        });
+        o.wox[i] = so.wo[0]; o.woy[i] = so.wo[1]; o.woz[i] = so.wo[2];
+        o.wr[i] = so.wgt[0]; o.wg[i] = so.wgt[1]; o.wb[i] = so.wgt[2];
+        o.pdf[i] = so.pdf;
+        o.exx[i] = so.ex[0]; o.exy[i] = so.ex[1]; o.exz[i] = so.ex[2];
+        o.lobe[i] = so.lobe;
+        o.node[i] = so.node;
+        o.flags[i] = fl;
     }
 }
 
@@ -1060,6 +1160,76 @@ extern "C" int bysdf_eval_sample(const bysdf_types_t* h, const bysdf_query_soa* 
     auto kern = BYSDF_PICK(k_eval_sample, h);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
                        h->d_tables, tx, qp, xi0, xi1, xi2, op, sop, n);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+static int check_footprint_args(const bysdf_footprint_soa* fp, bool sampler)
+{
+    if (!aligned4(fp->h1) || !aligned4(fp->h2) || !aligned4(fp->zeta) || (sampler && !aligned4(fp->xi_s)))
+        return fail(BYSDF_ERR_INVALID_ARG, "a footprint pointer is NULL or misaligned");
+    return 0;
+}
+
+extern "C" int bysdf_eval_multi(const bysdf_types_t* h, const bysdf_query_soa* q,
+                                const bysdf_footprint_soa* fp, int64_t n, int32_t n_max,
+                                const bysdf_eval_out_soa* o, hipStream_t stream)
+{
+    if (!h || !q || !o) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (!fp) return fail(BYSDF_ERR_INVALID_ARG, "NULL footprint");
+    if (n_max < 1 || n_max > kMaxStrata) return fail(BYSDF_ERR_INVALID_ARG, "n_max must be in 1..16");
+    if (n == 0) return BYSDF_OK;
+    if (int rc = check_footprint_args(fp, false)) return rc;
+    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y,
+                          q->wo_z, o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g,
+                          o->E_xB_b, o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query/output pointer is NULL or misaligned");
+    if ((q->shift0 == nullptr) != (q->shift1 == nullptr) ||
+        (q->shift0 && (!aligned4(q->shift0) || !aligned4(q->shift1))))
+        return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
+    QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
+             q->shift0, q->shift1};
+    FPtrs fpp{fp->h1, fp->h2, fp->zeta, nullptr};
+    OPtrs op{o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
+             o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
+    int grid = grid_for(n);
+    size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
+    int tx = h->single_table ? h->table_texels : 0;
+    auto kern = BYSDF_PICK(k_eval_multi, h);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                       h->d_tables, tx, qp, fpp, (int)n_max, op, n);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+extern "C" int bysdf_sample_multi(const bysdf_types_t* h, const bysdf_sample_soa* q,
+                                  const bysdf_footprint_soa* fp, int64_t n, int32_t n_max,
+                                  const bysdf_sample_out_soa* o, hipStream_t stream)
+{
+    if (!h || !q || !o) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (!fp) return fail(BYSDF_ERR_INVALID_ARG, "NULL footprint");
+    if (n_max < 1 || n_max > kMaxStrata) return fail(BYSDF_ERR_INVALID_ARG, "n_max must be in 1..16");
+    if (n == 0) return BYSDF_OK;
+    if (int rc = check_footprint_args(fp, true)) return rc;
+    if (int rc = check_sample_args(q)) return rc;
+    const void* need[] = {o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x,
+                          o->exit_y, o->exit_z, o->lobe, o->node, o->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "an output pointer is NULL or misaligned");
+    SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
+             q->shift0, q->shift1};
+    FPtrs fpp{fp->h1, fp->h2, fp->zeta, fp->xi_s};
+    SOPtrs op{o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x, o->exit_y,
+              o->exit_z, o->lobe, o->node, o->flags};
+    int grid = grid_for(n);
+    size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
+    int tx = h->single_table ? h->table_texels : 0;
+    auto kern = BYSDF_PICK(k_sample_multi, h);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                       h->d_tables, tx, sp, fpp, (int)n_max, op, n);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }

@@ -447,6 +447,18 @@ template <class G, class S, int MP> struct XState {
     G rawp, rawf;     // visibilities before the density blends
 };
 
+// The cosine at x and the lobe selection weights from the frame at x.
+template <class G, class S, int MP>
+__host__ __device__ inline void lobe_weights(const Derived<G, S>& P, XState<G, S, MP>& X)
+{
+    X.mu_i = Narrow<S>::from(dot(X.wi_g, X.fx.n));
+    S PR = fresnel<S>(val(X.mu_i) > 0.0f ? X.mu_i : S(0), P.eta);
+    X.w[0] = (S(1) - P.B) * PR;
+    X.w[1] = (S(1) - P.B) * (S(1) - PR);
+    X.w[2] = P.B * P.r;
+    X.w[3] = P.B * (S(1) - P.r);
+}
+
 template <class G, class S, int MP, class Tab>
 __host__ __device__ inline void state_after_plies(const Derived<G, S>& P, const Tab& tab, const V3<float>& wi,
                                                   XState<G, S, MP>& X)
@@ -469,12 +481,7 @@ __host__ __device__ inline void state_after_plies(const Derived<G, S>& P, const 
     X.rawf = gft;
     X.Gp = Narrow<S>::from(G(1) - G(val(P.rho_p)) * (G(1) - raw));
     X.Gf = Narrow<S>::from(G(1) - G(val(P.rho_f)) * (G(1) - gft));
-    X.mu_i = Narrow<S>::from(dot(X.wi_g, X.fx.n));
-    S PR = fresnel<S>(val(X.mu_i) > 0.0f ? X.mu_i : S(0), P.eta);
-    X.w[0] = (S(1) - P.B) * PR;
-    X.w[1] = (S(1) - P.B) * (S(1) - PR);
-    X.w[2] = P.B * P.r;
-    X.w[3] = P.B * (S(1) - P.r);
+    lobe_weights(P, X);
 }
 
 // Everything at x that does not depend on wo: ply hit, fiber frame,

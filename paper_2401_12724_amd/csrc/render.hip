@@ -8,8 +8,9 @@
 //               their radiance to the path's slot and end it
 //   k_r_shade   BYSDF at the hit (wave-uniform type): one state at x and one
 //               set of forward nodes serve the next-event evaluation and
-//               the sample; far field by the
-//               LOD rule; appends a shadow ray and the continued path
+//               the sample; far field by the LOD rule, or the
+//               multi-scale model over the pixel footprint of a camera
+//               hit; appends a shadow ray and the continued path
 //               (wave-aggregated atomics: compaction)
 //   k_r_shadow  shadow rays; a yarn whose implicit plies are missed is
 //               passed through; an unblocked ray adds its contribution
@@ -26,6 +27,7 @@
 
 #include "../../include/bysdf.h"
 #include "bysdf_model.hpp"
+#include "bysdf_multi.hpp"
 #include "lib_internal.hpp"
 #include "philox.hpp"
 #include "yarn_tube.hpp"
@@ -69,6 +71,7 @@ struct RView {
     double area, eu2, ev2;
     float Le[3], env[3];
     int W, H, cx, cy, cw, ch, spp, max_depth, n_h;
+    int multiscale;
     float lod_px;
     double eps;
     uint32_t key0, key1;
@@ -269,7 +272,46 @@ __device__ inline void far_eval(const Derived<double, float>& P, const TabPtr& t
     *pdf /= n_h;
 }
 
-template <int MP>
+// Custom ray differentials (Sec. 5.3): the azimuthal offsets covered by the
+// pixel of a camera hit.  The yarn is taken as the straight tube of radius R
+// along T through the hit's axis point c (the hit lies at azimuth
+// psi = atan2(wi) + asin h from c in the (N, T x N) plane), and a ray's
+// offset is its signed distance from that axis over R, the h of the
+// intersection.  The offsets of the rays one pixel to the right and one
+// pixel up give the screen-space gradient of h; the rays one pixel along and
+// against that gradient give the two ends, cut at +-1; h0 lies between.
+__device__ inline void camera_footprint(const RView& V, D3 o, D3 d, double t, D3 T, D3 N, double R,
+                                        float h0, float* h1, float* h2)
+{
+    const D3 B = yarn::cross(T, N);
+    const D3 p = o + d * t;
+    const double psi = atan2(-yarn::dot(d, B), -yarn::dot(d, N)) + asin((double)h0);
+    const D3 c = p - (N * cos(psi) + B * sin(psi)) * R;
+    const D3 e = o - c;
+    const double ex = yarn::dot(e, N), ey = yarn::dot(e, B);
+    const D3 f = dv(V.f), r = dv(V.r), u = dv(V.u);
+    const double df = yarn::dot(d, f);
+    const double sx = yarn::dot(d, r) / df, sy = yarn::dot(d, u) / df;
+    const double px = 2.0 * V.th * V.aspect / V.W, py = 2.0 * V.th / V.H;
+    auto offset = [&](double a, double b) {
+        const D3 dd = yarn::unit(f + r * (sx + a * px) + u * (sy + b * py));
+        const double dx = yarn::dot(dd, N), dy = yarn::dot(dd, B);
+        const double l = sqrt(dx * dx + dy * dy);
+        return l > 1e-12 ? (ex * dy - ey * dx) / (l * R) : (double)h0;
+    };
+    const double gx = offset(1.0, 0.0) - h0, gy = offset(0.0, 1.0) - h0;
+    const double gl = sqrt(gx * gx + gy * gy);
+    double lo = h0, hi = h0;
+    if (gl > 0.0) {
+        const double hp = offset(gx / gl, gy / gl), hm = offset(-gx / gl, -gy / gl);
+        lo = fmin(lo, fmax(-1.0, fmin(hp, hm)));
+        hi = fmax(hi, fmin(1.0, fmax(hp, hm)));
+    }
+    *h1 = (float)lo;
+    *h2 = (float)hi;
+}
+
+template <int MP, bool MS>
 #ifndef RENDER_SHADE_MIN_WAVES
 #define RENDER_SHADE_MIN_WAVES 1
 #endif
@@ -306,7 +348,12 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
         D3 p = o + d * (double)t;
         V3<float> wi = to_loc(T, N, d * -1.0);
         D3 pe = p - dv(V.eye);
-        const bool far = 2.0 * R / (sqrt(yarn::dot(pe, pe)) * V.pix_angle) < V.lod_px;
+        // multi-scale: the camera hits use their pixel footprint, later
+        // bounces the near field; otherwise the far field by the LOD rule
+        const bool msx = MS && depth == 0;
+        const bool far = !MS && 2.0 * R / (sqrt(yarn::dot(pe, pe)) * V.pix_angle) < V.lod_px;
+        float fh1 = hq, fh2 = hq;
+        if (msx && act) camera_footprint(V, o, d, (double)t, T, N, (double)R, hq, &fh1, &fh2);
         const uint64_t slot = (uint64_t)(lid / spp_batch) * V.spp + j0 + lid % spp_batch;
         float u1[4] = {0, 0, 0, 0}, u2[4] = {0, 0, 0, 0};
         if (act) {
@@ -332,7 +379,20 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             TabPtr tab{V.tables + V.types[tu].table_off};
             SampleOut<float> so;
             uint32_t sf = 0;
-            if (!far) {
+            if (msx) {
+                const TypeRec& Rt = V.types[tu];
+                bysdf::Footprint fp;
+                bysdf::make_footprint(hq, fh1, fh2, u2[2], V.n_h, fp);
+                const Derived<double, float> Pm = bysdf::widened(P, Rt.beta, Rt.aniso, fp);
+                if (cosl > 0.0) {
+                    EvalOut<float> e;
+                    bysdf::eval_multi<double, float, MP>(Pm, tab, fp, uq, vl, wi, wol, 0.0f, 0.0f, false, e);
+                    for (int c = 0; c < 3; ++c) En[c] = e.E[c];
+                    pb = e.pdf;
+                }
+                sf = bysdf::sample_multi<double, float, MP>(Pm, tab, fp, u2[1], uq, vl, wi, u1[2], u1[3],
+                                                            u2[0], 0.0f, 0.0f, false, so);
+            } else if (!far) {
                 // the light direction and the drawn one share the state at x
                 // and the forward nodes
                 XState<double, float, MP> X;
@@ -524,6 +584,10 @@ int check_settings(const render_settings* rs)
         return fail(BYSDF_ERR_INVALID_PARAM, "need spp >= 1, 0 <= max_depth <= 64, 1 <= n_h <= 64");
     if (rs->spp_batch < 0 || rs->spp_batch > rs->spp)
         return fail(BYSDF_ERR_INVALID_PARAM, "spp_batch must be in [0, spp]");
+    if (rs->multiscale != 0 && rs->multiscale != 1)
+        return fail(BYSDF_ERR_INVALID_PARAM, "multiscale must be 0 or 1");
+    if (rs->multiscale && rs->n_h > bysdf::kMaxStrata)
+        return fail(BYSDF_ERR_INVALID_PARAM, "multi-scale rendering needs n_h <= 16");
     if (!(rs->vfov > 0.f && rs->vfov < 3.1f) || !(rs->ray_eps >= 0.f) || !(rs->lod_px >= 0.f))
         return fail(BYSDF_ERR_INVALID_PARAM, "need 0 < vfov < 3.1, ray_eps >= 0, lod_px >= 0");
     int b = rs->spp_batch ? rs->spp_batch : rs->spp;
@@ -630,6 +694,7 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
     V.max_depth = rs->max_depth;
     V.n_h = rs->n_h;
     V.lod_px = rs->lod_px;
+    V.multiscale = rs->multiscale;
     V.eps = rs->ray_eps;
     V.key0 = (uint32_t)rs->seed;
     V.key1 = (uint32_t)(rs->seed >> 32);
@@ -692,12 +757,10 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
                                stream, V, Qs[a], cnt + a, Hh, L, n, depth);
             if (depth == rs->max_depth) break;
             hipLaunchKernelGGL(k_r_counters, dim3(1), dim3(64), 0, stream, cnt, b, 2, -1);
-            if (mp4)
-                hipLaunchKernelGGL(k_r_shade<4>, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream,
-                                   V, Qs[a], cnt + a, Hh, Qs[b], cnt + b, SQ, cnt + 2, n, depth, j0, nb);
-            else
-                hipLaunchKernelGGL(k_r_shade<8>, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream,
-                                   V, Qs[a], cnt + a, Hh, Qs[b], cnt + b, SQ, cnt + 2, n, depth, j0, nb);
+            auto shade = rs->multiscale ? (mp4 ? k_r_shade<4, true> : k_r_shade<8, true>)
+                                        : (mp4 ? k_r_shade<4, false> : k_r_shade<8, false>);
+            hipLaunchKernelGGL(shade, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream, V,
+                               Qs[a], cnt + a, Hh, Qs[b], cnt + b, SQ, cnt + 2, n, depth, j0, nb);
             hipLaunchKernelGGL(k_r_tally, dim3(1), dim3(64), 0, stream, cnt, 2, stats, 1);
             hipLaunchKernelGGL(mp4 ? k_r_shadow<4> : k_r_shadow<8>, dim3(grid_for(n, kTraceBlock, 16384)),
                                dim3(kTraceBlock), stk_bytes, stream, V, SQ, cnt + 2, L, n);

@@ -180,3 +180,33 @@ def test_invalid_migration_params_rejected(L, field, value):
     assert L.bysdf_types_create(arr, 1, C.byref(h), None) == bysdf.ERR_INVALID_PARAM
     assert h.value is None
     assert "mig" in L.bysdf_last_error().decode()
+
+
+def test_multi_scale_arguments_rejected_on_host(L):
+    """The multi-scale entry points check their arguments before any device
+    work: NULL handles or footprints, n_max outside 1..16, misaligned
+    footprint pointers.  (The handle is never dereferenced on these paths.)"""
+    assert L.bysdf_eval_multi(None, None, None, 0, 4, None, None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_sample_multi(None, None, None, 0, 4, None, None) == bysdf.ERR_INVALID_ARG
+    dummy = C.c_void_p(0x1000)
+    qs, ss, es, so = bysdf.QuerySoA(), bysdf.SampleSoA(), bysdf.EvalOutSoA(), bysdf.SampleOutSoA()
+    buf = (C.c_float * 8)()
+    base = C.addressof(buf)
+    fs = bysdf.FootprintSoA(base, base, base, base)
+    for n_max in (0, 17, -3):
+        assert L.bysdf_eval_multi(dummy, C.byref(qs), C.byref(fs), 1, n_max, C.byref(es),
+                                  None) == bysdf.ERR_INVALID_ARG
+        assert L.bysdf_sample_multi(dummy, C.byref(ss), C.byref(fs), 1, n_max, C.byref(so),
+                                    None) == bysdf.ERR_INVALID_ARG
+        assert "n_max" in L.bysdf_last_error().decode()
+    assert L.bysdf_eval_multi(dummy, C.byref(qs), None, 1, 4, C.byref(es), None) == bysdf.ERR_INVALID_ARG
+    bad = bysdf.FootprintSoA(base + 2, base, base, base)
+    assert L.bysdf_eval_multi(dummy, C.byref(qs), C.byref(bad), 1, 4, C.byref(es),
+                              None) == bysdf.ERR_INVALID_ARG
+    # the sampler needs xi_s, the evaluation does not
+    no_xs = bysdf.FootprintSoA(base, base, base, None)
+    assert L.bysdf_sample_multi(dummy, C.byref(ss), C.byref(no_xs), 1, 4, C.byref(so),
+                                None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_eval_multi(dummy, C.byref(qs), C.byref(no_xs), -1, 4, C.byref(es),
+                              None) == bysdf.ERR_INVALID_ARG
+    assert L.bysdf_eval_multi(dummy, C.byref(qs), C.byref(no_xs), 0, 4, C.byref(es), None) == bysdf.OK

@@ -1,0 +1,175 @@
+"""GPU parity of the multi-scale BYSDF (Sec. 4.2, Eq. 8-11) against the FP64
+oracle: bysdf_eval_multi and bysdf_sample_multi on footprints of every
+width (a point up to the whole yarn), on one type, on mixed types with
+fiber migration and up to 5 plies, in the near-field limit, on bad
+footprints, and on the full 2^24-query per-block workload in the launch the
+benchmark times (sampled)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_12724_amd import bysdf, workloads as W
+
+from parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _mixed_types():
+    return [W.default_params(), W.default_params(beta=0.08, aniso=2.0),
+            W.default_params(mig_tables=4, mig_period=3.0, mig_blend=0.25, mig_spread=0.4,
+                             mig_seed=11),
+            W.default_params(n_plies=5, ply_radius=W.packed_ply_radius(5), K=6),
+            W.default_params(n_plies=2, ply_radius=W.packed_ply_radius(2), fibers_per_ply=40,
+                             tex_size=256)]
+
+
+def _check_eval(ev, ef, o, of, tag, max_flagged=0.06):
+    rep = compare(ev.cpu().numpy().T, ef.cpu().numpy(), o[:, :12], of)
+    print(tag, "eval", {k: v for k, v in rep.items() if k != "bad_idx"})
+    assert_parity(rep, max_flagged=max_flagged)
+
+
+def _check_sample(sv, lobe, node, sf, so, sof, tag, max_flagged=0.06):
+    rep = compare(sv.cpu().numpy().T, sf.cpu().numpy(), so[:, :10], sof)
+    print(tag, "sample", {k: v for k, v in rep.items() if k != "bad_idx"})
+    assert_parity(rep, max_flagged=max_flagged)
+    ok = (sof & oracle.MARGIN_MASK) == 0
+    nd = node.cpu().numpy()
+    assert np.array_equal(lobe.cpu().numpy()[ok], so[ok, 10].astype(np.int32))
+    assert np.array_equal((nd & 15)[ok], so[ok, 11].astype(np.int32))
+    assert np.array_equal((nd >> 4)[ok], so[ok, 12].astype(np.int32))
+
+
+@pytest.mark.parametrize("n_max", [4, 16])
+def test_multi_single_type(torch_cuda, n_max):
+    torch = torch_cuda
+    P = [W.default_params()]
+    _, q = W.single_type(3 * 65536 + 77, 60, with_xi=True)
+    q = W.footprints(q, 61)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, n_max)
+    sv, lobe, node, sf = bysdf.bysdf_sample_multi(T, qd, n_max)
+    torch.cuda.synchronize()
+    o, of = oracle.eval_multi(P, q, n_max)
+    _check_eval(ev, ef, o, of, "single n_max=%d" % n_max)
+    so, sof = oracle.sample_multi(P, q, n_max)
+    _check_sample(sv, lobe, node, sf, so, sof, "single n_max=%d" % n_max)
+    # strata actually used: wide footprints reach n_max
+    nst = (node.cpu().numpy() >> 4)
+    assert nst.max() == n_max - 1
+
+
+def test_multi_mixed_types(torch_cuda):
+    torch = torch_cuda
+    P = _mixed_types()
+    n = 2 * 65536 + 301
+    q = W.queries(n, 62, n_types=len(P), with_xi=True, v_max=40.0)
+    q = W.footprints(q, 63)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, 8)
+    sv, lobe, node, sf = bysdf.bysdf_sample_multi(T, qd, 8)
+    torch.cuda.synchronize()
+    o, of = oracle.eval_multi(P, q, 8)
+    _check_eval(ev, ef, o, of, "mixed")
+    so, sof = oracle.sample_multi(P, q, 8)
+    _check_sample(sv, lobe, node, sf, so, sof, "mixed")
+
+
+def test_multi_zero_width_is_bysdf_eval(torch_cuda):
+    """h1 = h2 = h: the multi-scale kernels compute the near-field values."""
+    torch = torch_cuda
+    P = [W.default_params(), W.default_params(beta=0.1)]
+    q = W.queries(65536 + 5, 64, n_types=2, with_xi=True)
+    q["h1"] = q["h"].copy()
+    q["h2"] = q["h"].copy()
+    q["zeta"] = np.random.default_rng(65).random(len(q["h"])).astype(np.float32)
+    q["xi_s"] = np.random.default_rng(66).random(len(q["h"])).astype(np.float32)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval(T, qd)
+    mv, mf = bysdf.bysdf_eval_multi(T, qd, 4)
+    sv, lobe, node, sf = bysdf.bysdf_sample_pdf(T, qd)
+    tv, tlobe, tnode, tf = bysdf.bysdf_sample_multi(T, qd, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(ef, mf) and torch.equal(sf, tf) and torch.equal(lobe, tlobe)
+    assert torch.equal(node, tnode)
+    assert torch.allclose(ev, mv, rtol=2e-6, atol=1e-9)
+    assert torch.allclose(sv, tv, rtol=2e-6, atol=1e-9)
+
+
+def test_multi_edge_cases(torch_cuda):
+    """Empty input; bad footprints (reversed, outside [-1, 1], zeta or xi_s
+    out of [0, 1), NaN) flag BAD_INPUT with zero outputs; one query; a
+    footprint covering the whole yarn; n_max = 1."""
+    torch = torch_cuda
+    P = [W.default_params()]
+    T = bysdf.bysdf_types_create(P)
+    _, q = W.single_type(0, 67, with_xi=True)
+    q = W.footprints(q, 68)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, 4)
+    sv, _, _, sf = bysdf.bysdf_sample_multi(T, qd, 4)
+    assert ev.shape == (12, 0) and sv.shape == (10, 0)
+    _, q = W.single_type(8, 69, with_xi=True)
+    q["h"] = np.full(8, 0.1, np.float32)
+    q["h1"] = np.array([0.2, -0.2, -0.2, -0.2, -0.2, -1.5, np.nan, -1.0], np.float32)
+    q["h2"] = np.array([0.5, 0.05, 1.5, 0.5, 0.5, 0.5, 0.5, 1.0], np.float32)
+    q["zeta"] = np.array([0.5, 0.5, 0.5, 1.0, 0.5, 0.5, 0.5, 0.25], np.float32)
+    q["xi_s"] = np.array([0.5, 0.5, 0.5, 0.5, 1.0, 0.5, 0.5, 0.5], np.float32)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, 4)
+    sv, lobe, node, sf = bysdf.bysdf_sample_multi(T, qd, 4)
+    torch.cuda.synchronize()
+    efn, sfn = ef.cpu().numpy(), sf.cpu().numpy()
+    bad_e = [0, 1, 2, 3, 5, 6]
+    assert np.all(efn[bad_e] & bysdf.FLAG_BAD_INPUT)
+    assert not efn[4] & bysdf.FLAG_BAD_INPUT and not efn[7] & bysdf.FLAG_BAD_INPUT
+    assert np.all(ev.cpu().numpy()[:, bad_e] == 0)
+    assert np.all(sfn[:7] & bysdf.FLAG_BAD_INPUT) and not sfn[7] & bysdf.FLAG_BAD_INPUT
+    assert np.all(lobe.cpu().numpy()[:7] == -1)
+    o, of = oracle.eval_multi(P, q, 4)
+    so, sof = oracle.sample_multi(P, q, 4)
+    assert np.array_equal(efn & bysdf.FLAG_BAD_INPUT, of & oracle.BAD_INPUT)
+    assert np.array_equal(sfn & bysdf.FLAG_BAD_INPUT, sof & oracle.BAD_INPUT)
+    for i in (4, 7):
+        if not of[i] & oracle.MARGIN_MASK:
+            assert np.allclose(ev.cpu().numpy()[:, i], o[i, :12], rtol=1e-4, atol=1e-6)
+    # n_max = 1 on a wide footprint: one stratum with the widened roughness
+    _, q = W.single_type(65536, 70, with_xi=True)
+    q = W.footprints(q, 71)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, 1)
+    torch.cuda.synchronize()
+    o, of = oracle.eval_multi(P, q, 1)
+    _check_eval(ev, ef, o, of, "n_max=1", max_flagged=0.03)
+
+
+def test_multi_full_size_sampled(torch_cuda):
+    """The per-block workload (2^24 queries, 65,536 parameter blocks) with a
+    footprint per query in the launch the benchmark's multi-scale extra
+    times, checked on 6,000 sampled queries."""
+    torch = torch_cuda
+    P, q = W.per_block(65536, 256, seed=1)
+    q = W.footprints(q, 1)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, 4)
+    sv, lobe, node, sf = bysdf.bysdf_sample_multi(T, qd, 4)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(2).choice(len(q["h"]), 6000, replace=False))
+    sub = {k: (v[..., idx] if v is not None else None) for k, v in q.items()}
+    ts = oracle.TypeSet(P)
+    o, of = oracle.eval_multi(ts, sub, 4)
+    _check_eval(ev[:, idx], ef[idx], o, of, "full")
+    so, sof = oracle.sample_multi(ts, sub, 4)
+    _check_sample(sv[:, idx], lobe[idx], node[idx], sf[idx], so, sof, "full")

@@ -155,3 +155,18 @@ def test_small_weave_with_fiber_migration(torch_cuda):
     g, o, sq, _ = _render_both(torch, scene, P, rs)
     _check(g, o, sq, rs["spp"], "migration")
     _paths_equal(torch, scene, P, _settings(cam, (24, 12, 48, 48)), "migration", 0.85)
+
+
+def test_multiscale_matches_oracle(torch_cuda):
+    """Multi-scale mode (Sec. 4.2, 5.3): camera hits shaded by f_multi over
+    the footprint of their custom ray differentials (a distant view, so the
+    footprints span up to the whole yarn), later bounces near field."""
+    torch = torch_cuda
+    scene = W.weave(12, 12, 0.15, 0.05, 4)
+    P = [W.default_params()]
+    cam = W.camera((0.0, -3.2, 1.8), (0.0, 0.0, 0.0), width=96, height=72)
+    rs = _settings(cam, (36, 24, 24, 24), multiscale=1, n_h=8)
+    g, o, sq, _ = _render_both(torch, scene, P, rs)
+    _check(g, o, sq, rs["spp"], "multiscale")
+    _paths_equal(torch, scene, P, _settings(cam, (24, 12, 48, 48), multiscale=1, n_h=8),
+                 "multiscale", 0.85)

@@ -93,3 +93,99 @@ def test_nee_and_bysdf_sampling_agree():
     d = a.mean() - b.mean()
     print("nee", a.mean(), "bysdf only", b.mean(), "z", d / np.sqrt(va + vb))
     assert abs(d) < 4 * np.sqrt(va + vb)
+
+
+def _straight_yarn(R=0.05, n=12):
+    ctrl = np.zeros((n, 4), np.float32)
+    ctrl[:, 0] = np.linspace(-1.5, 1.5, n)
+    ctrl[:, 3] = R
+    return ctrl, np.array([0, n], np.int64)
+
+
+def _camera_rays(cam, px, py):
+    """The camera model written out: rays through pixel positions (px, py)."""
+    eye = np.array(cam["eye"], np.float64)
+    f = np.array(cam["look_at"], np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.array(cam["up"], np.float64))
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    th = np.tan(0.5 * cam["vfov"])
+    sx = (2.0 * np.asarray(px) / cam["width"] - 1.0) * th * cam["width"] / cam["height"]
+    sy = (1.0 - 2.0 * np.asarray(py) / cam["height"]) * th
+    d = f[None, :] + sx[:, None] * r[None, :] + sy[:, None] * u[None, :]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.repeat(eye[None, :], len(d), 0)
+    return o.astype(np.float32), d.astype(np.float32)
+
+
+def test_camera_footprint_against_cast_rays():
+    """Custom ray differentials (Sec. 5.3) on a straight yarn, where their
+    local straight-tube model is exact: h1 and h2 are the extreme offsets h
+    of the rays cast through the circle of one pixel around the sample
+    (brute-force intersections with the tube), cut at -1 and 1 where part
+    of the circle misses the yarn."""
+    ctrl, off = _straight_yarn()
+    S = oracle.Scene(ctrl, off)
+    checked = edges = 0
+    for eye, w, h in (((0.3, -1.0, 0.4), 160, 120), ((0.2, -3.0, 1.5), 96, 72)):
+        cam = W.camera(eye, (0.0, 0.0, 0.0), width=w, height=h)
+        rs = _settings(cam, (0, 0, w, h))
+        ang = 2 * np.pi * np.arange(256) / 256
+        for px in np.linspace(0.3 * w, 0.7 * w, 5):
+            for py in np.arange(0.5, h, 0.37):
+                y, h0, h1, h2 = oracle.camera_footprint(S, rs, px, py)
+                if y < 0:
+                    continue
+                o, d = _camera_rays(cam, px + np.cos(ang), py + np.sin(ang))
+                hit = oracle.intersect(S, o, d, np.full(len(o), 1e30, np.float32))
+                miss = (hit[:, 12].astype(np.int64) & oracle.HIT_MISS) != 0
+                assert h1 <= h0 <= h2
+                tol = 2e-3 * (h2 - h1) + 2e-6
+                if miss.any():
+                    if not miss.all():
+                        assert h1 <= -1.0 + tol or h2 >= 1.0 - tol, (px, py, h1, h2)
+                        edges += 1
+                    continue
+                hs = hit[:, 4]
+                assert abs(h1 - hs.min()) < tol and abs(h2 - hs.max()) < tol, (px, py, h1, h2,
+                                                                              hs.min(), hs.max())
+                checked += 1
+    assert checked >= 20 and edges >= 4, (checked, edges)
+
+
+def test_multiscale_nee_and_bysdf_sampling_agree():
+    """In multi-scale mode the camera hits are shaded by f_multi: next-event
+    estimation with MIS and BYSDF sampling alone estimate the same image
+    (pins the multi-scale pdf the renderer weights with)."""
+    S, ty, ph = _scene(6)
+    P = [W.default_params()]
+    cam = W.camera((0.0, -2.5, 1.8), (0.0, 0.0, 0.0), width=40, height=40)
+    base = dict(env_radiance=(0.0, 0.0, 0.0), light_corner=(-3.0, -3.0, 2.0),
+                light_u=(0.0, 6.0, 0.0), light_v=(6.0, 0.0, 0.0), light_radiance=(1.0, 1.0, 1.0),
+                max_depth=2, multiscale=1, n_h=8)
+    a, a2 = oracle.render(S, P, ty, ph, _settings(cam, (8, 8, 24, 24), spp=32, seed=1, **base))
+    b, b2 = oracle.render(S, P, ty, ph, _settings(cam, (8, 8, 24, 24), spp=256, seed=2, nee=0,
+                                                  **base))
+    va = np.maximum(a2 - a * a, 0).sum() / 32 / a.size ** 2
+    vb = np.maximum(b2 - b * b, 0).sum() / 256 / b.size ** 2
+    d = a.mean() - b.mean()
+    print("multiscale nee", a.mean(), "bysdf only", b.mean(), "z", d / np.sqrt(va + vb))
+    assert abs(d) < 4 * np.sqrt(va + vb)
+
+
+def test_multiscale_white_furnace_image():
+    """The multi-scale BYSDF is a weighted mean of lossless near-field
+    models (with pass-through for the strata between the plies), so the
+    white furnace still averages to one."""
+    S, ty, ph = _scene()
+    P = [W.default_params(B=1.0, albedo=(1.0, 1.0, 1.0), ply_density=0.0, fiber_density=0.0)]
+    cam = W.camera((0.0, -3.0, 1.6), (0.0, 0.0, 0.0), width=48, height=48)
+    rs = _settings(cam, (8, 8, 32, 32), light_radiance=(0.0, 0.0, 0.0), env_radiance=(1.0, 1.0, 1.0),
+                   light_corner=(-5.0, -5.0, -30.0), spp=16, max_depth=32, multiscale=1, n_h=8)
+    fb, sq = oracle.render(S, P, ty, ph, rs)
+    var = np.maximum(sq - fb * fb, 0.0)
+    m = fb.mean()
+    sigma = np.sqrt(var.mean() / (fb.size * rs["spp"] / 3))
+    print("multiscale furnace mean", m, "sigma", sigma)
+    assert abs(m - 1.0) < 4 * sigma + 2e-3
