@@ -470,10 +470,16 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sa
 }
 
 // ------------------------------------------------------------------ multi-scale
-// The multi-scale model (Sec. 4.2, Eq. 8-11): one query per lane, its
-// footprint's strata in a loop (first the aggregated geometry, then the
-// near-field lobes of every stratum with it).  Lanes of a wavefront with
-// fewer strata idle while the widest footprint finishes.
+// The multi-scale model (Sec. 4.2, Eq. 8-11).  A footprint costs one
+// near-field state per stratum for its aggregated geometry and one state
+// plus the lobes per stratum for f_multi, and its strata count ranges over
+// 1..n_max: one query per lane would let a wavefront run as long as its
+// widest footprint.  Instead each wavefront takes 64 queries, numbers their
+// (query, stratum) items (an exclusive scan of the strata counts) and deals
+// the items to its lanes 64 at a time; each item's result returns to the
+// lane of its query through cross-lane shuffles, summed in stratum order
+// (the arithmetic and its order are those of the one-query-per-lane model
+// functions, so results are bitwise reproducible).
 struct FPtrs {
     const float *h1, *h2, *zeta, *xi_s;
 };
@@ -481,6 +487,156 @@ struct FPtrs {
 #ifndef BYSDF_MULTI_MIN_WAVES
 #define BYSDF_MULTI_MIN_WAVES 2
 #endif
+
+__device__ inline int wave_excl_scan(int x)
+{
+    const int lane = __lane_id();
+    int s = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(s, d);
+        if (lane >= d) s += y;
+    }
+    return s - x;
+}
+
+__device__ inline int wave_max(int x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int y = __shfl_xor(x, d);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// The lane whose items include item k: the last lane whose first item is
+// at most k (a lane without items shares its first item with the next).
+__device__ inline int item_owner(int first, int k)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = kWave / 2; step >= 1; step >>= 1) {
+        const int c = lo + step;
+        if (__shfl(first, c) <= k) lo = c;
+    }
+    return lo;
+}
+
+__device__ inline V3<double> shfl3(const V3<double>& a, int src)
+{
+    return mk3<double>(__shfl(a.x, src), __shfl(a.y, src), __shfl(a.z, src));
+}
+
+// A multi-scale query read from the query arrays (eval or sampler layout).
+struct MQuery {
+    float h, u, v, h1, h2, zeta;
+    V3<float> wi;
+};
+template <class QP>
+__device__ inline MQuery load_mquery(const QP& q, const FPtrs& fp, int64_t i)
+{
+    MQuery m;
+    m.h = q.h[i];
+    m.u = q.u[i];
+    m.v = q.v[i];
+    m.h1 = fp.h1[i];
+    m.h2 = fp.h2[i];
+    m.zeta = fp.zeta[i];
+    m.wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+    return m;
+}
+
+// Aggregated geometry (Eq. 9-11) of the wavefront's 64 footprints.  On
+// return each lane holds its footprint's frame and shadowing, as
+// footprint_geometry computes them; `any` is false when no stratum of
+// positive weight hits a ply.
+template <bool kLds, int MP, bool MIG, class QP>
+__device__ inline void wave_footprint_geometry(const TypeRec* __restrict__ types,
+                                               const float4* __restrict__ tables, const float4* s_tab,
+                                               const QP& q, const FPtrs& fp, int n_max, int64_t b,
+                                               int t, int first, int nq, int S, Frame<double>& F,
+                                               float& Gm, bool& any, uint32_t& fl)
+{
+    V3<double> sn = mk3<double>(0.0, 0.0, 0.0), st = sn, n0 = sn, t0 = sn;
+    double sg = 0.0, sw = 0.0, g0 = 0.0;
+    int have = 0;
+    for (int r0 = 0; r0 < S; r0 += kWave) {
+        const int k = r0 + __lane_id();
+        const bool item = k < S;
+        const int own = item_owner(first, k);
+        const int j = k - __shfl(first, own);
+        const int to = __shfl(t, own);
+        double w_it = 0.0, g_it = 0.0;
+        V3<double> n_it = mk3<double>(0.0, 0.0, 0.0), t_it = n_it;
+        uint32_t f_it = 0;
+        for_each_wave_type(to, item, [&](int tu) {
+            const TypeRec& R = types[tu];
+            TabPtrT<MIG> tab;
+            tab.p = kLds ? s_tab : tables + R.table_off;
+            const MQuery m = load_mquery(q, fp, b + own);
+            Footprint fo;
+            make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, fo);
+            const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, fo);
+            const float hj = stratum_h(fo, j);
+            const double w = stratum_w(fo, (double)hj);
+            XState<double, float, MP> X;
+            state_at_x(Pm, tab, hj, m.u, m.v, m.wi, X);
+            f_it = X.ph.flags & ~F_PASS_THROUGH;
+            if (!X.ph.pass && w > 0.0) {
+                w_it = w;
+                n_it = X.fx.n;
+                t_it = X.fx.t;
+                g_it = 1.0 - (double)Pm.rho_f * (1.0 - X.rawf);
+            }
+        });
+        // this lane's items of the round, in stratum order
+        const int lo = first > r0 ? first : r0;
+        const int hi = first + nq < r0 + kWave ? first + nq : r0 + kWave;
+        const int cnt = hi > lo ? hi - lo : 0;
+        const int cmax = wave_max(cnt);
+        for (int jj = 0; jj < cmax; ++jj) {
+            const int src = (lo + jj - r0) & (kWave - 1);
+            const double ws = __shfl(w_it, src), gs = __shfl(g_it, src);
+            const V3<double> ns = shfl3(n_it, src), ts = shfl3(t_it, src);
+            const uint32_t fs = __shfl(f_it, src);
+            if (jj < cnt) {
+                fl |= fs;
+                if (ws > 0.0) {
+                    if (have == 0) {
+                        n0 = ns;
+                        t0 = ts;
+                        g0 = gs;
+                    }
+                    sn = sn + ns * ws;
+                    st = st + ts * ws;
+                    sg = sg + gs * ws;
+                    sw += ws;
+                    ++have;
+                }
+            }
+        }
+    }
+    any = have > 0;
+    F.n = n0;
+    F.t = t0;
+    F.b = cross(n0, t0);
+    Gm = (float)g0;
+    if (have > 1) {
+        Gm = (float)(sg / sw);
+        const double ln2 = dot(sn, sn);
+        if (ln2 > 1e-24 * sw * sw) {
+            const V3<double> nn = sn * rsqrt_(ln2);
+            const V3<double> tt = st - nn * dot(st, nn);
+            const double lt2 = dot(tt, tt);
+            if (lt2 > 1e-24 * sw * sw) {
+                F.n = nn;
+                F.t = tt * rsqrt_(lt2);
+                F.b = cross(F.n, F.t);
+            }
+        }
+    }
+}
 
 template <bool kLds, int MP, bool MIG>
 __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
@@ -492,33 +648,112 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
         __syncthreads();
     }
+    const int lane = __lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int t = q.type[i];
-        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
-        V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
-        float h = q.h[i], u = q.u[i], v = q.v[i];
-        float h1 = fp.h1[i], h2 = fp.h2[i], zeta = fp.zeta[i];
-        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
-        fl |= check_inputs(h, u, v, wi) | check_dir(wo) | check_footprint(h, h1, h2, zeta);
-        EvalOut<float> e;
-        for (int c = 0; c < 3; ++c) e.E[c] = e.ExB[c] = e.EyB[c] = 0.0f;
-        e.ExS = e.EyS = e.pdf = 0.0f;
-        for_each_wave_type(t, fl == 0u, [&](int tu) {
-            const TypeRec& R = types[tu];
-            TabPtrT<MIG> tab;
-            tab.p = kLds ? s_tab : tables + R.table_off;
-            Footprint f;
-            make_footprint(h, h1, h2, zeta, n_max, f);
-            const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, f);
-            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
-            fl = eval_multi<double, float, MP>(Pm, tab, f, u, v, wi, wo, s0, s1, q.s0 != nullptr, e);
-        });
-        o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
-        o.ExS[i] = e.ExS; o.EyS[i] = e.EyS;
-        o.ExBr[i] = e.ExB[0]; o.ExBg[i] = e.ExB[1]; o.ExBb[i] = e.ExB[2];
-        o.EyBr[i] = e.EyB[0]; o.EyBg[i] = e.EyB[1]; o.EyBb[i] = e.EyB[2];
-        o.pdf[i] = e.pdf;
+    // whole wavefronts iterate together (the cross-lane steps need every lane)
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); b < n; b += stride) {
+        const int64_t i = b + lane;
+        const bool in = i < n;
+        int t = in ? q.type[i] : 0;
+        uint32_t fl = F_BAD_INPUT;
+        Footprint f;
+        f.n = 0;
+        f.wsum = 1.0;
+        if (in) {
+            const MQuery m = load_mquery(q, fp, i);
+            const V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+            fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+            fl |= check_inputs(m.h, m.u, m.v, m.wi) | check_dir(wo) |
+                  check_footprint(m.h, m.h1, m.h2, m.zeta);
+            if (fl == 0u) make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, f);
+        }
+        const int nq = fl == 0u ? f.n : 0;
+        const int first = wave_excl_scan(nq);
+        const int S = __shfl(first + nq, kWave - 1);
+        Frame<double> F;
+        float Gm;
+        bool any;
+        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, first, nq, S, F,
+                                               Gm, any, fl);
+        if (nq > 0 && !any) fl |= F_PASS_THROUGH;
+        // f_multi: every stratum's lobes with the aggregated geometry
+        EvalOut<float> acc;
+        for (int c = 0; c < 3; ++c) acc.E[c] = acc.ExB[c] = acc.EyB[c] = 0.0f;
+        acc.ExS = acc.EyS = acc.pdf = 0.0f;
+        for (int r0 = 0; r0 < S; r0 += kWave) {
+            const int k = r0 + lane;
+            const int own = item_owner(first, k);
+            const int j = k - __shfl(first, own);
+            const int to = __shfl(t, own);
+            // every lane takes part in the shuffle (a lane outside the items
+            // may own items of this round)
+            const int any_o = __shfl((int)any, own);
+            const bool item = k < S && any_o != 0;
+            Frame<double> Fo;
+            Fo.n = shfl3(F.n, own);
+            Fo.t = shfl3(F.t, own);
+            Fo.b = shfl3(F.b, own);
+            const float Go = __shfl(Gm, own);
+            float ev[12];
+            for (int c = 0; c < 12; ++c) ev[c] = 0.0f;
+            float w_it = 0.0f;
+            int back = 0;
+            for_each_wave_type(to, item, [&](int tu) {
+                const TypeRec& R = types[tu];
+                TabPtrT<MIG> tab;
+                tab.p = kLds ? s_tab : tables + R.table_off;
+                const int64_t io = b + own;
+                const MQuery m = load_mquery(q, fp, io);
+                Footprint fo;
+                make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, fo);
+                const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, fo);
+                const float hj = stratum_h(fo, j);
+                XState<double, float, MP> X;
+                state_at_x(Pm, tab, hj, m.u, m.v, m.wi, X);
+                if (X.ph.pass) return;
+                apply_aggregate(Pm, X, Fo, Go);
+                back = !(X.mu_i > 0.0f);
+                const float s0 = q.s0 ? q.s0[io] : 0.0f, s1 = q.s1 ? q.s1[io] : 0.0f;
+                const V3<double> wo_g = mk3<double>(q.wox[io], q.woy[io], q.woz[io]);
+                EvalOut<float> e;
+                lobes(Pm, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
+                w_it = float(stratum_w(fo, (double)hj));
+                ev[0] = e.E[0]; ev[1] = e.E[1]; ev[2] = e.E[2];
+                ev[3] = e.ExS; ev[4] = e.EyS;
+                ev[5] = e.ExB[0]; ev[6] = e.ExB[1]; ev[7] = e.ExB[2];
+                ev[8] = e.EyB[0]; ev[9] = e.EyB[1]; ev[10] = e.EyB[2];
+                ev[11] = e.pdf;
+            });
+            const int lo = first > r0 ? first : r0;
+            const int hi = first + nq < r0 + kWave ? first + nq : r0 + kWave;
+            const int cnt = hi > lo ? hi - lo : 0;
+            const int cmax = wave_max(cnt);
+            for (int jj = 0; jj < cmax; ++jj) {
+                const int src = (lo + jj - r0) & (kWave - 1);
+                float es[12];
+                for (int c = 0; c < 12; ++c) es[c] = __shfl(ev[c], src);
+                const float ws = __shfl(w_it, src);
+                const int bs = __shfl(back, src);
+                if (jj < cnt) {
+                    if (bs) fl |= F_BACKFACING;
+                    for (int c = 0; c < 3; ++c) {
+                        acc.E[c] = acc.E[c] + ws * es[c];
+                        acc.ExB[c] = acc.ExB[c] + ws * es[5 + c];
+                        acc.EyB[c] = acc.EyB[c] + ws * es[8 + c];
+                    }
+                    acc.ExS = acc.ExS + ws * es[3];
+                    acc.EyS = acc.EyS + ws * es[4];
+                    acc.pdf = acc.pdf + ws * es[11];
+                }
+            }
+        }
+        if (!in) continue;
+        const float iw = float(1.0 / f.wsum);
+        o.Er[i] = acc.E[0] * iw; o.Eg[i] = acc.E[1] * iw; o.Eb[i] = acc.E[2] * iw;
+        o.ExS[i] = acc.ExS * iw; o.EyS[i] = acc.EyS * iw;
+        o.ExBr[i] = acc.ExB[0] * iw; o.ExBg[i] = acc.ExB[1] * iw; o.ExBb[i] = acc.ExB[2] * iw;
+        o.EyBr[i] = acc.EyB[0] * iw; o.EyBg[i] = acc.EyB[1] * iw; o.EyBb[i] = acc.EyB[2] * iw;
+        o.pdf[i] = acc.pdf * iw;
         o.flags[i] = fl;
     }
 }
@@ -533,31 +768,140 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
         __syncthreads();
     }
+    const int lane = __lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int t = q.type[i];
-        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
-        float h = q.h[i], u = q.u[i], v = q.v[i], x0 = q.xi0[i], x1 = q.xi1[i], x2 = q.xi2[i];
-        float h1 = fp.h1[i], h2 = fp.h2[i], zeta = fp.zeta[i], xs = fp.xi_s[i];
-        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
-        fl |= check_inputs(h, u, v, wi) | check_footprint(h, h1, h2, zeta);
-        if (!(xs >= 0.0f && xs < 1.0f)) fl |= F_BAD_INPUT;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); b < n; b += stride) {
+        const int64_t i = b + lane;
+        const bool in = i < n;
+        int t = in ? q.type[i] : 0;
+        uint32_t fl = F_BAD_INPUT;
+        Footprint f;
+        f.n = 0;
+        f.wsum = 1.0;
+        MQuery m{};
+        float xs = 0.0f;
+        if (in) {
+            m = load_mquery(q, fp, i);
+            xs = fp.xi_s[i];
+            fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+            fl |= check_inputs(m.h, m.u, m.v, m.wi) | check_footprint(m.h, m.h1, m.h2, m.zeta);
+            if (!(xs >= 0.0f && xs < 1.0f)) fl |= F_BAD_INPUT;
+            if (fl == 0u) make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, f);
+        }
+        const bool good = fl == 0u;
+        const int nq = good ? f.n : 0;
+        const int first = wave_excl_scan(nq);
+        const int S = __shfl(first + nq, kWave - 1);
+        Frame<double> F;
+        float Gm;
+        bool any;
+        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, first, nq, S, F,
+                                               Gm, any, fl);
+        // the stratum and the draw, per query
         SampleOut<float> so;
         for (int c = 0; c < 3; ++c) so.wo[c] = so.wgt[c] = so.ex[c] = 0.0f;
         so.pdf = 0.0f;
         so.lobe = -1;
         so.node = 0;
-        for_each_wave_type(t, fl == 0u, [&](int tu) {
+        int s = 0;
+        if (good) {
+            s = f.n - 1;
+            const double xw = (double)xs * f.wsum;
+            double cum = 0.0;
+            for (int jj = 0; jj < f.n - 1; ++jj) {
+                cum += stratum_w(f, (double)stratum_h(f, jj));
+                if (xw < cum) {
+                    s = jj;
+                    break;
+                }
+            }
+        }
+        V3<double> wo = mk3<double>(0.0, 0.0, 0.0);
+        bool drawn = false, pass = good && !any;
+        const float s0 = in && q.s0 ? q.s0[i] : 0.0f, s1 = in && q.s1 ? q.s1[i] : 0.0f;
+        for_each_wave_type(t, good && any, [&](int tu) {
             const TypeRec& R = types[tu];
             TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + R.table_off;
-            Footprint f;
-            make_footprint(h, h1, h2, zeta, n_max, f);
             const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, f);
-            float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
-            fl = sample_multi<double, float, MP>(Pm, tab, f, xs, u, v, wi, x0, x1, x2, s0, s1,
-                                                 q.s0 != nullptr, so);
+            XState<double, float, MP> X;
+            state_at_x(Pm, tab, stratum_h(f, s), m.u, m.v, m.wi, X);
+            pass = X.ph.pass;
+            if (pass) return;
+            apply_aggregate(Pm, X, F, Gm);
+            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
+            fl |= sample_draw(Pm, X, m.wi, q.xi0[i], q.xi1[i], q.xi2[i], nf, so, wo, drawn);
         });
+        if (pass) {
+            so.wo[0] = -m.wi.x;
+            so.wo[1] = -m.wi.y;
+            so.wo[2] = -m.wi.z;
+            so.wgt[0] = so.wgt[1] = so.wgt[2] = 1.0f;
+            so.lobe = 4;
+            fl |= F_PASS_THROUGH;
+        }
+        if (good) so.node += 16 * s;
+        // f_multi and its pdf at the drawn direction
+        EvalOut<float> em;
+        em.E[0] = em.E[1] = em.E[2] = 0.0f;
+        em.pdf = 0.0f;
+        for (int r0 = 0; r0 < S; r0 += kWave) {
+            const int k = r0 + lane;
+            const int own = item_owner(first, k);
+            const int j = k - __shfl(first, own);
+            const int to = __shfl(t, own);
+            const int drawn_o = __shfl((int)drawn, own);
+            const bool item = k < S && drawn_o != 0;
+            Frame<double> Fo;
+            Fo.n = shfl3(F.n, own);
+            Fo.t = shfl3(F.t, own);
+            Fo.b = shfl3(F.b, own);
+            const float Go = __shfl(Gm, own);
+            const V3<double> wd = shfl3(wo, own);
+            float ev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float w_it = 0.0f;
+            for_each_wave_type(to, item, [&](int tu) {
+                const TypeRec& R = types[tu];
+                TabPtrT<MIG> tab;
+                tab.p = kLds ? s_tab : tables + R.table_off;
+                const int64_t io = b + own;
+                const MQuery mo = load_mquery(q, fp, io);
+                Footprint fo;
+                make_footprint(mo.h, mo.h1, mo.h2, mo.zeta, n_max, fo);
+                const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, fo);
+                const float hj = stratum_h(fo, j);
+                XState<double, float, MP> X;
+                state_at_x(Pm, tab, hj, mo.u, mo.v, mo.wi, X);
+                if (X.ph.pass) return;
+                apply_aggregate(Pm, X, Fo, Go);
+                const float t0 = q.s0 ? q.s0[io] : 0.0f, t1 = q.s1 ? q.s1[io] : 0.0f;
+                EvalOut<float> e;
+                lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e);
+                w_it = float(stratum_w(fo, (double)hj));
+                ev[0] = e.E[0]; ev[1] = e.E[1]; ev[2] = e.E[2]; ev[3] = e.pdf;
+            });
+            const int lo = first > r0 ? first : r0;
+            const int hi = first + nq < r0 + kWave ? first + nq : r0 + kWave;
+            const int cnt = hi > lo ? hi - lo : 0;
+            const int cmax = wave_max(cnt);
+            for (int jj = 0; jj < cmax; ++jj) {
+                const int src = (lo + jj - r0) & (kWave - 1);
+                float es[4];
+                for (int c = 0; c < 4; ++c) es[c] = __shfl(ev[c], src);
+                const float ws = __shfl(w_it, src);
+                if (jj < cnt) {
+                    for (int c = 0; c < 3; ++c) em.E[c] = em.E[c] + ws * es[c];
+                    em.pdf = em.pdf + ws * es[3];
+                }
+            }
+        }
+        if (!in) continue;
+        if (drawn) {
+            const float iw = float(1.0 / f.wsum);
+            for (int c = 0; c < 3; ++c) em.E[c] = em.E[c] * iw;
+            em.pdf = em.pdf * iw;
+            fl = sample_finish(em, wo, fl, so);
+        }
         o.wox[i] = so.wo[0]; o.woy[i] = so.wo[1]; o.woz[i] = so.wo[2];
         o.wr[i] = so.wgt[0]; o.wg[i] = so.wgt[1]; o.wb[i] = so.wgt[2];
         o.pdf[i] = so.pdf;
