@@ -374,6 +374,32 @@ def _multiscale(torch, bysdf, W, P, q, qd, near_ms, n_max=4):
                     "geometry and as many again the lobes; the sampler adds its draw"}
 
 
+def _fit(torch, bysdf, W, steps=100):
+    """Image-space fitting (r, k^B, sigma_t by Adam on rendered gradients)
+    on a 48 x 48 crop of a 12 x 12 weave at 16 spp per step: time per step
+    (type record, image, image + gradient) and the parameters reached."""
+    from paper_2401_12724_amd import fit_image
+    ctrl, off, ty, ph = W.weave(12, 12, 0.15, 0.05, 4)
+    S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=96, height=72)
+    rs = dict(eye=cam["eye"], look_at=cam["look_at"], up=cam["up"], vfov=cam["vfov"], width=96,
+              height=72, crop_x=24, crop_y=12, crop_w=48, crop_h=48, light_corner=(-5.0, -5.0, 30.0),
+              light_u=(0.0, 10.0, 0.0), light_v=(10.0, 0.0, 0.0), light_radiance=(5.0, 5.0, 5.0),
+              env_radiance=(0.2, 0.2, 0.2), spp=16, max_depth=4, lod_px=1.0, n_h=4, seed=7,
+              ray_eps=1e-4, spp_batch=0)
+    hidden = W.default_params(r=0.35, sigma_t=1.2, albedo=(0.75, 0.45, 0.25))
+    target = bysdf.shade_wavefront(S, bysdf.bysdf_types_create([hidden]), dict(rs, spp=1024, seed=99))
+    th0 = fit_image.theta_of(W.default_params(r=0.6, sigma_t=0.4, albedo=(0.5, 0.5, 0.5)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, hist = fit_image.fit(S, [hidden], 0, target, rs, th0, steps=steps, lr=0.08)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"steps": steps, "ms_per_step": dt / steps * 1e3, "theta": [float(x) for x in th],
+            "truth": [float(x) for x in fit_image.theta_of(hidden)],
+            "params": "r, k^B (RGB), sigma_t"}
+
+
 def _weave_render(torch, bysdf, W, spp=4):
     """The plain weave (256 + 256 B-spline yarns, 524,288 spans) seen by the
     grazing 1920 x 1080 camera: primary-ray intersection of every pixel
@@ -415,6 +441,13 @@ def _weave_render(torch, bysdf, W, spp=4):
     fbm = torch.empty_like(fb)
     _, mcounts = bysdf.shade_wavefront(S, T, rm, fbm, ws, counts=True)
     mms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rm, fbm, ws), 3)
+    # the same frame with the image gradient in (r, k^B, sigma_t)
+    wsg = bysdf.alloc_workspace(int(bysdf.lib().shade_wavefront_grad_workspace_size(
+        bysdf.render_settings(rs))))
+    fbg = torch.empty_like(fb)
+    grd = torch.empty((cam["height"], cam["width"], 3, 3), dtype=torch.float32, device="cuda")
+    bysdf.shade_wavefront_grad(S, T, rs, 0, fbg, grd, wsg)
+    gms = _timed(torch, lambda: bysdf.shade_wavefront_grad(S, T, rs, 0, fbg, grd, wsg), 3)
     return {"scene": {"yarns": info["n_yarns"], "spans": info["n_spans"],
                       "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"],
                       "device_bytes": info["bytes"], "build_s": build_s},
@@ -425,6 +458,9 @@ def _weave_render(torch, bysdf, W, spp=4):
                        "rays_per_s": rays / (rms * 1e-3),
                        "paths_per_s": cam["width"] * cam["height"] * spp / (rms * 1e-3),
                        "mean_radiance": float(fb.mean())},
+            "render_grad": {"spp": spp, "ms": gms, "over_render_time": gms / rms,
+                            "mean_radiance": float(fbg.mean()),
+                            "note": "image and its gradient in r, k^B (RGB), sigma_t"},
             "render_multiscale": {"spp": spp, "n_max": 8, "ms": mms,
                                   "extension_rays": mcounts[0], "shadow_rays": mcounts[1],
                                   "paths_per_s": cam["width"] * cam["height"] * spp / (mms * 1e-3),
@@ -587,6 +623,7 @@ def main():
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
         out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
         out["weave"] = _weave_render(torch, bysdf, W)
+        out["fit"] = _fit(torch, bysdf, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(P, q, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -449,6 +449,29 @@ int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* types, const
  * verification against published known-answer vectors. */
 void bysdf_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* Workspace bytes of shade_wavefront_grad (the path queues carry the
+ * derivatives as well); 0 for invalid settings. */
+size_t shade_wavefront_grad_workspace_size(const render_settings* rs);
+
+/* shade_wavefront plus the image's gradient with respect to the body
+ * parameters that the paper fits by differentiable rendering (Sec. 5.2):
+ * r, the albedo k^B and sigma_t of yarn type grad_type.  grad: DEVICE
+ * float[crop_h][crop_w][3][3], grad[y][x][c][p] = d(pixel channel c) /
+ * d theta_p for theta = (r, k^B_c, sigma_t) (overwritten).  Each path
+ * carries d ln(throughput) / d theta; a hit adds dE/E of the value at the
+ * drawn direction, a shadow ray carries d(contribution)/d theta.  The
+ * sampling densities are held fixed (the MIS weights and the weights' pdf
+ * included), which keeps the estimate unbiased for the derivative of the
+ * expected image although the lobe choice depends on r.  The near field
+ * shades every hit (lod_px is not used); multiscale must be 0.  The
+ * derivatives are exact for r in (0, 1), k^B > 0, sigma_t > 0 (0 is
+ * returned for a parameter on its bound).  workspace:
+ * shade_wavefront_grad_workspace_size(rs) bytes, 256-byte aligned.  Other
+ * arguments and guarantees as shade_wavefront. */
+int shade_wavefront_grad(const yarn_scene_t* scene, const bysdf_types_t* types,
+                         const render_settings* rs, int32_t grad_type, float* framebuffer, float* grad,
+                         void* workspace, size_t ws_bytes, int64_t* ray_counts, hipStream_t stream);
+
 /* Host-only: algorithmic operation count of the kernels' formulation.
  * Runs the per-query model on the host with counting scalars over n
  * queries in HOST arrays (SoA: wi, wo, xi are [3][n]) of the single type

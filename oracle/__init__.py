@@ -61,7 +61,7 @@ class RenderSettings(C.Structure):
         ("light_radiance", C.c_float * 3), ("env_radiance", C.c_float * 3),
         ("spp", C.c_int32), ("max_depth", C.c_int32), ("lod_px", C.c_float), ("n_h", C.c_int32),
         ("seed", C.c_uint64), ("ray_eps", C.c_float), ("nee", C.c_int32),
-        ("multiscale", C.c_int32),
+        ("multiscale", C.c_int32), ("grad_type", C.c_int32),
     ]
 
 
@@ -70,6 +70,7 @@ def render_settings_struct(rs: dict) -> RenderSettings:
     rs = dict(rs)
     rs.setdefault("nee", 1)
     rs.setdefault("multiscale", 0)
+    rs.setdefault("grad_type", -1)
     for k, _ in RenderSettings._fields_:
         v = rs[k]
         if isinstance(v, (tuple, list)):
@@ -153,7 +154,7 @@ def lib():
         L.orc_scene_frame.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, dp]
         L.orc_intersect.argtypes = [C.c_void_p, C.c_int64, fp, fp, fp, C.c_double, dp, C.c_int]
         L.orc_render.argtypes = [C.c_void_p, pp, tp, C.c_int32, ip, fp, C.POINTER(RenderSettings),
-                                 dp, dp, C.c_int]
+                                 dp, dp, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -502,14 +503,18 @@ def camera_footprint(scene: Scene, rs: dict, px: float, py: float):
 def render(scene: Scene, ts, yarn_type, yarn_phase, rs: dict, nthreads: int = 0):
     """Crop of the image by the CPU path tracer (render_oracle.c).  ts: a
     TypeSet (or parameter dicts) indexed by yarn_type.  Returns (mean
-    (crop_h, crop_w, 3), mean of squares (crop_h, crop_w, 3))."""
+    (crop_h, crop_w, 3), mean of squares (crop_h, crop_w, 3)); with
+    rs["grad_type"] >= 0 also the gradient (crop_h, crop_w, 3, 3) of the
+    image with respect to (r, k^B_c, sigma_t) of that type."""
     ts = _types(ts)
     yt = np.ascontiguousarray(yarn_type, np.int32)
     ph = np.ascontiguousarray(yarn_phase, np.float32)
     st = render_settings_struct(rs)
     fb = np.zeros((rs["crop_h"], rs["crop_w"], 3))
     sq = np.zeros_like(fb)
+    want = rs.get("grad_type", -1) >= 0
+    gr = np.zeros((rs["crop_h"], rs["crop_w"], 3, 3)) if want else None
     lib().orc_render(scene._h, ts.structs, ts._tp, len(ts), _ptr(yt, C.c_int32),
                      _ptr(ph, C.c_float), C.byref(st), _ptr(fb, C.c_double), _ptr(sq, C.c_double),
-                     nthreads)
-    return fb, sq
+                     _ptr(gr, C.c_double), nthreads)
+    return (fb, sq, gr) if want else (fb, sq)

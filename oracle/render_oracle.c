@@ -200,9 +200,33 @@ int orc_camera_footprint(const void* scene, const orc_render_settings* rs, doubl
     return hr.yarn;
 }
 
+/* dE_c / d theta_p at one direction, theta = (r, k^B_c, sigma_t) (image
+ * fitting, Sec. 5.2): out[13] is the query's evaluation; the reflected body
+ * lobe is r times an r-free term and the transmitted one (1 - r) times one,
+ * both linear in k^B_c; sigma_t by central differences of the evaluation
+ * (only E_yS depends on it). */
+static void bysdf_derivs(const orc_params* P, const double* tab, double h, double u, double v,
+                         const double wi[3], const double wo[3], const double out[13], double dE[9])
+{
+    orc_params q = *P;
+    double hs = 1e-4 * (P->sigma_t > 1e-3 ? P->sigma_t : 1e-3);
+    double ep[13], em[13];
+    q.sigma_t = P->sigma_t + hs;
+    orc_eval_query(&q, tab, h, u, v, wi, wo, ep);
+    q.sigma_t = P->sigma_t - hs;
+    orc_eval_query(&q, tab, h, u, v, wi, wo, em);
+    double ds = (ep[4] - em[4]) / (2.0 * hs);
+    for (int c = 0; c < 3; ++c) {
+        double xb = out[5 + c], yb = out[8 + c];
+        dE[3 * c] = (P->r > 0.0 ? xb / P->r : 0.0) - (P->r < 1.0 ? yb / (1.0 - P->r) : 0.0);
+        dE[3 * c + 1] = P->albedo[c] > 0.0 ? (xb + yb) / P->albedo[c] : 0.0;
+        dE[3 * c + 2] = ds;
+    }
+}
+
 int orc_render(const void* scene, const orc_params* types, const double* const* tables,
                int32_t n_types, const int32_t* yarn_type, const float* yarn_phase,
-               const orc_render_settings* rs, double* fb, double* sq, int nthreads)
+               const orc_render_settings* rs, double* fb, double* sq, double* grad, int nthreads)
 {
     (void)n_types;
     ctx_t C = {scene, types, tables, yarn_type, yarn_phase};
@@ -226,7 +250,7 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
     for (int64_t pix = 0; pix < npix; ++pix) {
         int pxc = (int)(pix % rs->crop_w), pyc = (int)(pix / rs->crop_w);
         int px = rs->crop_x + pxc, py = rs->crop_y + pyc;
-        double acc[3] = {0, 0, 0}, acc2[3] = {0, 0, 0};
+        double acc[3] = {0, 0, 0}, acc2[3] = {0, 0, 0}, gacc[9] = {0};
         for (int j = 0; j < rs->spp; ++j) {
             uint64_t slot = (uint64_t)pix * rs->spp + j;
             double u0[4];
@@ -236,6 +260,9 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
             r3 o = r3f(eye);
             r3 d = r3f(runit(radd(f, radd(rscl(rr, sx), rscl(uu, sy)))));
             float thr[3] = {1.f, 1.f, 1.f}, L[3] = {0.f, 0.f, 0.f};
+            /* gradient mode: D = d ln(throughput_c) / d theta_p, g = the
+             * path's d(radiance_c) / d theta_p, index 3c + p */
+            double D[9] = {0}, g[9] = {0};
             double last_pdf = -1.0;
             /* distance from the last scattering event to the ray origin
              * along the straight line (pass-through keeps the line) */
@@ -267,10 +294,12 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                     }
                     float wf = (float)w;
                     for (int c = 0; c < 3; ++c) L[c] += thr[c] * rs->light_radiance[c] * wf;
+                    for (int k = 0; k < 9; ++k) g[k] += (double)thr[k / 3] * rs->light_radiance[k / 3] * wf * D[k];
                     break;
                 }
                 if (hr.miss) {
                     for (int c = 0; c < 3; ++c) L[c] += thr[c] * rs->env_radiance[c];
+                    for (int k = 0; k < 9; ++k) g[k] += (double)thr[k / 3] * rs->env_radiance[k / 3] * D[k];
                     break;
                 }
                 if (depth == rs->max_depth) break;
@@ -287,7 +316,8 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                 /* multi-scale: camera hits over their pixel footprint, later
                  * bounces near field; otherwise the LOD rule picks the far field */
                 int ms = rs->multiscale && depth == 0;
-                int far = !rs->multiscale && 2.0 * R / (dist_cam * pix_angle) < rs->lod_px;
+                int far = !rs->multiscale && !grad && 2.0 * R / (dist_cam * pix_angle) < rs->lod_px;
+                int gt = grad && yarn_type[y] == rs->grad_type;
                 double fh1 = hr.h, fh2 = hr.h;
                 if (ms)
                     camera_footprint(o, f, rr, uu, th, aspect, rs->width, rs->height, du, hr.t, &hr,
@@ -304,7 +334,7 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                 if (cosl > 0.0 && rs->nee) {
                     double wo[3];
                     to_loc(&hr, wl, wo);
-                    double E[3], pb;
+                    double E[3], pb, dEn[9] = {0};
                     if (ms) {
                         double out[13];
                         orc_eval_multi_query(P, tab, hr.h, fh1, fh2, u2[2], rs->n_h, uq, vl, wi, wo,
@@ -318,6 +348,7 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                         orc_eval_query(P, tab, hr.h, uq, vl, wi, wo, out);
                         for (int c = 0; c < 3; ++c) E[c] = f32(out[c]);
                         pb = f32(out[11]);
+                        if (gt) bysdf_derivs(P, tab, hr.h, uq, vl, wi, wo, out, dEn);
                     }
                     if (E[0] > 0.0 || E[1] > 0.0 || E[2] > 0.0) {
                         double pl = dist2 / (area * cosl);
@@ -327,8 +358,13 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                         for (int c = 0; c < 3; ++c)
                             ct[c] = thr[c] * (float)E[c] * rs->light_radiance[c] * fac;
                         r3 os = r3f(p), ds = runit(r3f(wl));
-                        if (unoccluded(&C, os, ds, sqrt(dist2) * (1.0 - 1e-5), y, rs->ray_eps))
+                        if (unoccluded(&C, os, ds, sqrt(dist2) * (1.0 - 1e-5), y, rs->ray_eps)) {
                             for (int c = 0; c < 3; ++c) L[c] += ct[c];
+                            if (grad)
+                                for (int k = 0; k < 9; ++k)
+                                    g[k] += (double)thr[k / 3] * rs->light_radiance[k / 3] * fac *
+                                            (dEn[k] + E[k / 3] * D[k]);
+                        }
                     }
                 }
                 /* continue the path with a BYSDF sample */
@@ -372,6 +408,14 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                     }
                     r3 B = rcross(hr.T, hr.N);
                     dnew = runit(radd(radd(rscl(hr.N, wo[0]), rscl(B, wo[1])), rscl(hr.T, wo[2])));
+                    if (gt) {
+                        /* the value at the drawn (unrounded) direction */
+                        double es[13], dEs[9];
+                        orc_eval_query(P, tab, hq, uq, vl, wi, so, es);
+                        bysdf_derivs(P, tab, hq, uq, vl, wi, so, es, dEs);
+                        for (int k = 0; k < 9; ++k)
+                            if (es[k / 3] > 0.0) D[k] += dEs[k] / es[k / 3];
+                    }
                     for (int c = 0; c < 3; ++c) thr[c] *= wgt[c];
                     last_pdf = pdf;
                     line0 = 0.0;
@@ -388,11 +432,14 @@ int orc_render(const void* scene, const orc_params* types, const double* const* 
                 acc[c] += L[c];
                 acc2[c] += (double)L[c] * L[c];
             }
+            for (int k = 0; k < 9; ++k) gacc[k] += g[k];
         }
         for (int c = 0; c < 3; ++c) {
             fb[3 * pix + c] = acc[c] / rs->spp;
             if (sq) sq[3 * pix + c] = acc2[c] / rs->spp;
         }
+        if (grad)
+            for (int k = 0; k < 9; ++k) grad[9 * pix + k] = gacc[k] / rs->spp;
     }
     return 0;
 }

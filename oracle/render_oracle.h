@@ -59,6 +59,8 @@ typedef struct {
     int32_t multiscale; /* 1: camera hits use the multi-scale model over their
                            pixel footprint (Sec. 4.2, 5.3), later bounces the
                            near field, no LOD switch */
+    int32_t grad_type;  /* type whose (r, k^B, sigma_t) the gradient output
+                           differentiates (when grad is not NULL) */
 } orc_render_settings;
 
 /* Footprint probe: h0, h1, h2 of the camera ray through pixel position
@@ -70,9 +72,13 @@ int orc_camera_footprint(const void* scene, const orc_render_settings* rs, doubl
  * NULL it receives the mean of the squared per-sample radiance (for the
  * sample variance).  types[yarn_type[y]] and tables[...] describe the
  * yarns' BYSDF types. */
+/* grad (nullable): [crop_h][crop_w][3][3], the mean per-pixel derivative
+ * d(radiance_c) / d theta_p for theta = (r, k^B_c, sigma_t) of type
+ * rs->grad_type, by path derivatives with the sampling densities held
+ * fixed; the near field shades every hit (no LOD switch). */
 int orc_render(const void* scene, const orc_params* types, const double* const* tables,
                int32_t n_types, const int32_t* yarn_type, const float* yarn_phase,
-               const orc_render_settings* rs, double* fb, double* sq, int nthreads);
+               const orc_render_settings* rs, double* fb, double* sq, double* grad, int nthreads);
 
 #ifdef __cplusplus
 }

@@ -156,6 +156,10 @@ def lib():
         L.shade_wavefront_workspace_size.restype = C.c_size_t
         L.shade_wavefront.argtypes = [_vp, _vp, C.POINTER(RenderSettings), _vp, _vp, C.c_size_t,
                                       C.POINTER(C.c_int64), _vp]
+        L.shade_wavefront_grad_workspace_size.argtypes = [C.POINTER(RenderSettings)]
+        L.shade_wavefront_grad_workspace_size.restype = C.c_size_t
+        L.shade_wavefront_grad.argtypes = [_vp, _vp, C.POINTER(RenderSettings), C.c_int32, _vp, _vp, _vp,
+                                           C.c_size_t, C.POINTER(C.c_int64), _vp]
         L.bysdf_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.bysdf_philox4x32_10.restype = None
         _lib = L
@@ -592,6 +596,29 @@ def shade_wavefront(scene: Scene, types: Types, rs: dict, fb=None, workspace=Non
     if counts:
         return fb, (int(rc_counts[0]), int(rc_counts[1]))
     return fb
+
+
+def shade_wavefront_grad(scene: Scene, types: Types, rs: dict, grad_type: int = 0, fb=None, grad=None,
+                         workspace=None, stream=None):
+    """Render the crop and the gradient of the image with respect to (r,
+    k^B_c, sigma_t) of type grad_type.  Returns (framebuffer float32
+    [crop_h, crop_w, 3], gradient float32 [crop_h, crop_w, 3, 3])."""
+    import torch
+    st = render_settings(rs)
+    nb = int(lib().shade_wavefront_grad_workspace_size(C.byref(st)))
+    if nb == 0:
+        _check(-2, "shade_wavefront_grad_workspace_size")
+    if fb is None:
+        fb = torch.empty((rs["crop_h"], rs["crop_w"], 3), dtype=torch.float32, device="cuda")
+    if grad is None:
+        grad = torch.empty((rs["crop_h"], rs["crop_w"], 3, 3), dtype=torch.float32, device="cuda")
+    if workspace is None:
+        workspace = alloc_workspace(nb)
+    buf, ptr = workspace
+    _check(lib().shade_wavefront_grad(scene.handle, types.handle, C.byref(st), grad_type, fb.data_ptr(),
+                                      grad.data_ptr(), ptr, buf.numel() - (ptr - buf.data_ptr()), None,
+                                      _stream(stream)), "shade_wavefront_grad")
+    return fb, grad
 
 
 def bysdf_philox4x32_10(ctr, key):

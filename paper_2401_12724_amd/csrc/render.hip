@@ -72,14 +72,21 @@ struct RView {
     float Le[3], env[3];
     int W, H, cx, cy, cw, ch, spp, max_depth, n_h;
     int multiscale;
+    int grad_type;  // -1: no image gradient
     float lod_px;
     double eps;
     uint32_t key0, key1;
 };
 
+// Gradient mode: per path, D[(3c + p) cap + i] is d ln(throughput_c) / d
+// theta_p for theta = (r, k^B_c, sigma_t) of the gradient type; per shadow
+// ray, G[(3c + p) cap + i] is d(contribution_c) / d theta_p.  NULL otherwise.
+constexpr int kGrad = 9;
+
 struct PathQ {
     float *ox, *oy, *oz, *dx, *dy, *dz, *tr, *tg, *tb, *pdf, *line0;
     int *skip, *lid;
+    float* D;
 };
 struct HitQ {
     float *t, *s, *h, *v, *R, *Tx, *Ty, *Tz, *Nx, *Ny, *Nz;
@@ -88,6 +95,7 @@ struct HitQ {
 struct ShadowQ {
     float *ox, *oy, *oz, *dx, *dy, *dz, *tmax, *cr, *cg, *cb;
     int *skip, *lid;
+    float* G;
 };
 
 __device__ inline D3 dv(const double* a) { return yarn::d3(a[0], a[1], a[2]); }
@@ -167,6 +175,11 @@ __global__ __launch_bounds__(256) void k_r_camera(RView V, PathQ A, float* L, in
         A.skip[lid] = -1;
         A.lid[lid] = lid;
         L[lid] = L[cap + lid] = L[2 * cap + lid] = 0.0f;
+        if (A.D)
+            for (int k = 0; k < kGrad; ++k) {
+                A.D[k * cap + lid] = 0.0f;
+                L[(3 + k) * cap + lid] = 0.0f;
+            }
     }
 }
 
@@ -211,11 +224,15 @@ __global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_exten
             }
             float wf = (float)w;
             for (int c = 0; c < 3; ++c) L[c * cap + lid] += thr[c] * V.Le[c] * wf;
+            if (Q.D)
+                for (int k = 0; k < kGrad; ++k) L[(3 + k) * cap + lid] += thr[k / 3] * V.Le[k / 3] * wf * Q.D[k * cap + i];
             H.yarn[i] = -1;
             continue;
         }
         if (miss) {
             for (int c = 0; c < 3; ++c) L[c * cap + lid] += thr[c] * V.env[c];
+            if (Q.D)
+                for (int k = 0; k < kGrad; ++k) L[(3 + k) * cap + lid] += thr[k / 3] * V.env[k / 3] * Q.D[k * cap + i];
             H.yarn[i] = -1;
             continue;
         }
@@ -311,7 +328,19 @@ __device__ inline void camera_footprint(const RView& V, D3 o, D3 d, double t, D3
     *h2 = (float)hi;
 }
 
-template <int MP, bool MS>
+// dE_c / d theta for theta = (r, k^B_c, sigma_t): the reflected body lobe
+// is linear in r and the transmitted one in 1 - r, both in k^B_c, and only
+// the forward specular lobe sees sigma_t (ds = dEyS / dsigma_t).
+__device__ inline void bysdf_grad(const Derived<double, float>& P, const EvalOut<float>& e, float ds, float dE[kGrad])
+{
+    for (int c = 0; c < 3; ++c) {
+        dE[3 * c] = (P.r > 0.0f ? e.ExB[c] / P.r : 0.0f) - (P.r < 1.0f ? e.EyB[c] / (1.0f - P.r) : 0.0f);
+        dE[3 * c + 1] = P.alb[c] > 0.0f ? (e.ExB[c] + e.EyB[c]) / P.alb[c] : 0.0f;
+        dE[3 * c + 2] = ds;
+    }
+}
+
+template <int MP, bool MS, bool GRAD>
 #ifndef RENDER_SHADE_MIN_WAVES
 #define RENDER_SHADE_MIN_WAVES 1
 #endif
@@ -351,7 +380,17 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
         // multi-scale: the camera hits use their pixel footprint, later
         // bounces the near field; otherwise the far field by the LOD rule
         const bool msx = MS && depth == 0;
-        const bool far = !MS && 2.0 * R / (sqrt(yarn::dot(pe, pe)) * V.pix_angle) < V.lod_px;
+        const bool far = !MS && !GRAD && 2.0 * R / (sqrt(yarn::dot(pe, pe)) * V.pix_angle) < V.lod_px;
+        // gradient mode: path log-derivatives in, BYSDF derivatives at the
+        // light direction and at the drawn one
+        // (Dp: into this hit; Dn: out of it along the drawn direction)
+        float Dp[GRAD ? kGrad : 1], Dn[GRAD ? kGrad : 1], dEn[GRAD ? kGrad : 1], dEs[GRAD ? kGrad : 1];
+        float Es[3] = {0.f, 0.f, 0.f};
+        if (GRAD)
+            for (int k = 0; k < kGrad; ++k) {
+                Dp[k] = Dn[k] = act ? Q.D[k * cap + i] : 0.0f;
+                dEn[k] = dEs[k] = 0.0f;
+            }
         float fh1 = hq, fh2 = hq;
         if (msx && act) camera_footprint(V, o, d, (double)t, T, N, (double)R, hq, &fh1, &fh2);
         const uint64_t slot = (uint64_t)(lid / spp_batch) * V.spp + j0 + lid % spp_batch;
@@ -379,7 +418,31 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             TabPtr tab{V.tables + V.types[tu].table_off};
             SampleOut<float> so;
             uint32_t sf = 0;
-            if (msx) {
+            if (GRAD) {
+                XState<double, float, MP> X;
+                bysdf::state_at_x(P, tab, hq, uq, vl, wi, X);
+                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false};
+                V3<double> ws;
+                bool ok;
+                sf = bysdf::sample_draw(P, X, wi, u1[2], u1[3], u2[0], nf, so, ws, ok);
+                if (!X.ph.pass) {
+                    EvalOut<float> en, es;
+                    float dsn = 0.0f, dss = 0.0f;
+                    bysdf::lobes_nodes2_dsigma(P, X, bysdf::mk3<double>(wol.x, wol.y, wol.z), cosl > 0.0, ws, ok,
+                                               nf, en, es, dsn, dss);
+                    const bool mine = tu == V.grad_type;
+                    if (cosl > 0.0) {
+                        for (int c = 0; c < 3; ++c) En[c] = en.E[c];
+                        pb = en.pdf;
+                        if (mine) bysdf_grad(P, en, dsn, dEn);
+                    }
+                    if (ok) {
+                        sf = bysdf::sample_finish(es, ws, sf, so);
+                        for (int c = 0; c < 3; ++c) Es[c] = es.E[c];
+                        if (mine) bysdf_grad(P, es, dss, dEs);
+                    }
+                }
+            } else if (msx) {
                 const TypeRec& Rt = V.types[tu];
                 bysdf::Footprint fp;
                 bysdf::make_footprint(hq, fh1, fh2, u2[2], V.n_h, fp);
@@ -441,6 +504,9 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                     line_new = 0.0f;
                     float nt[3];
                     for (int c = 0; c < 3; ++c) nt[c] = thr[c] * wgt[c];
+                    if (GRAD)
+                        for (int k = 0; k < kGrad; ++k)
+                            if (Es[k / 3] > 0.0f) Dn[k] = Dp[k] + dEs[k] / Es[k / 3];
                     cont = nt[0] > 0.f || nt[1] > 0.f || nt[2] > 0.f;
                     for (int c = 0; c < 3; ++c) thr[c] = nt[c];
                 }
@@ -455,6 +521,11 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             float fac = (float)(w / pl);
             float th0[3] = {act ? Q.tr[i] : 0.f, act ? Q.tg[i] : 0.f, act ? Q.tb[i] : 0.f};
             for (int c = 0; c < 3; ++c) ct[c] = th0[c] * (float)En[c] * V.Le[c] * fac;
+            if (GRAD)
+                for (int k = 0; k < kGrad; ++k) {
+                    const int c = k / 3;
+                    dEn[k] = th0[c] * V.Le[c] * fac * (dEn[k] + (float)En[c] * Dp[k]);
+                }
         }
         int js = wave_append(want_sh, cnt_sh);
         if (want_sh) {
@@ -471,6 +542,8 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             SQ.cb[js] = ct[2];
             SQ.skip[js] = yarn_id;
             SQ.lid[js] = lid;
+            if (GRAD)
+                for (int k = 0; k < kGrad; ++k) SQ.G[k * cap + js] = dEn[k];
         }
         // continued path: from the hit point, past its own yarn
         bool want = act && cont;
@@ -489,6 +562,8 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             O.line0[jo] = line_new;
             O.skip[jo] = yarn_id;
             O.lid[jo] = lid;
+            if (GRAD)
+                for (int k = 0; k < kGrad; ++k) O.D[k * cap + jo] = Dn[k];
         }
         (void)cap;
     }
@@ -551,12 +626,14 @@ __global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_shado
             L[lid] += SQ.cr[i];
             L[cap + lid] += SQ.cg[i];
             L[2 * cap + lid] += SQ.cb[i];
+            if (SQ.G)
+                for (int k = 0; k < kGrad; ++k) L[(3 + k) * cap + lid] += SQ.G[k * cap + i];
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_r_accum(const float* L, float* fb, int npix, int spp_batch, int cap,
-                                                 float inv_spp)
+__global__ __launch_bounds__(256) void k_r_accum(const float* L, float* fb, float* grad, int npix, int spp_batch,
+                                                 int cap, float inv_spp)
 {
     for (int pix = blockIdx.x * blockDim.x + threadIdx.x; pix < npix; pix += gridDim.x * blockDim.x) {
         for (int c = 0; c < 3; ++c) {
@@ -564,6 +641,12 @@ __global__ __launch_bounds__(256) void k_r_accum(const float* L, float* fb, int 
             for (int j = 0; j < spp_batch; ++j) s += L[c * cap + pix * spp_batch + j];
             fb[3 * pix + c] += s * inv_spp;
         }
+        if (grad)
+            for (int k = 0; k < kGrad; ++k) {
+                float s = 0.0f;
+                for (int j = 0; j < spp_batch; ++j) s += L[(3 + k) * cap + pix * spp_batch + j];
+                grad[kGrad * pix + k] += s * inv_spp;
+            }
     }
 }
 
@@ -601,10 +684,13 @@ int check_settings(const render_settings* rs)
     return 0;
 }
 
-size_t workspace_bytes(int64_t cap)
+size_t workspace_bytes(int64_t cap, bool grad)
 {
     size_t arr = align256(sizeof(float) * cap);
-    return arr * (2 * kPathArrays + kHitArrays + kShadowArrays + 3) + 256;
+    // gradient mode: path log-derivatives in both queues, shadow-ray
+    // derivatives and the gradient slots
+    const int extra = grad ? 4 * kGrad : 0;
+    return arr * (2 * kPathArrays + kHitArrays + kShadowArrays + 3 + extra) + 256;
 }
 
 struct HD {
@@ -632,7 +718,14 @@ extern "C" size_t shade_wavefront_workspace_size(const render_settings* rs)
 {
     if (check_settings(rs)) return 0;
     int b = rs->spp_batch ? rs->spp_batch : rs->spp;
-    return workspace_bytes((int64_t)rs->crop_w * rs->crop_h * b);
+    return workspace_bytes((int64_t)rs->crop_w * rs->crop_h * b, false);
+}
+
+extern "C" size_t shade_wavefront_grad_workspace_size(const render_settings* rs)
+{
+    if (check_settings(rs)) return 0;
+    int b = rs->spp_batch ? rs->spp_batch : rs->spp;
+    return workspace_bytes((int64_t)rs->crop_w * rs->crop_h * b, true);
 }
 
 extern "C" void bysdf_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
@@ -640,23 +733,27 @@ extern "C" void bysdf_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2]
     rng::philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1], out);
 }
 
-extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* types, const render_settings* rs,
-                               float* fb, void* ws, size_t ws_bytes, int64_t* ray_counts, hipStream_t stream)
+static int render(const yarn_scene_t* scene, const bysdf_types_t* types, const render_settings* rs, float* fb,
+                  float* grad, int grad_type, void* ws, size_t ws_bytes, int64_t* ray_counts, hipStream_t stream)
 {
     if (!scene || !types || !fb || !ws) return fail(BYSDF_ERR_INVALID_ARG, "scene, types, framebuffer and workspace must be non-NULL");
     int rc = check_settings(rs);
     if (rc) return rc;
-    if (((uintptr_t)ws & 255u) || ((uintptr_t)fb & 3u))
-        return fail(BYSDF_ERR_INVALID_ARG, "workspace must be 256-byte aligned, framebuffer 4-byte aligned");
+    if (((uintptr_t)ws & 255u) || ((uintptr_t)fb & 3u) || ((uintptr_t)grad & 3u))
+        return fail(BYSDF_ERR_INVALID_ARG, "workspace must be 256-byte aligned, framebuffer and gradient 4-byte aligned");
+    const bool g = grad != nullptr;
     const int spp_batch = rs->spp_batch ? rs->spp_batch : rs->spp;
     const int npix = rs->crop_w * rs->crop_h;
     const int cap = npix * spp_batch;
-    if (ws_bytes < workspace_bytes(cap))
-        return fail(BYSDF_ERR_INVALID_ARG, "workspace of %zu bytes, need %zu", ws_bytes, workspace_bytes(cap));
+    if (ws_bytes < workspace_bytes(cap, g))
+        return fail(BYSDF_ERR_INVALID_ARG, "workspace of %zu bytes, need %zu", ws_bytes, workspace_bytes(cap, g));
     BysdfTypesView tv = bysdf_types_view(types);
     if (yarn_scene_max_type(scene) >= tv.n_types)
         return fail(BYSDF_ERR_INVALID_PARAM, "the scene uses type %d, the handle has %d types", yarn_scene_max_type(scene),
                     tv.n_types);
+    if (g && (grad_type < 0 || grad_type >= tv.n_types))
+        return fail(BYSDF_ERR_INVALID_ARG, "grad_type %d outside the handle's %d types", grad_type, tv.n_types);
+    if (g && rs->multiscale) return fail(BYSDF_ERR_INVALID_PARAM, "the image gradient is of the near-field render");
     RView V;
     V.S = yarn_scene_view(scene);
     V.types = tv.types;
@@ -695,6 +792,7 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
     V.n_h = rs->n_h;
     V.lod_px = rs->lod_px;
     V.multiscale = rs->multiscale;
+    V.grad_type = g ? grad_type : -1;
     V.eps = rs->ray_eps;
     V.key0 = (uint32_t)rs->seed;
     V.key1 = (uint32_t)(rs->seed >> 32);
@@ -714,6 +812,7 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
         for (float** q : fp) *q = (float*)take();
         Qs[k].skip = (int*)take();
         Qs[k].lid = (int*)take();
+        Qs[k].D = nullptr;
     }
     HitQ Hh;
     {
@@ -728,9 +827,18 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
         for (float** q : fp) *q = (float*)take();
         SQ.skip = (int*)take();
         SQ.lid = (int*)take();
+        SQ.G = nullptr;
+    }
+    if (g) {
+        for (int k = 0; k < 2; ++k) {
+            Qs[k].D = (float*)w;
+            w += kGrad * arr;
+        }
+        SQ.G = (float*)w;
+        w += kGrad * arr;
     }
     float* L = (float*)w;
-    w += 3 * arr;
+    w += (g ? 3 + kGrad : 3) * arr;
     int* cnt = (int*)w;                                       // [0], [1]: path queues, [2]: shadow rays
     unsigned long long* stats = (unsigned long long*)(w + 64);  // extension, shadow rays
 
@@ -740,6 +848,9 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
     };
     hipLaunchKernelGGL(k_r_fill, dim3(grid_for(3 * (int64_t)npix, 256, 4096)), dim3(256), 0, stream, fb,
                        3 * (int64_t)npix);
+    if (g)
+        hipLaunchKernelGGL(k_r_fill, dim3(grid_for(kGrad * (int64_t)npix, 256, 4096)), dim3(256), 0, stream, grad,
+                           kGrad * (int64_t)npix);
     hipLaunchKernelGGL(k_r_fill, dim3(1), dim3(256), 0, stream, (float*)stats, (int64_t)4);
     const bool mp4 = tv.max_plies <= 4;
     int64_t sinfo[6];
@@ -757,16 +868,17 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
                                stream, V, Qs[a], cnt + a, Hh, L, n, depth);
             if (depth == rs->max_depth) break;
             hipLaunchKernelGGL(k_r_counters, dim3(1), dim3(64), 0, stream, cnt, b, 2, -1);
-            auto shade = rs->multiscale ? (mp4 ? k_r_shade<4, true> : k_r_shade<8, true>)
-                                        : (mp4 ? k_r_shade<4, false> : k_r_shade<8, false>);
+            auto shade = g ? (mp4 ? k_r_shade<4, false, true> : k_r_shade<8, false, true>)
+                           : rs->multiscale ? (mp4 ? k_r_shade<4, true, false> : k_r_shade<8, true, false>)
+                                            : (mp4 ? k_r_shade<4, false, false> : k_r_shade<8, false, false>);
             hipLaunchKernelGGL(shade, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream, V,
                                Qs[a], cnt + a, Hh, Qs[b], cnt + b, SQ, cnt + 2, n, depth, j0, nb);
             hipLaunchKernelGGL(k_r_tally, dim3(1), dim3(64), 0, stream, cnt, 2, stats, 1);
             hipLaunchKernelGGL(mp4 ? k_r_shadow<4> : k_r_shadow<8>, dim3(grid_for(n, kTraceBlock, 16384)),
                                dim3(kTraceBlock), stk_bytes, stream, V, SQ, cnt + 2, L, n);
         }
-        hipLaunchKernelGGL(k_r_accum, dim3(grid_for(npix, 256, 4096)), dim3(256), 0, stream, L, fb, npix, nb, n,
-                           1.0f / rs->spp);
+        hipLaunchKernelGGL(k_r_accum, dim3(grid_for(npix, 256, 4096)), dim3(256), 0, stream, L, fb, grad, npix, nb,
+                           n, 1.0f / rs->spp);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(BYSDF_ERR_LAUNCH, "shade_wavefront: %s", hipGetErrorString(e));
@@ -779,4 +891,18 @@ extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* t
         ray_counts[1] = (int64_t)h[1];
     }
     return 0;
+}
+
+extern "C" int shade_wavefront(const yarn_scene_t* scene, const bysdf_types_t* types, const render_settings* rs,
+                               float* fb, void* ws, size_t ws_bytes, int64_t* ray_counts, hipStream_t stream)
+{
+    return render(scene, types, rs, fb, nullptr, -1, ws, ws_bytes, ray_counts, stream);
+}
+
+extern "C" int shade_wavefront_grad(const yarn_scene_t* scene, const bysdf_types_t* types,
+                                    const render_settings* rs, int32_t grad_type, float* fb, float* grad,
+                                    void* ws, size_t ws_bytes, int64_t* ray_counts, hipStream_t stream)
+{
+    if (!grad) return fail(BYSDF_ERR_INVALID_ARG, "gradient buffer must be non-NULL");
+    return render(scene, types, rs, fb, grad, grad_type, ws, ws_bytes, ray_counts, stream);
 }

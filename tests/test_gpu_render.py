@@ -170,3 +170,66 @@ def test_multiscale_matches_oracle(torch_cuda):
     _check(g, o, sq, rs["spp"], "multiscale")
     _paths_equal(torch, scene, P, _settings(cam, (24, 12, 48, 48), multiscale=1, n_h=8),
                  "multiscale", 0.85)
+
+
+def test_image_gradient_matches_oracle(torch_cuda):
+    """shade_wavefront_grad against the oracle renderer's path derivatives
+    on the same random numbers: crop sums of each derivative channel within
+    sampling error, and at one path per pixel most paths' derivatives equal."""
+    torch = torch_cuda
+    scene = W.weave(12, 12, 0.15, 0.05, 4)
+    P = [W.default_params(r=0.4, sigma_t=0.6, albedo=(0.7, 0.5, 0.3))]
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=96, height=72)
+    ctrl, off, ty, ph = scene
+    Sg = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    Tg = bysdf.bysdf_types_create(P)
+    So = oracle.Scene(ctrl, off)
+    for spp, crop in ((8, (36, 24, 24, 24)), (1, (24, 12, 48, 48))):
+        rs = _settings(cam, crop, spp=spp)
+        fb, gr = bysdf.shade_wavefront_grad(Sg, Tg, rs, 0)
+        torch.cuda.synchronize()
+        g = gr.cpu().numpy().astype(np.float64)
+        o, sq, og = oracle.render(So, P, ty, ph, dict(rs, grad_type=0))
+        assert np.allclose(fb.cpu().numpy().mean(), o.mean(), rtol=0.02, atol=1e-4)
+        for k in range(9):
+            a, b = g[..., k // 3, k % 3], og[..., k // 3, k % 3]
+            scale = np.abs(b).mean() + 1e-6
+            print("spp", spp, "channel", k, "gpu", a.mean(), "oracle", b.mean())
+            if spp > 1:
+                assert abs(a.mean() - b.mean()) <= 0.03 * scale + 1e-6, k
+            else:
+                eq = (np.abs(a - b) <= 1e-2 * np.maximum(np.abs(b), 0.05 * scale)).mean()
+                print("   paths equal", eq)
+                assert eq >= 0.85, k
+
+
+def test_image_space_fit_recovers_parameters(torch_cuda):
+    """Image-space fitting (Sec. 5.2): r, k^B and sigma_t of a hidden type
+    are recovered from a target image (1,024 spp) by Adam on the renderer's
+    gradients (16 spp per step, 250 steps), from a start far from them; the
+    fitted type's 1,024-spp image is as close to the target as the hidden
+    type's own."""
+    from paper_2401_12724_amd import fit_image
+    torch = torch_cuda
+    ctrl, off, ty, ph = W.weave(12, 12, 0.15, 0.05, 4)
+    S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=96, height=72)
+    rs = _settings(cam, (24, 12, 48, 48), spp=16, max_depth=4)
+    hidden = W.default_params(r=0.35, sigma_t=1.2, albedo=(0.75, 0.45, 0.25))
+    T = bysdf.bysdf_types_create([hidden])
+    target = bysdf.shade_wavefront(S, T, dict(rs, spp=1024, seed=99))
+
+    def hi_loss(th):
+        Tt = bysdf.bysdf_types_create([fit_image.with_theta(hidden, th)])
+        im = bysdf.shade_wavefront(S, Tt, dict(rs, spp=1024, seed=5))
+        return float(((im - target) ** 2).mean())
+
+    th0 = fit_image.theta_of(W.default_params(r=0.6, sigma_t=0.4, albedo=(0.5, 0.5, 0.5)))
+    th, hist = fit_image.fit(S, [hidden], 0, target, rs, th0, steps=250, lr=0.08)
+    truth = fit_image.theta_of(hidden)
+    l0, lf, ls = hi_loss(th0), hi_loss(th), hi_loss(truth)
+    print("fit", th, "truth", truth, "1024-spp loss: start", l0, "fit", lf, "truth", ls)
+    assert abs(th[0] - truth[0]) < 0.03
+    assert np.all(np.abs(th[1:4] - truth[1:4]) < 0.02)
+    assert abs(th[4] - truth[4]) < 0.15
+    assert lf < 1.5 * ls and lf < 0.05 * l0

@@ -189,3 +189,63 @@ def test_multiscale_white_furnace_image():
     sigma = np.sqrt(var.mean() / (fb.size * rs["spp"] / 3))
     print("multiscale furnace mean", m, "sigma", sigma)
     assert abs(m - 1.0) < 4 * sigma + 2e-3
+
+
+def _grad_scene():
+    S, ty, ph = _scene(6)
+    cam = W.camera((0.0, -1.3, 0.9), (0.0, 0.0, 0.0), width=40, height=40)
+    return S, ty, ph, cam
+
+
+def test_image_gradient_albedo_and_extinction_match_differences():
+    """Image gradient for image-space fitting (Sec. 5.2): neither k^B nor
+    sigma_t changes a sampling decision, so with the same random numbers the
+    image is a smooth function of them and its central differences must
+    equal the path-derivative gradient."""
+    S, ty, ph, cam = _grad_scene()
+    base = W.default_params(r=0.4, sigma_t=0.6, albedo=(0.7, 0.5, 0.3))
+    rs = _settings(cam, (8, 8, 24, 24), spp=4, max_depth=4, grad_type=0)
+    _, _, g = oracle.render(S, [base], ty, ph, rs)
+    plain = dict(rs, grad_type=-1)
+    for p, name, step in ((1, "albedo", 0.01), (2, "sigma_t", 0.01)):
+        for c in range(3):
+            if p == 2 and c > 0:
+                break
+            def img(delta):
+                d = dict(base)
+                if name == "albedo":
+                    a = list(d["albedo"])
+                    a[c] += delta
+                    d["albedo"] = tuple(a)
+                else:
+                    d["sigma_t"] += delta
+                return oracle.render(S, [d], ty, ph, plain)[0]
+            fd = (img(step) - img(-step)) / (2 * step)
+            if name == "albedo":
+                gd, ref = g[..., c, 1], fd[..., c]
+            else:
+                gd, ref = g[..., :, 2].sum(-1), fd.sum(-1)
+            err = np.abs(gd - ref).sum() / max(np.abs(ref).sum(), 1e-12)
+            print(name, c, "sum grad", gd.sum(), "sum fd", ref.sum(), "rel", err)
+            assert abs(gd.sum() - ref.sum()) <= 2e-3 * abs(ref.sum()) + 1e-9
+            assert err < 2e-2
+
+
+def test_image_gradient_in_r_is_unbiased():
+    """r also moves the lobe choice; the gradient holds the sampling
+    densities fixed, which is unbiased for the derivative of the expected
+    image: its crop mean agrees with central differences of crop means over
+    independent random numbers."""
+    S, ty, ph, cam = _grad_scene()
+    base = W.default_params(r=0.4, sigma_t=0.6)
+    rs = _settings(cam, (8, 8, 24, 24), spp=128, max_depth=3, grad_type=0, seed=11)
+    _, _, g = oracle.render(S, [base], ty, ph, rs)
+    step = 0.1
+    hi, hsq = oracle.render(S, [dict(base, r=base["r"] + step)], ty, ph, dict(rs, grad_type=-1, seed=12))
+    lo, lsq = oracle.render(S, [dict(base, r=base["r"] - step)], ty, ph, dict(rs, grad_type=-1, seed=13))
+    fd = (hi.mean() - lo.mean()) / (2 * step)
+    var = (np.maximum(hsq - hi * hi, 0).sum() + np.maximum(lsq - lo * lo, 0).sum()) / 128 / hi.size ** 2
+    sd = np.sqrt(var) / (2 * step)
+    gm = g[..., :, 0].sum(-1).mean() / 3
+    print("d mean / dr: gradient", gm, "differences", fd / 1, "+-", sd)
+    assert abs(gm - fd) < 4 * sd + 0.05 * abs(fd)
