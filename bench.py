@@ -400,6 +400,22 @@ def _fit(torch, bysdf, W, steps=100):
             "params": "r, k^B (RGB), sigma_t"}
 
 
+def _cross_section(torch, bysdf, W, P, qd):
+    """The implicit ply hit alone (Sec. 3.4) on the per-block workload, with
+    the elliptical cross-section (5 fixed-point updates per ply) and the
+    circular one (none)."""
+    n = int(qd["h"].numel())
+    out = {"queries": n}
+    for name, it in (("circular", 0), ("elliptical", 5)):
+        T = bysdf.bysdf_types_create([dict(p, n_iter=it) for p in P])
+        f = lambda: bysdf.bysdf_ply_geometry(T, qd)
+        f()
+        torch.cuda.synchronize()
+        ms = _timed(torch, f, 5)
+        out[name] = {"n_iter": it, "ms": ms, "queries_per_s": n / (ms * 1e-3)}
+    return out
+
+
 def _weave_render(torch, bysdf, W, spp=4):
     """The plain weave (256 + 256 B-spline yarns, 524,288 spans) seen by the
     grazing 1920 x 1080 camera: primary-ray intersection of every pixel
@@ -620,6 +636,7 @@ def main():
         del ev, sv
         out["migration"] = _migration(torch, bysdf, W, P, qd, q, ktime["eval_sample"])
         out["multiscale"] = _multiscale(torch, bysdf, W, P, q, qd, unfused)
+        out["cross_section"] = _cross_section(torch, bysdf, W, P, qd)
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
         out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
         out["weave"] = _weave_render(torch, bysdf, W)

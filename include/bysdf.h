@@ -210,6 +210,28 @@ int bysdf_eval_sample(const bysdf_types_t* types, const bysdf_query_soa* q, cons
                       const bysdf_eval_out_soa* eval_out, const bysdf_sample_out_soa* sample_out,
                       hipStream_t stream);
 
+/* ----------------------------------------------------------- ply geometry */
+/* Outputs of bysdf_ply_geometry (device, n elements each). */
+typedef struct {
+    int32_t* ply;             /* hit ply index, -1 when the ray passes through   */
+    float *p_x, *p_y, *p_z;   /* ply hit point: projected cross-section (x, y)
+                                 and height v along the yarn, yarn radii        */
+    float *t_x, *t_y, *t_z;   /* ply tangent at the hit (unit, query frame)      */
+    float *n_x, *n_y, *n_z;   /* ply normal at the hit (unit, orthogonal to t)   */
+    uint32_t* flags;          /* PASS_THROUGH, AXIAL, BAD_INPUT                  */
+} bysdf_ply_out_soa;
+
+/* The implicit ply hit of a query alone (Sec. 3.4): the yarn hit at offset
+ * h, the n_iter fixed-point updates that move each ply centre to where its
+ * helix crosses the ray's ellipse plane (n_iter = 0: the circular cross
+ * section perpendicular to the yarn at the hit), the 2D ray / disc test and
+ * the nearest ply, with the ply's tangent (the derivative of its centre
+ * helix) and normal there.  q's wo and shift arrays are not read (may be
+ * NULL).  For comparing cross-section constructions against explicit
+ * helical plies; n == 0 is a no-op. */
+int bysdf_ply_geometry(const bysdf_types_t* types, const bysdf_query_soa* q, int64_t n,
+                       const bysdf_ply_out_soa* out, hipStream_t stream);
+
 /* ------------------------------------------------------------ multi-scale */
 /* The pixel footprint of a multi-scale query (Sec. 4.2 and 5.3): device
  * arrays of n elements.  h1 <= h <= h2 (q's h) in [-1, 1] are the

@@ -143,6 +143,11 @@ def lib():
         L.orc_set_margins.argtypes = [C.c_double] * 5
         L.orc_nodes.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp, dp]
         L.orc_nodes.restype = C.c_uint32
+        L.orc_ply_frame.argtypes = [pp, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_ply_frame.restype = C.c_uint32
+        L.orc_explicit_ply.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double, dp,
+                                       C.c_double, dp]
+        L.orc_explicit_ply.restype = C.c_int32
         L.orc_frame_x.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_frame_x.restype = C.c_uint32
         L.orc_camera_footprint.argtypes = [C.c_void_p, C.POINTER(RenderSettings), C.c_double,
@@ -430,6 +435,28 @@ def nodes(d, tab, h, u, v, wi, shift=None):
     fl = lib().orc_nodes(C.byref(p), _ptr(t, C.c_double), float(h), float(u), float(v),
                          _ptr(w, C.c_double), _ptr(sh, C.c_double), _ptr(out, C.c_double))
     return out, fl
+
+
+def ply_frame(d, h, u, v, wi):
+    """Implicit ply hit with the ply frame: (array[11], flags) = pass, ply,
+    hit (x, y, v), tangent (3), normal (3)."""
+    p = params_struct(d)
+    w = np.ascontiguousarray(wi, dtype=np.float64)
+    out = np.zeros(11)
+    fl = lib().orc_ply_frame(C.byref(p), float(h), float(u), float(v), _ptr(w, C.c_double),
+                             _ptr(out, C.c_double))
+    return out, fl
+
+
+def explicit_ply(d, kappa, h, u, v, wi, step=2e-3):
+    """Explicit helical plies around a circular-arc yarn of curvature kappa:
+    (first_hit_ok, array[7] = ply, hit (3), tangent (3))."""
+    p = params_struct(d)
+    w = np.ascontiguousarray(wi, dtype=np.float64)
+    out = np.zeros(7)
+    ok = lib().orc_explicit_ply(C.byref(p), float(kappa), float(h), float(u), float(v),
+                                _ptr(w, C.c_double), float(step), _ptr(out, C.c_double))
+    return bool(ok), out
 
 
 def frame_x(d, tab, h, u, v, wi):

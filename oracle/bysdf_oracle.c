@@ -796,6 +796,129 @@ static void exit_btdf(const orc_params* p, const fnode* nd, v3 wo, double* val, 
     *pdf = g1i * fabs(im) * D / fabs(ci) * jac;
 }
 
+/* The implicit ply hit with the ply's own frame (Sec. 3.4), for the
+ * cross-section study.  out: pass, ply, hit point (x, y, v), ply tangent
+ * (3, derivative of the centre helix), ply normal (3, the 2D outward normal
+ * made orthogonal to the tangent). */
+uint32_t orc_ply_frame(const orc_params* p, double h, double u, double v, const double wi[3],
+                       double out[11])
+{
+    plyhit g;
+    for (int i = 0; i < 11; ++i) out[i] = 0.0;
+    trace_plies(p, h, u, v, mk(wi[0], wi[1], wi[2]), &g);
+    out[0] = g.pass;
+    out[1] = -1;
+    if (g.pass) return g.flags;
+    int k = g.kstar;
+    double slope = p->ply_center_radius * helix_rate(p);
+    double chx = cos(g.th[k]), chy = sin(g.th[k]);
+    v3 tp = vnorm(mk(-slope * chy, slope * chx, 1.0));
+    v3 n23 = mk(g.n2[0], g.n2[1], 0.0);
+    v3 np = vnorm(vsub(n23, vscl(tp, vdot(n23, tp))));
+    out[1] = k;
+    out[2] = g.p2[0]; out[3] = g.p2[1]; out[4] = g.vhit;
+    out[5] = tp.x; out[6] = tp.y; out[7] = tp.z;
+    out[8] = np.x; out[9] = np.y; out[10] = np.z;
+    return g.flags;
+}
+
+/* Explicit helical plies around a yarn whose centreline is a circular arc
+ * of curvature kappa (per yarn radius; 0: straight), the reference of the
+ * cross-section study.  Coordinates are the query frame at the yarn hit
+ * (N, T x N, T) = (x, y, z).  The centreline bends towards +x:
+ * c(s) = ((1 - cos ks)/k, 0, sin(ks)/k), T(s) = (sin ks, 0, cos ks),
+ * N(s) = (cos ks, 0, -sin ks), B = y (the rotation-minimising frame of a
+ * planar arc).  Ply j's centre at arc length s is
+ * c(s) + R_pc (cos th N(s) + sin th B), th = u + 2 pi j / N_p + w_p (v + s),
+ * and the ply is the disc of radius r_p about it in the plane normal to
+ * T(s).  The ray enters the unit yarn tube at x2 (the query's hit, in the
+ * cross-section at s = 0) going along -wi; a point belongs to the cross
+ * section of its nearest centreline point.  The first point inside a ply
+ * (marching by `step`, then bisection) is the hit.  out: ply (-1: none),
+ * hit point (3), unit tangent of the ply's centre curve there (3).
+ * Returns 0 when the ray meets the tube before x2 (x2 is then not the yarn
+ * hit), else 1. */
+static void arc_section(double kappa, const double q[3], double* s, double c[3], double N[3])
+{
+    if (kappa == 0.0) {
+        *s = q[2];
+        c[0] = 0.0; c[1] = 0.0; c[2] = q[2];
+        N[0] = 1.0; N[1] = 0.0; N[2] = 0.0;
+        return;
+    }
+    double rc = 1.0 / kappa;
+    double a = atan2(q[2], rc - q[0]);
+    *s = a * rc;
+    c[0] = rc * (1.0 - cos(a)); c[1] = 0.0; c[2] = rc * sin(a);
+    N[0] = cos(a); N[1] = 0.0; N[2] = -sin(a);
+}
+
+/* -1: outside the tube, otherwise the index of a ply containing q, or
+ * `n_plies` when inside the tube but in no ply */
+static int explicit_inside(const orc_params* p, double kappa, double u, double v, const double q[3])
+{
+    double s, c[3], N[3];
+    arc_section(kappa, q, &s, c, N);
+    double d[3] = {q[0] - c[0], q[1] - c[1], q[2] - c[2]};
+    double x = d[0] * N[0] + d[1] * N[1] + d[2] * N[2], y = d[1];
+    if (x * x + y * y > 1.0) return -1;
+    double wp = helix_rate(p), rp = p->ply_radius, Rpc = p->ply_center_radius;
+    for (int j = 0; j < p->n_plies; ++j) {
+        double th = u + TWO_PI * j / p->n_plies + wp * (v + s);
+        double ex = x - Rpc * cos(th), ey = y - Rpc * sin(th);
+        if (ex * ex + ey * ey <= rp * rp) return j;
+    }
+    return p->n_plies;
+}
+
+int orc_explicit_ply(const orc_params* p, double kappa, double h, double u, double v,
+                     const double wi[3], double step, double out[7])
+{
+    for (int i = 0; i < 7; ++i) out[i] = 0.0;
+    out[0] = -1;
+    double sxy = sqrt(wi[0] * wi[0] + wi[1] * wi[1]);
+    if (!(sxy > 1e-9)) return 0;
+    double cx = wi[0] / sxy, cy = wi[1] / sxy, g = asin(h);
+    double x2[3] = {cx * cos(g) - cy * sin(g), cy * cos(g) + cx * sin(g), 0.0};
+    /* nothing of the tube before x2 along the ray */
+    for (double t = step; t < 4.0; t += step) {
+        double q[3] = {x2[0] + t * wi[0], x2[1] + t * wi[1], x2[2] + t * wi[2]};
+        if (explicit_inside(p, kappa, u, v, q) >= 0) return 0;
+    }
+    double tmax = 2.5 / sxy, tprev = 0.0;
+    for (double t = 0.0; t <= tmax; t += step) {
+        double q[3] = {x2[0] - t * wi[0], x2[1] - t * wi[1], x2[2] - t * wi[2]};
+        int j = explicit_inside(p, kappa, u, v, q);
+        if (j >= 0 && j < p->n_plies) {
+            double lo = tprev, hi = t;
+            for (int it = 0; it < 40; ++it) {
+                double mid = 0.5 * (lo + hi);
+                double qm[3] = {x2[0] - mid * wi[0], x2[1] - mid * wi[1], x2[2] - mid * wi[2]};
+                int jm = explicit_inside(p, kappa, u, v, qm);
+                if (jm >= 0 && jm < p->n_plies) hi = mid; else lo = mid;
+            }
+            double qh[3] = {x2[0] - hi * wi[0], x2[1] - hi * wi[1], x2[2] - hi * wi[2]};
+            j = explicit_inside(p, kappa, u, v, qh);
+            double s, c[3], N[3];
+            arc_section(kappa, qh, &s, c, N);
+            double T[3] = {kappa == 0.0 ? 0.0 : sin(kappa * s), 0.0, kappa == 0.0 ? 1.0 : cos(kappa * s)};
+            double wp = helix_rate(p), Rpc = p->ply_center_radius;
+            double th = u + TWO_PI * j / p->n_plies + wp * (v + s);
+            /* d/ds of c + R_pc (cos th N + sin th B), with dN/ds = -kappa T */
+            double a = 1.0 - kappa * Rpc * cos(th), bn = -Rpc * wp * sin(th), bb = Rpc * wp * cos(th);
+            double tg[3] = {a * T[0] + bn * N[0], bb, a * T[2] + bn * N[2]};
+            double l = sqrt(tg[0] * tg[0] + tg[1] * tg[1] + tg[2] * tg[2]);
+            out[0] = j;
+            out[1] = qh[0]; out[2] = qh[1]; out[3] = qh[2];
+            out[4] = tg[0] / l; out[5] = tg[1] / l; out[6] = tg[2] / l;
+            return 1;
+        }
+        if (j < 0 && t > 2.0 * step) break; /* left the tube */
+        tprev = t;
+    }
+    return 1;
+}
+
 static void lobes(const orc_params* p, const xgeom* g, v3 wi, v3 wo, double out[13],
                   uint32_t* flags)
 {

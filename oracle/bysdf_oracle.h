@@ -143,6 +143,16 @@ uint32_t orc_sample_multi_query(const orc_params* p, const double* tab, double h
 int orc_footprint(double h0, double h1, double h2, double zeta, int32_t n_max, double* hs,
                   double* ws);
 
+/* Implicit ply hit with the ply frame: out[11] = pass, ply, hit (x, y, v),
+ * tangent (3), normal (3). */
+uint32_t orc_ply_frame(const orc_params* p, double h, double u, double v, const double wi[3],
+                       double out[11]);
+/* Explicit helical plies around a circular-arc yarn of curvature kappa:
+ * out[7] = ply (-1 none), hit point (3, query frame), ply tangent (3);
+ * returns 0 when the ray meets the tube before the query's yarn hit. */
+int orc_explicit_ply(const orc_params* p, double kappa, double h, double u, double v,
+                     const double wi[3], double step, double out[7]);
+
 /* Central finite differences of sum_q sum_c gE[q][c] E_c(q) with respect to
  * theta = (albedo r g b, beta, ply_twist, fiber_twist, ply_density,
  * fiber_density).  grad: n_types x 8.  per_query (nullable): n x 8. */

@@ -70,6 +70,11 @@ class SampleSoA(C.Structure):
                                    "xi0", "xi1", "xi2", "shift0", "shift1")]
 
 
+class PlyOutSoA(C.Structure):
+    _fields_ = [(n, _vp) for n in ("ply", "p_x", "p_y", "p_z", "t_x", "t_y", "t_z", "n_x", "n_y", "n_z",
+                                   "flags")]
+
+
 class FootprintSoA(C.Structure):
     _fields_ = [(n, _vp) for n in ("h1", "h2", "zeta", "xi_s")]
 
@@ -132,6 +137,7 @@ def lib():
                                        C.POINTER(SampleOutSoA), _vp]
         L.bysdf_eval_sample.argtypes = [_vp, C.POINTER(QuerySoA), _vp, _vp, _vp, C.c_int64,
                                         C.POINTER(EvalOutSoA), C.POINTER(SampleOutSoA), _vp]
+        L.bysdf_ply_geometry.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, C.POINTER(PlyOutSoA), _vp]
         L.bysdf_eval_multi.argtypes = [_vp, C.POINTER(QuerySoA), C.POINTER(FootprintSoA),
                                        C.c_int64, C.c_int32, C.POINTER(EvalOutSoA), _vp]
         L.bysdf_sample_multi.argtypes = [_vp, C.POINTER(SampleSoA), C.POINTER(FootprintSoA),
@@ -393,6 +399,29 @@ def bysdf_eval_sample(types: Types, q: dict, out=None, stream=None):
     _check(lib().bysdf_eval_sample(types.handle, C.byref(qs), _ptr(xi[0]), _ptr(xi[1]), _ptr(xi[2]),
                                    n, C.byref(o), C.byref(s), _stream(stream)), "bysdf_eval_sample")
     return ev, ef, sv, lobe, node, sf
+
+
+def bysdf_ply_geometry(types: Types, q: dict, stream=None):
+    """Implicit ply hit per query (Sec. 3.4).  q needs type, h, u, v, wi.
+    Returns (ply int32[n], point float32[3, n], tangent float32[3, n],
+    normal float32[3, n], flags int32[n])."""
+    import torch
+    n = int(q["h"].numel())
+    dev = q["h"].device
+    ply = torch.empty(n, dtype=torch.int32, device=dev)
+    vals = torch.empty((9, n), dtype=torch.float32, device=dev)
+    flags = torch.empty(n, dtype=torch.int32, device=dev)
+    o = PlyOutSoA()
+    o.ply, o.flags = _ptr(ply), _ptr(flags)
+    for i, nm in enumerate(("p_x", "p_y", "p_z", "t_x", "t_y", "t_z", "n_x", "n_y", "n_z")):
+        setattr(o, nm, _ptr(vals[i]))
+    s = QuerySoA()
+    s.type_id, s.h, s.u, s.v = _ptr(q["type"]), _ptr(q["h"]), _ptr(q["u"]), _ptr(q["v"])
+    wi = q["wi"]
+    s.wi_x, s.wi_y, s.wi_z = _ptr(wi[0]), _ptr(wi[1]), _ptr(wi[2])
+    _check(lib().bysdf_ply_geometry(types.handle, C.byref(s), n, C.byref(o), _stream(stream)),
+           "bysdf_ply_geometry")
+    return ply, vals[0:3], vals[3:6], vals[6:9], flags
 
 
 def _fsoa(q, sampler):

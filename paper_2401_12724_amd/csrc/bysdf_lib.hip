@@ -912,6 +912,58 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
     }
 }
 
+// ------------------------------------------------------------------ ply geometry
+// The implicit ply hit of Sec. 3.4 on its own (no fiber table, no lobes):
+// the ply, the hit point and the ply's frame there, for studies of the
+// cross-section construction.
+struct PlyOPtrs {
+    int32_t* ply;
+    float *px, *py, *pz, *tx, *ty, *tz, *nx, *ny, *nz;
+    uint32_t* flags;
+};
+
+template <int MP>
+__global__ __launch_bounds__(kBlock) void k_ply_geometry(const TypeRec* __restrict__ types, int n_types,
+                                                         QPtrs q, PlyOPtrs o, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int t = q.type[i];
+        V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
+        float h = q.h[i], u = q.u[i], v = q.v[i];
+        uint32_t fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+        fl |= check_inputs(h, u, v, wi);
+        int ply = -1;
+        V3<double> pt = mk3<double>(0.0, 0.0, 0.0), tp = pt, np = pt;
+        for_each_wave_type(t, fl == 0u, [&](int tu) {
+            const Derived<double, float>& P = types[tu].d;
+            PlyHit<double, MP> ph;
+            trace_plies(P, h, u, v, wi, ph);
+            fl = ph.flags;
+            if (ph.pass) return;
+            double cth = 0.0, sth = 0.0;
+#pragma unroll
+            for (int k = 0; k < MP; ++k)
+                if (k == ph.ks) {
+                    cth = ph.cth[k];
+                    sth = ph.sth[k];
+                }
+            // ply tangent: derivative of the centre helix; normal: the 2D
+            // outward normal made orthogonal to it (as in the fiber frame)
+            tp = mk3<double>(-P.slope * sth * P.tnorm_inv, P.slope * cth * P.tnorm_inv, P.tnorm_inv);
+            const V3<double> n23 = mk3<double>(ph.n2x, ph.n2y, 0.0);
+            np = normalize(n23 - tp * dot(n23, tp));
+            pt = mk3<double>(ph.p2x, ph.p2y, ph.vhit);
+            ply = ph.ks;
+        });
+        o.ply[i] = ply;
+        o.px[i] = (float)pt.x; o.py[i] = (float)pt.y; o.pz[i] = (float)pt.z;
+        o.tx[i] = (float)tp.x; o.ty[i] = (float)tp.y; o.tz[i] = (float)tp.z;
+        o.nx[i] = (float)np.x; o.ny[i] = (float)np.y; o.nz[i] = (float)np.z;
+        o.flags[i] = fl;
+    }
+}
+
 // ------------------------------------------------------------------ furnace
 // One workgroup per furnace block.  Every draw shares the block's hit, so
 // the state at x is computed per lane (identical values) while the K
@@ -1574,6 +1626,24 @@ extern "C" int bysdf_sample_multi(const bysdf_types_t* h, const bysdf_sample_soa
     auto kern = BYSDF_PICK(k_sample_multi, h);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
                        h->d_tables, tx, sp, fpp, (int)n_max, op, n);
+    HIP_TRY(hipGetLastError());
+    return BYSDF_OK;
+}
+
+extern "C" int bysdf_ply_geometry(const bysdf_types_t* h, const bysdf_query_soa* q, int64_t n,
+                                  const bysdf_ply_out_soa* o, hipStream_t stream)
+{
+    if (!h || !q || !o) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(BYSDF_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return BYSDF_OK;
+    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, o->ply, o->p_x, o->p_y,
+                          o->p_z, o->t_x, o->t_y, o->t_z, o->n_x, o->n_y, o->n_z, o->flags};
+    for (const void* ptr : need)
+        if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query/output pointer is NULL or misaligned");
+    QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, nullptr, nullptr, nullptr, nullptr, nullptr};
+    PlyOPtrs op{o->ply, o->p_x, o->p_y, o->p_z, o->t_x, o->t_y, o->t_z, o->n_x, o->n_y, o->n_z, o->flags};
+    auto kern = h->max_plies <= 4 ? k_ply_geometry<4> : k_ply_geometry<8>;
+    hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0, stream, h->d_types, h->n_types, qp, op, n);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }
