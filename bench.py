@@ -56,7 +56,7 @@ def _src_hash():
 
 
 # bench stage -> kernel name prefix in rocprofv3 output
-_STAGE_KERNEL = {"eval_sample": "k_eval_sample<", "furnace": "k_furnace<"}
+_STAGE_KERNEL = {"eval_sample": "k_eval_sample<", "furnace": "k_furnace_w<"}
 
 
 def _kname(full):

@@ -580,14 +580,16 @@ __device__ inline void wave_footprint_geometry(const TypeRec* __restrict__ types
             const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, fo);
             const float hj = stratum_h(fo, j);
             const double w = stratum_w(fo, (double)hj);
-            XState<double, float, MP> X;
-            state_at_x(Pm, tab, hj, m.u, m.v, m.wi, X);
-            f_it = X.ph.flags & ~F_PASS_THROUGH;
-            if (!X.ph.pass && w > 0.0) {
+            Frame<double> fx;
+            double rawf;
+            uint32_t sfl;
+            const bool hit = stratum_frame<double, float, MP>(Pm, tab, hj, m.u, m.v, m.wi, fx, rawf, sfl);
+            f_it = sfl & ~F_PASS_THROUGH;
+            if (hit && w > 0.0) {
                 w_it = w;
-                n_it = X.fx.n;
-                t_it = X.fx.t;
-                g_it = 1.0 - (double)Pm.rho_f * (1.0 - X.rawf);
+                n_it = fx.n;
+                t_it = fx.t;
+                g_it = 1.0 - (double)Pm.rho_f * (1.0 - rawf);
             }
         });
         // this lane's items of the round, in stratum order
@@ -1055,6 +1057,95 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
         for (int c = 0; c < 3; ++c) {
             mean[3 * b + c] = m[c];
             var[3 * b + c] = s_red[c][0] / (float)(block - 1);
+        }
+    }
+}
+
+// One wavefront per furnace block of at most 256 draws (4 per lane), four
+// blocks per workgroup: each wavefront computes its own block's state at x
+// and K nodes into its LDS slot, so no wavefront waits on another's setup;
+// sums reduce across the wavefront's lanes in a fixed shuffle order.
+#ifndef BYSDF_FURNACE_WAVE
+#define BYSDF_FURNACE_WAVE 1
+#endif
+#ifndef BYSDF_FURNACE_MIN_WAVES
+#define BYSDF_FURNACE_MIN_WAVES 1
+#endif
+constexpr int kFurnaceWaves = kBlock / kWave;
+
+__device__ inline float wave_sum_f(float x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+    return x;
+}
+
+template <int MP, bool MIG>
+__global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(const TypeRec* __restrict__ types, int n_types,
+                                                      const float4* __restrict__ tables, SPtrs q,
+                                                      int block, int64_t nb, float* mean, float* var)
+{
+    __shared__ Node<double, float> s_nodes[kFurnaceWaves][kMaxNodes];
+    __shared__ XState<double, float, MP> s_X[kFurnaceWaves];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t b = (int64_t)blockIdx.x * kFurnaceWaves + wv;
+    const bool live = b < nb;
+    const int64_t q0 = live ? b * (int64_t)block : 0;
+    const int t = __builtin_amdgcn_readfirstlane(q.type[q0]);
+    const bool valid = t >= 0 && t < n_types;
+    const TypeRec& rec = types[valid ? t : 0];
+    const Derived<double, float>& P = rec.d;
+    TabPtrT<MIG> tab;
+    tab.p = tables + rec.table_off;
+    V3<float> wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
+    const float h = q.h[q0], u = q.u[q0], v = q.v[q0];
+    const float s0 = q.s0 ? q.s0[q0] : 0.0f, s1 = q.s1 ? q.s1[q0] : 0.0f;
+    const bool bad = !live || !valid || check_inputs(h, u, v, wi) != 0u;
+    if (!bad) {
+        XState<double, float, MP> X0;
+        state_at_x(P, tab, h, u, v, wi, X0);
+        if (lane == 0) s_X[wv] = X0;
+        if (!X0.ph.pass && lane < P.K) {
+            Node<double, float> nd;
+            forward_node(P, tab, X0, lane, s0, s1, q.s0 != nullptr, nd);
+            s_nodes[wv][lane] = nd;
+        }
+    }
+    __syncthreads();
+    const XState<double, float, MP>& X = s_X[wv];
+    NodesStored<double, float> nodes{s_nodes[wv]};
+    float w[kMaxDrawsPerLane][3];
+    float sum[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+        const int j = lane + d * kWave;
+        w[d][0] = w[d][1] = w[d][2] = 0.0f;
+        if (j < block && !bad) {
+            const int64_t qi = q0 + j;
+            SampleOut<float> so;
+            sample_from_x(P, X, wi, q.xi0[qi], q.xi1[qi], q.xi2[qi], nodes, so);
+            for (int c = 0; c < 3; ++c) w[d][c] = so.wgt[c];
+        }
+        for (int c = 0; c < 3; ++c) sum[c] += w[d][c];
+    }
+    float m[3];
+    for (int c = 0; c < 3; ++c) m[c] = wave_sum_f(sum[c]) / (float)block;
+    float sq[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+        const int j = lane + d * kWave;
+        if (j < block)
+            for (int c = 0; c < 3; ++c) {
+                const float dv = w[d][c] - m[c];
+                sq[c] += dv * dv;
+            }
+    }
+    float vs[3];
+    for (int c = 0; c < 3; ++c) vs[c] = wave_sum_f(sq[c]);
+    if (live && lane == 0) {
+        for (int c = 0; c < 3; ++c) {
+            mean[3 * b + c] = m[c];
+            var[3 * b + c] = vs[c] / (float)(block - 1);
         }
     }
 }
@@ -1662,10 +1753,18 @@ extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_s
     if (nb > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many blocks");
     SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
              q->shift0, q->shift1};
-    auto kern = h->any_mig ? (h->max_plies <= 4 ? k_furnace<4, true> : k_furnace<8, true>)
-                           : (h->max_plies <= 4 ? k_furnace<4, false> : k_furnace<8, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, stream, h->d_types, h->n_types,
-                       h->d_tables, sp, block, mean, var);
+    if (BYSDF_FURNACE_WAVE && block <= kWave * kMaxDrawsPerLane) {
+        auto kw = h->any_mig ? (h->max_plies <= 4 ? k_furnace_w<4, true> : k_furnace_w<8, true>)
+                             : (h->max_plies <= 4 ? k_furnace_w<4, false> : k_furnace_w<8, false>);
+        const int64_t groups = (nb + kFurnaceWaves - 1) / kFurnaceWaves;
+        hipLaunchKernelGGL(kw, dim3((unsigned)groups), dim3(kBlock), 0, stream, h->d_types, h->n_types,
+                           h->d_tables, sp, block, nb, mean, var);
+    } else {
+        auto kern = h->any_mig ? (h->max_plies <= 4 ? k_furnace<4, true> : k_furnace<8, true>)
+                               : (h->max_plies <= 4 ? k_furnace<4, false> : k_furnace<8, false>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, stream, h->d_types, h->n_types,
+                           h->d_tables, sp, block, mean, var);
+    }
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }

@@ -83,6 +83,29 @@ __host__ __device__ inline Derived<G, S> widened(const Derived<G, S>& P, double 
     return Pm;
 }
 
+// What the aggregation needs of a stratum: the ply hit, the fiber frame and
+// the raw fiber visibility (the values state_at_x computes for them; the
+// ply horizon and the lobe weights are left out).
+template <class G, class S, int MP, class Tab>
+__host__ __device__ inline bool stratum_frame(const Derived<G, S>& P, const Tab& tab, float h, float u, float v,
+                                              const V3<float>& wi, Frame<G>& fx, G& rawf, uint32_t& flags)
+{
+    PlyHit<G, MP> ph;
+    trace_plies(P, h, u, v, wi, ph);
+    flags = ph.flags;
+    if (ph.pass) return false;
+    G cth = G(0), sth = G(0);
+#pragma unroll
+    for (int k = 0; k < MP; ++k)
+        if (k == ph.ks) {
+            cth = ph.cth[k];
+            sth = ph.sth[k];
+        }
+    G a;
+    fx = fiber_frame(P, tab, cth, sth, ph.ks, ph.n2x, ph.n2y, ph.vhit, &rawf, &a);
+    return true;
+}
+
 // The aggregated frame and fiber shadowing of the footprint (Eq. 9-11).
 // Returns false when no stratum of positive weight hits a ply.  Flags of
 // the strata's ply traces (but pass-through) are or-ed into `flags`.
@@ -99,18 +122,21 @@ __host__ __device__ inline bool footprint_geometry(const Derived<G, S>& P, const
     for (int j = 0; j < f.n; ++j) {
         const float hj = stratum_h(f, j);
         const double w = stratum_w(f, (double)hj);
-        XState<G, S, MP> X;
-        state_at_x(P, tab, hj, u, v, wi, X);
-        flags |= X.ph.flags & ~F_PASS_THROUGH;
-        if (X.ph.pass || !(w > 0.0)) continue;
+        Frame<G> fx;
+        G rawf;
+        uint32_t sfl;
+        const bool hit = stratum_frame<G, S, MP>(P, tab, hj, u, v, wi, fx, rawf, sfl);
+        flags |= sfl & ~F_PASS_THROUGH;
+        if (!hit || !(w > 0.0)) continue;
+        const G gf = G(1) - G(val(P.rho_f)) * (G(1) - rawf);
         if (have == 0) {
-            F = X.fx;
-            Gm = X.Gf;
+            F = fx;
+            Gm = Narrow<S>::from(gf);
         }
         const G gw = G(w);
-        sn = sn + X.fx.n * gw;
-        st = st + X.fx.t * gw;
-        sg = sg + (G(1) - G(val(P.rho_f)) * (G(1) - X.rawf)) * gw;
+        sn = sn + fx.n * gw;
+        st = st + fx.t * gw;
+        sg = sg + gf * gw;
         sw += w;
         ++have;
     }

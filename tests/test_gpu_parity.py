@@ -214,6 +214,32 @@ def test_furnace_blocks(torch_cuda):
     assert np.array_equal(mean2.cpu().numpy(), gm) and np.array_equal(var2.cpu().numpy(), gv)
 
 
+@pytest.mark.parametrize("block", [64, 192, 512, 1024])
+def test_furnace_block_sizes(torch_cuda, block):
+    """Blocks of up to 256 draws run one wavefront per block (1-4 draws per
+    lane, a partial last workgroup), larger ones one workgroup per block:
+    both against the oracle on 37 blocks of a mixed-type batch."""
+    P = [W.default_params(), W.default_params(beta=0.1, albedo=(0.9, 0.6, 0.3))]
+    nb = 37
+    q = W.queries(block * nb, 19, n_types=2, with_xi=True)
+    # one type per block (the block's first query decides)
+    q["type"] = np.repeat(q["type"][::block][:nb], block).astype(np.int32)
+    T = bysdf.bysdf_types_create(P)
+    mean, var = bysdf.bysdf_furnace_blocks(T, bysdf.to_device(q), block)
+    torch_cuda.cuda.synchronize()
+    gm, gv = mean.cpu().numpy(), var.cpu().numpy()
+    om, ov = oracle.furnace(P, q, block)
+    qq = {k: v for k, v in q.items()}
+    for k in ("type", "h", "u", "v"):
+        qq[k] = np.repeat(q[k][::block][:nb], block)
+    qq["wi"] = np.repeat(q["wi"][:, ::block][:, :nb], block, axis=1)
+    _, sf = oracle.sample(P, qq)
+    blk_ok = ((sf & oracle.MARGIN_MASK) == 0).reshape(nb, block).all(1)
+    assert blk_ok.sum() >= nb // 2
+    assert np.all((np.abs(gm - om) <= 1e-4 * np.abs(om) + 1e-6)[blk_ok])
+    assert np.all((np.abs(gv - ov) <= 1e-3 * np.abs(ov) + 1e-6)[blk_ok])
+
+
 def test_edge_cases(torch_cuda):
     torch = torch_cuda
     P = [W.default_params()]
