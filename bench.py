@@ -458,8 +458,7 @@ def _weave_render(torch, bysdf, W, spp=4):
     _, mcounts = bysdf.shade_wavefront(S, T, rm, fbm, ws, counts=True)
     mms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rm, fbm, ws), 3)
     # the same frame with the image gradient in (r, k^B, sigma_t)
-    wsg = bysdf.alloc_workspace(int(bysdf.lib().shade_wavefront_grad_workspace_size(
-        bysdf.render_settings(rs))))
+    wsg = bysdf.alloc_workspace(bysdf.shade_wavefront_grad_workspace_size(rs))
     fbg = torch.empty_like(fb)
     grd = torch.empty((cam["height"], cam["width"], 3, 3), dtype=torch.float32, device="cuda")
     bysdf.shade_wavefront_grad(S, T, rs, 0, fbg, grd, wsg)

@@ -627,6 +627,10 @@ def shade_wavefront(scene: Scene, types: Types, rs: dict, fb=None, workspace=Non
     return fb
 
 
+def shade_wavefront_grad_workspace_size(rs: dict) -> int:
+    return int(lib().shade_wavefront_grad_workspace_size(C.byref(render_settings(rs))))
+
+
 def shade_wavefront_grad(scene: Scene, types: Types, rs: dict, grad_type: int = 0, fb=None, grad=None,
                          workspace=None, stream=None):
     """Render the crop and the gradient of the image with respect to (r,
@@ -634,7 +638,7 @@ def shade_wavefront_grad(scene: Scene, types: Types, rs: dict, grad_type: int = 
     [crop_h, crop_w, 3], gradient float32 [crop_h, crop_w, 3, 3])."""
     import torch
     st = render_settings(rs)
-    nb = int(lib().shade_wavefront_grad_workspace_size(C.byref(st)))
+    nb = shade_wavefront_grad_workspace_size(rs)
     if nb == 0:
         _check(-2, "shade_wavefront_grad_workspace_size")
     if fb is None:

@@ -68,8 +68,7 @@ def fit(scene, params: list, type_index: int, target, rs: dict, theta0, steps: i
         rb = dict(rs, seed=seed + 2 * it + 1)
         if ws_plain is None:
             ws_plain = bysdf.alloc_workspace(bysdf.shade_wavefront_workspace_size(ra))
-            ws_grad = bysdf.alloc_workspace(int(bysdf.lib().shade_wavefront_grad_workspace_size(
-                bysdf.render_settings(rb))))
+            ws_grad = bysdf.alloc_workspace(bysdf.shade_wavefront_grad_workspace_size(rb))
         img = bysdf.shade_wavefront(scene, T, ra, workspace=ws_plain)
         _, dimg = bysdf.shade_wavefront_grad(scene, T, rb, type_index, workspace=ws_grad)
         loss, g = loss_gradient(img, target, dimg)
