@@ -672,12 +672,19 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
         const int nq = fl == 0u ? f.n : 0;
         const int first = wave_excl_scan(nq);
         const int S = __shfl(first + nq, kWave - 1);
+        // a single stratum is its own aggregate: only wider footprints take
+        // part in the aggregation pass
+        const bool single = nq == 1;
+        const int nqa = nq > 1 ? nq : 0;
+        const int firsta = wave_excl_scan(nqa);
+        const int Sa = __shfl(firsta + nqa, kWave - 1);
         Frame<double> F;
         float Gm;
         bool any;
-        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, first, nq, S, F,
+        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, firsta, nqa, Sa, F,
                                                Gm, any, fl);
-        if (nq > 0 && !any) fl |= F_PASS_THROUGH;
+        if (nqa > 0 && !any) fl |= F_PASS_THROUGH;
+        bool hit1 = false;  // a single stratum that hits a ply
         // f_multi: every stratum's lobes with the aggregated geometry
         EvalOut<float> acc;
         for (int c = 0; c < 3; ++c) acc.E[c] = acc.ExB[c] = acc.EyB[c] = 0.0f;
@@ -690,7 +697,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
             // every lane takes part in the shuffle (a lane outside the items
             // may own items of this round)
             const int any_o = __shfl((int)any, own);
-            const bool item = k < S && any_o != 0;
+            const int single_o = __shfl((int)single, own);
+            const bool item = k < S && (any_o != 0 || single_o != 0);
             Frame<double> Fo;
             Fo.n = shfl3(F.n, own);
             Fo.t = shfl3(F.t, own);
@@ -699,7 +707,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
             float ev[12];
             for (int c = 0; c < 12; ++c) ev[c] = 0.0f;
             float w_it = 0.0f;
-            int back = 0;
+            int back = 0, hit_it = 0;
+            uint32_t f_it = 0;
             for_each_wave_type(to, item, [&](int tu) {
                 const TypeRec& R = types[tu];
                 TabPtrT<MIG> tab;
@@ -712,8 +721,10 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
                 const float hj = stratum_h(fo, j);
                 XState<double, float, MP> X;
                 state_at_x(Pm, tab, hj, m.u, m.v, m.wi, X);
+                f_it = X.ph.flags & ~F_PASS_THROUGH;
                 if (X.ph.pass) return;
-                apply_aggregate(Pm, X, Fo, Go);
+                hit_it = 1;
+                if (!single_o) apply_aggregate(Pm, X, Fo, Go);
                 back = !(X.mu_i > 0.0f);
                 const float s0 = q.s0 ? q.s0[io] : 0.0f, s1 = q.s1 ? q.s1[io] : 0.0f;
                 const V3<double> wo_g = mk3<double>(q.wox[io], q.woy[io], q.woz[io]);
@@ -736,8 +747,14 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
                 for (int c = 0; c < 12; ++c) es[c] = __shfl(ev[c], src);
                 const float ws = __shfl(w_it, src);
                 const int bs = __shfl(back, src);
+                const int hs = __shfl(hit_it, src);
+                const uint32_t fs = __shfl(f_it, src);
                 if (jj < cnt) {
                     if (bs) fl |= F_BACKFACING;
+                    if (single) {
+                        fl |= fs;
+                        hit1 = hs != 0;
+                    }
                     for (int c = 0; c < 3; ++c) {
                         acc.E[c] = acc.E[c] + ws * es[c];
                         acc.ExB[c] = acc.ExB[c] + ws * es[5 + c];
@@ -750,6 +767,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
             }
         }
         if (!in) continue;
+        if (single && !hit1) fl |= F_PASS_THROUGH;
         const float iw = float(1.0 / f.wsum);
         o.Er[i] = acc.E[0] * iw; o.Eg[i] = acc.E[1] * iw; o.Eb[i] = acc.E[2] * iw;
         o.ExS[i] = acc.ExS * iw; o.EyS[i] = acc.EyS * iw;
@@ -794,10 +812,14 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
         const int nq = good ? f.n : 0;
         const int first = wave_excl_scan(nq);
         const int S = __shfl(first + nq, kWave - 1);
+        const bool single = nq == 1;
+        const int nqa = nq > 1 ? nq : 0;
+        const int firsta = wave_excl_scan(nqa);
+        const int Sa = __shfl(firsta + nqa, kWave - 1);
         Frame<double> F;
         float Gm;
         bool any;
-        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, first, nq, S, F,
+        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, firsta, nqa, Sa, F,
                                                Gm, any, fl);
         // the stratum and the draw, per query
         SampleOut<float> so;
@@ -819,18 +841,19 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             }
         }
         V3<double> wo = mk3<double>(0.0, 0.0, 0.0);
-        bool drawn = false, pass = good && !any;
+        bool drawn = false, pass = good && !any && !single;
         const float s0 = in && q.s0 ? q.s0[i] : 0.0f, s1 = in && q.s1 ? q.s1[i] : 0.0f;
-        for_each_wave_type(t, good && any, [&](int tu) {
+        for_each_wave_type(t, good && (any || single), [&](int tu) {
             const TypeRec& R = types[tu];
             TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + R.table_off;
             const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, f);
             XState<double, float, MP> X;
             state_at_x(Pm, tab, stratum_h(f, s), m.u, m.v, m.wi, X);
+            if (single) fl |= X.ph.flags & ~F_PASS_THROUGH;
             pass = X.ph.pass;
             if (pass) return;
-            apply_aggregate(Pm, X, F, Gm);
+            if (!single) apply_aggregate(Pm, X, F, Gm);
             NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
             fl |= sample_draw(Pm, X, m.wi, q.xi0[i], q.xi1[i], q.xi2[i], nf, so, wo, drawn);
         });
@@ -853,6 +876,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             const int j = k - __shfl(first, own);
             const int to = __shfl(t, own);
             const int drawn_o = __shfl((int)drawn, own);
+            const int single_o = __shfl((int)single, own);
             const bool item = k < S && drawn_o != 0;
             Frame<double> Fo;
             Fo.n = shfl3(F.n, own);
@@ -875,7 +899,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
                 XState<double, float, MP> X;
                 state_at_x(Pm, tab, hj, mo.u, mo.v, mo.wi, X);
                 if (X.ph.pass) return;
-                apply_aggregate(Pm, X, Fo, Go);
+                if (!single_o) apply_aggregate(Pm, X, Fo, Go);
                 const float t0 = q.s0 ? q.s0[io] : 0.0f, t1 = q.s1 ? q.s1[io] : 0.0f;
                 EvalOut<float> e;
                 lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e);
