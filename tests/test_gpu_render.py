@@ -233,3 +233,23 @@ def test_image_space_fit_recovers_parameters(torch_cuda):
     assert np.all(np.abs(th[1:4] - truth[1:4]) < 0.02)
     assert abs(th[4] - truth[4]) < 0.15
     assert lf < 1.5 * ls and lf < 0.05 * l0
+
+
+def test_gradient_render_rejects_bad_requests(torch_cuda):
+    """The image gradient is of the near-field render of an existing type:
+    multi-scale mode and a type outside the handle are refused before any
+    launch, and the plain render still works afterwards."""
+    torch = torch_cuda
+    ctrl, off, ty, ph = W.weave(6, 6, 0.15, 0.05, 4)
+    S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    T = bysdf.bysdf_types_create([W.default_params()])
+    cam = W.camera((0.0, -1.4, 0.8), (0.0, 0.0, 0.0), width=32, height=24)
+    rs = _settings(cam, (0, 0, 32, 24), spp=1)
+    with pytest.raises(RuntimeError, match="near-field"):
+        bysdf.shade_wavefront_grad(S, T, dict(rs, multiscale=1), 0)
+    for bad in (-1, 1):
+        with pytest.raises(RuntimeError, match="grad_type"):
+            bysdf.shade_wavefront_grad(S, T, rs, bad)
+    fb = bysdf.shade_wavefront(S, T, rs)
+    torch.cuda.synchronize()
+    assert np.isfinite(fb.cpu().numpy()).all()
