@@ -127,13 +127,18 @@ typedef struct {
 
 /* Sampler inputs: like bysdf_query_soa without wo, plus three uniform
  * numbers in [0, 1) per query (xi0 picks the lobe and node, xi1 and xi2 the
- * direction). */
+ * direction).  With xi0, xi1 and xi2 all NULL the library draws them:
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (i mod 2^32, i >> 32,
+ * 0, 0x53414d50) for query index i and key (seed mod 2^32, seed >> 32),
+ * words 0..2 mapped to [0, 1) as (word >> 8) * 2^-24.  The furnace draws
+ * of query index j use the same stream. */
 typedef struct {
     const int32_t* type_id;
     const float *h, *u, *v;
     const float *wi_x, *wi_y, *wi_z;
     const float *xi0, *xi1, *xi2;
     const float *shift0, *shift1;
+    uint64_t seed;
 } bysdf_sample_soa;
 
 /* Sampler outputs.  lobe: 0 specular at x, 1 specular through the yarn to

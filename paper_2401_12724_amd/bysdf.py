@@ -67,7 +67,7 @@ class EvalOutSoA(C.Structure):
 
 class SampleSoA(C.Structure):
     _fields_ = [(n, _vp) for n in ("type_id", "h", "u", "v", "wi_x", "wi_y", "wi_z",
-                                   "xi0", "xi1", "xi2", "shift0", "shift1")]
+                                   "xi0", "xi1", "xi2", "shift0", "shift1")] + [("seed", C.c_uint64)]
 
 
 class PlyOutSoA(C.Structure):
@@ -281,11 +281,17 @@ def _qsoa(q):
 
 
 def _ssoa(q):
+    """Sampler queries; without q["xi"] the library draws the uniforms from
+    Philox keyed by q["seed"] (default 0)."""
     s = SampleSoA()
     s.type_id, s.h, s.u, s.v = _ptr(q["type"]), _ptr(q["h"]), _ptr(q["u"]), _ptr(q["v"])
-    wi, xi = q["wi"], q["xi"]
+    wi, xi = q["wi"], q.get("xi")
     s.wi_x, s.wi_y, s.wi_z = _ptr(wi[0]), _ptr(wi[1]), _ptr(wi[2])
-    s.xi0, s.xi1, s.xi2 = _ptr(xi[0]), _ptr(xi[1]), _ptr(xi[2])
+    if xi is not None:
+        s.xi0, s.xi1, s.xi2 = _ptr(xi[0]), _ptr(xi[1]), _ptr(xi[2])
+    else:
+        s.xi0 = s.xi1 = s.xi2 = None
+    s.seed = int(q.get("seed") or 0)
     sh = q.get("shift")
     s.shift0, s.shift1 = (_ptr(sh[0]), _ptr(sh[1])) if sh is not None else (None, None)
     return s

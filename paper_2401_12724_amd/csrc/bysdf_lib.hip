@@ -357,7 +357,28 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const Typ
 struct SPtrs {
     const int32_t* type;
     const float *h, *u, *v, *wix, *wiy, *wiz, *xi0, *xi1, *xi2, *s0, *s1;
+    uint64_t seed;  // the draws when xi0..xi2 are NULL
 };
+
+// The three uniforms of query i: the caller's arrays, or (arrays NULL)
+// Philox4x32-10 with counter (i, i >> 32, 0, "SAMP") and key = seed, words
+// 0-2 to [0, 1) by their top 24 bits.
+constexpr uint32_t kXiStream = 0x53414d50u;
+__device__ inline void query_xi(const SPtrs& q, int64_t i, float& x0, float& x1, float& x2)
+{
+    if (q.xi0) {
+        x0 = q.xi0[i];
+        x1 = q.xi1[i];
+        x2 = q.xi2[i];
+        return;
+    }
+    uint32_t o[4];
+    rng::philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, kXiStream, (uint32_t)q.seed,
+                       (uint32_t)(q.seed >> 32), o);
+    x0 = rng::u01(o[0]);
+    x1 = rng::u01(o[1]);
+    x2 = rng::u01(o[2]);
+}
 struct SOPtrs {
     float *wox, *woy, *woz, *wr, *wg, *wb, *pdf, *exx, *exy, *exz;
     int32_t *lobe, *node;
@@ -386,7 +407,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
         const bool need = fl == 0u;
         V3<float> wi = mk3<float>(q.wix[i], q.wiy[i], q.wiz[i]);
         float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
-        float h = q.h[i], u = q.u[i], v = q.v[i], x0 = q.xi0[i], x1 = q.xi1[i], x2 = q.xi2[i];
+        float h = q.h[i], u = q.u[i], v = q.v[i], x0, x1, x2;
+        query_xi(q, i, x0, x1, x2);
         for_each_wave_type(t, need, [&](int tu) {
             const Derived<double, float>& P = types[tu].d;
             TabPtrT<MIG> tab;
@@ -1054,7 +1076,9 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             if (pass) return;
             if (!single) apply_aggregate(Pm, X, F, Gm);
             NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
-            fl |= sample_draw(Pm, X, m.wi, q.xi0[i], q.xi1[i], q.xi2[i], nf, so, wo, drawn);
+            float x0, x1, x2;
+            query_xi(q, i, x0, x1, x2);
+            fl |= sample_draw(Pm, X, m.wi, x0, x1, x2, nf, so, wo, drawn);
         });
         if (pass) {
             so.wo[0] = -m.wi.x;
@@ -1244,7 +1268,9 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
         if (j < block && !bad) {
             const int64_t qi = q0 + j;
             SampleOut<float> so;
-            sample_from_x(P, X, wi, q.xi0[qi], q.xi1[qi], q.xi2[qi], nodes, so);
+            float x0, x1, x2;
+            query_xi(q, qi, x0, x1, x2);
+            sample_from_x(P, X, wi, x0, x1, x2, nodes, so);
             for (int c = 0; c < 3; ++c) w[d][c] = so.wgt[c];
         }
         for (int c = 0; c < 3; ++c) sum[c] += w[d][c];
@@ -1346,7 +1372,9 @@ __global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(c
         if (j < block && !bad) {
             const int64_t qi = q0 + j;
             SampleOut<float> so;
-            sample_from_x(P, X, wi, q.xi0[qi], q.xi1[qi], q.xi2[qi], nodes, so);
+            float x0, x1, x2;
+            query_xi(q, qi, x0, x1, x2);
+            sample_from_x(P, X, wi, x0, x1, x2, nodes, so);
             for (int c = 0; c < 3; ++c) w[d][c] = so.wgt[c];
         }
         for (int c = 0; c < 3; ++c) sum[c] += w[d][c];
@@ -1806,9 +1834,12 @@ extern "C" int bysdf_eval(const bysdf_types_t* h, const bysdf_query_soa* q, int6
 
 static int check_sample_args(const bysdf_sample_soa* q)
 {
-    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2};
+    const void* need[] = {q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z};
     for (const void* ptr : need)
         if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "a query pointer is NULL or misaligned");
+    const bool none = !q->xi0 && !q->xi1 && !q->xi2;
+    if (!none && (!aligned4(q->xi0) || !aligned4(q->xi1) || !aligned4(q->xi2)))
+        return fail(BYSDF_ERR_INVALID_ARG, "xi0..xi2 must all be NULL (Philox draws) or all valid");
     if ((q->shift0 == nullptr) != (q->shift1 == nullptr) ||
         (q->shift0 && (!aligned4(q->shift0) || !aligned4(q->shift1))))
         return fail(BYSDF_ERR_INVALID_ARG, "shift0/shift1 must both be NULL or both valid");
@@ -1827,7 +1858,7 @@ extern "C" int bysdf_sample_pdf(const bysdf_types_t* h, const bysdf_sample_soa* 
     for (const void* ptr : need)
         if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "an output pointer is NULL or misaligned");
     SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
-             q->shift0, q->shift1};
+             q->shift0, q->shift1, q->seed};
     SOPtrs op{o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x, o->exit_y,
               o->exit_z, o->lobe, o->node, o->flags};
     int grid = grid_for(n);
@@ -1930,7 +1961,7 @@ extern "C" int bysdf_sample_multi(const bysdf_types_t* h, const bysdf_sample_soa
     for (const void* ptr : need)
         if (!aligned4(ptr)) return fail(BYSDF_ERR_INVALID_ARG, "an output pointer is NULL or misaligned");
     SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
-             q->shift0, q->shift1};
+             q->shift0, q->shift1, q->seed};
     FPtrs fpp{fp->h1, fp->h2, fp->zeta, fp->xi_s};
     SOPtrs op{o->wo_x, o->wo_y, o->wo_z, o->w_r, o->w_g, o->w_b, o->pdf, o->exit_x, o->exit_y,
               o->exit_z, o->lobe, o->node, o->flags};
@@ -1975,7 +2006,7 @@ extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_s
     if (!aligned4(mean) || !aligned4(var)) return fail(BYSDF_ERR_INVALID_ARG, "mean/var NULL or misaligned");
     if (nb > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many blocks");
     SPtrs sp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->xi0, q->xi1, q->xi2,
-             q->shift0, q->shift1};
+             q->shift0, q->shift1, q->seed};
     if (BYSDF_FURNACE_WAVE && block <= kWave * kMaxDrawsPerLane) {
         auto kw = h->any_mig ? (h->max_plies <= 4 ? k_furnace_w<4, true> : k_furnace_w<8, true>)
                              : (h->max_plies <= 4 ? k_furnace_w<4, false> : k_furnace_w<8, false>);

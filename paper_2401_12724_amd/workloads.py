@@ -108,6 +108,37 @@ def footprints(q: dict, seed: int, w_min: float = 2.0 ** -6, w_max: float = 2.0)
     return q
 
 
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) on arrays: ctr (4, n) and key (2,
+    n) of uint32; ten rounds of the two 32 x 32 -> 64 multiplications, the
+    Weyl key schedule between rounds.  Returns (4, n) uint32."""
+    c = [np.asarray(x, np.uint64) & np.uint64(0xFFFFFFFF) for x in ctr]
+    k0 = np.asarray(key[0], np.uint64) & np.uint64(0xFFFFFFFF)
+    k1 = np.asarray(key[1], np.uint64) & np.uint64(0xFFFFFFFF)
+    m32 = np.uint64(0xFFFFFFFF)
+    for r in range(10):
+        p0 = np.uint64(0xD2511F53) * c[0]
+        p1 = np.uint64(0xCD9E8D57) * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & m32, (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & m32]
+        if r < 9:
+            k0 = (k0 + np.uint64(0x9E3779B9)) & m32
+            k1 = (k1 + np.uint64(0xBB67AE85)) & m32
+    return np.stack(c).astype(np.uint32)
+
+
+def sampler_xi(n: int, seed: int) -> np.ndarray:
+    """The three uniforms the library draws for sampler queries 0..n-1 when
+    no xi arrays are given: Philox4x32-10 with counter (i mod 2^32, i >> 32,
+    0, 0x53414d50), key (seed mod 2^32, seed >> 32), words 0..2 as
+    (word >> 8) * 2^-24.  (3, n) float32."""
+    i = np.arange(n, dtype=np.uint64)
+    ctr = [i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), np.zeros(n, np.uint64),
+           np.full(n, 0x53414D50, np.uint64)]
+    key = [np.full(n, seed & 0xFFFFFFFF, np.uint64), np.full(n, (seed >> 32) & 0xFFFFFFFF, np.uint64)]
+    w = philox4x32_10(ctr, key)[:3]
+    return ((w >> np.uint32(8)).astype(np.float64) * 2.0 ** -24).astype(np.float32)
+
+
 def queries(n: int, seed: int, n_types: int = 1, type_ids=None, with_xi: bool = False,
             v_max: float = 10.0) -> dict:
     """n queries: h~U[-1,1], u~U[0,2pi), v~U[0,v_max), wi, wo uniform on S^2."""

@@ -240,6 +240,41 @@ def test_furnace_block_sizes(torch_cuda, block):
     assert np.all((np.abs(gv - ov) <= 1e-3 * np.abs(ov) + 1e-6)[blk_ok])
 
 
+def test_sampler_draws_its_own_uniforms(torch_cuda):
+    """Without xi arrays the sampler and the furnace draw their uniforms
+    from Philox4x32-10 keyed by the seed (counter = query index): the same
+    as the oracle given those draws, generated on the host."""
+    P = [W.default_params()]
+    n = 256 * 64 + 77
+    q = W.queries(n, 23)
+    T = bysdf.bysdf_types_create(P)
+    seed = 0x9E3779B97F4A7C15
+    qd = bysdf.to_device(q)
+    qd["seed"] = seed
+    sv, lobe, node, sf = bysdf.bysdf_sample_pdf(T, qd)
+    mean, var = bysdf.bysdf_furnace_blocks(T, qd, 256)
+    torch_cuda.cuda.synchronize()
+    qx = dict(q, xi=W.sampler_xi(n, seed))
+    so, sof = oracle.sample(P, qx)
+    rep = compare(sv.cpu().numpy().T, sf.cpu().numpy(), so[:, :10], sof)
+    print("sample (own draws)", {k: v for k, v in rep.items() if k != "bad_idx"})
+    assert_parity(rep, max_flagged=0.03)
+    ok = (sof & oracle.MARGIN_MASK) == 0
+    assert np.array_equal(lobe.cpu().numpy()[ok], so[ok, 10].astype(np.int32))
+    om, ov = oracle.furnace(P, qx, 256)
+    nb = n // 256
+    qq = dict(qx)
+    for k in ("type", "h", "u", "v"):
+        qq[k] = np.repeat(qx[k][::256][:nb], 256)
+    qq["wi"] = np.repeat(qx["wi"][:, ::256][:, :nb], 256, axis=1)
+    qq["xi"] = qx["xi"][:, :nb * 256]
+    _, bsf = oracle.sample(P, qq)
+    blk = ((bsf & oracle.MARGIN_MASK) == 0).reshape(nb, 256).all(1)
+    assert blk.sum() >= nb // 2
+    gm = mean.cpu().numpy()
+    assert np.all((np.abs(gm - om) <= 1e-4 * np.abs(om) + 1e-6)[blk])
+
+
 def test_edge_cases(torch_cuda):
     torch = torch_cuda
     P = [W.default_params()]

@@ -178,3 +178,22 @@ def test_philox_known_answers(oracle_mod):
         f = [int(x, 16) for x in line.split()]
         out = oracle_mod.philox4x32_10(f[0:4], f[4:6])
         assert list(out) == f[6:10]
+
+
+def test_vectorised_philox_known_answers():
+    """The host Philox4x32-10 that reproduces the library's own sampler draws
+    (for queries without xi arrays) against the published known answers."""
+    import os
+    from paper_2401_12724_amd import workloads as W
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = []
+    for line in open(path):
+        f = line.split("#")[0].split()
+        if len(f) == 10:
+            rows.append([int(x, 16) for x in f])
+    assert len(rows) >= 3
+    a = np.array(rows, dtype=np.uint64).T
+    out = W.philox4x32_10(a[0:4], a[4:6])
+    assert np.array_equal(out.astype(np.uint64), a[6:10])
+    xi = W.sampler_xi(1000, 0x123456789)
+    assert xi.shape == (3, 1000) and xi.min() >= 0.0 and xi.max() < 1.0
