@@ -999,7 +999,10 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
     }
 }
 
-template <bool kLds, int MP, bool MIG>
+// OWNXI: the uniforms come from the generator (xi arrays NULL).  Only the
+// instance that needs it carries the generator: its code alone, never run,
+// costs the multi-scale sampler a quarter of its speed in registers.
+template <bool kLds, int MP, bool MIG, bool OWNXI>
 __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
     const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
     SPtrs q, FPtrs fp, int n_max, SOPtrs o, int64_t n)
@@ -1020,10 +1023,17 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
         f.n = 0;
         f.wsum = 1.0;
         MQuery m{};
-        float xs = 0.0f;
+        float xs = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
         if (in) {
             m = load_mquery(q, fp, i);
             xs = fp.xi_s[i];
+            if (OWNXI) {
+                query_xi(q, i, x0, x1, x2);
+            } else {
+                x0 = q.xi0[i];
+                x1 = q.xi1[i];
+                x2 = q.xi2[i];
+            }
             fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
             fl |= check_inputs(m.h, m.u, m.v, m.wi) | check_footprint(m.h, m.h1, m.h2, m.zeta);
             if (!(xs >= 0.0f && xs < 1.0f)) fl |= F_BAD_INPUT;
@@ -1076,8 +1086,6 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             if (pass) return;
             if (!single) apply_aggregate(Pm, X, F, Gm);
             NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
-            float x0, x1, x2;
-            query_xi(q, i, x0, x1, x2);
             fl |= sample_draw(Pm, X, m.wi, x0, x1, x2, nf, so, wo, drawn);
         });
         if (pass) {
@@ -1968,7 +1976,17 @@ extern "C" int bysdf_sample_multi(const bysdf_types_t* h, const bysdf_sample_soa
     int grid = grid_for(n);
     size_t lds = h->single_table ? sizeof(float4) * h->table_texels : 0;
     int tx = h->single_table ? h->table_texels : 0;
-    auto kern = BYSDF_PICK(k_sample_multi, h);
+#define BYSDF_PICK_SM(X)                                                                                 \
+    (h->any_mig ? (h->max_plies <= 4 ? (h->single_table ? k_sample_multi<true, 4, true, X>                  \
+                                                        : k_sample_multi<false, 4, true, X>)               \
+                                     : (h->single_table ? k_sample_multi<true, 8, true, X>                  \
+                                                        : k_sample_multi<false, 8, true, X>))              \
+                : (h->max_plies <= 4 ? (h->single_table ? k_sample_multi<true, 4, false, X>                 \
+                                                        : k_sample_multi<false, 4, false, X>)              \
+                                     : (h->single_table ? k_sample_multi<true, 8, false, X>                 \
+                                                        : k_sample_multi<false, 8, false, X>)))
+    auto kern = q->xi0 ? BYSDF_PICK_SM(false) : BYSDF_PICK_SM(true);
+#undef BYSDF_PICK_SM
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, h->d_types, h->n_types,
                        h->d_tables, tx, sp, fpp, (int)n_max, op, n);
     HIP_TRY(hipGetLastError());

@@ -173,3 +173,22 @@ def test_multi_full_size_sampled(torch_cuda):
     _check_eval(ev[:, idx], ef[idx], o, of, "full")
     so, sof = oracle.sample_multi(ts, sub, 4)
     _check_sample(sv[:, idx], lobe[idx], node[idx], sf[idx], so, sof, "full")
+
+
+def test_multi_sampler_own_draws(torch_cuda):
+    """Without xi arrays the multi-scale sampler draws Philox uniforms keyed
+    by the seed: bitwise the call given those draws (generated on the host)."""
+    torch = torch_cuda
+    P = [W.default_params()]
+    _, q = W.single_type(65536 + 9, 72)
+    q = W.footprints(q, 73)
+    T = bysdf.bysdf_types_create(P)
+    seed = 12345678901
+    qa = bysdf.to_device(q)
+    qa["seed"] = seed
+    qb = bysdf.to_device(dict(q, xi=W.sampler_xi(len(q["h"]), seed)))
+    a = bysdf.bysdf_sample_multi(T, qa, 4)
+    b = bysdf.bysdf_sample_multi(T, qb, 4)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
