@@ -370,6 +370,10 @@ def _multiscale(torch, bysdf, W, P, q, qd, near_ms, n_max=4):
             "eval_queries_per_s": n / (e_ms * 1e-3), "sample_queries_per_s": n / (s_ms * 1e-3),
             "eval_time_vs_near": e_ms / near_ms["eval"],
             "sample_time_vs_near": s_ms / near_ms["sample"],
+            # each stratum is one near-field evaluation with the aggregated
+            # geometry: their rate against the near-field kernel's
+            "eval_strata_per_s": n * float(strata.mean()) / (e_ms * 1e-3),
+            "eval_strata_rate_vs_near": (n * float(strata.mean()) / e_ms) / (n / near_ms["eval"]),
             "note": "strata_per_query near-field states per query enter the aggregated "
                     "geometry and as many again the lobes; the sampler adds its draw"}
 
