@@ -347,6 +347,34 @@ def _migration(torch, bysdf, W, P, qd, q, base_ms):
             "valu_frac": ops * n / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS}
 
 
+def _k_sweep(torch, bysdf, P, q, qd, Ks=(1, 4, 8)):
+    """The per-block workload with K forward nodes per query: the
+    evaluation alone and the fused eval + sample, against the VALU peak and
+    against HBM (92 and 156 algorithmic bytes per query).  At small K the
+    evaluation does the least arithmetic per byte."""
+    n = int(qd["h"].numel())
+    res = {}
+    for K in Ks:
+        PK = [dict(p, K=K) for p in P]
+        T = bysdf.bysdf_types_create(PK)
+        ev = bysdf.alloc_eval_out(n)
+        out = (ev, bysdf.alloc_sample_out(n))
+        row = {}
+        for name, mode, nbytes, f in (("eval", 0, 92, lambda: bysdf.bysdf_eval(T, qd, ev)),
+                                      ("eval_sample", 2, 156, lambda: bysdf.bysdf_eval_sample(T, qd, out))):
+            f()
+            torch.cuda.synchronize()
+            ms = _timed(torch, f, 5)
+            ops = _op_counts(bysdf, T, PK, q, mode).sum()
+            gbs = nbytes * n / (ms * 1e-3) / 1e9
+            row[name] = {"ms": ms, "queries_per_s": n / (ms * 1e-3), "ops_per_query": ops,
+                         "valu_frac": ops * n / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
+                         "gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        res["K%d" % K] = row
+        del T, ev, out
+    return res
+
+
 def _multiscale(torch, bysdf, W, P, q, qd, near_ms, n_max=4):
     """The per-block workload with a pixel footprint per query (widths
     log-uniform in [2^-6, 2] yarn half-widths, so from a point to the whole
@@ -638,6 +666,7 @@ def main():
         eval_qps = N / (unfused["eval"] * 1e-3)
         del ev, sv
         out["migration"] = _migration(torch, bysdf, W, P, qd, q, ktime["eval_sample"])
+        out["k_sweep"] = _k_sweep(torch, bysdf, P, q, qd)
         out["multiscale"] = _multiscale(torch, bysdf, W, P, q, qd, unfused)
         out["cross_section"] = _cross_section(torch, bysdf, W, P, qd)
         out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
