@@ -251,7 +251,13 @@ def _cpu_baseline(P, q, target_s):
         nb = int(min(len(P), max(nb + 1, nb * target_s / max(dt, 1e-3))))
         dt = run(nb)
     n = nb * 256
-    return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle", "cpu": cpu,
             "sample": "first %d blocks (%d queries) of the per-block workload, same "
                       "stages (eval, sample with pdf, furnace), %.1f s" % (nb, n, dt)}
 
