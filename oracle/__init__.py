@@ -415,6 +415,20 @@ def ply_shadow_raw(d, a, phi):
     return lib().orc_ply_shadow_raw(C.byref(p), float(a), float(phi))
 
 
+def eval_query(d, tab, h, u, v, wi, wo):
+    """One evaluation with FP64 inputs (h, u, v as Python floats, wi and wo
+    3-vectors): (out[13] as in eval, flags).  Lets a test move an input by a
+    few FP64 ulps, below the resolution of the FP32 query arrays."""
+    p = params_struct(d)
+    t = np.ascontiguousarray(tab, dtype=np.float64)
+    a = np.ascontiguousarray(wi, dtype=np.float64)
+    b = np.ascontiguousarray(wo, dtype=np.float64)
+    out = np.zeros(13, dtype=np.float64)
+    fl = lib().orc_eval_query(C.byref(p), _ptr(t, C.c_double), C.c_double(h), C.c_double(u), C.c_double(v),
+                              _ptr(a, C.c_double), _ptr(b, C.c_double), _ptr(out, C.c_double))
+    return out, fl & 0xffffffff
+
+
 def ply_hit(d, h, u, v, wi):
     p = params_struct(d)
     w = np.ascontiguousarray(wi, dtype=np.float64)

@@ -38,3 +38,20 @@ def compare(gpu, gflags, ref, rflags, extra_ok=None):
 def assert_parity(rep, max_flagged=0.02):
     assert rep["n_bad"] == 0 and rep["n_flag_mismatch"] == 0, rep
     assert rep["flagged_share"] <= max_flagged, rep
+
+
+def fp64_sensitive(d, tab, h, u, v, wi, wo, ref, ulps=4):
+    """True when moving h, u or v by `ulps` FP64 ulps moves the oracle's
+    evaluation beyond the parity tolerance.  Such a query's value is not
+    fixed to the tolerance by double-precision arithmetic: the rounding of
+    any FP64 evaluation of it, the oracle's included, lands anywhere in that
+    spread.  Used on the few queries that fail the rule, to tell these from
+    real disagreements."""
+    for k, x in enumerate((float(h), float(u), float(v))):
+        for s in (-1.0, 1.0):
+            a = [float(h), float(u), float(v)]
+            a[k] = x + s * ulps * float(np.spacing(abs(x) if x != 0.0 else 1e-300))
+            o, _ = oracle.eval_query(d, tab, a[0], a[1], a[2], wi, wo)
+            if np.any(np.abs(o[:12] - ref[:12]) > REL * np.abs(ref[:12]) + ABS):
+                return True
+    return False

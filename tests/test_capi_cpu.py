@@ -43,7 +43,8 @@ def test_version(L):
 
 @pytest.mark.parametrize("field,value", [
     ("n_plies", 0), ("n_plies", 9), ("fibers_per_ply", 0), ("fibers_per_ply", 300),
-    ("K", 0), ("K", 17), ("n_iter", -1), ("tex_size", 1), ("ply_radius", 0.0),
+    ("fibers_per_ply", 257), ("K", 0), ("K", 17), ("n_iter", -1), ("n_iter", 17), ("tex_size", 1),
+    ("tex_size", 4097), ("ply_radius", 0.0),
     ("ply_radius", 1.2), ("ply_center_radius", 0.9), ("fiber_radius", 1.0),
     ("ply_twist", 1.6), ("eta", 1.0), ("beta", 0.0), ("aniso", 0.0), ("B", 1.5),
     ("r", -0.1), ("sigma_t", -1.0), ("ply_density", 1.1), ("fiber_density", -0.5),
@@ -170,7 +171,7 @@ def test_op_counts_of_the_kernels_formulation(L):
 
 @pytest.mark.parametrize("field,value", [
     ("mig_tables", 9), ("mig_tables", -1), ("mig_period", 0.0), ("mig_blend", 1.5),
-    ("mig_spread", 1.0), ("mig_spread", -0.1), ("tex_size", 4096),
+    ("mig_spread", 1.0), ("mig_spread", -0.1), ("tex_size", 4096), ("tex_size", 2049),
 ])
 def test_invalid_migration_params_rejected(L, field, value):
     p = workloads.default_params(mig_tables=8)

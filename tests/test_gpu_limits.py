@@ -1,0 +1,111 @@
+"""GPU parity at the largest yarn types the library accepts: 8 plies of 256
+fibers with K = 16 forward nodes and 16 fixed-point steps on a 4,096-texel
+table (larger than the LDS staging, so read from global memory), and a
+type with 8 migration tables of 2,048 texels (the 16,384-texel limit).
+Tables, evaluation, sampling, the fused call and the furnace are checked
+against the FP64 oracle (one step past each limit is refused on the host,
+in the C-ABI tests)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_12724_amd import bysdf, workloads as W
+
+from parity import assert_parity, compare, fp64_sensitive
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _largest_types():
+    rp8 = W.packed_ply_radius(8)
+    return [W.default_params(n_plies=8, ply_radius=rp8, ply_center_radius=1 - rp8, fibers_per_ply=256,
+                             fiber_radius=0.03, K=16, n_iter=16, tex_size=4096),
+            W.default_params(mig_tables=8, mig_period=2.0, mig_blend=1.0, mig_spread=0.9, mig_seed=7,
+                             tex_size=2048, fibers_per_ply=128, K=16, n_iter=16)]
+
+
+def test_largest_types_tables(torch_cuda):
+    P = _largest_types()
+    T = bysdf.bysdf_types_create(P)
+    for i, d in enumerate(P):
+        g = bysdf.bysdf_types_table(T, i)
+        o = oracle.table(d)
+        assert g.shape == o.shape
+        assert np.abs(g - o).max() <= 1e-6
+        assert np.mean(g == o.astype(np.float32)) > 0.999
+
+
+def test_largest_types_eval_sample(torch_cuda):
+    torch = torch_cuda
+    P = _largest_types()
+    n = 65536 + 77
+    q = W.queries(n, 90, n_types=2, with_xi=True, v_max=40.0)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval(T, qd)
+    sv, lobe, node, sf = bysdf.bysdf_sample_pdf(T, qd)
+    fv, ff, gv, globe, gnode, gf = bysdf.bysdf_eval_sample(T, qd)
+    torch.cuda.synchronize()
+    o, of = oracle.eval(P, q)
+    g, gfl = ev.cpu().numpy().T, ef.cpu().numpy()
+    rep = compare(g, gfl, o[:, :12], of)
+    print("eval", rep)
+    # With 16 fixed-point steps at grazing incidence and a 4,096-texel
+    # table of 256 fibers, a rare query's value moves beyond the tolerance
+    # when an input moves by a few FP64 ulps: no FP64 evaluation fixes it to
+    # the tolerance.  Such queries are set aside (a handful at most); every
+    # other disagreement fails.
+    assert rep["n_bad"] <= 5 and rep["n_flag_mismatch"] == 0, rep
+    tabs = [oracle.table(d) for d in P]
+    ill = [i for i in rep["bad_idx"]
+           if fp64_sensitive(P[q["type"][i]], tabs[q["type"][i]], q["h"][i], q["u"][i], q["v"][i],
+                             q["wi"][:, i], q["wo"][:, i], o[i])]
+    print("ill-conditioned at FP64 resolution:", ill)
+    keep = np.ones(n, bool)
+    keep[ill] = False
+    assert_parity(compare(g, gfl, o[:, :12], of, extra_ok=keep), max_flagged=0.06)
+    so, sof = oracle.sample(P, q)
+    rep = compare(sv.cpu().numpy().T, sf.cpu().numpy(), so[:, :10], sof)
+    print("sample", {k: v for k, v in rep.items() if k != "bad_idx"})
+    assert_parity(rep, max_flagged=0.06)
+    ok = (sof & oracle.MARGIN_MASK) == 0
+    gl, gn = lobe.cpu().numpy(), node.cpu().numpy()
+    assert np.array_equal(gl[ok], so[ok, 10].astype(np.int32))
+    fw = ok & ((gl == 1) | (gl == 3))
+    assert np.array_equal(gn[fw], so[fw, 11].astype(np.int32))
+    assert gn[fw].max() == 15  # all 16 nodes are drawn
+    # the fused call: the same values, lobes and nodes
+    assert torch.equal(ff, ef) and torch.equal(gf, sf) and torch.equal(globe, lobe) and torch.equal(gnode, node)
+    assert np.abs(fv.cpu().numpy() - ev.cpu().numpy()).max() <= 1e-5 * np.abs(ev.cpu().numpy()).max()
+    assert np.abs(gv.cpu().numpy() - sv.cpu().numpy()).max() <= 1e-5 * np.abs(sv.cpu().numpy()).max()
+
+
+def test_largest_types_furnace(torch_cuda):
+    torch = torch_cuda
+    P = _largest_types()
+    nb = 128
+    tid = np.repeat(np.arange(nb, dtype=np.int32) % 2, 256)
+    q = W.queries(nb * 256, 91, type_ids=tid, with_xi=True, v_max=40.0)
+    T = bysdf.bysdf_types_create(P)
+    mean, var = bysdf.bysdf_furnace_blocks(T, bysdf.to_device(q), 256)
+    torch.cuda.synchronize()
+    om, ov = oracle.furnace(P, q, 256)
+    # blocks whose 256 draws at the block's first hit are all clear of margins
+    qq = dict(q)
+    for k in ("type", "h", "u", "v"):
+        qq[k] = np.repeat(q[k][::256], 256)
+    qq["wi"] = np.repeat(q["wi"][:, ::256], 256, axis=1)
+    _, sf = oracle.sample(P, qq)
+    blk = ((sf & oracle.MARGIN_MASK) == 0).reshape(nb, 256).all(1)
+    assert blk.sum() > nb // 2
+    gm, gv = mean.cpu().numpy(), var.cpu().numpy()
+    assert np.all((np.abs(gm - om) <= 1e-4 * np.abs(om) + 1e-6)[blk])
+    assert np.all((np.abs(gv - ov) <= 1e-3 * np.abs(ov) + 1e-6)[blk])
+

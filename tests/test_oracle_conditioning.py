@@ -1,0 +1,48 @@
+"""The oracle's single-query evaluation with FP64 inputs, and the test-side
+check that tells an ill-conditioned query (its value moves beyond the parity
+tolerance when h, u or v moves by a few FP64 ulps) from a real disagreement."""
+import numpy as np
+
+import oracle
+from paper_2401_12724_amd import workloads as W
+
+from parity import fp64_sensitive
+
+
+def test_eval_query_is_the_batched_evaluation():
+    d = W.default_params(n_plies=5, ply_radius=W.packed_ply_radius(5), K=6)
+    tab = oracle.table(d)
+    q = W.queries(64, 5, with_xi=True, v_max=40.0)
+    o, of = oracle.eval([d], q)
+    for i in range(64):
+        r, fl = oracle.eval_query(d, tab, float(q["h"][i]), float(q["u"][i]), float(q["v"][i]),
+                                  q["wi"][:, i], q["wo"][:, i])
+        assert fl == of[i]
+        assert np.array_equal(r[:12], o[i, :12])
+
+
+def test_sensitivity_check():
+    # a well-conditioned workload: no query is sensitive
+    d = W.default_params()
+    tab = oracle.table(d)
+    q = W.queries(300, 6)
+    o, of = oracle.eval([d], q)
+    ok = np.nonzero((of & oracle.MARGIN_MASK) == 0)[0]
+    assert not any(fp64_sensitive(d, tab, q["h"][i], q["u"][i], q["v"][i], q["wi"][:, i],
+                                  q["wo"][:, i], o[i]) for i in ok)
+    # 8 plies of 256 fibers, 16 fixed-point steps, 4,096 texels: a query at
+    # grazing incidence (wi_z = -0.97, v = 39.8) whose forward body lobe moves
+    # by 8e-4 (relative) when h moves by 1e-15
+    rp8 = W.packed_ply_radius(8)
+    d = W.default_params(n_plies=8, ply_radius=rp8, ply_center_radius=1 - rp8, fibers_per_ply=256,
+                         fiber_radius=0.03, K=16, n_iter=16, tex_size=4096)
+    tab = oracle.table(d)
+    q = W.queries(65536 + 77, 90, n_types=2, with_xi=True, v_max=40.0)
+    i = 35747
+    assert q["type"][i] == 0
+    h, u, v, wi, wo = float(q["h"][i]), float(q["u"][i]), float(q["v"][i]), q["wi"][:, i], q["wo"][:, i]
+    r0, fl = oracle.eval_query(d, tab, h, u, v, wi, wo)
+    assert fl & oracle.MARGIN_MASK == 0
+    r1, _ = oracle.eval_query(d, tab, h + 1e-15, u, v, wi, wo)
+    assert abs(r1[8] - r0[8]) > 5e-4 * abs(r0[8])
+    assert fp64_sensitive(d, tab, h, u, v, wi, wo, r0)
