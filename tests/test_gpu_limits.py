@@ -109,3 +109,35 @@ def test_largest_types_furnace(torch_cuda):
     assert np.all((np.abs(gm - om) <= 1e-4 * np.abs(om) + 1e-6)[blk])
     assert np.all((np.abs(gv - ov) <= 1e-3 * np.abs(ov) + 1e-6)[blk])
 
+
+
+def test_largest_types_batched(torch_cuda):
+    """The persistent batched evaluation over the two largest types, queries
+    grouped by type with uneven counts, with and without LDS staging in the
+    schedule; queries that fail the rule are set aside only when FP64
+    rounding alone moves the oracle's value beyond it."""
+    torch = torch_cuda
+    P = _largest_types()
+    counts = np.array([40000, 9001])
+    off = np.zeros(3, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    tid = np.repeat(np.arange(2, dtype=np.int32), counts)
+    q = W.queries(int(off[-1]), 92, type_ids=tid, v_max=40.0)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    offd = torch.from_numpy(off).cuda()
+    o, of = oracle.eval(P, q)
+    tabs = [oracle.table(d) for d in P]
+    for sched in (None, dict(chunk=4, grid=512, use_lds=0), dict(chunk=2, grid=2048, use_lds=1)):
+        vals, flags = bysdf.bysdf_eval_batched(T, offd, qd, sched=sched)
+        torch.cuda.synchronize()
+        g, gfl = vals.cpu().numpy().T, flags.cpu().numpy()
+        rep = compare(g, gfl, o[:, :12], of)
+        print("batched", sched, rep)
+        assert rep["n_bad"] <= 5 and rep["n_flag_mismatch"] == 0, rep
+        ill = [i for i in rep["bad_idx"]
+               if fp64_sensitive(P[q["type"][i]], tabs[q["type"][i]], q["h"][i], q["u"][i], q["v"][i],
+                                 q["wi"][:, i], q["wo"][:, i], o[i])]
+        keep = np.ones(len(tid), bool)
+        keep[ill] = False
+        assert_parity(compare(g, gfl, o[:, :12], of, extra_ok=keep), max_flagged=0.06)
