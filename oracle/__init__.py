@@ -429,6 +429,21 @@ def eval_query(d, tab, h, u, v, wi, wo):
     return out, fl & 0xffffffff
 
 
+def eval_multi_query(d, tab, h0, h1, h2, zeta, n_max, u, v, wi, wo):
+    """One multi-scale evaluation with FP64 inputs: (out[13] as in
+    eval_multi, flags)."""
+    p = params_struct(d)
+    t = np.ascontiguousarray(tab, dtype=np.float64)
+    a = np.ascontiguousarray(wi, dtype=np.float64)
+    b = np.ascontiguousarray(wo, dtype=np.float64)
+    out = np.zeros(13, dtype=np.float64)
+    fl = lib().orc_eval_multi_query(C.byref(p), _ptr(t, C.c_double), C.c_double(h0), C.c_double(h1),
+                                    C.c_double(h2), C.c_double(zeta), C.c_int32(n_max), C.c_double(u),
+                                    C.c_double(v), _ptr(a, C.c_double), _ptr(b, C.c_double),
+                                    _ptr(out, C.c_double))
+    return out, fl & 0xffffffff
+
+
 def ply_hit(d, h, u, v, wi):
     p = params_struct(d)
     w = np.ascontiguousarray(wi, dtype=np.float64)

@@ -55,3 +55,20 @@ def fp64_sensitive(d, tab, h, u, v, wi, wo, ref, ulps=4):
             if np.any(np.abs(o[:12] - ref[:12]) > REL * np.abs(ref[:12]) + ABS):
                 return True
     return False
+
+
+def fp64_sensitive_multi(d, tab, q, i, n_max, ref, ulps=4):
+    """fp64_sensitive for the multi-scale evaluation of query i of q: u or
+    v moved by `ulps` FP64 ulps (the strata heights are single precision by
+    construction, so the footprint itself stays put)."""
+    a = dict(h0=float(q["h"][i]), h1=float(q["h1"][i]), h2=float(q["h2"][i]), zeta=float(q["zeta"][i]),
+             u=float(q["u"][i]), v=float(q["v"][i]))
+    for k in ("u", "v"):
+        for s in (-1.0, 1.0):
+            b = dict(a)
+            b[k] = a[k] + s * ulps * float(np.spacing(abs(a[k]) if a[k] != 0.0 else 1e-300))
+            o, _ = oracle.eval_multi_query(d, tab, b["h0"], b["h1"], b["h2"], b["zeta"], n_max, b["u"],
+                                           b["v"], q["wi"][:, i], q["wo"][:, i])
+            if np.any(np.abs(o[:12] - ref[:12]) > REL * np.abs(ref[:12]) + ABS):
+                return True
+    return False

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2401_12724_amd import bysdf, workloads as W
 
-from parity import assert_parity, compare, fp64_sensitive
+from parity import assert_parity, compare, fp64_sensitive, fp64_sensitive_multi
 
 pytestmark = pytest.mark.gpu
 
@@ -141,3 +141,37 @@ def test_largest_types_batched(torch_cuda):
         keep = np.ones(len(tid), bool)
         keep[ill] = False
         assert_parity(compare(g, gfl, o[:, :12], of, extra_ok=keep), max_flagged=0.06)
+
+
+def test_largest_types_multiscale(torch_cuda):
+    """bysdf_eval_multi and bysdf_sample_multi with up to 16 strata per
+    footprint on the two largest types."""
+    torch = torch_cuda
+    P = _largest_types()
+    n = 16384 + 33
+    q = W.footprints(W.queries(n, 93, n_types=2, with_xi=True, v_max=40.0), 94)
+    T = bysdf.bysdf_types_create(P)
+    qd = bysdf.to_device(q)
+    ev, ef = bysdf.bysdf_eval_multi(T, qd, 16)
+    sv, lobe, node, sf = bysdf.bysdf_sample_multi(T, qd, 16)
+    torch.cuda.synchronize()
+    o, of = oracle.eval_multi(P, q, 16)
+    g, gfl = ev.cpu().numpy().T, ef.cpu().numpy()
+    rep = compare(g, gfl, o[:, :12], of)
+    print("eval_multi", rep)
+    assert rep["n_bad"] <= 5 and rep["n_flag_mismatch"] == 0, rep
+    tabs = [oracle.table(d) for d in P]
+    ill = [i for i in rep["bad_idx"]
+           if fp64_sensitive_multi(P[q["type"][i]], tabs[q["type"][i]], q, i, 16, o[i])]
+    print("ill-conditioned at FP64 resolution:", ill)
+    keep = np.ones(n, bool)
+    keep[ill] = False
+    assert_parity(compare(g, gfl, o[:, :12], of, extra_ok=keep), max_flagged=0.1)
+    so, sof = oracle.sample_multi(P, q, 16)
+    rep = compare(sv.cpu().numpy().T, sf.cpu().numpy(), so[:, :10], sof)
+    print("sample_multi", rep)
+    assert_parity(rep, max_flagged=0.1)
+    ok = (sof & oracle.MARGIN_MASK) == 0
+    nd = node.cpu().numpy()
+    assert np.array_equal(lobe.cpu().numpy()[ok], so[ok, 10].astype(np.int32))
+    assert np.array_equal((nd >> 4)[ok], so[ok, 12].astype(np.int32))

@@ -46,3 +46,16 @@ def test_sensitivity_check():
     r1, _ = oracle.eval_query(d, tab, h + 1e-15, u, v, wi, wo)
     assert abs(r1[8] - r0[8]) > 5e-4 * abs(r0[8])
     assert fp64_sensitive(d, tab, h, u, v, wi, wo, r0)
+
+
+def test_eval_multi_query_is_the_batched_evaluation():
+    d = W.default_params(n_plies=5, ply_radius=W.packed_ply_radius(5), K=6)
+    tab = oracle.table(d)
+    q = W.footprints(W.queries(48, 7, with_xi=True, v_max=40.0), 8)
+    o, of = oracle.eval_multi([d], q, 8)
+    for i in range(48):
+        r, fl = oracle.eval_multi_query(d, tab, float(q["h"][i]), float(q["h1"][i]), float(q["h2"][i]),
+                                        float(q["zeta"][i]), 8, float(q["u"][i]), float(q["v"][i]),
+                                        q["wi"][:, i], q["wo"][:, i])
+        assert fl == of[i]
+        assert np.array_equal(r[:12], o[i, :12])
