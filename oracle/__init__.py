@@ -97,71 +97,78 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        L = C.CDLL(build())
-        dp = C.POINTER(C.c_double)
-        fp = C.POINTER(C.c_float)
-        ip = C.POINTER(C.c_int32)
-        up = C.POINTER(C.c_uint32)
-        pp = C.POINTER(OrcParams)
-        tp = C.POINTER(dp)
-        L.orc_table.argtypes = [pp, dp]
-        L.orc_mig_table.argtypes = [pp, C.c_int64, C.c_int32]
-        L.orc_mig_table.restype = C.c_int32
-        L.orc_fiber_lookup.argtypes = [pp, dp, C.c_double, C.c_double, C.c_int32, dp]
-        L.orc_fiber_lookup.restype = None
-        L.orc_eval.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp, up,
-                               C.c_int]
-        L.orc_sample.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp,
-                                 up, C.c_int]
-        L.orc_furnace.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp, fp,
-                                  fp, fp, dp, dp, C.c_int]
-        L.orc_eval_far.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, C.c_double, ip, fp,
-                                   fp, fp, fp, dp, C.c_int]
-        L.orc_eval_multi.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp, fp,
-                                     fp, fp, fp, fp, fp, dp, up, C.c_int]
-        L.orc_sample_multi.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp,
-                                       fp, fp, fp, fp, fp, fp, fp, dp, up, C.c_int]
-        L.orc_footprint.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
-                                    dp, dp]
-        L.orc_footprint.restype = C.c_int32
-        L.orc_grad_fd.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp,
-                                  C.c_double, dp, dp, C.c_int]
-        L.orc_philox4x32_10.argtypes = [up, up, up]
-        L.orc_fresnel.argtypes = [C.c_double, C.c_double]
-        L.orc_fresnel.restype = C.c_double
-        L.orc_ggx_D.argtypes = [dp, C.c_double, C.c_double]
-        L.orc_ggx_D.restype = C.c_double
-        L.orc_smith_G1.argtypes = [dp, dp, C.c_double, C.c_double]
-        L.orc_smith_G1.restype = C.c_double
-        L.orc_vndf.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
-        L.orc_ls_albedo.argtypes = [C.c_double]
-        L.orc_ls_albedo.restype = C.c_double
-        L.orc_ply_shadow_raw.argtypes = [pp, C.c_double, C.c_double]
-        L.orc_ply_shadow_raw.restype = C.c_double
-        L.orc_ply_hit.argtypes = [pp, C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_ply_hit.restype = C.c_uint32
-        L.orc_set_margins.argtypes = [C.c_double] * 5
-        L.orc_nodes.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp, dp]
-        L.orc_nodes.restype = C.c_uint32
-        L.orc_ply_frame.argtypes = [pp, C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_ply_frame.restype = C.c_uint32
-        L.orc_explicit_ply.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double, dp,
-                                       C.c_double, dp]
-        L.orc_explicit_ply.restype = C.c_int32
-        L.orc_frame_x.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_frame_x.restype = C.c_uint32
-        L.orc_camera_footprint.argtypes = [C.c_void_p, C.POINTER(RenderSettings), C.c_double,
-                                           C.c_double, dp]
-        L.orc_camera_footprint.restype = C.c_int32
-        L.orc_scene_create.argtypes = [fp, C.POINTER(C.c_int64), C.c_int32]
-        L.orc_scene_create.restype = C.c_void_p
-        L.orc_scene_free.argtypes = [C.c_void_p]
-        L.orc_scene_frame.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, dp]
-        L.orc_intersect.argtypes = [C.c_void_p, C.c_int64, fp, fp, fp, C.c_double, dp, C.c_int]
-        L.orc_render.argtypes = [C.c_void_p, pp, tp, C.c_int32, ip, fp, C.POINTER(RenderSettings),
-                                 dp, dp, dp, C.c_int]
-        _lib = L
+        _lib = bind(build())
     return _lib
+
+
+def bind(path: str):
+    """Load an oracle library built from these sources (or from a variant of
+    them, for the tests that check the pins catch planted mistakes) and
+    declare its entry points."""
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    fp = C.POINTER(C.c_float)
+    ip = C.POINTER(C.c_int32)
+    up = C.POINTER(C.c_uint32)
+    pp = C.POINTER(OrcParams)
+    tp = C.POINTER(dp)
+    L.orc_table.argtypes = [pp, dp]
+    L.orc_mig_table.argtypes = [pp, C.c_int64, C.c_int32]
+    L.orc_mig_table.restype = C.c_int32
+    L.orc_fiber_lookup.argtypes = [pp, dp, C.c_double, C.c_double, C.c_int32, dp]
+    L.orc_fiber_lookup.restype = None
+    L.orc_eval.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp, up,
+                           C.c_int]
+    L.orc_sample.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp, dp,
+                             up, C.c_int]
+    L.orc_furnace.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp, fp,
+                              fp, fp, dp, dp, C.c_int]
+    L.orc_eval_far.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, C.c_double, ip, fp,
+                               fp, fp, fp, dp, C.c_int]
+    L.orc_eval_multi.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp, fp,
+                                 fp, fp, fp, fp, fp, dp, up, C.c_int]
+    L.orc_sample_multi.argtypes = [pp, tp, C.c_int32, C.c_int64, C.c_int32, ip, fp, fp, fp,
+                                   fp, fp, fp, fp, fp, fp, fp, dp, up, C.c_int]
+    L.orc_footprint.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                dp, dp]
+    L.orc_footprint.restype = C.c_int32
+    L.orc_grad_fd.argtypes = [pp, tp, C.c_int32, C.c_int64, ip, fp, fp, fp, fp, fp, fp,
+                              C.c_double, dp, dp, C.c_int]
+    L.orc_philox4x32_10.argtypes = [up, up, up]
+    L.orc_fresnel.argtypes = [C.c_double, C.c_double]
+    L.orc_fresnel.restype = C.c_double
+    L.orc_ggx_D.argtypes = [dp, C.c_double, C.c_double]
+    L.orc_ggx_D.restype = C.c_double
+    L.orc_smith_G1.argtypes = [dp, dp, C.c_double, C.c_double]
+    L.orc_smith_G1.restype = C.c_double
+    L.orc_vndf.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+    L.orc_ls_albedo.argtypes = [C.c_double]
+    L.orc_ls_albedo.restype = C.c_double
+    L.orc_ply_shadow_raw.argtypes = [pp, C.c_double, C.c_double]
+    L.orc_ply_shadow_raw.restype = C.c_double
+    L.orc_ply_hit.argtypes = [pp, C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_ply_hit.restype = C.c_uint32
+    L.orc_set_margins.argtypes = [C.c_double] * 5
+    L.orc_nodes.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp, dp]
+    L.orc_nodes.restype = C.c_uint32
+    L.orc_ply_frame.argtypes = [pp, C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_ply_frame.restype = C.c_uint32
+    L.orc_explicit_ply.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double, dp,
+                                   C.c_double, dp]
+    L.orc_explicit_ply.restype = C.c_int32
+    L.orc_frame_x.argtypes = [pp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_frame_x.restype = C.c_uint32
+    L.orc_camera_footprint.argtypes = [C.c_void_p, C.POINTER(RenderSettings), C.c_double,
+                                       C.c_double, dp]
+    L.orc_camera_footprint.restype = C.c_int32
+    L.orc_scene_create.argtypes = [fp, C.POINTER(C.c_int64), C.c_int32]
+    L.orc_scene_create.restype = C.c_void_p
+    L.orc_scene_free.argtypes = [C.c_void_p]
+    L.orc_scene_frame.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, dp]
+    L.orc_intersect.argtypes = [C.c_void_p, C.c_int64, fp, fp, fp, C.c_double, dp, C.c_int]
+    L.orc_render.argtypes = [C.c_void_p, pp, tp, C.c_int32, ip, fp, C.POINTER(RenderSettings),
+                             dp, dp, dp, C.c_int]
+    return L
 
 
 # ---------------------------------------------------------------- helpers
