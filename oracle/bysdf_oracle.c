@@ -513,11 +513,15 @@ static void trace_plies(const orc_params* p, double h, double u, double v, v3 wi
     }
     /* Rounding of the phase (relative 1e-16 of up to ~50 rad) reaches v*
      * amplified by A |kappa|; the steep fiber table then turns an error in
-     * v* into a value error a few thousand times larger. */
+     * v* into a value error a few thousand times larger.  The table is
+     * interpolated linearly between texels (Sec. 3.5.1), so its steepest
+     * slope grows with the texel count: the bound is priced per texel,
+     * relative to the 512-texel table at which the limit was set. */
     double amax = 0.0;
     for (int k = 0; k < Np; ++k) amax = g->amp[k] > amax ? g->amp[k] : amax;
     double ak = fabs(g->kappa);
-    if (amax * (ak > 1.0 ? ak : 1.0) > g_amplify_max) g->flags |= ORC_ILLCOND;
+    double texel_scale = p->tex_size > 512 ? p->tex_size / 512.0 : 1.0;
+    if (amax * (ak > 1.0 ? ak : 1.0) * texel_scale > g_amplify_max) g->flags |= ORC_ILLCOND;
     g->kstar = ks;
     g->sstar = sk[ks];
     g->p2[0] = g->x2[0] + g->sstar * g->dh[0];
