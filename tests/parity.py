@@ -72,3 +72,30 @@ def fp64_sensitive_multi(d, tab, q, i, n_max, ref, ulps=4):
             if np.any(np.abs(o[:12] - ref[:12]) > REL * np.abs(ref[:12]) + ABS):
                 return True
     return False
+
+
+def furnace_draws_clear(P, q, block, nb, seed, rounds=8):
+    """Furnace inputs whose draws sit on no margin: block b's draws all use
+    the hit of its first query, and a draw whose direction the oracle flags
+    (a lobe edge, a refraction next to the critical angle) gets fresh
+    uniforms from a seeded generator, on both sides alike.  Returns (the
+    modified query dict, per-block mask of blocks whose draws are all clear
+    -- a block stays out only when its hit itself is flagged)."""
+    q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in q.items()}
+    qq = dict(q)
+    for k in ("type", "h", "u", "v"):
+        qq[k] = np.repeat(q[k][::block][:nb], block)
+    qq["wi"] = np.repeat(q["wi"][:, ::block][:, :nb], block, axis=1)
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    n = nb * block
+    for _ in range(rounds):
+        qq["xi"] = q["xi"][:, :n]
+        _, sf = oracle.sample(P, qq)
+        bad = (sf & oracle.MARGIN_MASK) != 0
+        if not bad.any():
+            break
+        fresh = rng.random((3, int(bad.sum()))).astype(np.float32)
+        q["xi"][:, :n][:, bad] = np.minimum(fresh, np.float32(1.0 - 2.0 ** -24))
+    qq["xi"] = q["xi"][:, :n]
+    _, sf = oracle.sample(P, qq)
+    return q, ((sf & oracle.MARGIN_MASK) == 0).reshape(nb, block).all(1)
