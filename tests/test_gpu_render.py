@@ -1,6 +1,7 @@
 """GPU wavefront renderer (shade_wavefront) against the CPU path tracer of
-the oracle, on the same random streams: crop means within sampling error and, at
-one path per pixel, most paths equal to their oracle twin (a path departs
+the oracle, on the same random streams: every pixel within 3 sigma of the
+Monte Carlo noise and, at one path per pixel, most paths equal to their
+oracle twin (a path departs
 where the model's fiber-scale detail amplifies a last-bit difference),
 the far field, the white furnace, two crops
 of the full 512-yarn weave, determinism and independence of the batching.
@@ -47,15 +48,24 @@ def _render_both(torch, scene_args, P, rs):
     return g, o, sq, counts
 
 
-def _check(g, o, sq, spp, label):
-    """Crop means within sampling error (the two images share their random
-    numbers, so this bound is loose unless some path is treated
-    differently)."""
+def _check(g, o, sq, spp, label, max_fail=0.0027):
+    """Radiance within 3 sigma of the Monte Carlo noise, per pixel and
+    channel: |L_gpu - L_oracle| <= 3 sigma_px, with sigma_px the standard
+    error of the oracle's pixel mean from its per-pixel second moment.  The
+    share of pixel channels beyond it may not exceed what 3 sigma admits
+    for independent noise (0.27 %); the two images share their random
+    numbers, so a correct renderer stays far inside.  The crop mean is held
+    to 3 sigma of its own standard error as well."""
     var = np.maximum(sq - o * o, 0.0)
+    spx = np.sqrt(var / spp)
+    fail = np.abs(g - o) > 3.0 * spx + 1e-4 * np.abs(o) + 1e-6
     sigma = np.sqrt(var.sum() / spp) / o.size
     d = g.mean() - o.mean()
-    print(label, "gpu", g.mean(), "oracle", o.mean(), "z", d / max(sigma, 1e-12))
-    assert abs(d) <= 4 * sigma + 1e-6, label
+    print(label, "gpu", g.mean(), "oracle", o.mean(), "z", d / max(sigma, 1e-12),
+          "pixel channels beyond 3 sigma:", fail.mean(), "largest |d|/sigma_px:",
+          float((np.abs(g - o) / np.maximum(spx, 1e-12)).max()))
+    assert abs(d) <= 3 * sigma + 1e-6, label
+    assert fail.mean() <= max_fail, label
 
 
 def _paths_equal(torch, scene_args, P, rs, label, frac):
@@ -114,15 +124,17 @@ def test_white_furnace(torch_cuda):
 
 
 def test_weave_crops(torch_cuda):
-    """The 256 + 256 yarn weave seen from the grazing 1920 x 1080 camera:
-    a crop at the image centre and one near the far edge (far field)."""
+    """The 256 + 256 yarn weave seen from the grazing 1920 x 1080 camera at
+    64 spp: a 64 x 64 crop at the image centre and one near the far edge
+    (far field), per pixel within 3 sigma of the oracle's noise; at one
+    path per pixel most paths equal their oracle twin."""
     torch = torch_cuda
     scene = W.weave()
     P = [W.default_params()]
     cam = W.weave_camera()
-    for crop, lod, label in (((936, 516, 40, 40), 1.0, "centre"), ((936, 392, 40, 40), 4.0,
+    for crop, lod, label in (((928, 508, 64, 64), 1.0, "centre"), ((928, 384, 64, 64), 4.0,
                                                                       "far edge, far field")):
-        rs = _settings(cam, crop, spp=8, lod_px=lod)
+        rs = _settings(cam, crop, spp=64, lod_px=lod)
         g, o, sq, _ = _render_both(torch, scene, P, rs)
         _check(g, o, sq, rs["spp"], label)
         _paths_equal(torch, scene, P, rs, label, 0.75)
