@@ -4,15 +4,25 @@ BYSDFEval.apply(theta, types, q, offsets) returns E (n x 3, RGB) for the
 queries q grouped by type (offsets: int64 CSR on the device) at the per-type
 parameters theta (n_types x 8: albedo r g b, beta, ply twist, fiber twist,
 ply density, fiber density).  The forward pass writes theta into the handle
-(bysdf_types_set_theta) and runs bysdf_eval; the backward pass runs
-bysdf_eval_backward, which recomputes the model (shadowing included) with
-forward-mode tangents, so nothing but the inputs is kept between the passes.
+(bysdf_types_set_theta) and runs bysdf_eval; the backward pass writes the
+same theta back (another forward on the handle may have replaced it) and
+runs bysdf_eval_backward, which recomputes the model (shadowing included)
+with forward-mode tangents, so nothing but the inputs is kept between the
+passes.  The handle clamps theta to its valid ranges (albedo >= 0, beta in
+[1e-4, 10], twists in [-1.5, 1.5] rad, densities in [0, 1]); where a
+component lies strictly outside its range the value does not depend on it
+and its gradient is zero.
 """
 from __future__ import annotations
 
 import torch
 
 from . import bysdf
+
+# valid ranges of theta's columns (albedo rgb, beta, ply twist, fiber twist,
+# ply density, fiber density), as the handle clamps them
+_LO = (0.0, 0.0, 0.0, 1e-4, -1.5, -1.5, 0.0, 0.0)
+_HI = (float("inf"), float("inf"), float("inf"), 10.0, 1.5, 1.5, 1.0, 1.0)
 
 
 class BYSDFEval(torch.autograd.Function):
@@ -23,13 +33,18 @@ class BYSDFEval(torch.autograd.Function):
         bysdf.bysdf_types_set_theta(types, th)
         vals, _ = bysdf.bysdf_eval(types, q)
         ctx.types, ctx.q, ctx.offsets = types, q, offsets
-        ctx.keep = th  # keeps theta alive until the handle's copy has run
+        ctx.theta = th  # this forward's theta (and alive until the handle's copy has run)
         return vals[0:3].t().contiguous()
 
     @staticmethod
     def backward(ctx, grad_E):
+        th = ctx.theta
+        bysdf.bysdf_types_set_theta(ctx.types, th)
         g, _ = bysdf.bysdf_eval_backward(ctx.types, ctx.q, ctx.offsets, grad_E.contiguous())
-        return g, None, None, None
+        lo = torch.tensor(_LO, dtype=th.dtype, device=th.device)
+        hi = torch.tensor(_HI, dtype=th.dtype, device=th.device)
+        inside = (th >= lo) & (th <= hi)
+        return g * inside, None, None, None
 
 
 def bysdf_fit_step(theta, types, q, offsets, target, opt):

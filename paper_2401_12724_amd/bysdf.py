@@ -333,6 +333,15 @@ def bysdf_batched_workspace_size(n_types: int) -> int:
     return int(lib().bysdf_batched_workspace_size(n_types))
 
 
+def _check_workspace(t, ptr, ws, name):
+    """The caller's workspace tensor must hold ws bytes from ptr on."""
+    base = t.data_ptr()
+    end = base + t.numel() * t.element_size()
+    if not (base <= ptr and ptr + ws <= end):
+        raise ValueError("%s: workspace holds %d bytes past its pointer, %d needed"
+                         % (name, max(0, end - ptr), ws))
+
+
 def alloc_workspace(nbytes, device="cuda"):
     """Device workspace with a 256-byte aligned pointer: (tensor, ptr)."""
     import torch
@@ -351,6 +360,8 @@ def bysdf_eval_batched(types: Types, offsets, q: dict, out=None, sched=None, wor
     ws = bysdf_batched_workspace_size(types.n_types)
     if workspace is None:
         workspace = alloc_workspace(ws, q["h"].device)
+    else:
+        _check_workspace(workspace[0], workspace[1], ws, "bysdf_eval_batched")
     sc = None
     if sched is not None:
         sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]), 0)
@@ -504,10 +515,10 @@ def bysdf_eval_backward(types: Types, q: dict, offsets, grad_E, grad_theta=None,
     elif per_query is not False and per_query is not None:
         pq = per_query
     ws = bysdf_backward_workspace_size(n, types.n_types)
-    if workspace is None or workspace.numel() < ws:
+    if workspace is None:
         workspace = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
-    base = workspace.data_ptr()
-    aligned = (base + 255) & ~255
+    aligned = (workspace.data_ptr() + 255) & ~255
+    _check_workspace(workspace, aligned, ws, "bysdf_eval_backward")
     qs = _qsoa(q)
     _check(lib().bysdf_eval_backward(types.handle, C.byref(qs), n, offsets.data_ptr(),
                                      grad_E.data_ptr(), grad_theta.data_ptr(), _ptr(pq),

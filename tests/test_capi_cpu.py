@@ -211,3 +211,19 @@ def test_multi_scale_arguments_rejected_on_host(L):
     assert L.bysdf_eval_multi(dummy, C.byref(qs), C.byref(no_xs), -1, 4, C.byref(es),
                               None) == bysdf.ERR_INVALID_ARG
     assert L.bysdf_eval_multi(dummy, C.byref(qs), C.byref(no_xs), 0, 4, C.byref(es), None) == bysdf.OK
+
+
+def test_workspace_bounds_checked_on_host():
+    """A caller workspace must hold the requested bytes from the (aligned)
+    pointer the binding passes on: a misaligned view that is long enough
+    before alignment but not after is refused before any launch."""
+    import torch
+    from paper_2401_12724_amd import bysdf
+    buf = torch.empty(4096, dtype=torch.uint8)
+    view = buf[3:3 + 1024]
+    aligned = (view.data_ptr() + 255) & ~255
+    with pytest.raises(ValueError, match="workspace"):
+        bysdf._check_workspace(view, aligned, 1024, "bysdf_eval_backward")
+    bysdf._check_workspace(view, aligned, 1024 - (aligned - view.data_ptr()), "bysdf_eval_backward")
+    with pytest.raises(ValueError, match="workspace"):
+        bysdf._check_workspace(view, view.data_ptr() - 16, 64, "bysdf_eval_batched")

@@ -149,3 +149,42 @@ def test_autograd_fit_recovers_parameters(torch_cuda):
     assert err1[:, :3].mean() < 0.05 * err0[:, :3].mean()   # albedo
     assert err1[:, 3].mean() < 0.6 * err0[:, 3].mean()      # roughness
     assert err1[:, 6:].mean() < 0.6 * err0[:, 6:].mean()    # densities
+
+
+def test_autograd_backward_uses_its_own_theta(torch_cuda):
+    """Two forwards at different theta on one handle, then the backward of
+    the first: its gradient is that of the first theta (bitwise the one of a
+    lone forward and backward there), not of the theta the handle holds
+    last; components strictly outside the handle's valid range get zero
+    gradient."""
+    torch = torch_cuda
+    from paper_2401_12724_amd.autograd import BYSDFEval
+    hidden, start, q, off = _setup(torch, 2, 2048, seed=5)
+    T = bysdf.bysdf_types_create(start)
+    qd = bysdf.to_device(q)
+    offd = torch.from_numpy(off).cuda()
+    gE = torch.from_numpy(np.random.default_rng(2).normal(size=(len(q["h"]), 3)).astype(np.float32)).cuda()
+
+    def grad_at(th_list, which):
+        thetas = [torch.tensor(t, dtype=torch.float32, device="cuda", requires_grad=True) for t in th_list]
+        Es = [BYSDFEval.apply(t, T, qd, offd) for t in thetas]
+        (Es[which] * gE).sum().backward()
+        return thetas[which].grad.clone()
+
+    th1 = np.stack([W.theta_of(p) for p in start])
+    th2 = np.stack([W.theta_of(p) for p in hidden])
+    g_first = grad_at([th1, th2], 0)
+    g_alone = grad_at([th1], 0)
+    g_second = grad_at([th2], 0)
+    torch.cuda.synchronize()
+    assert torch.equal(g_first, g_alone)
+    assert not torch.allclose(g_first, g_second, rtol=1e-2)
+    # clamped components: a density above 1, a negative albedo and beta below
+    # its floor do not change the value, so their gradient is zero
+    th3 = th1.copy()
+    th3[0, 6] = 1.2
+    th3[1, 0] = -0.1
+    th3[1, 3] = 1e-6
+    g3 = grad_at([th3], 0).cpu().numpy()
+    assert g3[0, 6] == 0.0 and g3[1, 0] == 0.0 and g3[1, 3] == 0.0
+    assert np.all(g3[0, :6] != 0.0)
