@@ -316,6 +316,25 @@ int bysdf_eval_batched(const bysdf_types_t* types, const int64_t* type_offsets, 
                        const bysdf_schedule* sched, void* workspace, size_t ws_bytes,
                        hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, serving loops, harnesses that forbid allocation): bysdf_eval_batched
+ * with no workspace argument.  Its workspace (the per-type tile offsets and
+ * the queue counter) lives in a static device array of the library, one per
+ * GPU, held until the process ends: 4 B per type of up to
+ * BYSDF_NOALLOC_MAX_TYPES types plus 256 B (about 64 KB).  The call allocates
+ * nothing; its first call on a device looks up that device's copy of the
+ * array, so call it with the handle's device current.  The array keeps the
+ * last call's contents; every call recomputes the tile offsets and clears
+ * the counter with kernels on its stream before use.  Calls that overlap on
+ * one GPU (concurrent streams or threads) share the array and race: order
+ * them.  Arguments, outputs and errors as bysdf_eval_batched;
+ * BYSDF_ERR_INVALID_ARG when the handle holds more than
+ * BYSDF_NOALLOC_MAX_TYPES types. */
+#define BYSDF_NOALLOC_MAX_TYPES 16384
+int bysdf_eval_batched_noalloc(const bysdf_types_t* types, const int64_t* type_offsets, int64_t n,
+                               const bysdf_query_soa* q, const bysdf_eval_out_soa* out,
+                               const bysdf_schedule* sched, hipStream_t stream);
+
 /* Bytes of device workspace bysdf_eval_backward needs for n queries of a
  * handle with n_types types (0 on bad arguments). */
 size_t bysdf_backward_workspace_size(int64_t n, int32_t n_types);

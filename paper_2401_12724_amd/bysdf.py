@@ -149,6 +149,8 @@ def lib():
         L.bysdf_eval_batched.argtypes = [_vp, _vp, C.c_int64, C.POINTER(QuerySoA),
                                          C.POINTER(EvalOutSoA), C.POINTER(Schedule), _vp,
                                          C.c_size_t, _vp]
+        L.bysdf_eval_batched_noalloc.argtypes = [_vp, _vp, C.c_int64, C.POINTER(QuerySoA),
+                                                 C.POINTER(EvalOutSoA), C.POINTER(Schedule), _vp]
         L.bysdf_backward_workspace_size.argtypes = [C.c_int64, C.c_int32]
         L.bysdf_backward_workspace_size.restype = C.c_size_t
         L.bysdf_eval_backward.argtypes = [_vp, C.POINTER(QuerySoA), C.c_int64, _vp, _vp, _vp, _vp,
@@ -369,6 +371,23 @@ def bysdf_eval_batched(types: Types, offsets, q: dict, out=None, sched=None, wor
     _check(lib().bysdf_eval_batched(types.handle, offsets.data_ptr(), n, C.byref(qs), C.byref(o),
                                     C.byref(sc) if sc is not None else None, workspace[1], ws,
                                     _stream(stream)), "bysdf_eval_batched")
+    return vals, flags
+
+
+def bysdf_eval_batched_noalloc(types: Types, offsets, q: dict, out, sched=None, stream=None):
+    """bysdf_eval_batched with its workspace in the library's static device
+    memory: the call allocates nothing, so `out` (vals float32[12, n],
+    flags int32[n]) must be given.  Returns out."""
+    n = int(q["h"].numel())
+    vals, flags = out
+    o = _eval_out_soa(vals, flags)
+    sc = None
+    if sched is not None:
+        sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]), 0)
+    qs = _qsoa(q)
+    _check(lib().bysdf_eval_batched_noalloc(types.handle, offsets.data_ptr(), n, C.byref(qs), C.byref(o),
+                                            C.byref(sc) if sc is not None else None, _stream(stream)),
+           "bysdf_eval_batched_noalloc")
     return vals, flags
 
 

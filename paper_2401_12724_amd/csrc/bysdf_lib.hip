@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -2225,4 +2226,49 @@ extern "C" int bysdf_eval_batched(const bysdf_types_t* h, const int64_t* type_of
         launch_batched<8>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
+}
+
+// ------------------------------------------------------------------ no-alloc hetero API
+// Workspace of bysdf_eval_batched_noalloc in static device memory: the
+// per-type tile offsets of up to kNoAllocMaxTypes types and the queue
+// counter, laid out as bysdf_eval_batched lays out a caller's workspace.
+// Each GPU the library runs on holds its own copy until the process ends.
+constexpr int kNoAllocMaxTypes = BYSDF_NOALLOC_MAX_TYPES;
+constexpr size_t kNoAllocScratchBytes =
+    ((sizeof(int32_t) * (size_t)(kNoAllocMaxTypes + 1) + 255) / 256) * 256 + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of this GPU's copy of the scratch array, looked up once per
+// device with that device current.  In host code `scratch` only names the
+// symbol; kernels receive the address found here.
+static int scratch_address(void** out)
+{
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255u)) return fail(BYSDF_ERR_LAUNCH, "scratch address of device %d unusable", dev);
+        it = addr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return BYSDF_OK;
+}
+
+extern "C" int bysdf_eval_batched_noalloc(const bysdf_types_t* h, const int64_t* type_offsets, int64_t n,
+                                          const bysdf_query_soa* q, const bysdf_eval_out_soa* o,
+                                          const bysdf_schedule* sched, hipStream_t stream)
+{
+    if (!h) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
+    if (h->n_types > kNoAllocMaxTypes)
+        return fail(BYSDF_ERR_INVALID_ARG, "bysdf_eval_batched_noalloc serves at most %d types (handle has %d)",
+                    kNoAllocMaxTypes, h->n_types);
+    void* ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc != BYSDF_OK) return rc;
+    return bysdf_eval_batched(h, type_offsets, n, q, o, sched, ws, kNoAllocScratchBytes, stream);
 }
