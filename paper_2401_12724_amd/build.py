@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbysdf.so")
 SOURCES = ["bysdf_lib.hip", "yarn_scene.hip", "render.hip"]
-HEADERS = ["bysdf_math.hpp", "bysdf_model.hpp", "bysdf_multi.hpp", "bysdf_opcount.hpp", "bysdf_dual.hpp",
+HEADERS = ["bysdf_math.hpp", "math_tables.inc", "bysdf_model.hpp", "bysdf_multi.hpp", "bysdf_opcount.hpp", "bysdf_dual.hpp",
            "yarn_tube.hpp", "yarn_build.hpp", "philox.hpp",
            "lib_internal.hpp"]
 

@@ -194,6 +194,10 @@ __host__ __device__ inline Derived<DD, DF> derive_dual(const TypeRec& t, int see
     d.rp_s = DF(f.rp_s);
     d.Rpc_s = DF(f.Rpc_s);
     d.n_mig = f.n_mig; d.mig_seed = f.mig_seed; d.mig_period = f.mig_period; d.mig_blend = f.mig_blend;
+    for (int k = 0; k < kMaxPlies; ++k) {
+        d.ply_c[k] = f.ply_c[k];
+        d.ply_s[k] = f.ply_s[k];
+    }
     return d;
 }
 

@@ -15,6 +15,34 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kInvTwoPi = 0.15915494309189533577;
 
+// Tables of the FP64 sine/cosine and arctangent below (math_tables.inc,
+// written by gen_math_tables.py).  Device code reads them from constant
+// memory, host code from an ordinary array.
+#include "math_tables.inc"
+struct SinCos64 {
+    double c, s;
+};
+static __constant__ SinCos64 kSinCosTurnsDev[64] = {BYSDF_SINCOS_TABLE};
+static const SinCos64 kSinCosTurnsHost[64] = {BYSDF_SINCOS_TABLE};
+static __constant__ double kAtanDev[65] = {BYSDF_ATAN_TABLE};
+static const double kAtanHost[65] = {BYSDF_ATAN_TABLE};
+__host__ __device__ inline SinCos64 sincos_table(int j)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return kSinCosTurnsDev[j];
+#else
+    return kSinCosTurnsHost[j];
+#endif
+}
+__host__ __device__ inline double atan_table(int j)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return kAtanDev[j];
+#else
+    return kAtanHost[j];
+#endif
+}
+
 // ---------------------------------------------------------------- scalars
 __host__ __device__ inline float val(float x) { return x; }
 __host__ __device__ inline double val(double x) { return x; }
@@ -122,37 +150,29 @@ __host__ __device__ inline double rcp_(double x)
 }
 
 // atan2 in double precision: fold to the first octant (t = min/max in
-// [0, 1]), reduce once more with atan t = pi/6 + atan((sqrt3 t - 1)/(sqrt3 +
-// t)) to |t| <= tan(pi/12), then sum the odd Taylor series of atan to t^27
-// (remainder below 1e-18) and unfold.  Both reductions share one quotient:
-// (sqrt3 t - 1)/(sqrt3 + t) = (sqrt3 mn - mx)/(sqrt3 mx + mn).
+// [0, 1]), pick the table point j/64 nearest t from a single-precision
+// estimate of the quotient, and add to atan(j/64) (a correctly rounded table
+// entry) the arctangent of the remainder d = (t - j/64)/(1 + t j/64), |d| <
+// 1/127, from its odd Taylor series to d^7 (remainder below 1e-20).  The
+// remainder takes one quotient, (mn - tj mx)/(mx + tj mn).  Then unfold.
 __host__ __device__ inline double atan2_(double y, double x)
 {
     const double ax = fabs(x), ay = fabs(y);
     const double mx = fmax(ax, ay), mn = fmin(ax, ay);
-    const double k3 = 1.73205080756887729353;   // sqrt(3)
-    const double t12 = 0.26794919243112270647;  // tan(pi/12)
-    const bool big = mn > t12 * mx;
-    const double num = big ? fma(k3, mn, -mx) : mn;
-    const double den = big ? fma(k3, mx, mn) : mx;
-    const double tr = mx > 0.0 ? div_ordinary(num, den) : 0.0;
-    const double z = tr * tr;
-    double p = -1.0 / 27.0;
-    p = fma(p, z, 1.0 / 25.0);
-    p = fma(p, z, -1.0 / 23.0);
-    p = fma(p, z, 1.0 / 21.0);
-    p = fma(p, z, -1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, -1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, -1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, -1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, -1.0 / 3.0);
-    p = fma(p, z, 1.0);
-    double a = tr * p;
-    if (big) a += kPi / 6.0;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float te = (float)mn * __builtin_amdgcn_rcpf((float)mx);
+#else
+    const float te = (float)mn / (float)mx;
+#endif
+    float jf = rintf(64.0f * te);
+    jf = jf > 0.0f ? (jf < 64.0f ? jf : 64.0f) : 0.0f;  // also maps a NaN estimate to 0
+    const int j = (int)jf;
+    const double tj = (double)jf * (1.0 / 64.0);
+    const double num = fma(-tj, mx, mn), den = fma(tj, mn, mx);
+    const double d = mx > 0.0 ? div_ordinary(num, den) : 0.0;
+    const double d2 = d * d;
+    const double p = fma(d * d2, fma(fma(-1.0 / 7.0, d2, 1.0 / 5.0), d2, -1.0 / 3.0), d);
+    double a = atan_table(j) + p;
     if (ay > ax) a = 0.5 * kPi - a;
     if (x < 0.0) a = kPi - a;
     return y < 0.0 ? -a : a;
@@ -185,39 +205,21 @@ __host__ __device__ inline float max_(float a, float b) { return a > b ? a : b; 
 __host__ __device__ inline double max_(double a, double b) { return a > b ? a : b; }
 
 // sin and cos of 2 pi t for a phase t measured in turns.  The reduction is
-// exact: drop whole turns, then quarter turns, leaving |x| <= 1/8 turn
-// (|a| <= pi/4 rad).  Taylor series to a^15 (sin) and a^16 (cos) leave a
-// remainder below 5e-17 there, so the result is as accurate as a library
-// sin/cos while costing about twenty fused multiply-adds.
+// exact: drop whole turns, then the nearest 1/64 turn j, leaving |a| <= pi/64
+// rad; sin a and cos a from their Taylor series to a^7 and a^8 (remainders
+// below 5e-18), turned by (cos, sin)(2 pi j / 64) from a correctly rounded
+// table: about a dozen fused multiply-adds and one table read.
 __host__ __device__ inline void sincos_turns(double t, double* s, double* c)
 {
-    double r = t - rint(t);
-    double q = rint(4.0 * r);
-    double a = (r - 0.25 * q) * kTwoPi;
-    double a2 = a * a;
-    double sp = 1.0 / 1307674368000.0;
-    sp = fma(sp, -a2, 1.0 / 6227020800.0);
-    sp = fma(sp, -a2, 1.0 / 39916800.0);
-    sp = fma(sp, -a2, 1.0 / 362880.0);
-    sp = fma(sp, -a2, 1.0 / 5040.0);
-    sp = fma(sp, -a2, 1.0 / 120.0);
-    sp = fma(sp, -a2, 1.0 / 6.0);
-    sp = fma(sp, -a2, 1.0);
-    sp = sp * a;
-    double cp = 1.0 / 20922789888000.0;
-    cp = fma(cp, -a2, 1.0 / 87178291200.0);
-    cp = fma(cp, -a2, 1.0 / 479001600.0);
-    cp = fma(cp, -a2, 1.0 / 3628800.0);
-    cp = fma(cp, -a2, 1.0 / 40320.0);
-    cp = fma(cp, -a2, 1.0 / 720.0);
-    cp = fma(cp, -a2, 1.0 / 24.0);
-    cp = fma(cp, -a2, 0.5);
-    cp = fma(cp, -a2, 1.0);
-    int qi = ((int)q) & 3;
-    double s0 = (qi & 1) ? cp : sp;
-    double c0 = (qi & 1) ? sp : cp;
-    *s = (qi == 2 || qi == 3) ? -s0 : s0;
-    *c = (qi == 1 || qi == 2) ? -c0 : c0;
+    const double r = t - rint(t);
+    const double jd = rint(64.0 * r);
+    const double a = fma(jd, -1.0 / 64.0, r) * kTwoPi;
+    const double a2 = a * a;
+    const double sp = fma(fma(fma(-1.0 / 5040.0, a2, 1.0 / 120.0), a2, -1.0 / 6.0), a2 * a, a);
+    const double cp = fma(fma(fma(fma(1.0 / 40320.0, a2, -1.0 / 720.0), a2, 1.0 / 24.0), a2, -0.5), a2, 1.0);
+    const SinCos64 e = sincos_table((int)jd & 63);
+    *s = fma(e.s, cp, e.c * sp);
+    *c = fma(e.c, cp, -(e.s * sp));
 }
 
 // narrowing to the shading scalar

@@ -41,6 +41,9 @@ template <class G, class S> struct Derived {
     int n_mig;
     uint32_t mig_seed;
     double mig_period, mig_blend;
+    // directions of the ply centres of the nominal cross-section,
+    // (cos, sin)(2 pi k / N_p), k < N_p
+    double ply_c[kMaxPlies], ply_s[kMaxPlies];
 };
 
 // Per-type record resident in device memory: the primary parameters and
@@ -90,6 +93,11 @@ __host__ __device__ inline void fill_derived(TypeRec& t)
     d.mig_seed = t.mig_seed;
     d.mig_period = t.mig_period;
     d.mig_blend = t.mig_blend;
+    for (int k = 0; k < kMaxPlies; ++k) {
+        d.ply_c[k] = 1.0;
+        d.ply_s[k] = 0.0;
+        if (k < t.n_plies) sincos_turns(k * d.inv_np, &d.ply_s[k], &d.ply_c[k]);
+    }
 }
 
 __host__ __device__ inline Derived<double, float> derive(const TypeRec& t) { return t.d; }
@@ -219,14 +227,19 @@ __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, flo
     G vv = G((double)v);
     G best_s = G(0);
     int best = -1;
+    // every update starts from the hit height, where the ply centres are
+    // ply 0's turned by 2 pi k / N_p
+    G s0, c0;
+    sincos_turns_g(G(u_turn) + P.wp_turns * vv, &s0, &c0);
 #pragma unroll
     for (int k = 0; k < MP; ++k) {
         if (k >= P.Np) break;
         G base = G(u_turn + k * P.inv_np);
         G vj = vv;
-        G s, c;
+        const G ck = G(P.ply_c[k]), sk = G(P.ply_s[k]);
+        G c = c0 * ck - s0 * sk, s = s0 * ck + c0 * sk;
         for (int j = 0; j < P.N_it; ++j) {
-            sincos_turns_g(base + P.wp_turns * vj, &s, &c);
+            if (j > 0) sincos_turns_g(base + P.wp_turns * vj, &s, &c);
             vj = vv + g.kappa * ((P.Rpc * c - g.x2x) * g.dhx + (P.Rpc * s - g.x2y) * g.dhy);
         }
         sincos_turns_g(base + P.wp_turns * vj, &s, &c);
@@ -367,7 +380,8 @@ __host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Ta
 // meets the window in at most one piece (the window is shorter than the
 // gap between a set's 2 pi copies); the union length uses a sorting network.
 template <class G, int MP>
-__host__ __device__ inline G ply_shadow_raw(int Np, G rp, G Rpc, G dP, G a, G phi)
+__host__ __device__ inline G ply_shadow_raw(int Np, G rp, G Rpc, G dP, G a, G phi, const double* ply_c,
+                                            const double* ply_s)
 {
     G lo[MP], hi[MP];
     G wlo = phi - dP, whi = phi + dP;
@@ -383,9 +397,7 @@ __host__ __device__ inline G ply_shadow_raw(int Np, G rp, G Rpc, G dP, G a, G ph
             cen = G(kPi);
             half = G(0.5 * kPi);
         } else if (live) {
-            G cs, sn;
-            sincos_turns_g(G((double)s / (double)Np), &sn, &cs);
-            G wx = Rpc * cs - Px, wy = Rpc * sn - Py;
+            G wx = Rpc * G(ply_c[s]) - Px, wy = Rpc * G(ply_s[s]) - Py;
             G d2 = wx * wx + wy * wy;
             cen = atan2_(na_x * wy - na_y * wx, na_x * wx + na_y * wy);
             // asin(r_p / d) = atan2(r_p, sqrt(d^2 - r_p^2)); inside the disc: pi/2
@@ -476,7 +488,7 @@ __host__ __device__ inline void state_after_plies(const Derived<G, S>& P, const 
     // shadowing in the geometry scalar: a mostly occluded window leaves a
     // small visible share that single precision cannot resolve
     G phi = atan2_(X.ph.n2x * X.wi_g.y - X.ph.n2y * X.wi_g.x, X.ph.n2x * X.wi_g.x + X.ph.n2y * X.wi_g.y);
-    G raw = ply_shadow_raw<G, MP>(P.Np, P.rp, P.Rpc, G(val(P.dP)), X.a, phi);
+    G raw = ply_shadow_raw<G, MP>(P.Np, P.rp, P.Rpc, G(val(P.dP)), X.a, phi, P.ply_c, P.ply_s);
     X.rawp = raw;
     X.rawf = gft;
     X.Gp = Narrow<S>::from(G(1) - G(val(P.rho_p)) * (G(1) - raw));
@@ -871,11 +883,12 @@ template <class S> struct SampleOut {
 // cosine lobes the body lobes.  The weight is the full value over the full
 // mixture pdf at the drawn direction.  Lobes: 0 x-specular, 1 y-specular,
 // 2 x-body, 3 y-body, 4 pass-through.
-template <class G, class S, int MP, class NodeFn>
-__host__ __device__ inline uint32_t sample_draw(const Derived<G, S>& P, const XState<G, S, MP>& X,
-                                                const V3<float>& wi, float xi0, float xi1, float xi2,
-                                                const NodeFn& node_of, SampleOut<S>& so, V3<G>& wo,
-                                                bool& ok)
+//
+// First step: the lobe and node from xi0 (so.lobe, so.node; a pass-through
+// fills the whole output).  Returns the flags.
+template <class G, class S, int MP>
+__host__ __device__ inline uint32_t sample_pick(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                const V3<float>& wi, float xi0, SampleOut<S>& so)
 {
     for (int c = 0; c < 3; ++c) {
         so.wo[c] = S(0); so.wgt[c] = S(0); so.ex[c] = S(0);
@@ -883,8 +896,6 @@ __host__ __device__ inline uint32_t sample_draw(const Derived<G, S>& P, const XS
     so.pdf = S(0);
     so.lobe = -1;
     so.node = 0;
-    wo = mk3<G>(G(0), G(0), G(0));
-    ok = false;
     uint32_t flags = X.ph.flags;
     if (X.ph.pass) {
         so.wo[0] = S(-wi.x); so.wo[1] = S(-wi.y); so.wo[2] = S(-wi.z);
@@ -906,16 +917,25 @@ __host__ __device__ inline uint32_t sample_draw(const Derived<G, S>& P, const XS
     }
     so.lobe = lobe;
     so.node = node;
-    V3<G> ex = mk3<G>(X.ph.p2x, X.ph.p2y, X.ph.vhit);
+    return flags;
+}
+
+// Second step: the direction of the picked lobe.  nd is the picked node
+// (read for the forward lobes only).  Each step below runs once per
+// wavefront whatever mix of lobes its lanes drew: one visible-normal sample
+// (specular lobes: the frame at x or the node's inside-facing exit frame),
+// one cosine sample (body lobes).  Sets the exit point and returns whether a
+// direction was drawn (wo normalised).
+template <class G, class S, int MP>
+__host__ __device__ inline bool sample_dir(const Derived<G, S>& P, const XState<G, S, MP>& X, int lobe,
+                                           const Node<G, S>& nd, float xi1, float xi2, SampleOut<S>& so,
+                                           V3<G>& wo)
+{
+    bool ok = false;
+    wo = mk3<G>(G(0), G(0), G(0));
+    const bool fwd = lobe == 1 || lobe == 3;
+    V3<G> ex = fwd ? nd.y : mk3<G>(X.ph.p2x, X.ph.p2y, X.ph.vhit);
     const G gx1 = G((double)xi1), gx2 = G((double)xi2);
-    // Each step below runs once per wavefront whatever mix of lobes its
-    // lanes drew: the chosen node (forward lobes), one visible-normal
-    // sample (specular lobes), one cosine sample (body lobes).
-    Node<G, S> nd;
-    if (lobe == 1 || lobe == 3) {
-        node_of(node, nd);
-        ex = nd.y;
-    }
     if (lobe <= 1) {
         // reflection at x, or refraction out of the yarn at the node's
         // exit point (visible normals seen from inside, up = -n_y)
@@ -961,9 +981,25 @@ __host__ __device__ inline uint32_t sample_draw(const Derived<G, S>& P, const XS
     so.ex[0] = Narrow<S>::from(ex.x);
     so.ex[1] = Narrow<S>::from(ex.y);
     so.ex[2] = Narrow<S>::from(ex.z);
-    if (!ok) return flags | F_SAMPLE_FAIL;
-    wo = normalize(wo);
-    return flags;
+    if (ok) wo = normalize(wo);
+    return ok;
+}
+
+// Both steps: the drawn direction in wo, ok when a direction was drawn.
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline uint32_t sample_draw(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                const V3<float>& wi, float xi0, float xi1, float xi2,
+                                                const NodeFn& node_of, SampleOut<S>& so, V3<G>& wo,
+                                                bool& ok)
+{
+    wo = mk3<G>(G(0), G(0), G(0));
+    ok = false;
+    uint32_t flags = sample_pick(P, X, wi, xi0, so);
+    if (X.ph.pass) return flags;
+    Node<G, S> nd;
+    if (so.lobe == 1 || so.lobe == 3) node_of(so.node, nd);
+    ok = sample_dir(P, X, so.lobe, nd, xi1, xi2, so, wo);
+    return ok ? flags : flags | F_SAMPLE_FAIL;
 }
 
 // Last step of the sampler: weight and pdf from the lobes at the drawn
@@ -982,19 +1018,58 @@ __host__ __device__ inline uint32_t sample_finish(const EvalOut<S>& e, const V3<
     return flags;
 }
 
+// A drawn direction and, optionally, a given one on the same hit, with the
+// forward nodes computed once.  The node loop starts at the node the draw
+// picked (node 0 for the lobes at x), so the draw takes its frame from the
+// first iteration and every node serves both directions: K nodes per query,
+// summed in the rotated order.  The given direction's output is written only
+// when eval_ok and the hit is not a pass-through; returns the sampler's flags.
+template <class G, class S, int MP, class NodeFn>
+__host__ __device__ inline uint32_t sample_eval_nodes(const Derived<G, S>& P, const XState<G, S, MP>& X,
+                                                      const V3<float>& wi, const V3<G>& wo_q, bool eval_ok,
+                                                      float xi0, float xi1, float xi2, const NodeFn& node_of,
+                                                      EvalOut<S>& eo, SampleOut<S>& so)
+{
+    uint32_t flags = sample_pick(P, X, wi, xi0, so);
+    if (X.ph.pass) return flags;
+    const int lobe = so.lobe;
+    const int k0 = (lobe == 1 || lobe == 3) ? so.node : 0;
+    LobeAcc<S> a, b;
+    if (eval_ok) lobes_at_x(P, X, wo_q, a);
+    const bool front_i = val(X.mu_i) > 0.0f;
+    V3<G> ws;
+    bool ok;
+    {
+        Node<G, S> nd;
+        node_of(k0, nd);
+        ok = sample_dir(P, X, lobe, nd, xi1, xi2, so, ws);
+        if (ok) lobes_at_x(P, X, ws, b);
+        if (eval_ok) lobes_node_step(P, front_i, nd, wo_q, a);
+        if (ok) lobes_node_step(P, front_i, nd, ws, b);
+    }
+    for (int j = 1; j < P.K; ++j) {
+        int k = k0 + j;
+        k = k >= P.K ? k - P.K : k;
+        Node<G, S> nd;
+        node_of(k, nd);
+        if (eval_ok) lobes_node_step(P, front_i, nd, wo_q, a);
+        if (ok) lobes_node_step(P, front_i, nd, ws, b);
+    }
+    if (eval_ok) lobes_finish(P, X, a, eo);
+    if (!ok) return flags | F_SAMPLE_FAIL;
+    EvalOut<S> es;
+    lobes_finish(P, X, b, es);
+    return sample_finish(es, ws, flags, so);
+}
+
 template <class G, class S, int MP, class NodeFn>
 __host__ __device__ inline uint32_t sample_from_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
                                                   const V3<float>& wi, float xi0, float xi1,
                                                   float xi2, const NodeFn& node_of,
                                                   SampleOut<S>& so)
 {
-    V3<G> wo;
-    bool ok;
-    const uint32_t flags = sample_draw(P, X, wi, xi0, xi1, xi2, node_of, so, wo, ok);
-    if (!ok) return flags;
-    EvalOut<S> e;
-    lobes_nodes(P, X, wo, node_of, e);
-    return sample_finish(e, wo, flags, so);
+    EvalOut<S> unused;
+    return sample_eval_nodes(P, X, wi, mk3<G>(G(0), G(0), G(0)), false, xi0, xi1, xi2, node_of, unused, so);
 }
 
 // Evaluation at a given direction wo_q and one sampled direction for the
@@ -1008,14 +1083,7 @@ __host__ __device__ inline uint32_t eval_sample_from_x(const Derived<G, S>& P, c
                                                        const NodeFn& node_of, EvalOut<S>& eo,
                                                        SampleOut<S>& so)
 {
-    V3<G> ws;
-    bool ok;
-    const uint32_t flags = sample_draw(P, X, wi, xi0, xi1, xi2, node_of, so, ws, ok);
-    if (X.ph.pass) return flags;
-    EvalOut<S> es;
-    lobes_nodes2(P, X, wo_q, eval_ok, ws, ok, node_of, eo, es);
-    if (!ok) return flags;
-    return sample_finish(es, ws, flags, so);
+    return sample_eval_nodes(P, X, wi, wo_q, eval_ok, xi0, xi1, xi2, node_of, eo, so);
 }
 
 template <class G, class S, int MP, class Tab>

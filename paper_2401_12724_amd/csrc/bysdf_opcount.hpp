@@ -81,6 +81,10 @@ inline Derived<CD, CF> derive_counted(const TypeRec& t)
     for (int c = 0; c < 3; ++c) d.alb[c] = f.alb[c];
     d.rp_s = f.rp_s; d.Rpc_s = f.Rpc_s;
     d.n_mig = f.n_mig; d.mig_seed = f.mig_seed; d.mig_period = f.mig_period; d.mig_blend = f.mig_blend;
+    for (int k = 0; k < kMaxPlies; ++k) {
+        d.ply_c[k] = f.ply_c[k];
+        d.ply_s[k] = f.ply_s[k];
+    }
     return d;
 }
 
