@@ -152,6 +152,25 @@ template <class S> __host__ __device__ inline S smith_G1(const V3<S>& w, const V
     return S(2) * rcp_(S(1) + sqrt_(S(1) + a2t2));
 }
 
+// Isotropic roughness (alpha_x = alpha_y = a): D and G1 depend on the
+// microfacet and the directions through their cosines with the normal only.
+// mz = m.n, ms2 = 1 - mz^2 (formed before narrowing, where it does not
+// cancel); wm = w.m (the sign test), wz = w.n, ws2 = 1 - wz^2.
+template <class S> __host__ __device__ inline S ggx_D_iso(S mz, S ms2, S a)
+{
+    if (!(val(mz) > 0.0f)) return S(0);
+    const S ia2 = rcp_(a * a);
+    S t = ms2 * ia2 + mz * mz;
+    return rcp_(S(float(kPi)) * a * a * t * t);
+}
+template <class S> __host__ __device__ inline S smith_G1_iso(S wm, S wz, S ws2, S a)
+{
+    if (!(val(wm) * val(wz) > 0.0f)) return S(0);
+    S a2t2 = a * a * ws2 * rcp_(wz * wz);
+    return S(2) * rcp_(S(1) + sqrt_(S(1) + a2t2));
+}
+template <class G> __host__ __device__ inline G one_minus_sq(const G& z) { return G(1) - z * z; }
+
 // Visible-normal sampling of GGX (Heitz 2018): stretch the view to unit
 // roughness, build a basis around it, sample the projected hemisphere disc
 // with its far half compressed according to the view elevation, lift,
@@ -557,8 +576,15 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
         V3<G> wt = X.wi_g * (-ie) + m * (c * ie - ct);
         r.wt = wt;
         S cs = Narrow<S>::from(c);
-        r.T = fresnel_T<S>(cs, P.eta) *
-              smith_G1<S>(narrow3<S>(to_local(X.fx, wt)), narrow3<S>(ml), P.ax, P.ay);
+        S g1t;
+        if (val(P.ax) == val(P.ay)) {
+            const G tz = dot(wt, X.fx.n);
+            g1t = smith_G1_iso<S>(Narrow<S>::from(dot(wt, m)), Narrow<S>::from(tz),
+                                  Narrow<S>::from(one_minus_sq(tz)), P.ax);
+        } else {
+            g1t = smith_G1<S>(narrow3<S>(to_local(X.fx, wt)), narrow3<S>(ml), P.ax, P.ay);
+        }
+        r.T = fresnel_T<S>(cs, P.eta) * g1t;
         // chord in the projected cross-section, starting at the ply hit
         G le2 = wt.x * wt.x + wt.y * wt.y;
         G il = val(le2) > 0.0 ? rsqrt_(le2) : G(0);
@@ -640,15 +666,28 @@ __host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& w
     G ml2 = dot(mh, mh);
     if (!(val(ml2) > 0.0)) return;
     mh = mh * rsqrt_(ml2);
-    if (val(dot(mh, fy.n)) < 0.0) mh = -mh;
+    G mz = dot(mh, fy.n);
+    if (val(mz) < 0.0) {
+        mh = -mh;
+        mz = -mz;
+    }
     G im = dot(wip, mh), om = dot(wo, mh);
     if (!(val(im) < 0.0 && val(om) > 0.0)) return;
     G den = P.eta_g * im + om;
     G Ft = fresnel_T<G>(-im, P.inv_eta_g);
-    V3<S> ml = narrow3<S>(to_local(fy, mh));
-    S D = ggx_D<S>(ml, P.ax, P.ay);
-    S g1i = smith_G1<S>(narrow3<S>(to_local(fy, wip)), ml, P.ax, P.ay);
-    S g1o = smith_G1<S>(narrow3<S>(to_local(fy, wo)), ml, P.ax, P.ay);
+    S D, g1i, g1o;
+    if (val(P.ax) == val(P.ay)) {
+        D = ggx_D_iso<S>(Narrow<S>::from(mz), Narrow<S>::from(one_minus_sq(mz)), P.ax);
+        g1i = smith_G1_iso<S>(Narrow<S>::from(im), Narrow<S>::from(ci), Narrow<S>::from(one_minus_sq(ci)),
+                              P.ax);
+        g1o = smith_G1_iso<S>(Narrow<S>::from(om), Narrow<S>::from(co), Narrow<S>::from(one_minus_sq(co)),
+                              P.ax);
+    } else {
+        V3<S> ml = narrow3<S>(to_local(fy, mh));
+        D = ggx_D<S>(ml, P.ax, P.ay);
+        g1i = smith_G1<S>(narrow3<S>(to_local(fy, wip)), ml, P.ax, P.ay);
+        g1o = smith_G1<S>(narrow3<S>(to_local(fy, wo)), ml, P.ax, P.ay);
+    }
     // |wi'.m| |wo.m| / (|wi'.n| |wo.n|) * Jacobian / (eta wi'.m + wo.m)^2,
     // times |wo.n| for the returned value
     S geo = Narrow<S>::from((im * om) * rcp_(ci * (den * den)));
@@ -686,11 +725,21 @@ __host__ __device__ inline void lobes_at_x(const Derived<G, S>& P, const XState<
     bool front_i = val(mu_i) > 0.0f;
     if (front_i && val(mu_o_g) > 0.0) {
         V3<G> hv = normalize(X.wi_g + wo_g);
-        V3<S> hl = narrow3<S>(to_local(X.fx, hv));
-        S D = ggx_D<S>(hl, P.ax, P.ay);
-        S g1i = smith_G1<S>(narrow3<S>(to_local(X.fx, X.wi_g)), hl, P.ax, P.ay);
-        S g1o = smith_G1<S>(narrow3<S>(to_local(X.fx, wo_g)), hl, P.ax, P.ay);
-        S ih = Narrow<S>::from(dot(X.wi_g, hv)), oh = Narrow<S>::from(dot(wo_g, hv));
+        const G ih_g = dot(X.wi_g, hv), oh_g = dot(wo_g, hv);
+        S D, g1i, g1o;
+        if (val(P.ax) == val(P.ay)) {
+            const G hz = dot(hv, X.fx.n), iz = dot(X.wi_g, X.fx.n);
+            D = ggx_D_iso<S>(Narrow<S>::from(hz), Narrow<S>::from(one_minus_sq(hz)), P.ax);
+            g1i = smith_G1_iso<S>(Narrow<S>::from(ih_g), Narrow<S>::from(iz), Narrow<S>::from(one_minus_sq(iz)),
+                                  P.ax);
+            g1o = smith_G1_iso<S>(Narrow<S>::from(oh_g), mu_o, Narrow<S>::from(one_minus_sq(mu_o_g)), P.ax);
+        } else {
+            V3<S> hl = narrow3<S>(to_local(X.fx, hv));
+            D = ggx_D<S>(hl, P.ax, P.ay);
+            g1i = smith_G1<S>(narrow3<S>(to_local(X.fx, X.wi_g)), hl, P.ax, P.ay);
+            g1o = smith_G1<S>(narrow3<S>(to_local(X.fx, wo_g)), hl, P.ax, P.ay);
+        }
+        S ih = Narrow<S>::from(ih_g), oh = Narrow<S>::from(oh_g);
         S ihp = val(ih) > 0.0f ? ih : S(0);
         const S q4 = rcp_(S(4) * mu_i);
         ExS = (S(1) - P.B) * P.kS * fresnel<S>(ihp, P.eta) * g1i * g1o * D * q4;
