@@ -223,12 +223,26 @@ def _op_counts(bysdf, T, P, q, mode, n=4096):
     return c
 
 
+def _host_cores():
+    """Cores this process may run on (its affinity set) and the host's count."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, aff), os.cpu_count()
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        return None
+
+
 def _cpu_baseline(P, q, target_s):
     """FP64 oracle on the first blocks of the workload, same stages (eval at
-    wo, one sampled direction with its pdf, furnace per block)."""
+    wo, one sampled direction with its pdf, furnace per block), on every core
+    the process may use."""
     import oracle
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
+    cores, host_cpus = _host_cores()
 
     def run(nb):
         n = nb * 256
@@ -251,15 +265,162 @@ def _cpu_baseline(P, q, target_s):
         nb = int(min(len(P), max(nb + 1, nb * target_s / max(dt, 1e-3))))
         dt = run(nb)
     n = nb * 256
-    cpu = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
-    except OSError:
-        pass
-    return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle", "cpu": cpu,
+    return {"value": n / dt, "unit": "queries/s", "cores": cores, "host_cpus": host_cpus,
+            "kind": "oracle", "cpu": _cpu_model(),
             "sample": "first %d blocks (%d queries) of the per-block workload, same "
                       "stages (eval, sample with pdf, furnace), %.1f s" % (nb, n, dt)}
+
+
+def _cpu_configs(torch, bysdf, W):
+    """The oracle on the other workloads, on every core the process may use:
+    the single-type 2^16-query evaluation and the 4,096-type batch in full,
+    the fitting workload (forward at the hidden and the starting parameters,
+    and the 17-evaluation central-difference gradient of the loss), and the
+    two 64 x 64 crops of the weave view at 64 spp.  The fitting record also
+    carries what needs the oracle's targets and differences: the GPU
+    adjoint's gradient error against them and an Adam fit's parameter
+    recovery."""
+    import oracle
+    cores, _ = _host_cores()
+    out = {}
+    # single type, 2^16 queries
+    P0, q0 = W.single_type(65536, 0)
+    t0 = time.perf_counter()
+    oracle.eval(P0, q0, nthreads=cores)
+    dt = time.perf_counter() - t0
+    out["single_type_2e16"] = {"queries": 65536, "s": dt, "value": 65536 / dt, "unit": "queries/s",
+                               "stage": "eval"}
+    # 4,096 types, ~2^26 queries, in chunks of 4 M queries
+    P3, q3, off3 = W.heterogeneous(4096, 3)
+    ts3 = oracle.TypeSet(P3)
+    n3 = len(q3["h"])
+    t0 = time.perf_counter()
+    for a in range(0, n3, 1 << 22):
+        b = min(n3, a + (1 << 22))
+        oracle.eval(ts3, {k: (v[..., a:b] if v is not None else None) for k, v in q3.items()},
+                    nthreads=cores)
+    dt = time.perf_counter() - t0
+    out["hetero_4096_types"] = {"queries": n3, "s": dt, "value": n3 / dt, "unit": "queries/s",
+                                "stage": "eval (in full)"}
+    del q3, ts3
+    out["fitting_64x65536"] = _fit_c4(torch, bysdf, W, oracle, cores)
+    out["weave_crops_64spp"] = _weave_crops_oracle(W, oracle, cores)
+    return out
+
+
+def _fit_c4(torch, bysdf, W, oracle, cores, steps=500):
+    """Fitting workload (64 types x 65,536 queries): the oracle's forward and
+    its 17-evaluation central-difference gradient of the loss at the
+    starting parameters; the GPU adjoint's per-type gradient against those
+    differences; and an Adam fit (lr 1e-2, 500 steps, every parameter free,
+    projected into the valid ranges) from the range midpoints towards the
+    oracle's targets at the hidden parameters."""
+    from paper_2401_12724_amd.autograd import bysdf_fit_step
+    hidden, start, q = W.fitting(64, 65536, 4)
+    n = len(q["h"])
+    ts_h, ts_s = oracle.TypeSet(hidden), oracle.TypeSet(start)
+    t0 = time.perf_counter()
+    target = oracle.eval(ts_h, q, nthreads=cores)[0][:, :3]
+    fwd_s = time.perf_counter() - t0
+    E0 = oracle.eval(ts_s, q, nthreads=cores)[0][:, :3]
+    gE = (2.0 * (E0 - target)).astype(np.float32)
+    t0 = time.perf_counter()
+    _, pa = oracle.grad_fd(ts_s, q, gE, 1e-7, nthreads=cores)
+    fd_s = time.perf_counter() - t0
+    # a difference quotient counts where a second step size agrees with it:
+    # a texel centre of the piecewise-linear fiber table inside the step, or
+    # a non-contracting ply fixed point, makes it meaningless elsewhere
+    _, pb = oracle.grad_fd(ts_s, q, gE, 3e-8, nthreads=cores)
+    ok = np.abs(pa - pb) <= 1e-4 * np.maximum(np.abs(pa), 1e-7) + 1e-9
+    # the GPU adjoint of the same loss at the same parameters, per query
+    T = bysdf.bysdf_types_create(start)
+    qd = bysdf.to_device(q)
+    off = torch.from_numpy(np.arange(65, dtype=np.int64) * 65536).cuda()
+    _, pq = bysdf.bysdf_eval_backward(T, qd, off, torch.from_numpy(gE).cuda(), per_query=True)
+    pq = pq.cpu().numpy().astype(np.float64)
+    tid = q["type"]
+    g_fd = np.zeros((64, 8))
+    g_gpu = np.zeros((64, 8))
+    np.add.at(g_fd, tid, np.where(ok, pa, 0.0))
+    np.add.at(g_gpu, tid, np.where(ok, pq, 0.0))
+    rel = np.abs(g_gpu - g_fd) / np.maximum(np.abs(g_fd), 1e-30)
+    names = W.THETA_NAMES
+    grad_err = {nm: {"median": float(np.median(rel[:, k])), "p90": float(np.percentile(rel[:, k], 90)),
+                     "max": float(rel[:, k].max()), "queries_counted": float(ok[:, k].mean())}
+                for k, nm in enumerate(names)}
+    # Adam fits against the oracle's targets: every parameter free, and with
+    # the twists known (held at their hidden values, as the paper's fitting
+    # takes the geometry as given)
+    tgt = torch.from_numpy(target.astype(np.float32)).cuda()
+    th_true = np.stack([W.theta_of(p) for p in hidden])
+    th_mid = np.stack([W.theta_of(p) for p in start])
+    groups = {"albedo": [0, 1, 2], "beta": [3], "ply_twist": [4], "fiber_twist": [5],
+              "densities": [6, 7]}
+    fits = {}
+    fit_s = 0.0
+    for label, known in (("all_free", ()), ("twists_known", (4, 5))):
+        th0 = th_mid.copy()
+        free = np.ones(8, np.float32)
+        for k in known:
+            th0[:, k] = th_true[:, k]
+            free[k] = 0.0
+        theta = torch.tensor(th0, dtype=torch.float32, device="cuda", requires_grad=True)
+        mask = torch.from_numpy(free).cuda()
+        theta.register_hook(lambda g, m=mask: g * m)
+        opt = torch.optim.Adam([theta], lr=1e-2, betas=(0.9, 0.999))
+        losses = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            losses.append(bysdf_fit_step(theta, T, qd, off, tgt, opt))
+        torch.cuda.synchronize()
+        fit_s = time.perf_counter() - t0
+        err0 = np.abs(th0 - th_true)
+        err1 = np.abs(theta.detach().cpu().numpy() - th_true)
+        fits[label] = {"loss_start": float(losses[0]), "loss_end": float(losses[-1]),
+                       "mean_abs_param_error": {
+                           g: {"start": float(err0[:, ix].mean()), "fitted": float(err1[:, ix].mean())}
+                           for g, ix in groups.items() if not set(ix) & set(known)}}
+    return {"queries": n, "types": 64, "cores": cores,
+            "oracle_forward_s": fwd_s, "oracle_forward_queries_per_s": n / fwd_s,
+            "oracle_fd_gradient_s": fd_s, "oracle_fd_queries_per_s": n / fd_s,
+            "fd_evaluations_per_query": 17,
+            "gpu_grad_rel_error_vs_fd": grad_err,
+            "grad_note": "per type and parameter, the GPU adjoint of the loss sum_q sum_c "
+                         "(E - E*)^2 at the starting parameters against the oracle's central "
+                         "differences of the same sum, over the queries whose differences at "
+                         "relative steps 1e-7 and 3e-8 agree to 1e-4 (queries_counted)",
+            "fit": dict(steps=steps, lr=1e-2, ms_per_step=fit_s / steps * 1e3, **fits)}
+
+
+def _weave_crops_oracle(W, oracle, cores):
+    """The oracle's path tracer on the two 64 x 64 validation crops of the
+    weave view at 64 spp (centre; far edge with the far field); the
+    full-frame time is extrapolated from the crops' path rate."""
+    ctrl, off, ty, ph = W.weave()
+    S = oracle.Scene(ctrl, off)
+    cam = W.weave_camera()
+    rows = {}
+    total_paths, total_s = 0, 0.0
+    for name, (cx, cy), lod in (("centre", (928, 508), 1.0), ("far_edge", (928, 384), 4.0)):
+        rs = dict(eye=cam["eye"], look_at=cam["look_at"], up=cam["up"], vfov=cam["vfov"],
+                  width=cam["width"], height=cam["height"], crop_x=cx, crop_y=cy, crop_w=64,
+                  crop_h=64, light_corner=(-5.0, -5.0, 30.0), light_u=(0.0, 10.0, 0.0),
+                  light_v=(10.0, 0.0, 0.0), light_radiance=(5.0, 5.0, 5.0),
+                  env_radiance=(0.2, 0.2, 0.2), spp=64, max_depth=8, lod_px=lod, n_h=4, seed=2,
+                  ray_eps=1e-4, spp_batch=0)
+        t0 = time.perf_counter()
+        oracle.render(S, [W.default_params()], ty, ph, rs, nthreads=cores)
+        dt = time.perf_counter() - t0
+        paths = 64 * 64 * 64
+        rows[name] = {"paths": paths, "s": dt, "paths_per_s": paths / dt}
+        total_paths += paths
+        total_s += dt
+    rate = total_paths / total_s
+    rows["full_frame_extrapolated_s"] = cam["width"] * cam["height"] * 64 / rate
+    rows["note"] = ("full_frame_extrapolated_s: 1920 x 1080 x 64 paths at the crops' mean "
+                    "path rate (extrapolated, not run)")
+    return rows
 
 
 def _timed(torch, fn, reps):
@@ -454,11 +615,13 @@ def _cross_section(torch, bysdf, W, P, qd):
     return out
 
 
-def _weave_render(torch, bysdf, W, spp=4):
+def _weave_render(torch, bysdf, W, spp=4, spp_full=64):
     """The plain weave (256 + 256 B-spline yarns, 524,288 spans) seen by the
     grazing 1920 x 1080 camera: primary-ray intersection of every pixel
-    centre, and a full-frame render at spp samples per pixel (depth <= 8,
-    next-event estimation with MIS, 1-pixel LOD)."""
+    centre, the full frame at spp_full samples per pixel (depth <= 8,
+    next-event estimation with MIS, 1-pixel LOD), and at spp samples per
+    pixel the same frame plain, in multi-scale mode and with the image
+    gradient."""
     ctrl, off, ty, ph = W.weave()
     t0 = time.perf_counter()
     S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
@@ -486,6 +649,11 @@ def _weave_render(torch, bysdf, W, spp=4):
               ray_eps=1e-4, spp_batch=1)
     ws = bysdf.alloc_workspace(bysdf.shade_wavefront_workspace_size(rs))
     fb = torch.empty((cam["height"], cam["width"], 3), dtype=torch.float32, device="cuda")
+    # the full frame at its configured sample count
+    rf = dict(rs, spp=spp_full)
+    _, fcounts = bysdf.shade_wavefront(S, T, rf, fb, ws, counts=True)
+    fms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rf, fb, ws), 1)
+    full_mean = float(fb.mean())
     _, counts = bysdf.shade_wavefront(S, T, rs, fb, ws, counts=True)
     rms = _timed(torch, lambda: bysdf.shade_wavefront(S, T, rs, fb, ws), 3)
     rays = counts[0] + counts[1]
@@ -506,7 +674,12 @@ def _weave_render(torch, bysdf, W, spp=4):
                       "device_bytes": info["bytes"], "build_s": build_s},
             "intersect": {"rays": n, "ms": ims, "rays_per_s": n / (ims * 1e-3),
                           "hit_fraction": hit_frac},
-            "render": {"width": cam["width"], "height": cam["height"], "spp": spp, "ms": rms,
+            "render": {"width": cam["width"], "height": cam["height"], "spp": spp_full, "ms": fms,
+                       "extension_rays": fcounts[0], "shadow_rays": fcounts[1],
+                       "rays_per_s": (fcounts[0] + fcounts[1]) / (fms * 1e-3),
+                       "paths_per_s": cam["width"] * cam["height"] * spp_full / (fms * 1e-3),
+                       "mean_radiance": full_mean},
+            "render_4spp": {"width": cam["width"], "height": cam["height"], "spp": spp, "ms": rms,
                        "extension_rays": counts[0], "shadow_rays": counts[1],
                        "rays_per_s": rays / (rms * 1e-3),
                        "paths_per_s": cam["width"] * cam["height"] * spp / (rms * 1e-3),
@@ -528,6 +701,8 @@ def main():
     ap.add_argument("--blocks", type=int, default=65536, help="parameter blocks of 256 queries")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-configs", action="store_true",
+                    help="time the oracle on the bench workload only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for PMC byte scaling)")
     ap.add_argument("--no-extras", action="store_true",
@@ -681,6 +856,8 @@ def main():
         out["fit"] = _fit(torch, bysdf, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(P, q, args.cpu_seconds)
+        if not args.no_cpu_configs:
+            out["cpu_baseline"]["configs"] = _cpu_configs(torch, bysdf, W)
     print(json.dumps(out), flush=True)
 
 

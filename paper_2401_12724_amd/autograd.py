@@ -47,11 +47,24 @@ class BYSDFEval(torch.autograd.Function):
         return g * inside, None, None, None
 
 
+def project_(theta):
+    """Clamp theta (n_types x 8) into the ranges the handle accepts, in place:
+    a step that leaves a range would otherwise park the component where the
+    value, and with it the gradient, no longer depends on it."""
+    with torch.no_grad():
+        lo = torch.tensor(_LO, dtype=theta.dtype, device=theta.device)
+        hi = torch.tensor(_HI, dtype=theta.dtype, device=theta.device)
+        theta.copy_(torch.maximum(torch.minimum(theta, hi), lo))
+    return theta
+
+
 def bysdf_fit_step(theta, types, q, offsets, target, opt):
-    """One step of the least-squares fit sum (E - target)^2 with optimiser opt."""
+    """One step of the least-squares fit sum (E - target)^2 with optimiser
+    opt, projected back into the valid parameter ranges."""
     opt.zero_grad(set_to_none=True)
     E = BYSDFEval.apply(theta, types, q, offsets)
     loss = ((E - target) ** 2).sum()
     loss.backward()
     opt.step()
+    project_(theta)
     return loss.detach()
