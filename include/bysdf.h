@@ -291,11 +291,15 @@ int bysdf_furnace_blocks(const bysdf_types_t* types, const bysdf_sample_soa* q, 
 /* Schedule of bysdf_eval_batched (see paper_2401_12724_amd/autotune.py,
  * which picks one by timing candidates on the workload at hand). */
 typedef struct {
-    int32_t chunk;    /* consecutive tiles a workgroup takes per visit, 1..64 */
-    int32_t grid;     /* persistent workgroups (0: 2048)                      */
-    int32_t use_lds;  /* stage each tile's fiber table in LDS (when <= 2048
-                         texels) instead of reading it through the caches     */
-    int32_t reserved;
+    int32_t chunk;     /* consecutive tiles a workgroup takes per visit, 1..64 */
+    int32_t grid;      /* persistent workgroups (0: 2048)                      */
+    int32_t use_lds;   /* stage each tile's fiber table in LDS (when <= 2048
+                          texels) instead of reading it through the caches     */
+    int32_t block;     /* lanes per workgroup = queries per tile: 128 or 256
+                          (0: 256)                                            */
+    int32_t min_waves; /* register budget: 1 or 2 wavefronts per SIMD (0: 2);
+                          one wavefront keeps every value in registers, two
+                          hide more latency but spill                          */
 } bysdf_schedule;
 
 /* Bytes of device workspace bysdf_eval_batched needs (0 on bad arguments). */
@@ -306,7 +310,8 @@ size_t bysdf_batched_workspace_size(int32_t n_types);
  * DEVICE int64 CSR of n_types + 1 entries, type_offsets[n_types] == n;
  * q->type_id is not read), cut into tiles of at most 256 queries of one
  * type that workgroups take from a device queue.  Same outputs as
- * bysdf_eval.  sched may be NULL (chunk 4, grid 2048, LDS staging).  The
+ * bysdf_eval.  sched may be NULL (chunk 4, grid 2048, LDS staging, 256
+ * lanes, two wavefronts per SIMD).  The
  * launch sequence (a scan, a counter reset, the persistent kernel) contains
  * no memset and no host synchronisation, so it can be captured in a graph;
  * calls sharing one workspace must not overlap.  workspace: DEVICE buffer

@@ -2,9 +2,11 @@
 
 For a given handle and batch, times every candidate schedule of
 bysdf_eval_batched (chunk of tiles per queue visit, persistent grid size,
-LDS staging of fiber tables) with HIP events on the current stream, keeps
-the fastest, and caches it per (device, workload signature) in a JSON file.
-Schedules change only which workgroup evaluates which tile, never the
+LDS staging of fiber tables, workgroup size = queries per tile, and the
+register budget: one or two wavefronts per SIMD) with HIP events on the
+current stream, keeps the fastest, and caches it per (device, workload
+signature) in a JSON file.  Schedules change only which workgroup
+evaluates which tile and how many registers its kernel may hold, never the
 arithmetic of a query, so every candidate returns identical outputs.
 """
 from __future__ import annotations
@@ -17,8 +19,9 @@ import numpy as np
 
 from . import bysdf
 
-DEFAULT_CANDIDATES = [dict(chunk=c, grid=g, use_lds=l)
-                      for c in (1, 2, 4, 8) for g in (256, 512, 1024, 2048, 4096) for l in (1, 0)]
+DEFAULT_CANDIDATES = [dict(chunk=c, grid=g, use_lds=l, block=b, min_waves=w)
+                      for c in (1, 4, 16) for g in (512, 1024, 2048, 4096) for l in (1, 0)
+                      for b in (128, 256) for w in (1, 2)]
 
 
 def signature(types: bysdf.Types, offsets_host) -> str:

@@ -81,7 +81,7 @@ class FootprintSoA(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("chunk", C.c_int32), ("grid", C.c_int32), ("use_lds", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("block", C.c_int32), ("min_waves", C.c_int32)]
 
 
 class SampleOutSoA(C.Structure):
@@ -366,7 +366,8 @@ def bysdf_eval_batched(types: Types, offsets, q: dict, out=None, sched=None, wor
         _check_workspace(workspace[0], workspace[1], ws, "bysdf_eval_batched")
     sc = None
     if sched is not None:
-        sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]), 0)
+        sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]),
+                      int(sched.get("block", 0)), int(sched.get("min_waves", 0)))
     qs = _qsoa(q)
     _check(lib().bysdf_eval_batched(types.handle, offsets.data_ptr(), n, C.byref(qs), C.byref(o),
                                     C.byref(sc) if sc is not None else None, workspace[1], ws,
@@ -383,7 +384,8 @@ def bysdf_eval_batched_noalloc(types: Types, offsets, q: dict, out, sched=None, 
     o = _eval_out_soa(vals, flags)
     sc = None
     if sched is not None:
-        sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]), 0)
+        sc = Schedule(int(sched["chunk"]), int(sched["grid"]), int(sched["use_lds"]),
+                      int(sched.get("block", 0)), int(sched.get("min_waves", 0)))
     qs = _qsoa(q)
     _check(lib().bysdf_eval_batched_noalloc(types.handle, offsets.data_ptr(), n, C.byref(qs), C.byref(o),
                                             C.byref(sc) if sc is not None else None, _stream(stream)),

@@ -1416,14 +1416,14 @@ __global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(c
 // tile_first[t] = index of the first tile of type t (exclusive scan of
 // ceil(count_t / kBlock)); tile_first[n_types] = number of tiles.
 __global__ __launch_bounds__(1024) void k_tile_scan(const int64_t* __restrict__ off, int n_types,
-                                                    int32_t* __restrict__ tile_first)
+                                                    int32_t* __restrict__ tile_first, int tile_size)
 {
     __shared__ int32_t s[1024];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int chunk = (n_types + nt - 1) / nt;
     const int lo = min(n_types, tid * chunk), hi = min(n_types, lo + chunk);
     int32_t sum = 0;
-    for (int t = lo; t < hi; ++t) sum += (int32_t)((off[t + 1] - off[t] + kBlock - 1) / kBlock);
+    for (int t = lo; t < hi; ++t) sum += (int32_t)((off[t + 1] - off[t] + tile_size - 1) / tile_size);
     s[tid] = sum;
     __syncthreads();
     for (int st = 1; st < nt; st <<= 1) {  // inclusive Hillis-Steele scan
@@ -1435,7 +1435,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int64_t* __restrict__ 
     int32_t run = s[tid] - sum;  // exclusive prefix of this chunk
     for (int t = lo; t < hi; ++t) {
         tile_first[t] = run;
-        run += (int32_t)((off[t + 1] - off[t] + kBlock - 1) / kBlock);
+        run += (int32_t)((off[t + 1] - off[t] + tile_size - 1) / tile_size);
     }
     if (tid == nt - 1) tile_first[n_types] = s[tid];
 }
@@ -1443,7 +1443,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int64_t* __restrict__ 
 // tile -> (type, first query, count); false past the last tile
 __device__ inline bool locate_tile(int tile, const int32_t* __restrict__ tile_first, int n_types,
                                    const int64_t* __restrict__ off, int* type, int64_t* start,
-                                   int* count)
+                                   int* count, int tile_size = kBlock)
 {
     if (tile >= tile_first[n_types]) return false;
     int lo = 0, hi = n_types - 1;  // last t with tile_first[t] <= tile
@@ -1453,9 +1453,9 @@ __device__ inline bool locate_tile(int tile, const int32_t* __restrict__ tile_fi
         else hi = mid - 1;
     }
     *type = lo;
-    *start = off[lo] + (int64_t)(tile - tile_first[lo]) * kBlock;
+    *start = off[lo] + (int64_t)(tile - tile_first[lo]) * tile_size;
     int64_t left = off[lo + 1] - *start;
-    *count = (int)(left < kBlock ? left : kBlock);
+    *count = (int)(left < tile_size ? left : tile_size);
     return true;
 }
 
@@ -1574,12 +1574,13 @@ __global__ void k_backward_sum(const int32_t* __restrict__ tile_first, int n_typ
 // last tile, so the grid always drains.
 __global__ void k_reset_counter(int* counter) { *counter = 0; }
 
-template <int MP, bool kLds>
-__global__ __launch_bounds__(kBlock, BYSDF_BATCHED_MIN_WAVES) void k_eval_batched(
+template <int MP, bool kLds, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void k_eval_batched(
     const TypeRec* __restrict__ types, const float4* __restrict__ tables,
     const int64_t* __restrict__ off, int n_types, const int32_t* __restrict__ tile_first,
     int* counter, QPtrs q, OPtrs o, int chunk)
 {
+    // a tile holds as many queries as the workgroup has lanes (128 or 256)
     __shared__ float4 s_tab[kLds ? kMaxLdsTexels : 1];
     __shared__ int s_next;
     const int tid = threadIdx.x;
@@ -1594,14 +1595,14 @@ __global__ __launch_bounds__(kBlock, BYSDF_BATCHED_MIN_WAVES) void k_eval_batche
         for (int c = 0; c < chunk; ++c) {
             int type = 0, count = 0;
             int64_t start = 0;
-            if (!locate_tile(t0 + c, tile_first, n_types, off, &type, &start, &count)) break;
+            if (!locate_tile(t0 + c, tile_first, n_types, off, &type, &start, &count, (int)blockDim.x)) break;
             type = __builtin_amdgcn_readfirstlane(type);
             const TypeRec& rec = types[type];
             TabPtr tab;
             if (kLds) {
                 if (type != staged) {
                     __syncthreads();
-                    for (int k = tid; k < rec.table_texels; k += kBlock) s_tab[k] = tables[rec.table_off + k];
+                    for (int k = tid; k < rec.table_texels; k += blockDim.x) s_tab[k] = tables[rec.table_off + k];
                     __syncthreads();
                     staged = type;
                 }
@@ -2140,7 +2141,8 @@ extern "C" int bysdf_eval_backward(const bysdf_types_t* h, const bysdf_query_soa
     float* partials = (float*)((char*)workspace + align256(sizeof(int32_t) * (h->n_types + 1)));
     QPtrs qp{q->type_id, q->h, q->u, q->v, q->wi_x, q->wi_y, q->wi_z, q->wo_x, q->wo_y, q->wo_z,
              q->shift0, q->shift1};
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, type_offsets, h->n_types, tile_first);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, type_offsets, h->n_types, tile_first,
+                       kBlock);
     HIP_TRY(hipGetLastError());
     int64_t tiles = max_tiles(n, h->n_types);
     if (tiles > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many tiles");
@@ -2167,16 +2169,14 @@ extern "C" size_t bysdf_batched_workspace_size(int32_t n_types)
 }
 
 template <int MP>
-static void launch_batched(const bysdf_types_t* h, bool lds, int grid, hipStream_t stream,
-                           const int64_t* off, const int32_t* tile_first, int* counter, QPtrs qp,
-                           OPtrs op, int chunk)
+static void launch_batched(const bysdf_types_t* h, bool lds, int waves, int block, int grid,
+                           hipStream_t stream, const int64_t* off, const int32_t* tile_first, int* counter,
+                           QPtrs qp, OPtrs op, int chunk)
 {
-    if (lds)
-        hipLaunchKernelGGL((k_eval_batched<MP, true>), dim3(grid), dim3(kBlock), 0, stream, h->d_types,
-                           h->d_tables, off, h->n_types, tile_first, counter, qp, op, chunk);
-    else
-        hipLaunchKernelGGL((k_eval_batched<MP, false>), dim3(grid), dim3(kBlock), 0, stream, h->d_types,
-                           h->d_tables, off, h->n_types, tile_first, counter, qp, op, chunk);
+    auto kern = lds ? (waves == 1 ? k_eval_batched<MP, true, 1> : k_eval_batched<MP, true, 2>)
+                    : (waves == 1 ? k_eval_batched<MP, false, 1> : k_eval_batched<MP, false, 2>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, h->d_types, h->d_tables, off, h->n_types,
+                       tile_first, counter, qp, op, chunk);
 }
 
 extern "C" int bysdf_eval_batched(const bysdf_types_t* h, const int64_t* type_offsets, int64_t n,
@@ -2197,14 +2197,18 @@ extern "C" int bysdf_eval_batched(const bysdf_types_t* h, const int64_t* type_of
     size_t need_ws = bysdf_batched_workspace_size(h->n_types);
     if (!workspace || ws_bytes < need_ws || ((uintptr_t)workspace & 255u))
         return fail(BYSDF_ERR_INVALID_ARG, "workspace needs %zu bytes, 256-byte aligned", need_ws);
-    int chunk = 4, grid = 0, use_lds = 1;
+    int chunk = 4, grid = 0, use_lds = 1, block = kBlock, waves = BYSDF_BATCHED_MIN_WAVES;
     if (sched) {
         chunk = sched->chunk;
         grid = sched->grid;
         use_lds = sched->use_lds;
+        if (sched->block) block = sched->block;
+        if (sched->min_waves) waves = sched->min_waves;
     }
     if (chunk < 1 || chunk > 64) return fail(BYSDF_ERR_INVALID_ARG, "schedule chunk must be in 1..64");
     if (grid < 0 || grid > (1 << 20)) return fail(BYSDF_ERR_INVALID_ARG, "schedule grid out of range");
+    if (block != 128 && block != 256) return fail(BYSDF_ERR_INVALID_ARG, "schedule block must be 128 or 256");
+    if (waves != 1 && waves != 2) return fail(BYSDF_ERR_INVALID_ARG, "schedule min_waves must be 1 or 2");
     bool lds = use_lds != 0;
     for (int i = 0; lds && i < h->n_tables; ++i)
         if (h->h_table_size[i] > kMaxLdsTexels) lds = false;
@@ -2216,14 +2220,14 @@ extern "C" int bysdf_eval_batched(const bysdf_types_t* h, const int64_t* type_of
              q->shift0, q->shift1};
     OPtrs op{o->E_r, o->E_g, o->E_b, o->E_xS, o->E_yS, o->E_xB_r, o->E_xB_g, o->E_xB_b,
              o->E_yB_r, o->E_yB_g, o->E_yB_b, o->pdf, o->flags};
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, type_offsets, h->n_types, tile_first);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, type_offsets, h->n_types, tile_first, block);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, stream, counter);
     if (h->max_plies <= 4)
-        launch_batched<4>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
+        launch_batched<4>(h, lds, waves, block, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
     else if (h->max_plies <= 6)
-        launch_batched<6>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
+        launch_batched<6>(h, lds, waves, block, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
     else
-        launch_batched<8>(h, lds, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
+        launch_batched<8>(h, lds, waves, block, grid, stream, type_offsets, tile_first, counter, qp, op, chunk);
     HIP_TRY(hipGetLastError());
     return BYSDF_OK;
 }

@@ -43,12 +43,19 @@ def test_batched_parity_and_schedules(torch_cuda):
     torch.cuda.synchronize()
     assert np.array_equal(pf.cpu().numpy(), f0.cpu().numpy())
     assert np.allclose(pv.cpu().numpy(), v0.cpu().numpy(), rtol=1e-6, atol=1e-9)
-    # schedules only move tiles between workgroups: outputs are identical
+    # schedules only move tiles between workgroups (and change the register
+    # budget of the kernel): outputs are identical
     for sc in (dict(chunk=1, grid=64, use_lds=0), dict(chunk=8, grid=4096, use_lds=1),
-               dict(chunk=3, grid=7, use_lds=1)):
+               dict(chunk=3, grid=7, use_lds=1), dict(chunk=2, grid=512, use_lds=1, block=128),
+               dict(chunk=4, grid=1024, use_lds=0, min_waves=1),
+               dict(chunk=1, grid=300, use_lds=1, block=128, min_waves=1)):
         v1, f1 = bysdf.bysdf_eval_batched(T, offd, qd, sched=sc)
         torch.cuda.synchronize()
         assert torch.equal(v1, v0) and torch.equal(f1, f0), sc
+    for bad, what in ((dict(chunk=1, grid=64, use_lds=0, block=100), "block"),
+                      (dict(chunk=1, grid=64, use_lds=0, min_waves=3), "min_waves")):
+        with pytest.raises(RuntimeError, match=what):
+            bysdf.bysdf_eval_batched(T, offd, qd, sched=bad)
 
 
 def test_batched_graph_replays(torch_cuda):
@@ -90,7 +97,8 @@ def test_autotuner_picks_a_schedule(torch_cuda, tmp_path):
     qd = bysdf.to_device(q)
     offd = torch.from_numpy(off).cuda()
     cache = str(tmp_path / "tune.json")
-    cands = [dict(chunk=c, grid=g, use_lds=1) for c in (1, 4) for g in (256, 2048)]
+    cands = [dict(chunk=c, grid=g, use_lds=1, block=b, min_waves=w) for c in (1, 4) for g in (256, 2048)
+             for b in (128, 256) for w in (1, 2)]
     r = autotune.autotune_batched(T, offd, qd, off, candidates=cands, reps=2, cache_path=cache)
     assert r["schedule"] in cands and r["ms"] == min(t[1] for t in r["timings"])
     r2 = autotune.autotune_batched(T, offd, qd, off, candidates=cands, cache_path=cache)
