@@ -60,6 +60,7 @@ _STAGE_KERNEL = {"eval_sample": "k_eval_sample<", "furnace": "k_furnace_w<"}
 
 
 def _kname(full):
+    full = full.replace("(anonymous namespace)::", "")
     return full.split("(")[0].replace("void ", "").strip()
 
 
@@ -148,8 +149,9 @@ def _summarize(prof_dir, bench_json, workload_tag):
              "|---|---|---|---|---|---|---|---|---|---|"]
     traffic = {}
     mean = lambda xs: sum(xs) / len(xs)
+    main_kernels = ("k_eval_sample<", "k_furnace_w<", "k_eval<", "k_sample<")
     for k in inst:
-        if "copy" in k.lower() or k not in fetch:
+        if "copy" in k.lower() or k not in fetch or not k.startswith(main_kernels):
             continue
         g = mean([gs for (_, _, gs) in inst[k]["SQ_INSTS_VALU"]])
         valu = mean([v for (_, v, _) in inst[k]["SQ_INSTS_VALU"]])
@@ -171,7 +173,7 @@ def _summarize(prof_dir, bench_json, workload_tag):
                                         sorted(next(iter(flops.values())))) + " |",
               "|---|" + "---|" * len(next(iter(flops.values())))]
     for k, cs in flops.items():
-        if "copy" in k.lower():
+        if "copy" in k.lower() or not k.startswith(main_kernels):
             continue
         lines.append("| `%s` | " % k + " | ".join(
             "%.1f" % (mean([v for (_, v, _) in cs[c]]) / N) for c in sorted(cs)) + " |")
@@ -198,12 +200,63 @@ def _summarize(prof_dir, bench_json, workload_tag):
             k, fq, kms[st], rate, 100 * rate / PEAK_VALU_TFLOPS, 100 * rate / 157.3))
     open(os.path.join(ROOT, "profiles", "bysdf_%s_counters.md" % tag), "w").write(
         "\n".join(lines) + "\n")
+    if os.path.isdir(os.path.join(prof_dir, "l2")):
+        _summarize_all(prof_dir, stats, counters, f_scale, w_scale, cmd)
     json.dump({"src_hash": _src_hash(), "workload": workload_tag,
                "unit": "bytes per launch",
                "calibration": {"fetch_scale": f_scale, "write_scale": w_scale,
                                "copy_bytes": 1 << 30},
                "kernels": traffic},
               open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    print("\n".join(lines))
+
+
+def _summarize_all(prof_dir, stats, counters, f_scale, w_scale, cmd):
+    """Every kernel of the profiled bench run (main step and extras): per
+    launch, the executed floating-point work from the FLOPS counters and
+    the HBM bytes from FETCH_SIZE and WRITE_SIZE, priced at the kernel's
+    trace-average duration against the 78.6 TFLOP/s vector peak and 8 TB/s;
+    VALU issue; L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS))."""
+    inst, meta = counters("inst")
+    flops, _ = counters("flops")
+    fetch, _ = counters("fetch")
+    write, _ = counters("write")
+    l2, _ = counters("l2")
+    mean = lambda xs: sum(xs) / len(xs) if xs else float("nan")
+    lines = ["# rocprofv3: every kernel of the bench run", "",
+             "Commands (repo root on the GPU host; one counter pass per run):", "", cmd, "",
+             "Per launch (mean over the launches of the kernel in the counter passes), priced at "
+             "the kernel-trace average duration.  Executed TFLOP/s = (FLOPS_FP64 + FLOPS_FP64_TRANS "
+             "+ FLOPS_FP32 + FLOPS_FP32_TRANS) x 64 lanes / duration, against 78.6 TFLOP/s; HBM = "
+             "FETCH_SIZE + WRITE_SIZE (scaled by the 1 GiB copy: %.4f, %.4f) / duration, against "
+             "8 TB/s; VALU issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 "
+             "XCDs); L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS)." % (f_scale, w_scale), "",
+             "| kernel | launches | avg us | VGPR | scratch B/lane | VALU issue | executed TFLOP/s "
+             "| of 78.6 | HBM GB/launch | HBM GB/s | of 8 TB/s | L2 hit |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    rows = []
+    for k, (calls, avg_us, _, _, _) in stats.items():
+        if k not in inst or "copy" in k.lower() or "fill" in k.lower():
+            continue
+        t = avg_us * 1e-6
+        fl = 64 * sum(mean([v for (_, v, _) in flops[k][c]]) for c in flops.get(k, {}) if "FLOPS" in c)
+        fb = mean([v for (_, v, _) in fetch[k]["FETCH_SIZE"]]) * 1024 * f_scale if k in fetch else 0.0
+        wb = mean([v for (_, v, _) in write[k]["WRITE_SIZE"]]) * 1024 * w_scale if k in write else 0.0
+        gui = mean([v for (_, v, _) in inst[k]["GRBM_GUI_ACTIVE"]])
+        valu = mean([v for (_, v, _) in inst[k]["SQ_INSTS_VALU"]])
+        hit = mean([v for (_, v, _) in l2[k]["TCC_HIT_sum"]]) if k in l2 else float("nan")
+        miss = mean([v for (_, v, _) in l2[k]["TCC_MISS_sum"]]) if k in l2 else float("nan")
+        tf = fl / t / 1e12 if t > 0 else 0.0
+        gbs = (fb + wb) / t / 1e9 if t > 0 else 0.0
+        m = meta[k]
+        rows.append((calls * avg_us, "| `%s` | %d | %.1f | %s | %s | %.2f | %.2f | %.1f %% | %.3f | %.0f | "
+                     "%.1f %% | %.2f |" % (k, calls, avg_us, m["VGPR_Count"], m["Scratch_Size"],
+                                          valu * 4 / (1024 * gui / 8) if gui else 0.0, tf,
+                                          100 * tf / PEAK_VALU_TFLOPS, (fb + wb) / 1e9, gbs,
+                                          100 * gbs / PEAK_HBM_GBS, hit / (hit + miss)
+                                          if hit + miss > 0 else float("nan"))))
+    lines += [r for _, r in sorted(rows, key=lambda x: -x[0])]
+    open(os.path.join(ROOT, "profiles", "all_kernels_bench_counters.md"), "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
@@ -447,8 +500,8 @@ def _hetero(torch, bysdf, W, single_type_eval_qps):
     del q
     offd = torch.from_numpy(off).cuda()
     out = bysdf.alloc_eval_out(n)
-    cands = [dict(chunk=c, grid=g, use_lds=l) for c in (1, 4, 16) for g in (1024, 4096)
-             for l in (1, 0)]
+    cands = [dict(chunk=c, grid=g, use_lds=l, block=b, min_waves=w) for c in (1, 4, 16)
+             for g in (1024, 4096) for l in (1, 0) for b in (128, 256) for w in (1, 2)]
     tune = autotune.autotune_batched(T, offd, qd, off, out=out, candidates=cands, reps=2)
     ws = bysdf.alloc_workspace(bysdf.bysdf_batched_workspace_size(T.n_types))
     sc = tune["schedule"]
