@@ -179,6 +179,8 @@ __device__ inline double mig_scale(int j, int m, double spread, uint32_t seed)
 __global__ __launch_bounds__(256) void k_fiber_table(int M, double rho, int Nu, float4* out, int m,
                                                       double spread, uint32_t seed)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     __shared__ double s_val[256];
     __shared__ int s_idx[256];
     __shared__ double s_lo[256], s_hi[256];
@@ -314,6 +316,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const Typ
                                                  const float4* __restrict__ tables, int lds_texels,
                                                  QPtrs q, OPtrs o, int64_t n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     extern __shared__ float4 s_tab[];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
@@ -391,6 +395,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
                                                    const float4* __restrict__ tables,
                                                    int lds_texels, SPtrs q, SOPtrs o, int64_t n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     extern __shared__ float4 s_tab[];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
@@ -438,6 +444,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sa
     QPtrs q, const float* __restrict__ xi0, const float* __restrict__ xi1,
     const float* __restrict__ xi2, OPtrs o, SOPtrs so_p, int64_t n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     extern __shared__ float4 s_tab[];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
@@ -842,6 +850,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
     const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
     QPtrs q, FPtrs fp, int n_max, OPtrs o, int64_t n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     extern __shared__ float4 s_tab[];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
@@ -1008,6 +1018,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
     const TypeRec* __restrict__ types, int n_types, const float4* __restrict__ tables, int lds_texels,
     SPtrs q, FPtrs fp, int n_max, SOPtrs o, int64_t n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     extern __shared__ float4 s_tab[];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
@@ -1184,6 +1196,8 @@ template <int MP>
 __global__ __launch_bounds__(kBlock) void k_ply_geometry(const TypeRec* __restrict__ types, int n_types,
                                                          QPtrs q, PlyOPtrs o, int64_t n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         int t = q.type[i];
@@ -1236,6 +1250,8 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
                                                     const float4* __restrict__ tables, SPtrs q,
                                                     int block, float* mean, float* var)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     __shared__ Node<double, float> s_nodes[kMaxNodes];
     __shared__ XState<double, float, MP> s_X;
     __shared__ float s_red[3][kBlock];
@@ -1343,6 +1359,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(c
                                                       const float4* __restrict__ tables, SPtrs q,
                                                       int block, int64_t nb, float* mean, float* var)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     __shared__ Node<double, float> s_nodes[kFurnaceWaves][kMaxNodes];
     __shared__ XState<double, float, MP> s_X[kFurnaceWaves];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -1481,6 +1499,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_BACKWARD_MIN_WAVES) void k_backward(c
                                                      float* __restrict__ partials,
                                                      float* __restrict__ per_query)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     constexpr int NS = PASS == 0 ? 6 : 1;
     // theta slots written by this pass
     constexpr int kSlot0[6] = {0, 1, 2, 3, 6, 7};
@@ -1580,6 +1600,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_eval_batched(
     const int64_t* __restrict__ off, int n_types, const int32_t* __restrict__ tile_first,
     int* counter, QPtrs q, OPtrs o, int chunk)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     // a tile holds as many queries as the workgroup has lanes (128 or 256)
     __shared__ float4 s_tab[kLds ? kMaxLdsTexels : 1];
     __shared__ int s_next;
@@ -1644,6 +1666,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_eval_batched(
 // ------------------------------------------------------------------ theta
 __global__ void k_set_theta(TypeRec* types, const float* theta, int n)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     TypeRec t = types[i];

@@ -348,6 +348,8 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                                                             int* cnt_out, ShadowQ SQ, int* cnt_sh, int cap,
                                                             int depth, int j0, int spp_batch)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     const int n = *cnt_in;
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const int i = base + threadIdx.x;
@@ -574,6 +576,8 @@ __global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_shado
                                                                                   const int* cnt, float* L,
                                                                                   int cap)
 {
+    bysdf::stage_math_tables();
+    __syncthreads();
     extern __shared__ int stk[];  // yarn::stack_entries(BVH depth) x kTraceBlock
     int* my = stk + threadIdx.x;
     const int n = *cnt;
