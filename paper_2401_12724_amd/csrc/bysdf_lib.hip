@@ -125,39 +125,6 @@ static int validate(const bysdf_type_params& p, int i)
     return 0;
 }
 
-static TypeRec make_rec(const bysdf_type_params& p)
-{
-    TypeRec t;
-    memset(&t, 0, sizeof(t));
-    t.n_plies = p.n_plies;
-    t.K = p.K;
-    t.n_iter = p.n_iter;
-    t.tex_size = p.tex_size;
-    t.rp = p.ply_radius;
-    t.Rpc = p.ply_center_radius;
-    t.ply_twist = p.ply_twist;
-    t.fiber_twist = p.fiber_twist;
-    t.rho_f_geom = p.fiber_radius;
-    t.beta = p.beta;
-    t.aniso = p.aniso;
-    t.eta = p.eta;
-    for (int c = 0; c < 3; ++c) t.albedo[c] = p.albedo[c];
-    t.k_spec = p.k_spec;
-    t.B = p.B;
-    t.r = p.r;
-    t.sigma_t = p.sigma_t;
-    t.ply_density = p.ply_density;
-    t.fiber_density = p.fiber_density;
-    t.shadow_hw = p.shadow_halfwidth;
-    t.mig_tables = p.mig_tables > 1 ? p.mig_tables : 1;
-    t.mig_seed = p.mig_seed;
-    t.mig_period = p.mig_tables > 1 ? p.mig_period : 1.0;
-    t.mig_blend = p.mig_blend;
-    t.mig_spread = p.mig_spread;
-    t.table_texels = t.mig_tables * p.tex_size;
-    fill_derived(t);
-    return t;
-}
 
 // ------------------------------------------------------------------ K1 tables
 // One workgroup per texel (Sec. 3.5.1).  Fiber centres: Vogel spiral of M
@@ -1741,7 +1708,7 @@ extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, b
         } else {
             ti = it->second;
         }
-        TypeRec r = make_rec(p[i]);
+        TypeRec r = bysdf_make_rec(p[i]);
         r.table_off = h->h_table_off[ti];
         h->h_types.push_back(r);
         h->h_type_table.push_back(ti);
@@ -2087,7 +2054,7 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
     if (mode != 1 && !wo) return fail(BYSDF_ERR_INVALID_ARG, "modes 0 and 2 need wo");
     if (mode != 0 && !xi) return fail(BYSDF_ERR_INVALID_ARG, "modes 1 and 2 need xi");
     if (int rc = validate(*p, 0)) return rc;
-    TypeRec rec = make_rec(*p);
+    TypeRec rec = bysdf_make_rec(*p);
     std::vector<float4> tb(rec.table_texels);
     for (int i = 0; i < rec.table_texels; ++i)
         tb[i] = make_float4(table[3 * i], table[3 * i + 1], table[3 * i + 2], 0.0f);

@@ -238,6 +238,8 @@ template <class To> struct Narrow;
 template <> struct Narrow<float> {
     __host__ __device__ static float from(double x) { return (float)x; }
     __host__ __device__ static float from(float x) { return x; }
+    // other geometry scalars (host-side tools) narrow through their value
+    template <class G> static float from(const G& x) { return (float)val(x); }
 };
 template <> struct Narrow<double> {
     __host__ __device__ static double from(double x) { return x; }

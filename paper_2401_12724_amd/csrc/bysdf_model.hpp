@@ -27,6 +27,27 @@ constexpr uint32_t F_BACKFACING = 1u << 5;
 constexpr uint32_t F_SAMPLE_FAIL = 1u << 6;
 constexpr uint32_t F_BAD_INPUT = 1u << 9;
 
+// Stages of the geometry chain.  A scope of the model names the stage it
+// belongs to with a StageMark of the geometry scalar.  For the kernels'
+// scalars the mark is empty and compiles to nothing; a host-side
+// measurement scalar specialises it to change the arithmetic of one stage
+// at a time (the precision audit).
+enum GeomStage : int {
+    kStagePlies = 0,  // yarn hit, ply-centre fixed point, ray/disc tests (Sec. 3.3-3.4)
+    kStageFrame,      // fiber table lookup and fiber frame (Sec. 3.5)
+    kStageShadow,     // ply horizon G_p (Sec. 4.1.4)
+    kStageRefract,    // visible normal and refraction into the yarn at x (Sec. 4.1.1)
+    kStageChord,      // chord through the cross-section, exit ply and point (Sec. 4.1.1)
+    kStageHalfX,      // half vector and cosines of the lobes at x (Eq. 2, 5)
+    kStageExit,       // half vector, cosines and transmittance of the exit (Eq. 3)
+    kStageSample,     // drawn directions (Sec. 4.1.5)
+    kStageRest,       // everything else in the geometry scalar
+    kNumStages
+};
+template <class G> struct StageMark {
+    __host__ __device__ explicit StageMark(int) {}
+};
+
 // Scalars one query needs, in the kernel's scalar types.
 template <class G, class S> struct Derived {
     int Np, K, N_it, Nu;
@@ -101,6 +122,28 @@ __host__ __device__ inline void fill_derived(TypeRec& t)
 }
 
 __host__ __device__ inline Derived<double, float> derive(const TypeRec& t) { return t.d; }
+
+// The derived scalars in other scalar types (host-side tools: the op counter
+// and the precision audit).
+template <class G2, class S2> inline Derived<G2, S2> rebind(const Derived<double, float>& f)
+{
+    Derived<G2, S2> d;
+    d.Np = f.Np; d.K = f.K; d.N_it = f.N_it; d.Nu = f.Nu; d.inv_np = f.inv_np;
+    d.rp = G2(f.rp); d.Rpc = G2(f.Rpc); d.slope = G2(f.slope); d.wp_turns = G2(f.wp_turns);
+    d.tnorm_inv = G2(f.tnorm_inv); d.vply_scale = G2(f.vply_scale); d.wf_turns = G2(f.wf_turns);
+    d.tan_af = G2(f.tan_af); d.ax_g = G2(f.ax_g); d.ay_g = G2(f.ay_g); d.eta_g = G2(f.eta_g);
+    d.inv_eta_g = G2(f.inv_eta_g);
+    d.ax = S2(f.ax); d.ay = S2(f.ay); d.eta = S2(f.eta); d.kS = S2(f.kS); d.B = S2(f.B); d.r = S2(f.r);
+    d.sigma_t = S2(f.sigma_t); d.rho_p = S2(f.rho_p); d.rho_f = S2(f.rho_f); d.dP = S2(f.dP);
+    for (int c = 0; c < 3; ++c) d.alb[c] = S2(f.alb[c]);
+    d.rp_s = S2(f.rp_s); d.Rpc_s = S2(f.Rpc_s);
+    d.n_mig = f.n_mig; d.mig_seed = f.mig_seed; d.mig_period = f.mig_period; d.mig_blend = f.mig_blend;
+    for (int k = 0; k < kMaxPlies; ++k) {
+        d.ply_c[k] = f.ply_c[k];
+        d.ply_s[k] = f.ply_s[k];
+    }
+    return d;
+}
 
 // sin and cos of 2 pi t (t in turns) for the geometry scalar
 template <class G> __host__ __device__ inline void sincos_turns_g(const G& t, G* s, G* c);
@@ -224,6 +267,7 @@ template <class G, class S, int MP>
 __host__ __device__ inline void trace_plies(const Derived<G, S>& P, float h, float u, float v,
                                             const V3<float>& wi, PlyHit<G, MP>& g)
 {
+    StageMark<G> mark(kStagePlies);
     g.pass = false;
     g.flags = 0;
     g.ks = -1;
@@ -349,6 +393,7 @@ template <class G, class S, class Tab>
 __host__ __device__ inline Frame<G> fiber_frame(const Derived<G, S>& P, const Tab& tab, G cth, G sth, int k,
                                                 G n2x, G n2y, G z, G* gf_out, G* a_out)
 {
+    StageMark<G> mark(kStageFrame);
     V3<G> tp = mk3<G>(-P.slope * sth * P.tnorm_inv, P.slope * cth * P.tnorm_inv, P.tnorm_inv);
     V3<G> n23 = mk3<G>(n2x, n2y, G(0));
     V3<G> np = normalize(n23 - tp * dot(n23, tp));
@@ -506,8 +551,12 @@ __host__ __device__ inline void state_after_plies(const Derived<G, S>& P, const 
     X.fxs = narrowf<S>(X.fx);
     // shadowing in the geometry scalar: a mostly occluded window leaves a
     // small visible share that single precision cannot resolve
-    G phi = atan2_(X.ph.n2x * X.wi_g.y - X.ph.n2y * X.wi_g.x, X.ph.n2x * X.wi_g.x + X.ph.n2y * X.wi_g.y);
-    G raw = ply_shadow_raw<G, MP>(P.Np, P.rp, P.Rpc, G(val(P.dP)), X.a, phi, P.ply_c, P.ply_s);
+    G raw;
+    {
+        StageMark<G> mark(kStageShadow);
+        G phi = atan2_(X.ph.n2x * X.wi_g.y - X.ph.n2y * X.wi_g.x, X.ph.n2x * X.wi_g.x + X.ph.n2y * X.wi_g.y);
+        raw = ply_shadow_raw<G, MP>(P.Np, P.rp, P.Rpc, G(val(P.dP)), X.a, phi, P.ply_c, P.ply_s);
+    }
     X.rawp = raw;
     X.rawf = gft;
     X.Gp = Narrow<S>::from(G(1) - G(val(P.rho_p)) * (G(1) - raw));
@@ -558,6 +607,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
     r.fy.b = cross(r.fy.n, r.fy.t);
     r.y = mk3<G>(ph.p2x, ph.p2y, ph.vhit);
     if (val(X.mu_i) > 0.0f) {
+        StageMark<G> mark(kStageRefract);
         const double phig = 0.61803398874989484820;
         double a1 = (k + 0.5) / P.K, a2 = (k + 0.5) * phig;
         if (has_shift) {
@@ -586,6 +636,7 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
         }
         r.T = fresnel_T<S>(cs, P.eta) * g1t;
         // chord in the projected cross-section, starting at the ply hit
+        StageMark<G> chord_mark(kStageChord);
         G le2 = wt.x * wt.x + wt.y * wt.y;
         G il = val(le2) > 0.0 ? rsqrt_(le2) : G(0);
         G le = le2 * il;
@@ -657,6 +708,7 @@ template <class G, class S>
 __host__ __device__ inline void exit_btdf(const Derived<G, S>& P, const V3<G>& wt, const Frame<G>& fy,
                                           const V3<G>& wo, S* val_out, S* pdf_out)
 {
+    StageMark<G> mark(kStageExit);
     *val_out = S(0);
     *pdf_out = S(0);
     V3<G> wip = -wt;
@@ -718,6 +770,7 @@ template <class G, class S, int MP>
 __host__ __device__ inline void lobes_at_x(const Derived<G, S>& P, const XState<G, S, MP>& X,
                                            const V3<G>& wo_g, LobeAcc<S>& a)
 {
+    StageMark<G> mark(kStageHalfX);
     S mu_i = X.mu_i;
     G mu_o_g = dot(wo_g, X.fx.n);
     S mu_o = Narrow<S>::from(mu_o_g);
@@ -980,6 +1033,7 @@ __host__ __device__ inline bool sample_dir(const Derived<G, S>& P, const XState<
                                            const Node<G, S>& nd, float xi1, float xi2, SampleOut<S>& so,
                                            V3<G>& wo)
 {
+    StageMark<G> mark(kStageSample);
     bool ok = false;
     wo = mk3<G>(G(0), G(0), G(0));
     const bool fwd = lobe == 1 || lobe == 3;

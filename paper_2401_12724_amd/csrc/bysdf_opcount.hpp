@@ -67,25 +67,6 @@ template <> struct Narrow<CF> {
     static CF from(double x) { return mkc<float, 1>((float)x); }
 };
 
-inline Derived<CD, CF> derive_counted(const TypeRec& t)
-{
-    Derived<double, float> f = derive(t);
-    Derived<CD, CF> d;
-    d.Np = f.Np; d.K = f.K; d.N_it = f.N_it; d.Nu = f.Nu; d.inv_np = f.inv_np;
-    d.rp = f.rp; d.Rpc = f.Rpc; d.slope = f.slope; d.wp_turns = f.wp_turns;
-    d.tnorm_inv = f.tnorm_inv; d.vply_scale = f.vply_scale; d.wf_turns = f.wf_turns;
-    d.tan_af = f.tan_af; d.ax_g = f.ax_g; d.ay_g = f.ay_g; d.eta_g = f.eta_g;
-    d.inv_eta_g = f.inv_eta_g;
-    d.ax = f.ax; d.ay = f.ay; d.eta = f.eta; d.kS = f.kS; d.B = f.B; d.r = f.r;
-    d.sigma_t = f.sigma_t; d.rho_p = f.rho_p; d.rho_f = f.rho_f; d.dP = f.dP;
-    for (int c = 0; c < 3; ++c) d.alb[c] = f.alb[c];
-    d.rp_s = f.rp_s; d.Rpc_s = f.Rpc_s;
-    d.n_mig = f.n_mig; d.mig_seed = f.mig_seed; d.mig_period = f.mig_period; d.mig_blend = f.mig_blend;
-    for (int k = 0; k < kMaxPlies; ++k) {
-        d.ply_c[k] = f.ply_c[k];
-        d.ply_s[k] = f.ply_s[k];
-    }
-    return d;
-}
+inline Derived<CD, CF> derive_counted(const TypeRec& t) { return rebind<CD, CF>(derive(t)); }
 
 }  // namespace bysdf

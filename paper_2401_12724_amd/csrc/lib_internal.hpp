@@ -2,6 +2,8 @@
 // libbysdf (hidden from the C ABI).
 #pragma once
 
+#include <cstring>
+
 #include "../../include/bysdf.h"
 #include "bysdf_model.hpp"
 #include "yarn_tube.hpp"
@@ -15,6 +17,41 @@ template <bool MIG> struct TabPtrT {
     __host__ __device__ float4 operator()(int i) const { return p[i]; }
 };
 using TabPtr = TabPtrT<true>;
+
+// The device record of one type: its parameters and the derived scalars.
+inline bysdf::TypeRec bysdf_make_rec(const bysdf_type_params& p)
+{
+    bysdf::TypeRec t;
+    memset(&t, 0, sizeof(t));
+    t.n_plies = p.n_plies;
+    t.K = p.K;
+    t.n_iter = p.n_iter;
+    t.tex_size = p.tex_size;
+    t.rp = p.ply_radius;
+    t.Rpc = p.ply_center_radius;
+    t.ply_twist = p.ply_twist;
+    t.fiber_twist = p.fiber_twist;
+    t.rho_f_geom = p.fiber_radius;
+    t.beta = p.beta;
+    t.aniso = p.aniso;
+    t.eta = p.eta;
+    for (int c = 0; c < 3; ++c) t.albedo[c] = p.albedo[c];
+    t.k_spec = p.k_spec;
+    t.B = p.B;
+    t.r = p.r;
+    t.sigma_t = p.sigma_t;
+    t.ply_density = p.ply_density;
+    t.fiber_density = p.fiber_density;
+    t.shadow_hw = p.shadow_halfwidth;
+    t.mig_tables = p.mig_tables > 1 ? p.mig_tables : 1;
+    t.mig_seed = p.mig_seed;
+    t.mig_period = p.mig_tables > 1 ? p.mig_period : 1.0;
+    t.mig_blend = p.mig_blend;
+    t.mig_spread = p.mig_spread;
+    t.table_texels = t.mig_tables * p.tex_size;
+    bysdf::fill_derived(t);
+    return t;
+}
 
 // record a thread-local error message and return `code`
 int bysdf_set_error(int code, const char* msg);
