@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_MIN_WAVES) void k_eval(const Typ
                 if (!(X.mu_i > 0.0f)) fl |= F_BACKFACING;
                 float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
                 V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
-                lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
+                lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e, types[tu].node_disk);
             }
         });
         o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_SAMPLE_MIN_WAVES) void k_sample(const
             TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + types[tu].table_off;
             fl = sample_query<double, float, MP>(P, tab, h, u, v, wi, x0, x1, x2, s0, s1,
-                                                 q.s0 != nullptr, so);
+                                                 q.s0 != nullptr, so, types[tu].node_disk);
         });
         o.wox[i] = so.wo[0]; o.woy[i] = so.wo[1]; o.woz[i] = so.wo[2];
         o.wr[i] = so.wgt[0]; o.wg[i] = so.wgt[1]; o.wb[i] = so.wgt[2];
@@ -443,7 +443,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_EVAL_SAMPLE_MIN_WAVES) void k_eval_sa
             XState<double, float, MP> X;
             state_at_x(P, tab, h, u, v, wi, X);
             float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
-            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{P, tab, X, s0, s1, q.s0 != nullptr};
+            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{P, tab, X, s0, s1, q.s0 != nullptr,
+                                                               types[tu].node_disk};
             V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
             fs = eval_sample_from_x(P, X, wi, wo_g, bad_wo == 0u, x0, x1, x2, nf, e, so);
             if (bad_wo == 0u) {
@@ -915,7 +916,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
                 const float s0 = q.s0 ? q.s0[io] : 0.0f, s1 = q.s1 ? q.s1[io] : 0.0f;
                 const V3<double> wo_g = mk3<double>(q.wox[io], q.woy[io], q.woz[io]);
                 EvalOut<float> e;
-                lobes(Pm, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
+                lobes(Pm, tab, X, wo_g, s0, s1, q.s0 != nullptr, e, R.node_disk);
                 w_it = float(stratum_w(fo, (double)hj));
                 ev[0] = e.E[0]; ev[1] = e.E[1]; ev[2] = e.E[2];
                 ev[3] = e.ExS; ev[4] = e.EyS;
@@ -1065,7 +1066,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             pass = X.ph.pass;
             if (pass) return;
             if (!single) apply_aggregate(Pm, X, F, Gm);
-            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
+            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr,
+                                                               R.node_disk};
             fl |= sample_draw(Pm, X, m.wi, x0, x1, x2, nf, so, wo, drawn);
         });
         if (pass) {
@@ -1113,7 +1115,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
                 if (!single_o) apply_aggregate(Pm, X, Fo, Go);
                 const float t0 = q.s0 ? q.s0[io] : 0.0f, t1 = q.s1 ? q.s1[io] : 0.0f;
                 EvalOut<float> e;
-                lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e);
+                lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e, R.node_disk);
                 w_it = float(stratum_w(fo, (double)hj));
                 ev[0] = e.E[0]; ev[1] = e.E[1]; ev[2] = e.E[2]; ev[3] = e.pdf;
             });
@@ -1617,7 +1619,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_eval_batched(
                     if (!(X.mu_i > 0.0f)) fl |= F_BACKFACING;
                     const float s0 = q.s0 ? q.s0[i] : 0.0f, s1 = q.s1 ? q.s1[i] : 0.0f;
                     V3<double> wo_g = mk3<double>(wo.x, wo.y, wo.z);
-                    lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
+                    lobes(P, tab, X, wo_g, s0, s1, q.s0 != nullptr, e, rec.node_disk);
                 }
             }
             o.Er[i] = e.E[0]; o.Eg[i] = e.E[1]; o.Eb[i] = e.E[2];
@@ -2072,19 +2074,19 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
             if (X.ph.pass) continue;
             V3<CD> b = mk3<CD>(CD((double)wo[i]), CD((double)wo[n + i]), CD((double)wo[2 * n + i]));
             EvalOut<CF> e;
-            lobes(P, tab, X, b, 0.0f, 0.0f, false, e);
+            lobes(P, tab, X, b, 0.0f, 0.0f, false, e, rec.node_disk);
         } else if (mode == 2) {
             XState<CD, CF, kMaxPlies> X;
             state_at_x(P, tab, h[i], u[i], v[i], a, X);
             V3<CD> b = mk3<CD>(CD((double)wo[i]), CD((double)wo[n + i]), CD((double)wo[2 * n + i]));
-            NodesComputed<CD, CF, kMaxPlies, HostTab> nf{P, tab, X, 0.0f, 0.0f, false};
+            NodesComputed<CD, CF, kMaxPlies, HostTab> nf{P, tab, X, 0.0f, 0.0f, false, rec.node_disk};
             EvalOut<CF> e;
             SampleOut<CF> so;
             eval_sample_from_x(P, X, a, b, true, xi[i], xi[n + i], xi[2 * n + i], nf, e, so);
         } else {
             SampleOut<CF> so;
             sample_query<CD, CF, kMaxPlies>(P, tab, h[i], u[i], v[i], a, xi[i], xi[n + i],
-                                            xi[2 * n + i], 0.0f, 0.0f, false, so);
+                                            xi[2 * n + i], 0.0f, 0.0f, false, so, rec.node_disk);
         }
     }
     g_tally = nullptr;

@@ -80,6 +80,10 @@ struct TypeRec {
     uint32_t mig_seed;
     double mig_period, mig_blend, mig_spread;
     Derived<double, float> d;
+    // disk points (d1, d2) of the visible-normal samples of the K forward
+    // nodes without a lattice shift: they depend on K alone, so they are
+    // formed once at creation and read with scalar loads
+    double node_disk[2 * kMaxNodes];
 };
 
 // Fill the derived scalars of a record (host at creation, device when the
@@ -218,18 +222,23 @@ template <class G> __host__ __device__ inline G one_minus_sq(const G& z) { retur
 // roughness, build a basis around it, sample the projected hemisphere disc
 // with its far half compressed according to the view elevation, lift,
 // unstretch.  w local with w.z > 0; u1, u2 in [0, 1).
-template <class T> __host__ __device__ inline V3<T> sample_vndf(const V3<T>& w, T ax, T ay, T u1, T u2)
+// The uniform point (d1, d2) of the unit disc for the uniforms u1, u2.
+template <class T> __host__ __device__ inline void vndf_disk(T u1, T u2, T& d1, T& d2)
+{
+    T rad = sqrt_(u1);
+    T su, cu;
+    sincos_turns_g(u2, &su, &cu);
+    d1 = rad * cu;
+    d2 = rad * su;
+}
+// The visible normal for the disc point (d1, d2).
+template <class T> __host__ __device__ inline V3<T> sample_vndf_disk(const V3<T>& w, T ax, T ay, T d1, T d2)
 {
     V3<T> vh = normalize(mk3<T>(ax * w.x, ay * w.y, w.z));
     T l2 = vh.x * vh.x + vh.y * vh.y;
     V3<T> b1 = val(l2) > 0.0 ? mk3<T>(-vh.y, vh.x, T(0)) * rsqrt_(l2)
                              : mk3<T>(T(1), T(0), T(0));
     V3<T> b2 = cross(vh, b1);
-    T rad = sqrt_(u1);
-    T su, cu;
-    sincos_turns_g(u2, &su, &cu);
-    T d1 = rad * cu;
-    T d2 = rad * su;
     T blend = T(0.5) * (T(1) + vh.z);
     d2 = (T(1) - blend) * sqrt_(T(1) - d1 * d1) + blend * d2;
     T h2 = T(1) - d1 * d1 - d2 * d2;
@@ -237,6 +246,12 @@ template <class T> __host__ __device__ inline V3<T> sample_vndf(const V3<T>& w, 
     V3<T> nh = b1 * d1 + b2 * d2 + vh * hz;
     T nz = val(nh.z) > 0.0 ? nh.z : T(0);
     return normalize(mk3<T>(ax * nh.x, ay * nh.y, nz));
+}
+template <class T> __host__ __device__ inline V3<T> sample_vndf(const V3<T>& w, T ax, T ay, T u1, T u2)
+{
+    T d1, d2;
+    vndf_disk(u1, u2, d1, d2);
+    return sample_vndf_disk(w, ax, ay, d1, d2);
 }
 
 // Lommel-Seeliger single-scatter albedo 1/2 [1 - mu ln(1 + 1/mu)].
@@ -576,6 +591,37 @@ __host__ __device__ inline void state_at_x(const Derived<G, S>& P, const Tab& ta
 
 // ---------------------------------------------------------------- forward nodes
 
+// Point k of the rank-1 lattice of the forward-node integral (Eq. 1):
+// ((k + 1/2) / K, (k + 1/2) (sqrt 5 - 1) / 2) modulo 1, shifted by (s0, s1)
+// when the query carries a shift.
+__host__ __device__ inline void node_lattice(int k, int K, float s0, float s1, bool has_shift, double& xi1,
+                                             double& xi2)
+{
+    const double phig = 0.61803398874989484820;
+    double a1 = (k + 0.5) / K, a2 = (k + 0.5) * phig;
+    if (has_shift) {
+        a1 += s0;
+        a2 += s1;
+    }
+    xi1 = a1 - floor(a1);
+    xi2 = a2 - floor(a2);
+}
+
+// The unshifted nodes' disc points of a record (host, at creation).
+inline void fill_node_disk(TypeRec& t)
+{
+    for (int k = 0; k < kMaxNodes; ++k) {
+        double d1 = 0.0, d2 = 0.0;
+        if (k < t.K) {
+            double xi1, xi2;
+            node_lattice(k, t.K, 0.0f, 0.0f, false, xi1, xi2);
+            vndf_disk<double>(xi1, xi2, d1, d2);
+        }
+        t.node_disk[2 * k] = d1;
+        t.node_disk[2 * k + 1] = d2;
+    }
+}
+
 template <class G, class S> struct Node {
     S T, att;        // refraction weight at x, tau^N
     V3<G> wt;        // refracted direction
@@ -590,7 +636,8 @@ template <class G, class S> struct Node {
 template <class G, class S, int MP, class Tab>
 __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& tab,
                                              const XState<G, S, MP>& X, int k, float s0, float s1,
-                                             bool has_shift, Node<G, S>& nd)
+                                             bool has_shift, Node<G, S>& nd,
+                                             const double* disk = nullptr)
 {
     // The node is assembled in a local and stored once: partial stores on
     // several return paths get merged by the optimiser into stores through a
@@ -608,15 +655,17 @@ __host__ __device__ inline void forward_node(const Derived<G, S>& P, const Tab& 
     r.y = mk3<G>(ph.p2x, ph.p2y, ph.vhit);
     if (val(X.mu_i) > 0.0f) {
         StageMark<G> mark(kStageRefract);
-        const double phig = 0.61803398874989484820;
-        double a1 = (k + 0.5) / P.K, a2 = (k + 0.5) * phig;
-        if (has_shift) {
-            a1 += s0;
-            a2 += s1;
-        }
-        double xi1 = a1 - floor(a1), xi2 = a2 - floor(a2);
         V3<G> wl = to_local(X.fx, X.wi_g);
-        V3<G> ml = sample_vndf<G>(wl, P.ax_g, P.ay_g, G(xi1), G(xi2));
+        G d1, d2;
+        if (disk && !has_shift) {
+            d1 = G(disk[2 * k]);
+            d2 = G(disk[2 * k + 1]);
+        } else {
+            double xi1, xi2;
+            node_lattice(k, P.K, s0, s1, has_shift, xi1, xi2);
+            vndf_disk<G>(G(xi1), G(xi2), d1, d2);
+        }
+        V3<G> ml = sample_vndf_disk<G>(wl, P.ax_g, P.ay_g, d1, d2);
         V3<G> m = to_world(X.fx, ml);
         G c = dot(X.wi_g, m);
         c = val(c) > 0.0 ? c : G(0);
@@ -928,15 +977,18 @@ __host__ __device__ inline void lobes_nodes2_dsigma(const Derived<G, S>& P, cons
 
 // node providers: compute node k from the state at x, or read it from an
 // array filled beforehand (hits shared by many directions)
+// disk: the record's node_disk (nullable: the disc points are then formed
+// per node)
 template <class G, class S, int MP, class Tab> struct NodesComputed {
     const Derived<G, S>& P;
     const Tab& tab;
     const XState<G, S, MP>& X;
     float s0, s1;
     bool has_shift;
+    const double* disk = nullptr;
     __host__ __device__ void operator()(int k, Node<G, S>& nd) const
     {
-        forward_node(P, tab, X, k, s0, s1, has_shift, nd);
+        forward_node(P, tab, X, k, s0, s1, has_shift, nd, disk);
     }
 };
 template <class G, class S> struct NodesStored {
@@ -947,9 +999,9 @@ template <class G, class S> struct NodesStored {
 template <class G, class S, int MP, class Tab>
 __host__ __device__ inline void lobes(const Derived<G, S>& P, const Tab& tab, const XState<G, S, MP>& X,
                                       const V3<G>& wo_g, float s0, float s1, bool has_shift,
-                                      EvalOut<S>& o)
+                                      EvalOut<S>& o, const double* disk = nullptr)
 {
-    NodesComputed<G, S, MP, Tab> nf{P, tab, X, s0, s1, has_shift};
+    NodesComputed<G, S, MP, Tab> nf{P, tab, X, s0, s1, has_shift, disk};
     lobes_nodes(P, X, wo_g, nf, o);
 }
 
@@ -1193,7 +1245,8 @@ template <class G, class S, int MP, class Tab>
 __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const Tab& tab, float h,
                                                  float u, float v, const V3<float>& wi, float xi0,
                                                  float xi1, float xi2, float s0, float s1,
-                                                 bool has_shift, SampleOut<S>& so)
+                                                 bool has_shift, SampleOut<S>& so,
+                                                 const double* disk = nullptr)
 {
     uint32_t bad = check_inputs(h, u, v, wi);
     if (bad) {
@@ -1207,7 +1260,7 @@ __host__ __device__ inline uint32_t sample_query(const Derived<G, S>& P, const T
     }
     XState<G, S, MP> X;
     state_at_x(P, tab, h, u, v, wi, X);
-    NodesComputed<G, S, MP, Tab> nf{P, tab, X, s0, s1, has_shift};
+    NodesComputed<G, S, MP, Tab> nf{P, tab, X, s0, s1, has_shift, disk};
     return sample_from_x(P, X, wi, xi0, xi1, xi2, nf, so);
 }
 

@@ -50,6 +50,7 @@ inline bysdf::TypeRec bysdf_make_rec(const bysdf_type_params& p)
     t.mig_spread = p.mig_spread;
     t.table_texels = t.mig_tables * p.tex_size;
     bysdf::fill_derived(t);
+    bysdf::fill_node_disk(t);
     return t;
 }
 
@@ -71,7 +72,11 @@ int yarn_scene_max_type(const yarn_scene_t* s);
 // Lanes of a wavefront are served one distinct type at a time (a wavefront
 // of one type -- sorted or per-block input -- takes a single pass): the
 // type index is made wavefront-uniform, so its record is read with scalar
-// loads and its scalars stay out of the vector registers.
+// loads and its scalars stay out of the vector registers.  The index handed
+// to the body goes through readfirstlane: inside the body the optimiser
+// knows it equals the lane's own index and would otherwise address the
+// record with that per-lane value, turning every parameter read into a
+// vector load.
 template <class F>
 __device__ inline void for_each_wave_type(int t, bool need, F&& body)
 {
@@ -82,7 +87,7 @@ __device__ inline void for_each_wave_type(int t, bool need, F&& body)
         // straight-line path: no value has to stay live around a loop
         const int t0 = __builtin_amdgcn_readlane(t, __ffsll((long long)pending) - 1);
         if (__ballot(need && t != t0) == 0ull) {
-            if (need) body(t0);
+            if (need) body(__builtin_amdgcn_readfirstlane(t0));
             return;
         }
     }
@@ -90,7 +95,7 @@ __device__ inline void for_each_wave_type(int t, bool need, F&& body)
         const int lead = __ffsll((long long)pending) - 1;
         const int tu = __builtin_amdgcn_readlane(t, lead);
         const bool mine = need && t == tu;
-        if (mine) body(tu);
+        if (mine) body(__builtin_amdgcn_readfirstlane(tu));
         pending &= ~__ballot(mine);
     }
 }

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kTraceBlock, RENDER_TRACE_MIN_WAVES) void k_r_exten
 template <int MP>
 __device__ inline void far_eval(const Derived<double, float>& P, const TabPtr& tab, float u, float v,
                                 const V3<float>& wi, const V3<float>& wo, int n_h, float zeta, double E[3],
-                                double* pdf)
+                                double* pdf, const double* disk)
 {
     E[0] = E[1] = E[2] = 0.0;
     *pdf = 0.0;
@@ -281,7 +281,7 @@ __device__ inline void far_eval(const Derived<double, float>& P, const TabPtr& t
         bysdf::state_at_x(P, tab, hj, u, v, wi, X);
         if (X.ph.pass) continue;
         EvalOut<float> e;
-        bysdf::lobes(P, tab, X, wo_g, 0.0f, 0.0f, false, e);
+        bysdf::lobes(P, tab, X, wo_g, 0.0f, 0.0f, false, e, disk);
         for (int c = 0; c < 3; ++c) E[c] += e.E[c];
         *pdf += e.pdf;
     }
@@ -423,7 +423,8 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             if (GRAD) {
                 XState<double, float, MP> X;
                 bysdf::state_at_x(P, tab, hq, uq, vl, wi, X);
-                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false};
+                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false,
+                                                            V.types[tu].node_disk};
                 V3<double> ws;
                 bool ok;
                 sf = bysdf::sample_draw(P, X, wi, u1[2], u1[3], u2[0], nf, so, ws, ok);
@@ -462,7 +463,8 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                 // and the forward nodes
                 XState<double, float, MP> X;
                 bysdf::state_at_x(P, tab, hq, uq, vl, wi, X);
-                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false};
+                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false,
+                                                            V.types[tu].node_disk};
                 EvalOut<float> e;
                 for (int c = 0; c < 3; ++c) e.E[c] = 0.0f;
                 e.pdf = 0.0f;
@@ -473,13 +475,15 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                     pb = e.pdf;
                 }
             } else {
-                if (cosl > 0.0) far_eval<MP>(P, tab, uq, vl, wi, wol, V.n_h, u2[2], En, &pb);
+                if (cosl > 0.0)
+                    far_eval<MP>(P, tab, uq, vl, wi, wol, V.n_h, u2[2], En, &pb, V.types[tu].node_disk);
                 int js = (int)floorf(u2[1] * V.n_h);
                 js = js > V.n_h - 1 ? V.n_h - 1 : js;
                 float hs = (float)(-1.0 + 2.0 * (js + (double)u2[2]) / V.n_h);
                 XState<double, float, MP> X;
                 bysdf::state_at_x(P, tab, hs, uq, vl, wi, X);
-                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false};
+                NodesComputed<double, float, MP, TabPtr> nf{P, tab, X, 0.0f, 0.0f, false,
+                                                            V.types[tu].node_disk};
                 sf = bysdf::sample_from_x(P, X, wi, u1[2], u1[3], u2[0], nf, so);
             }
             if (depth == V.max_depth) return;
@@ -493,7 +497,7 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                 bool ok = true;
                 if (far) {
                     double E[3];
-                    far_eval<MP>(P, tab, uq, vl, wi, wo, V.n_h, u2[2], E, &pdf);
+                    far_eval<MP>(P, tab, uq, vl, wi, wo, V.n_h, u2[2], E, &pdf, V.types[tu].node_disk);
                     ok = pdf > 0.0;
                     for (int c = 0; c < 3; ++c) wgt[c] = ok ? (float)(E[c] / pdf) : 0.0f;
                 } else {
