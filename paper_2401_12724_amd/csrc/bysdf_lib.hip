@@ -569,7 +569,7 @@ __device__ inline void wave_footprint_geometry(const TypeRec* __restrict__ types
         double w_it = 0.0, g_it = 0.0;
         V3<double> n_it = mk3<double>(0.0, 0.0, 0.0), t_it = n_it;
         uint32_t f_it = 0;
-        for_each_wave_type(to, item, [&](int tu) {
+        for_each_wave_type<false>(to, item, [&](int tu) {
             const TypeRec& R = types[tu];
             TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + R.table_off;
@@ -737,7 +737,7 @@ __device__ inline void wave_geometry_q(const TypeRec* __restrict__ types, const 
         double w_it = 0.0, g_it = 0.0;
         V3<double> n_it = mk3<double>(0.0, 0.0, 0.0), t_it = n_it;
         uint32_t f_it = 0;
-        for_each_wave_type(to, item, [&](int tu) {
+        for_each_wave_type<false>(to, item, [&](int tu) {
             const TypeRec& R = types[tu];
             TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + R.table_off;
@@ -896,7 +896,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
             float w_it = 0.0f;
             int back = 0, hit_it = 0;
             uint32_t f_it = 0;
-            for_each_wave_type(to, item, [&](int tu) {
+            for_each_wave_type<false>(to, item, [&](int tu) {
                 const TypeRec& R = types[tu];
                 TabPtrT<MIG> tab;
                 tab.p = kLds ? s_tab : tables + R.table_off;
@@ -916,7 +916,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
                 const float s0 = q.s0 ? q.s0[io] : 0.0f, s1 = q.s1 ? q.s1[io] : 0.0f;
                 const V3<double> wo_g = mk3<double>(q.wox[io], q.woy[io], q.woz[io]);
                 EvalOut<float> e;
-                lobes(Pm, tab, X, wo_g, s0, s1, q.s0 != nullptr, e, R.node_disk);
+                lobes(Pm, tab, X, wo_g, s0, s1, q.s0 != nullptr, e);
                 w_it = float(stratum_w(fo, (double)hj));
                 ev[0] = e.E[0]; ev[1] = e.E[1]; ev[2] = e.E[2];
                 ev[3] = e.ExS; ev[4] = e.EyS;
@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
         V3<double> wo = mk3<double>(0.0, 0.0, 0.0);
         bool drawn = false, pass = good && !any && !single;
         const float s0 = in && q.s0 ? q.s0[i] : 0.0f, s1 = in && q.s1 ? q.s1[i] : 0.0f;
-        for_each_wave_type(t, good && (any || single), [&](int tu) {
+        for_each_wave_type<false>(t, good && (any || single), [&](int tu) {
             const TypeRec& R = types[tu];
             TabPtrT<MIG> tab;
             tab.p = kLds ? s_tab : tables + R.table_off;
@@ -1066,8 +1066,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             pass = X.ph.pass;
             if (pass) return;
             if (!single) apply_aggregate(Pm, X, F, Gm);
-            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr,
-                                                               R.node_disk};
+            NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
             fl |= sample_draw(Pm, X, m.wi, x0, x1, x2, nf, so, wo, drawn);
         });
         if (pass) {
@@ -1099,7 +1098,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             const V3<double> wd = shfl3(wo, own);
             float ev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             float w_it = 0.0f;
-            for_each_wave_type(to, item, [&](int tu) {
+            for_each_wave_type<false>(to, item, [&](int tu) {
                 const TypeRec& R = types[tu];
                 TabPtrT<MIG> tab;
                 tab.p = kLds ? s_tab : tables + R.table_off;
@@ -1115,7 +1114,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
                 if (!single_o) apply_aggregate(Pm, X, Fo, Go);
                 const float t0 = q.s0 ? q.s0[io] : 0.0f, t1 = q.s1 ? q.s1[io] : 0.0f;
                 EvalOut<float> e;
-                lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e, R.node_disk);
+                lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e);
                 w_it = float(stratum_w(fo, (double)hj));
                 ev[0] = e.E[0]; ev[1] = e.E[1]; ev[2] = e.E[2]; ev[3] = e.pdf;
             });

@@ -76,8 +76,10 @@ int yarn_scene_max_type(const yarn_scene_t* s);
 // to the body goes through readfirstlane: inside the body the optimiser
 // knows it equals the lane's own index and would otherwise address the
 // record with that per-lane value, turning every parameter read into a
-// vector load.
-template <class F>
+// vector load.  kScalar = false hands over the index unchanged: the
+// multi-scale kernels copy the record into a per-footprint variant, and
+// there the vector loads measured faster.
+template <bool kScalar = true, class F>
 __device__ inline void for_each_wave_type(int t, bool need, F&& body)
 {
     unsigned long long pending = __ballot(need);
@@ -87,7 +89,7 @@ __device__ inline void for_each_wave_type(int t, bool need, F&& body)
         // straight-line path: no value has to stay live around a loop
         const int t0 = __builtin_amdgcn_readlane(t, __ffsll((long long)pending) - 1);
         if (__ballot(need && t != t0) == 0ull) {
-            if (need) body(__builtin_amdgcn_readfirstlane(t0));
+            if (need) body(kScalar ? __builtin_amdgcn_readfirstlane(t0) : t0);
             return;
         }
     }
@@ -95,7 +97,7 @@ __device__ inline void for_each_wave_type(int t, bool need, F&& body)
         const int lead = __ffsll((long long)pending) - 1;
         const int tu = __builtin_amdgcn_readlane(t, lead);
         const bool mine = need && t == tu;
-        if (mine) body(__builtin_amdgcn_readfirstlane(tu));
+        if (mine) body(kScalar ? __builtin_amdgcn_readfirstlane(tu) : tu);
         pending &= ~__ballot(mine);
     }
 }
