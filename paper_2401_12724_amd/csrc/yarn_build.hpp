@@ -1,6 +1,7 @@
 // yarn_build.hpp -- host side of a yarn scene build (see yarn_scene.hip):
 // validation, per-span records, rotation-minimising frames and arc lengths,
-// the binned-SAH BVH, spans in leaf order.  No device call; the library
+// the binned-SAH BVH collapsed to four children per node, spans in leaf
+// order.  No device call; the library
 // uploads the result.
 #pragma once
 
@@ -32,7 +33,7 @@ struct HostScene {
     std::vector<float4> cp;
     std::vector<SpanRec> span;
     std::vector<float4> frame;
-    std::vector<BNode> node;
+    std::vector<WNode> node;  // the 4-wide tree
     std::vector<float> phase;
     std::vector<int> type;
     int depth = 0;
@@ -227,6 +228,89 @@ struct Builder {
     }
 };
 
+// Collapse of the binary tree to four children per node: a node takes its
+// binary children and, while it has fewer than four, replaces the internal
+// child with the largest box surface by that child's two children.  Leaf
+// codes are kept; node codes are renumbered in the wide array (root 0).
+struct Collapse {
+    const std::vector<BNode>& bin;
+    std::vector<WNode> wide;
+    int max_depth = 0;
+    struct Child {
+        float lo[3], hi[3];
+        int code;
+    };
+
+    explicit Collapse(const std::vector<BNode>& b) : bin(b) {}
+
+    static void children(const BNode& n, Child* c)
+    {
+        const float v[12] = {n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w};
+        for (int k = 0; k < 2; ++k) {
+            for (int q = 0; q < 3; ++q) {
+                c[k].lo[q] = v[6 * k + q];
+                c[k].hi[q] = v[6 * k + 3 + q];
+            }
+        }
+        c[0].code = n.d.x;
+        c[1].code = n.d.y;
+    }
+    static float area(const Child& c)
+    {
+        float dx = std::max(0.f, c.hi[0] - c.lo[0]), dy = std::max(0.f, c.hi[1] - c.lo[1]),
+              dz = std::max(0.f, c.hi[2] - c.lo[2]);
+        return 2.f * (dx * dy + dy * dz + dz * dx);
+    }
+
+    int run(int bcode, int depth)
+    {
+        max_depth = std::max(max_depth, depth);
+        Child ch[4];
+        children(bin[bcode], ch);
+        int nch = 2;
+        while (nch < 4) {
+            int pick = -1;
+            float best = -1.f;
+            for (int k = 0; k < nch; ++k)
+                if (ch[k].code >= 0 && area(ch[k]) > best) {
+                    best = area(ch[k]);
+                    pick = k;
+                }
+            if (pick < 0) break;
+            Child two[2];
+            children(bin[ch[pick].code], two);
+            ch[pick] = two[0];
+            ch[nch++] = two[1];
+        }
+        const int self = (int)wide.size();
+        wide.push_back(WNode{});
+        int code[4];
+        for (int k = 0; k < nch; ++k) code[k] = ch[k].code >= 0 ? run(ch[k].code, depth + 1) : ch[k].code;
+        WNode& w = wide[self];
+        float lo[3][4], hi[3][4];
+        int cw[4];
+        for (int k = 0; k < 4; ++k) {
+            // an unused slot, or a slot with an inverted box, is never entered
+            bool empty = k >= nch;
+            for (int q = 0; q < 3 && !empty; ++q) empty = !(ch[k].lo[q] <= ch[k].hi[q]);
+            for (int q = 0; q < 3; ++q) {
+                lo[q][k] = empty ? INFINITY : ch[k].lo[q];
+                hi[q][k] = empty ? INFINITY : ch[k].hi[q];
+            }
+            cw[k] = empty ? 0 : code[k];
+        }
+        w.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+        w.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+        w.loz = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+        w.hix = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+        w.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+        w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+        w.code = make_int4(cw[0], cw[1], cw[2], cw[3]);
+        w.pad = make_int4(0, 0, 0, 0);
+        return self;
+    }
+};
+
 }  // namespace detail
 
 using namespace detail;
@@ -351,8 +435,14 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
         if (yarn_type) type[y] = yarn_type[y];
     }
 
-    hs->node = std::move(B.nodes);
-    hs->depth = B.max_depth;
+    Collapse W(B.nodes);
+    W.wide.reserve(B.nodes.size() / 2 + 1);
+    W.run(0, 0);
+    if (W.max_depth > kWideDepthMax)
+        return build_fail(err, BYSDF_ERR_INVALID_PARAM, "4-wide BVH depth %d exceeds %d", W.max_depth,
+                          kWideDepthMax);
+    hs->node = std::move(W.wide);
+    hs->depth = W.max_depth;
     hs->n_yarns = n_yarns;
     return 0;
 }

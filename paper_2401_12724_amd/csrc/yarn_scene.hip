@@ -5,11 +5,11 @@
 // frame at its start (double reflection, 16 steps per span) and the arc
 // length from the yarn start (5-point Gauss-Legendre per span); a binned
 // SAH BVH over the span boxes (control-point hull grown by R), with object
-// median splits below depth 40 so the depth stays within the traversal
-// stack.  Spans are stored in leaf order next to their records.
+// median splits below depth 40, collapsed to four children per node.
+// Spans are stored in leaf order next to their records.
 //
 // Kernel k_intersect: one ray per lane, 128-lane workgroups, an LDS stack
-// per lane ([entry][lane], no bank conflicts) of depth + 1 entries.  A point query
+// per lane ([entry][lane], no bank conflicts) of 3 (depth + 1) entries.  A point query
 // first collects the yarns whose tube holds the origin, then the closest
 // entering hit is searched; hit frame, h and v are formed for the winner.
 #include <hip/hip_runtime.h>
@@ -57,7 +57,7 @@ struct yarn_scene {
     float4* d_cp = nullptr;
     SpanRec* d_span = nullptr;
     float4* d_frame = nullptr;
-    BNode* d_node = nullptr;
+    WNode* d_node = nullptr;
     float* d_phase = nullptr;
     int* d_type = nullptr;
     size_t bytes = 0;
@@ -135,7 +135,7 @@ extern "C" int yarn_scene_create(const float* ctrl, const int64_t* off, int32_t 
     std::vector<float>& phase = hs.phase;
     std::vector<int>& type = hs.type;
     struct {
-        std::vector<BNode>& nodes;
+        std::vector<WNode>& nodes;
         int max_depth;
     } B{hs.node, hs.depth};
     yarn_scene* s = new yarn_scene();
@@ -157,7 +157,7 @@ extern "C" int yarn_scene_create(const float* ctrl, const int64_t* off, int32_t 
     if ((rc = up((void**)&s->d_cp, cp.data(), sizeof(float4) * n_cp)) ||
         (rc = up((void**)&s->d_span, rec_o.data(), sizeof(SpanRec) * n_spans)) ||
         (rc = up((void**)&s->d_frame, frame_o.data(), sizeof(float4) * n_spans)) ||
-        (rc = up((void**)&s->d_node, B.nodes.data(), sizeof(BNode) * B.nodes.size())) ||
+        (rc = up((void**)&s->d_node, B.nodes.data(), sizeof(WNode) * B.nodes.size())) ||
         (rc = up((void**)&s->d_phase, phase.data(), sizeof(float) * n_yarns)) ||
         (rc = up((void**)&s->d_type, type.data(), sizeof(int) * n_yarns))) {
         (void)hipStreamSynchronize(stream);

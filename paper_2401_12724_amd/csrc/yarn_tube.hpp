@@ -10,8 +10,11 @@
 // sampled at a few points, the best sample is bracketed and polished by
 // safeguarded Newton on dT/ds in double precision.
 //
-// The BVH is binary; a node holds both child boxes (64 bytes), children
-// are visited near first, and the per-thread stack lives in LDS.
+// The BVH is built binary (binned SAH) and collapsed to four children per
+// node: a node holds its four child boxes as structure of arrays and the
+// child codes in one 128-byte line, so a ray fetches half as many nodes
+// one after another as in the binary tree.  Hit children are visited near
+// first, and the per-thread stack lives in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,13 +26,14 @@
 
 namespace yarn {
 
-constexpr int kStack = 64;        // BVH depth bound enforced by the builder
-// Entries of a lane's traversal stack for a BVH of the given depth: a push
-// happens at most once per level above the current node, so depth + 1
-// entries never overflow.  The traversal kernels size their LDS stacks
-// with this at launch, which leaves LDS for more wavefronts per CU on
-// shallow trees.
-inline int stack_entries(int depth) { return depth + 1; }
+constexpr int kStack = 64;        // binary BVH depth bound enforced by the builder
+constexpr int kWideDepthMax = 40; // depth bound of the 4-wide tree (LDS stack: 123 entries)
+// Entries of a lane's traversal stack for a 4-wide BVH whose deepest node
+// sits at the given depth (root 0): a visit pushes at most three siblings,
+// and a path holds depth + 1 nodes, so 3 (depth + 1) entries never
+// overflow.  The traversal kernels size their LDS stacks with this at
+// launch, which leaves LDS for more wavefronts per CU on shallow trees.
+inline int stack_entries(int depth) { return 3 * (depth + 1); }
 constexpr int kMaxExcluded = 4;   // yarns holding the ray origin
 constexpr double kExcludeFrac = 1e-3;
 
@@ -39,9 +43,18 @@ constexpr uint32_t HIT_CAP = 1u << 1;
 constexpr uint32_t HIT_EXCLUDED = 1u << 2;
 constexpr uint32_t HIT_BAD_INPUT = 1u << 9;
 
+// binary node of the build: child boxes lo0 hi0 lo1 hi1 packed, child codes
+// (>= 0 node, < 0 leaf: -(first*4 + count-1) - 1)
 struct BNode {
-    float4 a, b, c;  // child boxes: lo0 hi0 lo1 hi1 packed
-    int4 d;          // child codes: >= 0 node, < 0 leaf (-(first*4 + count-1) - 1)
+    float4 a, b, c;
+    int4 d;
+};
+// node of the traversed 4-wide tree: bounds of child c in component c of
+// each float4; an unused slot has an empty box (lo +inf, hi -inf)
+struct WNode {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    int4 code;  // child codes as above (node codes index the wide nodes)
+    int4 pad;   // to 128 bytes
 };
 
 // span record (leaf order): first control point, yarn, index in the
@@ -54,7 +67,7 @@ struct SceneView {
     const float4* cp;       // x y z R per control point
     const SpanRec* span;    // leaf order
     const float4* frame;    // per span (leaf order): RMF normal at s = 0, arc length at s = 0
-    const BNode* node;
+    const WNode* node;
     const float* yarn_phase;
     const int* yarn_type;
     int n_nodes;
@@ -381,12 +394,14 @@ __host__ __device__ inline void decode_leaf(int code, int* first, int* count)
     *count = (c & 3) + 1;
 }
 
-__host__ __device__ inline void child_boxes(const BNode& n, float3* lo0, float3* hi0, float3* lo1, float3* hi1)
+// box of child c (0..3) of a wide node
+__host__ __device__ inline float comp4(const float4& v, int c)
 {
-    *lo0 = make_float3(n.a.x, n.a.y, n.a.z);
-    *hi0 = make_float3(n.a.w, n.b.x, n.b.y);
-    *lo1 = make_float3(n.b.z, n.b.w, n.c.x);
-    *hi1 = make_float3(n.c.y, n.c.z, n.c.w);
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+__host__ __device__ inline int comp4i(const int4& v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
 
 __host__ __device__ inline bool box_ray(float3 lo, float3 hi, float3 o, float3 inv, float t0, float t1, float* tn)
@@ -419,25 +434,25 @@ __host__ __device__ inline int excluded_yarns(const SceneView& S, D3 o, int* stk
     if (skip >= 0) ex[nex++] = skip;
     while (true) {
         if (code >= 0) {
-            BNode n = S.node[code];
-            float3 lo0, hi0, lo1, hi1;
-            child_boxes(n, &lo0, &hi0, &lo1, &hi1);
+            const WNode n = S.node[code];
             // the float origin may sit a rounding step outside a box that
             // holds the double origin: grow the test box by a relative ulp
             float3 e = make_float3(fabsf(of.x) * 2.4e-7f + 1e-30f, fabsf(of.y) * 2.4e-7f + 1e-30f,
                                    fabsf(of.z) * 2.4e-7f + 1e-30f);
-            lo0 = make_float3(lo0.x - e.x, lo0.y - e.y, lo0.z - e.z);
-            hi0 = make_float3(hi0.x + e.x, hi0.y + e.y, hi0.z + e.z);
-            lo1 = make_float3(lo1.x - e.x, lo1.y - e.y, lo1.z - e.z);
-            hi1 = make_float3(hi1.x + e.x, hi1.y + e.y, hi1.z + e.z);
-            bool h0 = box_point(lo0, hi0, of), h1 = box_point(lo1, hi1, of);
-            if (h0 && h1) {
-                stk[sp++ * stride] = n.d.y;
-                code = n.d.x;
-                continue;
+            int next = 0, nh = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float3 lo = make_float3(comp4(n.lox, c) - e.x, comp4(n.loy, c) - e.y, comp4(n.loz, c) - e.z);
+                float3 hi = make_float3(comp4(n.hix, c) + e.x, comp4(n.hiy, c) + e.y, comp4(n.hiz, c) + e.z);
+                if (box_point(lo, hi, of)) {
+                    // the first hit child is visited next, the others pushed
+                    if (nh > 0) stk[sp++ * stride] = next;
+                    next = comp4i(n.code, c);
+                    ++nh;
+                }
             }
-            if (h0 || h1) {
-                code = h0 ? n.d.x : n.d.y;
+            if (nh > 0) {
+                code = next;
                 continue;
             }
         } else {
@@ -505,20 +520,40 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
     while (true) {
         float t1 = (float)tb + slack;
         if (code >= 0) {
-            BNode n = S.node[code];
-            float3 lo0, hi0, lo1, hi1;
-            child_boxes(n, &lo0, &hi0, &lo1, &hi1);
-            float tn0, tn1;
-            bool h0 = box_ray(lo0, hi0, of, inv, t0, t1, &tn0);
-            bool h1 = box_ray(lo1, hi1, of, inv, t0, t1, &tn1);
-            if (h0 && h1) {
-                bool first0 = tn0 <= tn1;
-                stk[sp++ * stride] = first0 ? n.d.y : n.d.x;
-                code = first0 ? n.d.x : n.d.y;
-                continue;
+            const WNode n = S.node[code];
+            float tn[4];
+            int cc[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float3 lo = make_float3(comp4(n.lox, c), comp4(n.loy, c), comp4(n.loz, c));
+                float3 hi = make_float3(comp4(n.hix, c), comp4(n.hiy, c), comp4(n.hiz, c));
+                float t;
+                tn[c] = box_ray(lo, hi, of, inv, t0, t1, &t) ? t : INFINITY;
+                cc[c] = comp4i(n.code, c);
             }
-            if (h0 || h1) {
-                code = h0 ? n.d.x : n.d.y;
+            // hit children near first (a sorting network; misses sort last)
+#define YARN_CSWAP(a, b)                                      \
+    do {                                                      \
+        const bool sw_ = tn[b] < tn[a];                       \
+        const float ta_ = tn[a];                              \
+        const int ca_ = cc[a];                                \
+        tn[a] = sw_ ? tn[b] : tn[a];                          \
+        tn[b] = sw_ ? ta_ : tn[b];                            \
+        cc[a] = sw_ ? cc[b] : cc[a];                          \
+        cc[b] = sw_ ? ca_ : cc[b];                            \
+    } while (0)
+            YARN_CSWAP(0, 1);
+            YARN_CSWAP(2, 3);
+            YARN_CSWAP(0, 2);
+            YARN_CSWAP(1, 3);
+            YARN_CSWAP(1, 2);
+#undef YARN_CSWAP
+            if (tn[0] < INFINITY) {
+                // push the farther hits, farthest first
+                if (tn[3] < INFINITY) stk[sp++ * stride] = cc[3];
+                if (tn[2] < INFINITY) stk[sp++ * stride] = cc[2];
+                if (tn[1] < INFINITY) stk[sp++ * stride] = cc[1];
+                code = cc[0];
                 continue;
             }
         } else {
