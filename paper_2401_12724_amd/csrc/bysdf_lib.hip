@@ -1315,6 +1315,17 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
 #endif
 constexpr int kFurnaceWaves = kBlock / kWave;
 
+// Orders the LDS accesses of one wavefront's lanes to each other's slots
+// (wavefront-scope fences around a wave barrier: the LDS serves a
+// wavefront's operations in issue order, so this emits no wait and only
+// keeps the compiler from moving accesses across it).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline float wave_sum_f(float x)
 {
 #pragma unroll
@@ -1322,76 +1333,129 @@ __device__ inline float wave_sum_f(float x)
     return x;
 }
 
+// Each wavefront serves `group` consecutive blocks.  Their setups run side by
+// side: lane g forms the state at block g's shared hit, then the lanes take
+// the (block, node) items and form the forward nodes, all into the
+// wavefront's LDS slots; a block's setup alone would keep the whole
+// wavefront busy for one lane's work.  Then the blocks are drawn one after
+// another, four draws per lane, reduced with shuffles in a fixed order.
+#ifndef BYSDF_FURNACE_GROUP_MAX
+#define BYSDF_FURNACE_GROUP_MAX 8
+#endif
+#ifndef BYSDF_FURNACE_NODE_ITEMS
+#define BYSDF_FURNACE_NODE_ITEMS 32
+#endif
+constexpr int kFurnaceGroupMax = BYSDF_FURNACE_GROUP_MAX;
+
 template <int MP, bool MIG>
 __global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(const TypeRec* __restrict__ types, int n_types,
                                                       const float4* __restrict__ tables, SPtrs q,
-                                                      int block, int64_t nb, float* mean, float* var)
+                                                      int block, int64_t nb, int group, int kmax, float* mean,
+                                                      float* var)
 {
     bysdf::stage_math_tables();
     __syncthreads();
-    __shared__ Node<double, float> s_nodes[kFurnaceWaves][kMaxNodes];
-    __shared__ XState<double, float, MP> s_X[kFurnaceWaves];
+    __shared__ XState<double, float, MP> s_X[kFurnaceWaves][kFurnaceGroupMax];
+    extern __shared__ Node<double, float> s_nd[];  // [kFurnaceWaves][group][kmax]
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t b = (int64_t)blockIdx.x * kFurnaceWaves + wv;
-    const bool live = b < nb;
-    const int64_t q0 = live ? b * (int64_t)block : 0;
-    const int t = __builtin_amdgcn_readfirstlane(q.type[q0]);
-    const bool valid = t >= 0 && t < n_types;
-    const TypeRec& rec = types[valid ? t : 0];
-    const Derived<double, float>& P = rec.d;
-    TabPtrT<MIG> tab;
-    tab.p = tables + rec.table_off;
-    V3<float> wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
-    const float h = q.h[q0], u = q.u[q0], v = q.v[q0];
-    const float s0 = q.s0 ? q.s0[q0] : 0.0f, s1 = q.s1 ? q.s1[q0] : 0.0f;
-    const bool bad = !live || !valid || check_inputs(h, u, v, wi) != 0u;
-    if (!bad) {
-        XState<double, float, MP> X0;
-        state_at_x(P, tab, h, u, v, wi, X0);
-        if (lane == 0) s_X[wv] = X0;
-        if (!X0.ph.pass && lane < P.K) {
-            Node<double, float> nd;
-            forward_node(P, tab, X0, lane, s0, s1, q.s0 != nullptr, nd);
-            s_nodes[wv][lane] = nd;
+    Node<double, float>* nodes_w = s_nd + wv * group * kmax;
+    const int64_t b0 = ((int64_t)blockIdx.x * kFurnaceWaves + wv) * group;
+    const bool has_shift = q.s0 != nullptr;
+    // the hit of block b and whether it can be drawn
+    auto block_hit = [&](int64_t b, int& t, V3<float>& wi, float& h, float& u, float& v, float& s0,
+                         float& s1) -> bool {
+        const int64_t q0 = b * (int64_t)block;
+        t = q.type[q0];
+        wi = mk3<float>(q.wix[q0], q.wiy[q0], q.wiz[q0]);
+        h = q.h[q0];
+        u = q.u[q0];
+        v = q.v[q0];
+        s0 = has_shift ? q.s0[q0] : 0.0f;
+        s1 = has_shift ? q.s1[q0] : 0.0f;
+        return t >= 0 && t < n_types && check_inputs(h, u, v, wi) == 0u;
+    };
+    // ---- states at the hits, lane g for block g
+    if (lane < group && b0 + lane < nb) {
+        int t;
+        V3<float> wi;
+        float h, u, v, s0, s1;
+        if (block_hit(b0 + lane, t, wi, h, u, v, s0, s1)) {
+            const TypeRec& rec = types[t];
+            TabPtrT<MIG> tab;
+            tab.p = tables + rec.table_off;
+            XState<double, float, MP> X0;
+            state_at_x(rec.d, tab, h, u, v, wi, X0);
+            s_X[wv][lane] = X0;
         }
     }
-    __syncthreads();
-    const XState<double, float, MP>& X = s_X[wv];
-    NodesStored<double, float> nodes{s_nodes[wv]};
-    float w[kMaxDrawsPerLane][3];
-    float sum[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int d = 0; d < kMaxDrawsPerLane; ++d) {
-        const int j = lane + d * kWave;
-        w[d][0] = w[d][1] = w[d][2] = 0.0f;
-        if (j < block && !bad) {
-            const int64_t qi = q0 + j;
-            SampleOut<float> so;
-            float x0, x1, x2;
-            query_xi(q, qi, x0, x1, x2);
-            sample_from_x(P, X, wi, x0, x1, x2, nodes, so);
-            for (int c = 0; c < 3; ++c) w[d][c] = so.wgt[c];
-        }
-        for (int c = 0; c < 3; ++c) sum[c] += w[d][c];
+    wave_lds_sync();
+    // ---- forward nodes, one (block, node) item per lane
+    for (int it = lane; it < group * kmax; it += kWave) {
+        const int g = it / kmax, k = it - g * kmax;
+        const int64_t b = b0 + g;
+        if (b >= nb) continue;
+        int t;
+        V3<float> wi;
+        float h, u, v, s0, s1;
+        if (!block_hit(b, t, wi, h, u, v, s0, s1)) continue;
+        const TypeRec& rec = types[t];
+        const XState<double, float, MP>& Xg = s_X[wv][g];
+        if (Xg.ph.pass || k >= rec.d.K) continue;
+        TabPtrT<MIG> tab;
+        tab.p = tables + rec.table_off;
+        Node<double, float> nd;
+        forward_node(rec.d, tab, Xg, k, s0, s1, has_shift, nd, rec.node_disk);
+        nodes_w[g * kmax + k] = nd;
     }
-    float m[3];
-    for (int c = 0; c < 3; ++c) m[c] = wave_sum_f(sum[c]) / (float)block;
-    float sq[3] = {0.0f, 0.0f, 0.0f};
+    wave_lds_sync();
+    // ---- the draws, block after block
+    for (int g = 0; g < group; ++g) {
+        const int64_t b = b0 + g;
+        if (b >= nb) break;
+        int t;
+        V3<float> wi;
+        float h, u, v, s0, s1;
+        const bool bad = !block_hit(b, t, wi, h, u, v, s0, s1);
+        t = __builtin_amdgcn_readfirstlane(bad ? 0 : t);
+        const Derived<double, float>& P = types[t].d;
+        const int64_t q0 = b * (int64_t)block;
+        const XState<double, float, MP>& X = s_X[wv][g];
+        NodesStored<double, float> nodes{nodes_w + g * kmax};
+        float w[kMaxDrawsPerLane][3];
+        float sum[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int d = 0; d < kMaxDrawsPerLane; ++d) {
-        const int j = lane + d * kWave;
-        if (j < block)
-            for (int c = 0; c < 3; ++c) {
-                const float dv = w[d][c] - m[c];
-                sq[c] += dv * dv;
+        for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+            const int j = lane + d * kWave;
+            w[d][0] = w[d][1] = w[d][2] = 0.0f;
+            if (j < block && !bad) {
+                const int64_t qi = q0 + j;
+                SampleOut<float> so;
+                float x0, x1, x2;
+                query_xi(q, qi, x0, x1, x2);
+                sample_from_x(P, X, wi, x0, x1, x2, nodes, so);
+                for (int c = 0; c < 3; ++c) w[d][c] = so.wgt[c];
             }
-    }
-    float vs[3];
-    for (int c = 0; c < 3; ++c) vs[c] = wave_sum_f(sq[c]);
-    if (live && lane == 0) {
-        for (int c = 0; c < 3; ++c) {
-            mean[3 * b + c] = m[c];
-            var[3 * b + c] = vs[c] / (float)(block - 1);
+            for (int c = 0; c < 3; ++c) sum[c] += w[d][c];
+        }
+        float m[3];
+        for (int c = 0; c < 3; ++c) m[c] = wave_sum_f(sum[c]) / (float)block;
+        float sq[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+            const int j = lane + d * kWave;
+            if (j < block)
+                for (int c = 0; c < 3; ++c) {
+                    const float dv = w[d][c] - m[c];
+                    sq[c] += dv * dv;
+                }
+        }
+        float vs[3];
+        for (int c = 0; c < 3; ++c) vs[c] = wave_sum_f(sq[c]);
+        if (lane == 0) {
+            for (int c = 0; c < 3; ++c) {
+                mean[3 * b + c] = m[c];
+                var[3 * b + c] = vs[c] / (float)(block - 1);
+            }
         }
     }
 }
@@ -2022,9 +2086,16 @@ extern "C" int bysdf_furnace_blocks(const bysdf_types_t* h, const bysdf_sample_s
     if (BYSDF_FURNACE_WAVE && block <= kWave * kMaxDrawsPerLane) {
         auto kw = h->any_mig ? (h->max_plies <= 4 ? k_furnace_w<4, true> : k_furnace_w<8, true>)
                              : (h->max_plies <= 4 ? k_furnace_w<4, false> : k_furnace_w<8, false>);
-        const int64_t groups = (nb + kFurnaceWaves - 1) / kFurnaceWaves;
-        hipLaunchKernelGGL(kw, dim3((unsigned)groups), dim3(kBlock), 0, stream, h->d_types, h->n_types,
-                           h->d_tables, sp, block, nb, mean, var);
+        // blocks per wavefront: up to 8, and at most 32 forward nodes to form
+        const int kmax = h->max_K;
+        int group = BYSDF_FURNACE_NODE_ITEMS / kmax;
+        group = group < 1 ? 1 : (group > kFurnaceGroupMax ? kFurnaceGroupMax : group);
+        const int64_t per_wg = (int64_t)kFurnaceWaves * group;
+        const int64_t wgs = (nb + per_wg - 1) / per_wg;
+        if (wgs > 0x7fffffffLL) return fail(BYSDF_ERR_INVALID_ARG, "too many blocks");
+        const size_t lds = sizeof(Node<double, float>) * kFurnaceWaves * group * kmax;
+        hipLaunchKernelGGL(kw, dim3((unsigned)wgs), dim3(kBlock), lds, stream, h->d_types, h->n_types,
+                           h->d_tables, sp, block, nb, group, kmax, mean, var);
     } else {
         auto kern = h->any_mig ? (h->max_plies <= 4 ? k_furnace<4, true> : k_furnace<8, true>)
                                : (h->max_plies <= 4 ? k_furnace<4, false> : k_furnace<8, false>);
