@@ -222,6 +222,10 @@ def _summarize_all(prof_dir, stats, counters, f_scale, w_scale, cmd):
     fetch, _ = counters("fetch")
     write, _ = counters("write")
     l2, _ = counters("l2")
+    # optional pass: VALU lane utilisation and the share of wave time spent
+    # waiting (SQ_THREAD_CYCLES_VALU, SQ_ACTIVE_INST_VALU, SQ_WAIT_ANY,
+    # SQ_WAVE_CYCLES)
+    util = counters("util")[0] if os.path.isdir(os.path.join(prof_dir, "util")) else {}
     mean = lambda xs: sum(xs) / len(xs) if xs else float("nan")
     lines = ["# rocprofv3: every kernel of the bench run", "",
              "Commands (repo root on the GPU host; one counter pass per run):", "", cmd, "",
@@ -230,10 +234,13 @@ def _summarize_all(prof_dir, stats, counters, f_scale, w_scale, cmd):
              "+ FLOPS_FP32 + FLOPS_FP32_TRANS) x 64 lanes / duration, against 78.6 TFLOP/s; HBM = "
              "FETCH_SIZE + WRITE_SIZE (scaled by the 1 GiB copy: %.4f, %.4f) / duration, against "
              "8 TB/s; VALU issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 "
-             "XCDs); L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS)." % (f_scale, w_scale), "",
+             "XCDs); L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS); lane util. = SQ_THREAD_CYCLES_VALU / "
+             "(64 x SQ_ACTIVE_INST_VALU), the share of the 64 lanes active in the VALU cycles "
+             "issued; waiting = SQ_WAIT_ANY / SQ_WAVE_CYCLES, the share of resident-wave time spent "
+             "at a wait." % (f_scale, w_scale), "",
              "| kernel | launches | avg us | VGPR | scratch B/lane | VALU issue | executed TFLOP/s "
-             "| of 78.6 | HBM GB/launch | HBM GB/s | of 8 TB/s | L2 hit |",
-             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+             "| of 78.6 | HBM GB/launch | HBM GB/s | of 8 TB/s | L2 hit | lane util. | waiting |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     rows = []
     for k, (calls, avg_us, _, _, _) in stats.items():
         if k not in inst or "copy" in k.lower() or "fill" in k.lower():
@@ -249,12 +256,19 @@ def _summarize_all(prof_dir, stats, counters, f_scale, w_scale, cmd):
         tf = fl / t / 1e12 if t > 0 else 0.0
         gbs = (fb + wb) / t / 1e9 if t > 0 else 0.0
         m = meta[k]
+        lane = wait = float("nan")
+        if k in util:
+            u = {c: mean([v for (_, v, _) in util[k][c]]) for c in util[k]}
+            if u.get("SQ_ACTIVE_INST_VALU", 0) > 0:
+                lane = u["SQ_THREAD_CYCLES_VALU"] / (64 * u["SQ_ACTIVE_INST_VALU"])
+            if u.get("SQ_WAVE_CYCLES", 0) > 0:
+                wait = u["SQ_WAIT_ANY"] / u["SQ_WAVE_CYCLES"]
         rows.append((calls * avg_us, "| `%s` | %d | %.1f | %s | %s | %.2f | %.2f | %.1f %% | %.3f | %.0f | "
-                     "%.1f %% | %.2f |" % (k, calls, avg_us, m["VGPR_Count"], m["Scratch_Size"],
-                                          valu * 4 / (1024 * gui / 8) if gui else 0.0, tf,
-                                          100 * tf / PEAK_VALU_TFLOPS, (fb + wb) / 1e9, gbs,
-                                          100 * gbs / PEAK_HBM_GBS, hit / (hit + miss)
-                                          if hit + miss > 0 else float("nan"))))
+                     "%.1f %% | %.2f | %.2f | %.2f |" % (k, calls, avg_us, m["VGPR_Count"], m["Scratch_Size"],
+                                                      valu * 4 / (1024 * gui / 8) if gui else 0.0, tf,
+                                                      100 * tf / PEAK_VALU_TFLOPS, (fb + wb) / 1e9, gbs,
+                                                      100 * gbs / PEAK_HBM_GBS, hit / (hit + miss)
+                                                      if hit + miss > 0 else float("nan"), lane, wait)))
     lines += [r for _, r in sorted(rows, key=lambda x: -x[0])]
     open(os.path.join(ROOT, "profiles", "all_kernels_bench_counters.md"), "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -899,14 +913,17 @@ def main():
     if not args.no_extras:
         eval_qps = N / (unfused["eval"] * 1e-3)
         del ev, sv
-        out["migration"] = _migration(torch, bysdf, W, P, qd, q, ktime["eval_sample"])
-        out["k_sweep"] = _k_sweep(torch, bysdf, P, q, qd)
-        out["multiscale"] = _multiscale(torch, bysdf, W, P, q, qd, unfused)
-        out["cross_section"] = _cross_section(torch, bysdf, W, P, qd)
-        out["hetero"] = _hetero(torch, bysdf, W, eval_qps)
-        out["fwd_bwd"] = _fwd_bwd(torch, bysdf, W)
-        out["weave"] = _weave_render(torch, bysdf, W)
-        out["fit"] = _fit(torch, bysdf, W)
+        extras = (("migration", lambda: _migration(torch, bysdf, W, P, qd, q, ktime["eval_sample"])),
+                  ("k_sweep", lambda: _k_sweep(torch, bysdf, P, q, qd)),
+                  ("multiscale", lambda: _multiscale(torch, bysdf, W, P, q, qd, unfused)),
+                  ("cross_section", lambda: _cross_section(torch, bysdf, W, P, qd)),
+                  ("hetero", lambda: _hetero(torch, bysdf, W, eval_qps)),
+                  ("fwd_bwd", lambda: _fwd_bwd(torch, bysdf, W)),
+                  ("weave", lambda: _weave_render(torch, bysdf, W)),
+                  ("fit", lambda: _fit(torch, bysdf, W)))
+        for name, fn in extras:
+            out[name] = fn()
+            print("bench.py: %s done" % name, file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(P, q, args.cpu_seconds)
         if not args.no_cpu_configs:

@@ -393,6 +393,9 @@ __host__ __device__ inline void decode_leaf(int code, int* first, int* count)
     *first = c >> 2;
     *count = (c & 3) + 1;
 }
+__host__ __device__ inline int leaf_code(int first, int count) { return -((first << 2) | (count - 1)) - 1; }
+// end of a traversal: below every leaf code of a scene of fewer than 2^29 spans
+constexpr int kTraceDone = INT32_MIN;
 
 // box of child c (0..3) of a wide node
 __host__ __device__ inline float comp4(const float4& v, int c)
@@ -517,9 +520,15 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
     double tb = t_max;  // best sampled entry (bounds the true first entry)
     int sp = 0, code = 0;
     float t0 = (float)t_min - slack;
-    while (true) {
-        float t1 = (float)tb + slack;
-        if (code >= 0) {
+    // Two inner loops (the while-while form of Aila and Laine, HPG 2009):
+    // a lane descends through nodes until it holds a leaf, then scans that
+    // leaf one span per step.  In a wavefront the node loop runs until
+    // every lane holds a leaf or is done, so the expensive span scans run
+    // with most lanes active instead of alternating with node steps.  The
+    // visiting order of each ray, and so its result, is unchanged.
+    while (code != kTraceDone) {
+        while (code >= 0) {
+            const float t1 = (float)tb + slack;
             const WNode n = S.node[code];
             float tn[4];
             int cc[4];
@@ -554,16 +563,17 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
                 if (tn[2] < INFINITY) stk[sp++ * stride] = cc[2];
                 if (tn[1] < INFINITY) stk[sp++ * stride] = cc[1];
                 code = cc[0];
-                continue;
+            } else {
+                code = sp > 0 ? stk[--sp * stride] : kTraceDone;
             }
-        } else {
+        }
+        while (code < 0 && code != kTraceDone) {
             int first, count;
             decode_leaf(code, &first, &count);
-            for (int k = 0; k < count; ++k) {
-                SpanRec r = S.span[first + k];
-                bool skip = false;
-                for (int j = 0; j < nex; ++j) skip |= ex[j] == r.yarn;
-                if (skip) continue;
+            SpanRec r = S.span[first];
+            bool skip = false;
+            for (int j = 0; j < nex; ++j) skip |= ex[j] == r.yarn;
+            if (!skip) {
                 SpanGeo g;
                 load_span(S, r, o, &g);
                 double t;
@@ -572,7 +582,7 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
                 if (span_scan(g, d, e1, e2, t_min, lim, r.info & 0xffff, &t, &bi)) {
                     tb = fmin(tb, t);
                     double nt = t;
-                    int nsp = first + k, nbi = bi;
+                    int nsp = first, nbi = bi;
 #pragma unroll
                     for (int q = 0; q < kCand; ++q) {
                         if (nt < ct[q]) {
@@ -588,9 +598,12 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
                     }
                 }
             }
+            // the leaf's next span, or the next entry of the stack
+            if (count > 1)
+                code = leaf_code(first + 1, count - 1);
+            else
+                code = sp > 0 ? stk[--sp * stride] : kTraceDone;
         }
-        if (sp == 0) break;
-        code = stk[--sp * stride];
     }
     RayHit best{t_max, 0.0, -1};
 #pragma unroll
