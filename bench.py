@@ -164,10 +164,13 @@ def _summarize(prof_dir, bench_json, workload_tag):
         lines.append("| `%s` | %s | %s | %s | %s | %.0f | %.1f | %.2f | %.3f | %.3f |" % (
             k, m["VGPR_Count"], m["Accum_VGPR_Count"], m["Scratch_Size"], m["LDS_Block_Size"],
             valu * 64 / nq, salu * 64 / nq, valu * 4 / (1024 * gui / 8), fb / 1e9, wb / 1e9))
+        # a stage's kernel is the variant the step launches most (the extras
+        # launch other instantiations a few times)
+        nd = len(inst[k]["SQ_INSTS_VALU"])
         for st, pre in _STAGE_KERNEL.items():
-            if k.startswith(pre):
+            if k.startswith(pre) and nd > traffic.get(st, {}).get("dispatches", 0):
                 traffic[st] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb,
-                               "kernel": k}
+                               "kernel": k, "dispatches": nd}
     lines += ["", "FLOP-class counters per query (counter total / queries):", "",
               "| kernel | " + " | ".join(c.replace("SQ_INSTS_VALU_", "") for c in
                                         sorted(next(iter(flops.values())))) + " |",
