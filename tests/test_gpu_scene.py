@@ -1,8 +1,9 @@
 """GPU ray / yarn-tube intersection (yarn_scene_create, yarn_tube_intersect)
 against the FP64 intersection oracle: a small weave with random rays (every
 ray), the full 512-yarn weave with camera and random rays (sampled rays),
-a non-planar yarn, and the edge cases (misses, t_max, origins inside a
-tube, end caps, bad rays, empty batches)."""
+a non-planar yarn, scenes of 1 to 9 spans (wide BVH nodes with unused
+slots), and the edge cases (misses, t_max, origins inside a tube, end caps,
+bad rays, empty batches)."""
 import numpy as np
 import pytest
 
@@ -116,6 +117,29 @@ def test_non_planar_yarn(torch_cuda):
     r = oracle.intersect(oracle.Scene(ctrl, off), o, d, tm, 1e-4)
     both = _compare(g, r, np.zeros(1, np.float32), "helix", frame_tol=5e-6)
     assert both.sum() > 100
+
+
+@pytest.mark.parametrize("n_spans", [1, 2, 5, 9])
+def test_tiny_scenes(torch_cuda, n_spans):
+    """A single gently bent yarn of 1, 2, 5 or 9 spans: the root of the wide
+    BVH has unused child slots (and a 1-span scene a root whose second
+    binary child is empty), which must never be entered.  The bend is kept
+    small: the frame's transport within a span (16 steps on the device, 64
+    in the oracle) is checked on the helix above."""
+    torch = torch_cuda
+    n_cp = n_spans + 3
+    x = np.linspace(-1.0, 1.0, n_cp)
+    ctrl = np.stack([x, 0.02 * np.sin(3.0 * x), 0.01 * np.cos(2.0 * x), np.full(n_cp, 0.15)],
+                    1).astype(np.float32)
+    off = np.array([0, n_cp], np.int64)
+    S = bysdf.yarn_scene_create(ctrl, off)
+    assert bysdf.yarn_scene_info(S)["n_spans"] == n_spans
+    o, d = W.random_rays(2000, 20 + n_spans, (-2, -2, -2), (2, 2, 2), (-1, -0.3, -0.3), (1, 0.3, 0.3))
+    tm = np.full(len(o), 20.0, np.float32)
+    g = _run(torch, S, o, d, tm)
+    r = oracle.intersect(oracle.Scene(ctrl, off), o, d, tm, 1e-4)
+    both = _compare(g, r, np.zeros(1, np.float32), "tiny %d" % n_spans)
+    assert both.sum() > 200
 
 
 def test_edge_cases(torch_cuda):
