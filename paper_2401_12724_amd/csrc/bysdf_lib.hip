@@ -487,6 +487,17 @@ struct FPtrs {
 #define BYSDF_MULTI_MIN_WAVES 2
 #endif
 
+// Orders the LDS accesses of one wavefront's lanes to each other's slots
+// (wavefront-scope fences around a wave barrier: the LDS serves a
+// wavefront's operations in issue order, so this emits no wait and only
+// keeps the compiler from moving accesses across it).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline int wave_excl_scan(int x)
 {
     const int lane = __lane_id();
@@ -639,179 +650,26 @@ __device__ inline void wave_footprint_geometry(const TypeRec* __restrict__ types
     }
 }
 
-// The evaluation takes kMultiQ groups of 64 queries per wavefront pass
-// (lane l owns queries b + 64 g + l): their items are numbered group by
-// group, and more queries per pass leave fewer lanes idle in the last,
-// partly filled round of items.
-#ifndef BYSDF_MULTI_Q
-#define BYSDF_MULTI_Q 1
-#endif
-constexpr int kMultiQ = BYSDF_MULTI_Q;
+// Per-wavefront LDS of the multi-scale kernels: each lane's aggregated
+// frame and shadowing (read by the lanes that take its footprint's strata)
+// and its running sums.  Out of registers, they leave the per-stratum model
+// (fixed point, nodes, lobes) its full register budget.
+struct MultiLds {
+    double fn[3][kWave], ft[3][kWave];
+    float gm[kWave];
+    int use[kWave];        // bit 0: single stratum, bit 1: aggregated frame
+    float acc[12][kWave];  // E rgb, ExS, EyS, ExB rgb, EyB rgb, pdf
+};
 
-// exclusive scan of the per-slot item counts over kMultiQ x 64 slots, group
-// by group; returns the total
-__device__ inline int scan_slots(const int (&nq)[kMultiQ], int (&first)[kMultiQ])
-{
-    int base = 0;
-#pragma unroll
-    for (int g = 0; g < kMultiQ; ++g) {
-        const int e = wave_excl_scan(nq[g]);
-        first[g] = base + e;
-        base += __shfl(e + nq[g], kWave - 1);
-    }
-    return base;
-}
-
-// first item of slot c (slot c = 64 g + lane)
-__device__ inline int slot_first(const int (&first)[kMultiQ], int c)
-{
-    int fc = 0;
-#pragma unroll
-    for (int g = 0; g < kMultiQ; ++g) {
-        const int v = __shfl(first[g], c & (kWave - 1));
-        if ((c / kWave) == g) fc = v;
-    }
-    return fc;
-}
-
-// the slot whose items include item k
-__device__ inline int slot_owner(const int (&first)[kMultiQ], int k)
-{
-    int lo = 0;
-#pragma unroll
-    for (int step = kWave * kMultiQ / 2; step >= 1; step >>= 1) {
-        const int c = lo + step;
-        if (slot_first(first, c) <= k) lo = c;
-    }
-    return lo;
-}
-
-template <class T>
-__device__ inline T slot_get(const T (&a)[kMultiQ], int c)
-{
-    T r = a[0];
-#pragma unroll
-    for (int g = 0; g < kMultiQ; ++g) {
-        const T v = __shfl(a[g], c & (kWave - 1));
-        if ((c / kWave) == g) r = v;
-    }
-    return r;
-}
-
-__device__ inline V3<double> slot_get3(const V3<double> (&a)[kMultiQ], int c)
-{
-    V3<double> r = a[0];
-#pragma unroll
-    for (int g = 0; g < kMultiQ; ++g) {
-        const V3<double> v = shfl3(a[g], c & (kWave - 1));
-        if ((c / kWave) == g) r = v;
-    }
-    return r;
-}
-
-// Aggregated geometry (Eq. 9-11) of the wavefront's footprints, one set per
-// slot group, as footprint_geometry computes it.
-template <bool kLds, int MP, bool MIG, class QP>
-__device__ inline void wave_geometry_q(const TypeRec* __restrict__ types, const float4* __restrict__ tables,
-                                       const float4* s_tab, const QP& q, const FPtrs& fp, int n_max, int64_t b,
-                                       const int (&t)[kMultiQ], const int (&first)[kMultiQ],
-                                       const int (&nq)[kMultiQ], int S, V3<double> (&Fn)[kMultiQ],
-                                       V3<double> (&Ft)[kMultiQ], float (&Gm)[kMultiQ], int (&any)[kMultiQ],
-                                       uint32_t (&fl)[kMultiQ])
-{
-    V3<double> sn[kMultiQ], st[kMultiQ];
-    double sg[kMultiQ], sw[kMultiQ], g0[kMultiQ];
-    int have[kMultiQ];
-#pragma unroll
-    for (int g = 0; g < kMultiQ; ++g) {
-        sn[g] = st[g] = Fn[g] = Ft[g] = mk3<double>(0.0, 0.0, 0.0);
-        sg[g] = sw[g] = g0[g] = 0.0;
-        have[g] = 0;
-    }
-    for (int r0 = 0; r0 < S; r0 += kWave) {
-        const int k = r0 + __lane_id();
-        const bool item = k < S;
-        const int own = slot_owner(first, k);
-        const int j = k - slot_first(first, own);
-        const int to = slot_get(t, own);
-        double w_it = 0.0, g_it = 0.0;
-        V3<double> n_it = mk3<double>(0.0, 0.0, 0.0), t_it = n_it;
-        uint32_t f_it = 0;
-        for_each_wave_type<false>(to, item, [&](int tu) {
-            const TypeRec& R = types[tu];
-            TabPtrT<MIG> tab;
-            tab.p = kLds ? s_tab : tables + R.table_off;
-            const MQuery m = load_mquery(q, fp, b + own);
-            Footprint fo;
-            make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, fo);
-            const Derived<double, float> Pm = widened(R.d, R.beta, R.aniso, fo);
-            const float hj = stratum_h(fo, j);
-            const double w = stratum_w(fo, (double)hj);
-            Frame<double> fx;
-            double rawf;
-            uint32_t sfl;
-            const bool hit = stratum_frame<double, float, MP>(Pm, tab, hj, m.u, m.v, m.wi, fx, rawf, sfl);
-            f_it = sfl & ~F_PASS_THROUGH;
-            if (hit && w > 0.0) {
-                w_it = w;
-                n_it = fx.n;
-                t_it = fx.t;
-                g_it = 1.0 - (double)Pm.rho_f * (1.0 - rawf);
-            }
-        });
-        int lo[kMultiQ], cnt[kMultiQ], cm = 0;
-#pragma unroll
-        for (int g = 0; g < kMultiQ; ++g) {
-            lo[g] = first[g] > r0 ? first[g] : r0;
-            const int hi = first[g] + nq[g] < r0 + kWave ? first[g] + nq[g] : r0 + kWave;
-            cnt[g] = hi > lo[g] ? hi - lo[g] : 0;
-            cm = cnt[g] > cm ? cnt[g] : cm;
-        }
-        const int cmax = wave_max(cm);
-        for (int jj = 0; jj < cmax; ++jj) {
-#pragma unroll
-            for (int g = 0; g < kMultiQ; ++g) {
-                const int src = (lo[g] + jj - r0) & (kWave - 1);
-                const double ws = __shfl(w_it, src), gs = __shfl(g_it, src);
-                const V3<double> ns = shfl3(n_it, src), ts = shfl3(t_it, src);
-                const uint32_t fs = __shfl(f_it, src);
-                if (jj < cnt[g]) {
-                    fl[g] |= fs;
-                    if (ws > 0.0) {
-                        if (have[g] == 0) {
-                            Fn[g] = ns;
-                            Ft[g] = ts;
-                            g0[g] = gs;
-                        }
-                        sn[g] = sn[g] + ns * ws;
-                        st[g] = st[g] + ts * ws;
-                        sg[g] = sg[g] + gs * ws;
-                        sw[g] += ws;
-                        ++have[g];
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < kMultiQ; ++g) {
-        any[g] = have[g] > 0;
-        Gm[g] = (float)g0[g];
-        if (have[g] > 1) {
-            Gm[g] = (float)(sg[g] / sw[g]);
-            const double ln2 = dot(sn[g], sn[g]);
-            if (ln2 > 1e-24 * sw[g] * sw[g]) {
-                const V3<double> nn = sn[g] * rsqrt_(ln2);
-                const V3<double> tt = st[g] - nn * dot(st[g], nn);
-                const double lt2 = dot(tt, tt);
-                if (lt2 > 1e-24 * sw[g] * sw[g]) {
-                    Fn[g] = nn;
-                    Ft[g] = tt * rsqrt_(lt2);
-                }
-            }
-        }
-    }
-}
+// The sampler's: the aggregated frame and shadowing, and each lane's draw
+// (direction, exit point, lobe and node) while the strata evaluate it.
+struct MultiSampleLds {
+    double fn[3][kWave], ft[3][kWave], wo[3][kWave];
+    float gm[kWave];
+    int use[kWave];  // bit 0: single stratum
+    float ex[3][kWave];
+    int lobe[kWave], node[kWave];
+};
 
 template <bool kLds, int MP, bool MIG>
 __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
@@ -821,76 +679,66 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
     bysdf::stage_math_tables();
     __syncthreads();
     extern __shared__ float4 s_tab[];
+    __shared__ MultiLds s_ml[kBlock / kWave];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
         __syncthreads();
     }
     const int lane = __lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * kMultiQ;
+    MultiLds& L = s_ml[threadIdx.x / kWave];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // whole wavefronts iterate together (the cross-lane steps need every lane)
-    for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane)) * kMultiQ; b < n; b += stride) {
-        int t[kMultiQ], nq[kMultiQ], nqa[kMultiQ], single[kMultiQ];
-        uint32_t fl[kMultiQ];
-        double wsum[kMultiQ];
-#pragma unroll
-        for (int g = 0; g < kMultiQ; ++g) {
-            const int64_t i = b + g * kWave + lane;
-            const bool in = i < n;
-            t[g] = in ? q.type[i] : 0;
-            fl[g] = F_BAD_INPUT;
-            wsum[g] = 1.0;
-            nq[g] = 0;
-            if (in) {
-                const MQuery m = load_mquery(q, fp, i);
-                const V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
-                fl[g] = (t[g] < 0 || t[g] >= n_types) ? F_BAD_INPUT : 0u;
-                fl[g] |= check_inputs(m.h, m.u, m.v, m.wi) | check_dir(wo) |
-                         check_footprint(m.h, m.h1, m.h2, m.zeta);
-                if (fl[g] == 0u) {
-                    Footprint f;
-                    make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, f);
-                    nq[g] = f.n;
-                    wsum[g] = f.wsum;
-                }
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); b < n; b += stride) {
+        const int64_t i = b + lane;
+        const bool in = i < n;
+        const int t = in ? q.type[i] : 0;
+        uint32_t fl = F_BAD_INPUT;
+        double wsum = 1.0;
+        int nq = 0;
+        if (in) {
+            const MQuery m = load_mquery(q, fp, i);
+            const V3<float> wo = mk3<float>(q.wox[i], q.woy[i], q.woz[i]);
+            fl = (t < 0 || t >= n_types) ? F_BAD_INPUT : 0u;
+            fl |= check_inputs(m.h, m.u, m.v, m.wi) | check_dir(wo) | check_footprint(m.h, m.h1, m.h2, m.zeta);
+            if (fl == 0u) {
+                Footprint f;
+                make_footprint(m.h, m.h1, m.h2, m.zeta, n_max, f);
+                nq = f.n;
+                wsum = f.wsum;
             }
-            // a single stratum is its own aggregate: only wider footprints
-            // take part in the aggregation pass
-            single[g] = nq[g] == 1;
-            nqa[g] = nq[g] > 1 ? nq[g] : 0;
         }
-        int firsta[kMultiQ], first[kMultiQ];
-        const int Sa = scan_slots(nqa, firsta);
-        const int S = scan_slots(nq, first);
-        V3<double> Fn[kMultiQ], Ft[kMultiQ];
-        float Gm[kMultiQ];
-        int any[kMultiQ];
-        wave_geometry_q<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, firsta, nqa, Sa, Fn, Ft, Gm,
-                                       any, fl);
-        EvalOut<float> acc[kMultiQ];
-        int hit1[kMultiQ];
-#pragma unroll
-        for (int g = 0; g < kMultiQ; ++g) {
-            if (nqa[g] > 0 && !any[g]) fl[g] |= F_PASS_THROUGH;
-            for (int c = 0; c < 3; ++c) acc[g].E[c] = acc[g].ExB[c] = acc[g].EyB[c] = 0.0f;
-            acc[g].ExS = acc[g].EyS = acc[g].pdf = 0.0f;
-            hit1[g] = 0;
+        // a single stratum is its own aggregate: only wider footprints take
+        // part in the aggregation pass
+        const bool single = nq == 1;
+        const int nqa = nq > 1 ? nq : 0;
+        const int firsta = wave_excl_scan(nqa);
+        const int Sa = __shfl(firsta + nqa, kWave - 1);
+        const int first = wave_excl_scan(nq);
+        const int S = __shfl(first + nq, kWave - 1);
+        {
+            Frame<double> F;
+            float Gm;
+            bool any;
+            wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, firsta, nqa, Sa,
+                                                   F, Gm, any, fl);
+            if (nqa > 0 && !any) fl |= F_PASS_THROUGH;
+            wave_lds_sync();
+            L.fn[0][lane] = F.n.x; L.fn[1][lane] = F.n.y; L.fn[2][lane] = F.n.z;
+            L.ft[0][lane] = F.t.x; L.ft[1][lane] = F.t.y; L.ft[2][lane] = F.t.z;
+            L.gm[lane] = Gm;
+            L.use[lane] = (single ? 1 : 0) | (any ? 2 : 0);
+            for (int c = 0; c < 12; ++c) L.acc[c][lane] = 0.0f;
+            wave_lds_sync();
         }
+        int hit1 = 0;
         // f_multi: every stratum's lobes with the aggregated geometry
         for (int r0 = 0; r0 < S; r0 += kWave) {
             const int k = r0 + lane;
-            const int own = slot_owner(first, k);
-            const int j = k - slot_first(first, own);
-            const int to = slot_get(t, own);
-            // every lane takes part in the shuffles (a lane outside the
-            // items may own items of this round)
-            const int any_o = slot_get(any, own);
-            const int single_o = slot_get(single, own);
-            const bool item = k < S && (any_o != 0 || single_o != 0);
-            Frame<double> Fo;
-            Fo.n = slot_get3(Fn, own);
-            Fo.t = slot_get3(Ft, own);
-            Fo.b = cross(Fo.n, Fo.t);
-            const float Go = slot_get(Gm, own);
+            const int own = item_owner(first, k);
+            const int j = k - __shfl(first, own);
+            const int to = __shfl(t, own);
+            const int use_o = L.use[own];
+            const bool item = k < S && use_o != 0;
             float ev[12];
             for (int c = 0; c < 12; ++c) ev[c] = 0.0f;
             float w_it = 0.0f;
@@ -911,7 +759,13 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
                 f_it = X.ph.flags & ~F_PASS_THROUGH;
                 if (X.ph.pass) return;
                 hit_it = 1;
-                if (!single_o) apply_aggregate(Pm, X, Fo, Go);
+                if (!(use_o & 1)) {
+                    Frame<double> Fo;
+                    Fo.n = mk3<double>(L.fn[0][own], L.fn[1][own], L.fn[2][own]);
+                    Fo.t = mk3<double>(L.ft[0][own], L.ft[1][own], L.ft[2][own]);
+                    Fo.b = cross(Fo.n, Fo.t);
+                    apply_aggregate(Pm, X, Fo, L.gm[own]);
+                }
                 back = !(X.mu_i > 0.0f);
                 const float s0 = q.s0 ? q.s0[io] : 0.0f, s1 = q.s1 ? q.s1[io] : 0.0f;
                 const V3<double> wo_g = mk3<double>(q.wox[io], q.woy[io], q.woz[io]);
@@ -924,57 +778,42 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_eval_multi(
                 ev[8] = e.EyB[0]; ev[9] = e.EyB[1]; ev[10] = e.EyB[2];
                 ev[11] = e.pdf;
             });
-            int lo[kMultiQ], cnt[kMultiQ], cm = 0;
-#pragma unroll
-            for (int g = 0; g < kMultiQ; ++g) {
-                lo[g] = first[g] > r0 ? first[g] : r0;
-                const int hi = first[g] + nq[g] < r0 + kWave ? first[g] + nq[g] : r0 + kWave;
-                cnt[g] = hi > lo[g] ? hi - lo[g] : 0;
-                cm = cnt[g] > cm ? cnt[g] : cm;
-            }
-            const int cmax = wave_max(cm);
+            // this lane's strata of the round, in stratum order
+            const int lo = first > r0 ? first : r0;
+            const int hi = first + nq < r0 + kWave ? first + nq : r0 + kWave;
+            const int cnt = hi > lo ? hi - lo : 0;
+            const int cmax = wave_max(cnt);
+            float a[12];
+            for (int c = 0; c < 12; ++c) a[c] = L.acc[c][lane];
             for (int jj = 0; jj < cmax; ++jj) {
-#pragma unroll
-                for (int g = 0; g < kMultiQ; ++g) {
-                    const int src = (lo[g] + jj - r0) & (kWave - 1);
-                    float es[12];
-                    for (int c = 0; c < 12; ++c) es[c] = __shfl(ev[c], src);
-                    const float ws = __shfl(w_it, src);
-                    const int bs = __shfl(back, src);
-                    const int hs = __shfl(hit_it, src);
-                    const uint32_t fs = __shfl(f_it, src);
-                    if (jj < cnt[g]) {
-                        if (bs) fl[g] |= F_BACKFACING;
-                        if (single[g]) {
-                            fl[g] |= fs;
-                            hit1[g] = hs != 0;
-                        }
-                        for (int c = 0; c < 3; ++c) {
-                            acc[g].E[c] = acc[g].E[c] + ws * es[c];
-                            acc[g].ExB[c] = acc[g].ExB[c] + ws * es[5 + c];
-                            acc[g].EyB[c] = acc[g].EyB[c] + ws * es[8 + c];
-                        }
-                        acc[g].ExS = acc[g].ExS + ws * es[3];
-                        acc[g].EyS = acc[g].EyS + ws * es[4];
-                        acc[g].pdf = acc[g].pdf + ws * es[11];
+                const int src = (lo + jj - r0) & (kWave - 1);
+                float es[12];
+                for (int c = 0; c < 12; ++c) es[c] = __shfl(ev[c], src);
+                const float ws = __shfl(w_it, src);
+                const int bs = __shfl(back, src);
+                const int hs = __shfl(hit_it, src);
+                const uint32_t fs = __shfl(f_it, src);
+                if (jj < cnt) {
+                    if (bs) fl |= F_BACKFACING;
+                    if (single) {
+                        fl |= fs;
+                        hit1 = hs != 0;
                     }
+                    for (int c = 0; c < 12; ++c) a[c] = a[c] + ws * es[c];
                 }
             }
+            for (int c = 0; c < 12; ++c) L.acc[c][lane] = a[c];
+            wave_lds_sync();
         }
-#pragma unroll
-        for (int g = 0; g < kMultiQ; ++g) {
-            const int64_t i = b + g * kWave + lane;
-            if (i >= n) continue;
-            if (single[g] && !hit1[g]) fl[g] |= F_PASS_THROUGH;
-            const float iw = float(1.0 / wsum[g]);
-            const EvalOut<float>& a = acc[g];
-            o.Er[i] = a.E[0] * iw; o.Eg[i] = a.E[1] * iw; o.Eb[i] = a.E[2] * iw;
-            o.ExS[i] = a.ExS * iw; o.EyS[i] = a.EyS * iw;
-            o.ExBr[i] = a.ExB[0] * iw; o.ExBg[i] = a.ExB[1] * iw; o.ExBb[i] = a.ExB[2] * iw;
-            o.EyBr[i] = a.EyB[0] * iw; o.EyBg[i] = a.EyB[1] * iw; o.EyBb[i] = a.EyB[2] * iw;
-            o.pdf[i] = a.pdf * iw;
-            o.flags[i] = fl[g];
-        }
+        if (!in) continue;
+        if (single && !hit1) fl |= F_PASS_THROUGH;
+        const float iw = float(1.0 / wsum);
+        o.Er[i] = L.acc[0][lane] * iw; o.Eg[i] = L.acc[1][lane] * iw; o.Eb[i] = L.acc[2][lane] * iw;
+        o.ExS[i] = L.acc[3][lane] * iw; o.EyS[i] = L.acc[4][lane] * iw;
+        o.ExBr[i] = L.acc[5][lane] * iw; o.ExBg[i] = L.acc[6][lane] * iw; o.ExBb[i] = L.acc[7][lane] * iw;
+        o.EyBr[i] = L.acc[8][lane] * iw; o.EyBg[i] = L.acc[9][lane] * iw; o.EyBb[i] = L.acc[10][lane] * iw;
+        o.pdf[i] = L.acc[11][lane] * iw;
+        o.flags[i] = fl;
     }
 }
 
@@ -989,11 +828,13 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
     bysdf::stage_math_tables();
     __syncthreads();
     extern __shared__ float4 s_tab[];
+    __shared__ MultiSampleLds s_ml[kBlock / kWave];
     if (kLds) {
         for (int i = threadIdx.x; i < lds_texels; i += blockDim.x) s_tab[i] = tables[i];
         __syncthreads();
     }
     const int lane = __lane_id();
+    MultiSampleLds& L = s_ml[threadIdx.x / kWave];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); b < n; b += stride) {
         const int64_t i = b + lane;
@@ -1028,17 +869,24 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
         const int nqa = nq > 1 ? nq : 0;
         const int firsta = wave_excl_scan(nqa);
         const int Sa = __shfl(firsta + nqa, kWave - 1);
-        Frame<double> F;
-        float Gm;
         bool any;
-        wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, firsta, nqa, Sa, F,
-                                               Gm, any, fl);
+        {
+            Frame<double> F;
+            float Gm;
+            wave_footprint_geometry<kLds, MP, MIG>(types, tables, s_tab, q, fp, n_max, b, t, firsta, nqa, Sa,
+                                                   F, Gm, any, fl);
+            wave_lds_sync();
+            L.fn[0][lane] = F.n.x; L.fn[1][lane] = F.n.y; L.fn[2][lane] = F.n.z;
+            L.ft[0][lane] = F.t.x; L.ft[1][lane] = F.t.y; L.ft[2][lane] = F.t.z;
+            L.gm[lane] = Gm;
+            L.use[lane] = single ? 1 : 0;
+            L.wo[0][lane] = L.wo[1][lane] = L.wo[2][lane] = 0.0;
+            L.ex[0][lane] = L.ex[1][lane] = L.ex[2][lane] = 0.0f;
+            L.lobe[lane] = -1;
+            L.node[lane] = 0;
+            wave_lds_sync();
+        }
         // the stratum and the draw, per query
-        SampleOut<float> so;
-        for (int c = 0; c < 3; ++c) so.wo[c] = so.wgt[c] = so.ex[c] = 0.0f;
-        so.pdf = 0.0f;
-        so.lobe = -1;
-        so.node = 0;
         int s = 0;
         if (good) {
             s = f.n - 1;
@@ -1052,7 +900,6 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
                 }
             }
         }
-        V3<double> wo = mk3<double>(0.0, 0.0, 0.0);
         bool drawn = false, pass = good && !any && !single;
         const float s0 = in && q.s0 ? q.s0[i] : 0.0f, s1 = in && q.s1 ? q.s1[i] : 0.0f;
         for_each_wave_type<false>(t, good && (any || single), [&](int tu) {
@@ -1065,19 +912,23 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             if (single) fl |= X.ph.flags & ~F_PASS_THROUGH;
             pass = X.ph.pass;
             if (pass) return;
-            if (!single) apply_aggregate(Pm, X, F, Gm);
+            if (!single) {
+                Frame<double> Fo;
+                Fo.n = mk3<double>(L.fn[0][lane], L.fn[1][lane], L.fn[2][lane]);
+                Fo.t = mk3<double>(L.ft[0][lane], L.ft[1][lane], L.ft[2][lane]);
+                Fo.b = cross(Fo.n, Fo.t);
+                apply_aggregate(Pm, X, Fo, L.gm[lane]);
+            }
             NodesComputed<double, float, MP, TabPtrT<MIG>> nf{Pm, tab, X, s0, s1, q.s0 != nullptr};
+            SampleOut<float> so;
+            V3<double> wo;
             fl |= sample_draw(Pm, X, m.wi, x0, x1, x2, nf, so, wo, drawn);
+            L.wo[0][lane] = wo.x; L.wo[1][lane] = wo.y; L.wo[2][lane] = wo.z;
+            L.ex[0][lane] = so.ex[0]; L.ex[1][lane] = so.ex[1]; L.ex[2][lane] = so.ex[2];
+            L.lobe[lane] = so.lobe;
+            L.node[lane] = so.node;
         });
-        if (pass) {
-            so.wo[0] = -m.wi.x;
-            so.wo[1] = -m.wi.y;
-            so.wo[2] = -m.wi.z;
-            so.wgt[0] = so.wgt[1] = so.wgt[2] = 1.0f;
-            so.lobe = 4;
-            fl |= F_PASS_THROUGH;
-        }
-        if (good) so.node += 16 * s;
+        wave_lds_sync();
         // f_multi and its pdf at the drawn direction
         EvalOut<float> em;
         em.E[0] = em.E[1] = em.E[2] = 0.0f;
@@ -1088,14 +939,8 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             const int j = k - __shfl(first, own);
             const int to = __shfl(t, own);
             const int drawn_o = __shfl((int)drawn, own);
-            const int single_o = __shfl((int)single, own);
+            const int single_o = L.use[own] & 1;
             const bool item = k < S && drawn_o != 0;
-            Frame<double> Fo;
-            Fo.n = shfl3(F.n, own);
-            Fo.t = shfl3(F.t, own);
-            Fo.b = shfl3(F.b, own);
-            const float Go = __shfl(Gm, own);
-            const V3<double> wd = shfl3(wo, own);
             float ev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             float w_it = 0.0f;
             for_each_wave_type<false>(to, item, [&](int tu) {
@@ -1111,8 +956,15 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
                 XState<double, float, MP> X;
                 state_at_x(Pm, tab, hj, mo.u, mo.v, mo.wi, X);
                 if (X.ph.pass) return;
-                if (!single_o) apply_aggregate(Pm, X, Fo, Go);
+                if (!single_o) {
+                    Frame<double> Fo;
+                    Fo.n = mk3<double>(L.fn[0][own], L.fn[1][own], L.fn[2][own]);
+                    Fo.t = mk3<double>(L.ft[0][own], L.ft[1][own], L.ft[2][own]);
+                    Fo.b = cross(Fo.n, Fo.t);
+                    apply_aggregate(Pm, X, Fo, L.gm[own]);
+                }
                 const float t0 = q.s0 ? q.s0[io] : 0.0f, t1 = q.s1 ? q.s1[io] : 0.0f;
+                const V3<double> wd = mk3<double>(L.wo[0][own], L.wo[1][own], L.wo[2][own]);
                 EvalOut<float> e;
                 lobes(Pm, tab, X, wd, t0, t1, q.s0 != nullptr, e);
                 w_it = float(stratum_w(fo, (double)hj));
@@ -1134,10 +986,28 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
             }
         }
         if (!in) continue;
+        SampleOut<float> so;
+        for (int c = 0; c < 3; ++c) {
+            so.wo[c] = so.wgt[c] = 0.0f;
+            so.ex[c] = L.ex[c][lane];
+        }
+        so.pdf = 0.0f;
+        so.lobe = L.lobe[lane];
+        so.node = L.node[lane];
+        if (pass) {
+            so.wo[0] = -q.wix[i];
+            so.wo[1] = -q.wiy[i];
+            so.wo[2] = -q.wiz[i];
+            so.wgt[0] = so.wgt[1] = so.wgt[2] = 1.0f;
+            so.lobe = 4;
+            fl |= F_PASS_THROUGH;
+        }
+        if (good) so.node += 16 * s;
         if (drawn) {
             const float iw = float(1.0 / f.wsum);
             for (int c = 0; c < 3; ++c) em.E[c] = em.E[c] * iw;
             em.pdf = em.pdf * iw;
+            const V3<double> wo = mk3<double>(L.wo[0][lane], L.wo[1][lane], L.wo[2][lane]);
             fl = sample_finish(em, wo, fl, so);
         }
         o.wox[i] = so.wo[0]; o.woy[i] = so.wo[1]; o.woz[i] = so.wo[2];
@@ -1149,7 +1019,6 @@ __global__ __launch_bounds__(kBlock, BYSDF_MULTI_MIN_WAVES) void k_sample_multi(
         o.flags[i] = fl;
     }
 }
-
 // ------------------------------------------------------------------ ply geometry
 // The implicit ply hit of Sec. 3.4 on its own (no fiber table, no lobes):
 // the ply, the hit point and the ply's frame there, for studies of the
@@ -1315,16 +1184,6 @@ __global__ __launch_bounds__(kBlock) void k_furnace(const TypeRec* __restrict__ 
 #endif
 constexpr int kFurnaceWaves = kBlock / kWave;
 
-// Orders the LDS accesses of one wavefront's lanes to each other's slots
-// (wavefront-scope fences around a wave barrier: the LDS serves a
-// wavefront's operations in issue order, so this emits no wait and only
-// keeps the compiler from moving accesses across it).
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ inline float wave_sum_f(float x)
 {
