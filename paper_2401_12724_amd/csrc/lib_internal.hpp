@@ -78,7 +78,9 @@ int yarn_scene_max_type(const yarn_scene_t* s);
 // record with that per-lane value, turning every parameter read into a
 // vector load.  kScalar = false hands over the index unchanged: the
 // multi-scale kernels copy the record into a per-footprint variant, and
-// there the vector loads measured faster.
+// there the vector loads measured faster.  The body is inlined at both of
+// its call sites: a body left as a call keeps everything it captures, and
+// its own structures, on the private stack.
 template <bool kScalar = true, class F>
 __device__ inline void for_each_wave_type(int t, bool need, F&& body)
 {
@@ -89,7 +91,7 @@ __device__ inline void for_each_wave_type(int t, bool need, F&& body)
         // straight-line path: no value has to stay live around a loop
         const int t0 = __builtin_amdgcn_readlane(t, __ffsll((long long)pending) - 1);
         if (__ballot(need && t != t0) == 0ull) {
-            if (need) body(kScalar ? __builtin_amdgcn_readfirstlane(t0) : t0);
+            if (need) [[clang::always_inline]] body(kScalar ? __builtin_amdgcn_readfirstlane(t0) : t0);
             return;
         }
     }
@@ -97,7 +99,7 @@ __device__ inline void for_each_wave_type(int t, bool need, F&& body)
         const int lead = __ffsll((long long)pending) - 1;
         const int tu = __builtin_amdgcn_readlane(t, lead);
         const bool mine = need && t == tu;
-        if (mine) body(kScalar ? __builtin_amdgcn_readfirstlane(tu) : tu);
+        if (mine) [[clang::always_inline]] body(kScalar ? __builtin_amdgcn_readfirstlane(tu) : tu);
         pending &= ~__ballot(mine);
     }
 }

@@ -356,33 +356,65 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
         const bool act = i < n && H.yarn[i] >= 0;
         int yarn_id = act ? H.yarn[i] : 0;
         int type = act ? V.S.yarn_type[yarn_id] : 0;
-        // path and hit
-        D3 o = yarn::d3(0, 0, 0), d = yarn::d3(0, 0, 1), T = yarn::d3(0, 0, 1), N = yarn::d3(1, 0, 0);
-        float thr[3] = {0.f, 0.f, 0.f}, hq = 0.f, uq = 0.f, vl = 0.f, R = 0.f, t = 0.f, line0 = 0.f;
-        int lid = 0;
+        // the path and its hit are read again after the BYSDF (below), so
+        // that only the BYSDF's inputs and outputs stay live through it
+        auto path_at = [&](D3& o, D3& d, D3& T, D3& N, float& t, float& R) {
+            o = yarn::d3(0, 0, 0), d = yarn::d3(0, 0, 1), T = yarn::d3(0, 0, 1), N = yarn::d3(1, 0, 0);
+            t = 0.f;
+            R = 0.f;
+            if (act) {
+                o = yarn::d3(Q.ox[i], Q.oy[i], Q.oz[i]);
+                d = yarn::unit(yarn::d3(Q.dx[i], Q.dy[i], Q.dz[i]));
+                t = H.t[i];
+                R = H.R[i];
+                T = yarn::d3(H.Tx[i], H.Ty[i], H.Tz[i]);
+                N = yarn::d3(H.Nx[i], H.Ny[i], H.Nz[i]);
+            }
+        };
+        // next-event estimation: a uniform point of the light
+        auto light_at = [&](D3 p, const float* u1, D3& wl, double& dist2, double& cosl) {
+            D3 yl = dv(V.lc) + dv(V.leu) * (double)u1[0] + dv(V.lev) * (double)u1[1];
+            D3 lv = yl - p;
+            dist2 = yarn::dot(lv, lv);
+            wl = lv * (1.0 / sqrt(dist2));
+            cosl = -yarn::dot(wl, dv(V.ln));
+        };
+        const int lid = act ? Q.lid[i] : 0;
+        const uint64_t slot = (uint64_t)(lid / spp_batch) * V.spp + j0 + lid % spp_batch;
+        float u1[4] = {0, 0, 0, 0}, u2[4] = {0, 0, 0, 0};
         if (act) {
-            o = yarn::d3(Q.ox[i], Q.oy[i], Q.oz[i]);
-            d = yarn::unit(yarn::d3(Q.dx[i], Q.dy[i], Q.dz[i]));
-            thr[0] = Q.tr[i];
-            thr[1] = Q.tg[i];
-            thr[2] = Q.tb[i];
-            line0 = Q.line0[i];
-            lid = Q.lid[i];
-            t = H.t[i];
-            hq = H.h[i];
-            R = H.R[i];
-            vl = (float)((double)H.v[i] / (double)R);
-            uq = V.S.yarn_phase[yarn_id];
-            T = yarn::d3(H.Tx[i], H.Ty[i], H.Tz[i]);
-            N = yarn::d3(H.Nx[i], H.Ny[i], H.Nz[i]);
+            rnd(V, slot, (uint32_t)depth, 1, u1);
+            rnd(V, slot, (uint32_t)depth, 2, u2);
         }
-        D3 p = o + d * (double)t;
-        V3<float> wi = to_loc(T, N, d * -1.0);
-        D3 pe = p - dv(V.eye);
         // multi-scale: the camera hits use their pixel footprint, later
         // bounces the near field; otherwise the far field by the LOD rule
         const bool msx = MS && depth == 0;
-        const bool far = !MS && !GRAD && 2.0 * R / (sqrt(yarn::dot(pe, pe)) * V.pix_angle) < V.lod_px;
+        bool far;
+        float hq = 0.f, uq = 0.f, vl = 0.f, fh1, fh2;
+        V3<float> wi, wol;
+        bool lit;
+        {
+            D3 o, d, T, N;
+            float t, R;
+            path_at(o, d, T, N, t, R);
+            if (act) {
+                hq = H.h[i];
+                vl = (float)((double)H.v[i] / (double)R);
+                uq = V.S.yarn_phase[yarn_id];
+            }
+            const D3 p = o + d * (double)t;
+            wi = to_loc(T, N, d * -1.0);
+            const D3 pe = p - dv(V.eye);
+            far = !MS && !GRAD && 2.0 * R / (sqrt(yarn::dot(pe, pe)) * V.pix_angle) < V.lod_px;
+            fh1 = hq;
+            fh2 = hq;
+            if (msx && act) camera_footprint(V, o, d, (double)t, T, N, (double)R, hq, &fh1, &fh2);
+            D3 wl;
+            double dist2, cosl;
+            light_at(p, u1, wl, dist2, cosl);
+            wol = to_loc(T, N, wl);
+            lit = cosl > 0.0;
+        }
         // gradient mode: path log-derivatives in, BYSDF derivatives at the
         // light direction and at the drawn one
         // (Dp: into this hit; Dn: out of it along the drawn direction)
@@ -393,28 +425,12 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                 Dp[k] = Dn[k] = act ? Q.D[k * cap + i] : 0.0f;
                 dEn[k] = dEs[k] = 0.0f;
             }
-        float fh1 = hq, fh2 = hq;
-        if (msx && act) camera_footprint(V, o, d, (double)t, T, N, (double)R, hq, &fh1, &fh2);
-        const uint64_t slot = (uint64_t)(lid / spp_batch) * V.spp + j0 + lid % spp_batch;
-        float u1[4] = {0, 0, 0, 0}, u2[4] = {0, 0, 0, 0};
-        if (act) {
-            rnd(V, slot, (uint32_t)depth, 1, u1);
-            rnd(V, slot, (uint32_t)depth, 2, u2);
-        }
-        // next-event estimation: a uniform point of the light
-        D3 yl = dv(V.lc) + dv(V.leu) * (double)u1[0] + dv(V.lev) * (double)u1[1];
-        D3 lv = yl - p;
-        double dist2 = yarn::dot(lv, lv);
-        D3 wl = lv * (1.0 / sqrt(dist2));
-        double cosl = -yarn::dot(wl, dv(V.ln));
-        V3<float> wol = to_loc(T, N, wl);
         double En[3] = {0, 0, 0}, pb = 0.0;
-        // the continued path
-        bool cont = false;
-        D3 dnew = d;
-        float wgt[3] = {1.f, 1.f, 1.f};
-        float pdf_new = act ? Q.pdf[i] : -1.0f;
-        float line_new = line0;
+        // the BYSDF's continuation: 0 none, 1 straight through the yarn,
+        // 2 a drawn direction wo with weight wgt and density pdf_s
+        int mode = 0;
+        float wo_s[3] = {0.f, 0.f, 0.f}, wgt[3] = {1.f, 1.f, 1.f};
+        double pdf_s = 0.0;
         for_each_wave_type(type, act, [&](int tu) {
             const Derived<double, float>& P = V.types[tu].d;
             TabPtr tab{V.tables + V.types[tu].table_off};
@@ -431,10 +447,10 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                 if (!X.ph.pass) {
                     EvalOut<float> en, es;
                     float dsn = 0.0f, dss = 0.0f;
-                    bysdf::lobes_nodes2_dsigma(P, X, bysdf::mk3<double>(wol.x, wol.y, wol.z), cosl > 0.0, ws, ok,
+                    bysdf::lobes_nodes2_dsigma(P, X, bysdf::mk3<double>(wol.x, wol.y, wol.z), lit, ws, ok,
                                                nf, en, es, dsn, dss);
                     const bool mine = tu == V.grad_type;
-                    if (cosl > 0.0) {
+                    if (lit) {
                         for (int c = 0; c < 3; ++c) En[c] = en.E[c];
                         pb = en.pdf;
                         if (mine) bysdf_grad(P, en, dsn, dEn);
@@ -450,7 +466,7 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                 bysdf::Footprint fp;
                 bysdf::make_footprint(hq, fh1, fh2, u2[2], V.n_h, fp);
                 const Derived<double, float> Pm = bysdf::widened(P, Rt.beta, Rt.aniso, fp);
-                if (cosl > 0.0) {
+                if (lit) {
                     EvalOut<float> e;
                     bysdf::eval_multi<double, float, MP>(Pm, tab, fp, uq, vl, wi, wol, 0.0f, 0.0f, false, e);
                     for (int c = 0; c < 3; ++c) En[c] = e.E[c];
@@ -468,15 +484,14 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                 EvalOut<float> e;
                 for (int c = 0; c < 3; ++c) e.E[c] = 0.0f;
                 e.pdf = 0.0f;
-                sf = bysdf::eval_sample_from_x(P, X, wi, bysdf::mk3<double>(wol.x, wol.y, wol.z),
-                                               cosl > 0.0, u1[2], u1[3], u2[0], nf, e, so);
-                if (!X.ph.pass && cosl > 0.0) {
+                sf = bysdf::eval_sample_from_x(P, X, wi, bysdf::mk3<double>(wol.x, wol.y, wol.z), lit, u1[2],
+                                               u1[3], u2[0], nf, e, so);
+                if (!X.ph.pass && lit) {
                     for (int c = 0; c < 3; ++c) En[c] = e.E[c];
                     pb = e.pdf;
                 }
             } else {
-                if (cosl > 0.0)
-                    far_eval<MP>(P, tab, uq, vl, wi, wol, V.n_h, u2[2], En, &pb, V.types[tu].node_disk);
+                if (lit) far_eval<MP>(P, tab, uq, vl, wi, wol, V.n_h, u2[2], En, &pb, V.types[tu].node_disk);
                 int js = (int)floorf(u2[1] * V.n_h);
                 js = js > V.n_h - 1 ? V.n_h - 1 : js;
                 float hs = (float)(-1.0 + 2.0 * (js + (double)u2[2]) / V.n_h);
@@ -488,9 +503,7 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
             }
             if (depth == V.max_depth) return;
             if (so.lobe == 4) {
-                // straight through the yarn: the last scattering event stays in force
-                cont = true;
-                line_new = line0 + t;
+                mode = 1;
             } else if (so.lobe >= 0 && !(sf & kSampleFail) && so.pdf > 0.0f) {
                 V3<float> wo = bysdf::mk3<float>(so.wo[0], so.wo[1], so.wo[2]);
                 double pdf = so.pdf;
@@ -504,21 +517,51 @@ __global__ __launch_bounds__(kShadeBlock, RENDER_SHADE_MIN_WAVES) void k_r_shade
                     for (int c = 0; c < 3; ++c) wgt[c] = so.wgt[c];
                 }
                 if (ok) {
-                    D3 B = yarn::cross(T, N);
-                    dnew = yarn::unit(N * (double)wo.x + B * (double)wo.y + T * (double)wo.z);
-                    pdf_new = (float)pdf;
-                    line_new = 0.0f;
-                    float nt[3];
-                    for (int c = 0; c < 3; ++c) nt[c] = thr[c] * wgt[c];
-                    if (GRAD)
-                        for (int k = 0; k < kGrad; ++k)
-                            if (Es[k / 3] > 0.0f) Dn[k] = Dp[k] + dEs[k] / Es[k / 3];
-                    cont = nt[0] > 0.f || nt[1] > 0.f || nt[2] > 0.f;
-                    for (int c = 0; c < 3; ++c) thr[c] = nt[c];
+                    mode = 2;
+                    wo_s[0] = wo.x;
+                    wo_s[1] = wo.y;
+                    wo_s[2] = wo.z;
+                    pdf_s = pdf;
                 }
             }
         });
+        D3 o, d, T, N;
+        float t, R;
+        path_at(o, d, T, N, t, R);
+        const D3 p = o + d * (double)t;
+        float thr[3] = {0.f, 0.f, 0.f}, line0 = 0.f;
+        if (act) {
+            thr[0] = Q.tr[i];
+            thr[1] = Q.tg[i];
+            thr[2] = Q.tb[i];
+            line0 = Q.line0[i];
+        }
+        // the continued path
+        bool cont = false;
+        D3 dnew = d;
+        float pdf_new = act ? Q.pdf[i] : -1.0f;
+        float line_new = line0;
+        if (mode == 1) {
+            // straight through the yarn: the last scattering event stays in force
+            cont = true;
+            line_new = line0 + t;
+        } else if (mode == 2) {
+            D3 B = yarn::cross(T, N);
+            dnew = yarn::unit(N * (double)wo_s[0] + B * (double)wo_s[1] + T * (double)wo_s[2]);
+            pdf_new = (float)pdf_s;
+            line_new = 0.0f;
+            float nt[3];
+            for (int c = 0; c < 3; ++c) nt[c] = thr[c] * wgt[c];
+            if (GRAD)
+                for (int k = 0; k < kGrad; ++k)
+                    if (Es[k / 3] > 0.0f) Dn[k] = Dp[k] + dEs[k] / Es[k / 3];
+            cont = nt[0] > 0.f || nt[1] > 0.f || nt[2] > 0.f;
+            for (int c = 0; c < 3; ++c) thr[c] = nt[c];
+        }
         // shadow ray
+        D3 wl;
+        double dist2, cosl;
+        light_at(p, u1, wl, dist2, cosl);
         bool want_sh = act && cosl > 0.0 && (En[0] > 0.0 || En[1] > 0.0 || En[2] > 0.0);
         float ct[3] = {0, 0, 0};
         if (want_sh) {
