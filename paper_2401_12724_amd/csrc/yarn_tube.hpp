@@ -312,9 +312,16 @@ __host__ __device__ inline void load_span(const SceneView& S, const SpanRec& r, 
     }
 }
 
-// squared distance from the origin of the span view to the curve: samples,
-// then safeguarded Newton on the derivative of |C(s)|^2
-__host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
+// Whether the curve comes closer than lim to the origin of the span view,
+// as the squared distance from the samples refined by safeguarded Newton on
+// the derivative of |C(s)|^2 decides it.  Two exits skip the refinement
+// without changing the answer: a sample already closer than lim (the
+// refinement only lowers the minimum), and samples all farther than
+// lim + L / (2 nsamp), with L = max_k |c_{k+1} - c_k| bounding the speed
+// |C'(s)| (the derivative of a uniform cubic B-spline segment is a convex
+// combination of its control-point differences), so that no point of the
+// curve, being within 1 / (2 nsamp) of a sample, can come closer than lim.
+__host__ __device__ inline bool span_within(const SpanGeo& g, int nsamp, double lim)
 {
     // the centreline relative to the point, a cubic per coordinate
     double cx[4], cy[4], cz[4], ax[4], ay[4], az[4];
@@ -338,6 +345,17 @@ __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
             bi = i;
         }
     }
+    const double lim2 = lim * lim;
+    if (bv < lim2) return true;
+    double L2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const D3 dc = g.c[k + 1] - g.c[k];
+        L2 = fmax(L2, dot(dc, dc));
+    }
+    // the relative margin covers the rounding of the samples and of L
+    const double m = lim + 0.5 * bysdf::sqrt_(L2) * inv;
+    if (bv > m * m * (1.0 + 1e-9)) return false;
     double lo = bi > 0 ? (bi - 1) * inv : 0.0, hi = bi < nsamp ? (bi + 1) * inv : 1.0, s = bi * inv;
     for (int it = 0; it < 20; ++it) {
         D3 p = at(s);
@@ -358,7 +376,7 @@ __host__ __device__ inline double span_dist2(const SpanGeo& g, int nsamp)
     }
     D3 p = at(s);
     double v = dot(p, p);
-    return v < bv ? v : bv;
+    return (v < bv ? v : bv) < lim2;
 }
 // True when the span is certainly farther than lim from the origin of the
 // span view: the curve lies in the hull of its control points, which lies
@@ -470,7 +488,7 @@ __host__ __device__ inline int excluded_yarns(const SceneView& S, D3 o, int* stk
                 load_span(S, r, o, &g);
                 double lim = g.R * (1.0 - kExcludeFrac);
                 if (span_far(g, lim)) continue;
-                if (span_dist2(g, r.info & 0xffff) < lim * lim) ex[nex++] = r.yarn;
+                if (span_within(g, r.info & 0xffff, lim)) ex[nex++] = r.yarn;
             }
         }
         if (sp == 0) break;
