@@ -1215,6 +1215,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(c
     bysdf::stage_math_tables();
     __syncthreads();
     __shared__ XState<double, float, MP> s_X[kFurnaceWaves][kFurnaceGroupMax];
+    __shared__ int s_ord[kFurnaceWaves][kMaxDrawsPerLane * kWave];
     extern __shared__ Node<double, float> s_nd[];  // [kFurnaceWaves][group][kmax]
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     Node<double, float>* nodes_w = s_nd + wv * group * kmax;
@@ -1280,14 +1281,44 @@ __global__ __launch_bounds__(kBlock, BYSDF_FURNACE_MIN_WAVES) void k_furnace_w(c
         const int64_t q0 = b * (int64_t)block;
         const XState<double, float, MP>& X = s_X[wv][g];
         NodesStored<double, float> nodes{nodes_w + g * kmax};
+        // the draws in lobe order: a draw's lobe follows from its first
+        // uniform and the block's lobe weights alone, so a stable counting
+        // sort by lobe lets a wavefront's lanes take the same sampling and
+        // evaluation branches (VNDF or cosine, at x or at a node)
+        int key[kMaxDrawsPerLane];
+#pragma unroll
+        for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+            const int j = lane + d * kWave;
+            key[d] = -1;
+            if (j < block && !bad) {
+                SampleOut<float> so;
+                float x0, x1, x2;
+                query_xi(q, q0 + j, x0, x1, x2);
+                sample_pick(P, X, wi, x0, so);
+                key[d] = so.lobe < 0 ? 0 : so.lobe;
+            }
+        }
+        wave_lds_sync();
+        {
+            const unsigned long long below = (1ull << lane) - 1ull;
+            int base = 0;
+            for (int v = 0; v <= 4; ++v)
+#pragma unroll
+                for (int d = 0; d < kMaxDrawsPerLane; ++d) {
+                    const unsigned long long m = __ballot(key[d] == v);
+                    if (key[d] == v) s_ord[wv][base + __popcll(m & below)] = lane + d * kWave;
+                    base += __popcll(m);
+                }
+        }
+        wave_lds_sync();
         float w[kMaxDrawsPerLane][3];
         float sum[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int d = 0; d < kMaxDrawsPerLane; ++d) {
-            const int j = lane + d * kWave;
+            const int p = lane + d * kWave;
             w[d][0] = w[d][1] = w[d][2] = 0.0f;
-            if (j < block && !bad) {
-                const int64_t qi = q0 + j;
+            if (p < block && !bad) {
+                const int64_t qi = q0 + s_ord[wv][p];
                 SampleOut<float> so;
                 float x0, x1, x2;
                 query_xi(q, qi, x0, x1, x2);
