@@ -1463,7 +1463,7 @@ __global__ __launch_bounds__(kBlock, BYSDF_BACKWARD_MIN_WAVES) void k_backward(c
             }
             if (!X.ph.pass) {
                 EvalOut<DF> e;
-                lobes(P, tab, X, wo_d, s0, s1, q.s0 != nullptr, e);
+                lobes(P, tab, X, wo_d, s0, s1, q.s0 != nullptr, e, rec.node_disk);
                 const float dE = ge[0] * e.E[0].d + ge[1] * e.E[1].d + ge[2] * e.E[2].d;
                 if (PASS == 0) {
                     const float b0 = e.body0.v, Gp = X.Gp.v, Gf = X.Gf.v;

@@ -2,7 +2,7 @@
 against the FP64 intersection oracle: a small weave with random rays (every
 ray), the full 512-yarn weave with camera and random rays (sampled rays),
 a non-planar yarn, scenes of 1 to 9 spans (wide BVH nodes with unused
-slots), and the edge cases (misses, t_max, origins inside a tube, end caps,
+slots), rays starting inside and just outside the tubes, and the edge cases (misses, t_max, origins inside a tube, end caps,
 bad rays, empty batches)."""
 import numpy as np
 import pytest
@@ -98,6 +98,37 @@ def test_full_weave_sampled(torch_cuda):
     r = oracle.intersect(oracle.Scene(ctrl, off), o, d, tm, 1e-4)
     both = _compare(g, r, ph, "full weave")
     assert both.sum() > 3000
+
+
+def test_origins_inside_and_near_tubes(torch_cuda):
+    """Rays in random directions from points at 0 to 1.2 R off a yarn's
+    centreline on the small weave: inside the tube the point query excludes
+    the yarn (and any other tube holding the point), just outside it does
+    not.  The fractions stay clear of the exclusion limit R (1 - 1e-3), where
+    rounding would decide."""
+    torch = torch_cuda
+    ctrl, off, ty, ph = W.weave(8, 8, 0.15, 0.05, 4)
+    S = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    sc = oracle.Scene(ctrl, off)
+    rng = np.random.default_rng(21)
+    fr = np.array([0.0, 0.3, 0.7, 0.95, 0.99, 1.01, 1.05, 1.2])
+    o, d = [], []
+    for i in range(4000):
+        y = int(rng.integers(len(off) - 1))
+        seg = int(rng.integers(off[y + 1] - off[y] - 3))
+        f = sc.frame(y, seg, float(rng.random()))
+        T, N, c = f[0:3], f[3:6], f[7:10]
+        phi = 2.0 * np.pi * rng.random()
+        rr = float(ctrl[off[y], 3]) * fr[i % len(fr)]
+        o.append(c + rr * (np.cos(phi) * N + np.sin(phi) * np.cross(T, N)))
+        v = rng.normal(size=3)
+        d.append(v / np.linalg.norm(v))
+    o, d = np.array(o, np.float32), np.array(d, np.float32)
+    tm = np.full(len(o), 100.0, np.float32)
+    g = _run(torch, S, o, d, tm)
+    r = oracle.intersect(sc, o, d, tm, 1e-4)
+    both = _compare(g, r, ph, "origins inside and near tubes")
+    assert both.sum() > 1500
 
 
 def test_non_planar_yarn(torch_cuda):
