@@ -919,10 +919,16 @@ static int render(const yarn_scene_t* scene, const bysdf_types_t* types, const r
                                stream, V, Qs[a], cnt + a, Hh, L, n, depth);
             if (depth == rs->max_depth) break;
             hipLaunchKernelGGL(k_r_counters, dim3(1), dim3(64), 0, stream, cnt, b, 2, -1);
+            // multi-scale mode: only the camera hits (depth 0) take the
+            // footprint; later bounces are near field, which the plain
+            // kernel computes when its view disables the far-field rule
+            const bool ms0 = rs->multiscale && depth == 0;
             auto shade = g ? (mp4 ? k_r_shade<4, false, true> : k_r_shade<8, false, true>)
-                           : rs->multiscale ? (mp4 ? k_r_shade<4, true, false> : k_r_shade<8, true, false>)
-                                            : (mp4 ? k_r_shade<4, false, false> : k_r_shade<8, false, false>);
-            hipLaunchKernelGGL(shade, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream, V,
+                           : ms0 ? (mp4 ? k_r_shade<4, true, false> : k_r_shade<8, true, false>)
+                                 : (mp4 ? k_r_shade<4, false, false> : k_r_shade<8, false, false>);
+            RView Vs = V;
+            if (rs->multiscale && !ms0) Vs.lod_px = 0.0f;
+            hipLaunchKernelGGL(shade, dim3(grid_for(n, kShadeBlock, 8192)), dim3(kShadeBlock), 0, stream, Vs,
                                Qs[a], cnt + a, Hh, Qs[b], cnt + b, SQ, cnt + 2, n, depth, j0, nb);
             hipLaunchKernelGGL(k_r_tally, dim3(1), dim3(64), 0, stream, cnt, 2, stats, 1);
             hipLaunchKernelGGL(mp4 ? k_r_shadow<4> : k_r_shadow<8>, dim3(grid_for(n, kTraceBlock, 16384)),
