@@ -25,7 +25,7 @@ HEADERS = ["bysdf_math.hpp", "math_tables.inc", "bysdf_model.hpp", "bysdf_multi.
            "lib_internal.hpp", "bysdf_precision.hpp"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # FP32 division and square root from the hardware reciprocal / root
     # (about 1 ulp); FP64 stays correctly rounded
@@ -57,7 +57,7 @@ def build(verbose: bool = False) -> str:
         if any(rcs):
             raise subprocess.CalledProcessError(max(rcs), "hipcc -c")
         tmp = LIB + ".tmp" + tag
-        cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

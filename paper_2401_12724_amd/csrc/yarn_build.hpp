@@ -1,8 +1,9 @@
 // yarn_build.hpp -- host side of a yarn scene build (see yarn_scene.hip):
 // validation, per-span records, rotation-minimising frames and arc lengths,
 // the binned-SAH BVH collapsed to four children per node, spans in leaf
-// order.  No device call; the library
-// uploads the result.
+// order.  No device call; the library uploads the result.  The per-yarn
+// frames and the top levels of the tree are built on host threads; the
+// result does not depend on their number.
 #pragma once
 
 #include <algorithm>
@@ -10,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bysdf.h"
@@ -134,6 +136,62 @@ struct Builder {
         max_depth = std::max(max_depth, depth);
         int n = e - b;
         if (n <= kLeafMax && depth > 0) return leaf_code(b, n);
+        const int mid = split(b, e, depth);
+        int self = (int)nodes.size();
+        nodes.push_back(BNode{});
+        int c0 = build(b, mid, depth + 1);
+        int c1 = build(mid, e, depth + 1);
+        set_node(self, b, mid, e, c0, c1);
+        return self;
+    }
+
+    // As build, with the subtree of the upper half of each of the top
+    // `levels` splits built by its own builder on another thread, its
+    // nodes appended afterwards.  The prims of the two halves are disjoint
+    // ranges, and each split sees the same range as in build, so the tree
+    // (and its collapse, which renumbers nodes in its own order) is the same.
+    int build_par(int b, int e, int depth, int levels)
+    {
+        if (levels <= 0 || e - b < 8192) return build(b, e, depth);
+        max_depth = std::max(max_depth, depth);
+        const int mid = split(b, e, depth);
+        int self = (int)nodes.size();
+        nodes.push_back(BNode{});
+        Builder up(prims);
+        int c1 = 0;
+        std::thread th([&] { c1 = up.build_par(mid, e, depth + 1, levels - 1); });
+        int c0 = build_par(b, mid, depth + 1, levels - 1);
+        th.join();
+        const int base = (int)nodes.size();
+        for (BNode nd : up.nodes) {
+            if (nd.d.x >= 0) nd.d.x += base;
+            if (nd.d.y >= 0) nd.d.y += base;
+            nodes.push_back(nd);
+        }
+        if (c1 >= 0) c1 += base;
+        max_depth = std::max(max_depth, up.max_depth);
+        set_node(self, b, mid, e, c0, c1);
+        return self;
+    }
+
+    void set_node(int self, int b, int mid, int e, int c0, int c1)
+    {
+        float lo0[3], hi0[3], lo1[3], hi1[3];
+        bounds(b, mid, lo0, hi0);
+        bounds(mid, e, lo1, hi1);
+        BNode& nd = nodes[self];
+        nd.a = make_float4(lo0[0], lo0[1], lo0[2], hi0[0]);
+        nd.b = make_float4(hi0[1], hi0[2], lo1[0], lo1[1]);
+        nd.c = make_float4(lo1[2], hi1[0], hi1[1], hi1[2]);
+        nd.d = make_int4(c0, c1, 0, 0);
+    }
+
+    // the split of prims [b, e) (n > kLeafMax or the root): binned SAH over
+    // the three axes, else the object median along the widest centroid
+    // axis; the prims are partitioned and the first of the upper part returned
+    int split(int b, int e, int depth)
+    {
+        const int n = e - b;
         float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int i = b; i < e; ++i)
             for (int k = 0; k < 3; ++k) {
@@ -212,19 +270,7 @@ struct Builder {
             std::nth_element(prims.begin() + b, prims.begin() + mid, prims.begin() + e,
                              [axis](const Prim& p, const Prim& q) { return p.c[axis] < q.c[axis]; });
         }
-        int self = (int)nodes.size();
-        nodes.push_back(BNode{});
-        float lo0[3], hi0[3], lo1[3], hi1[3];
-        bounds(b, mid, lo0, hi0);
-        bounds(mid, e, lo1, hi1);
-        int c0 = build(b, mid, depth + 1);
-        int c1 = build(mid, e, depth + 1);
-        BNode& nd = nodes[self];
-        nd.a = make_float4(lo0[0], lo0[1], lo0[2], hi0[0]);
-        nd.b = make_float4(hi0[1], hi0[2], lo1[0], lo1[1]);
-        nd.c = make_float4(lo1[2], hi1[0], hi1[1], hi1[2]);
-        nd.d = make_int4(c0, c1, 0, 0);
-        return self;
+        return mid;
     }
 };
 
@@ -341,12 +387,16 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
     std::vector<SpanRec> rec(n_spans);
     std::vector<float4> frame(n_spans);
     std::vector<Prim> prims(n_spans);
-    int64_t g = 0;
-    for (int y = 0; y < n_yarns; ++y) {
+    // yarns are independent: each thread takes every nt-th yarn
+    std::vector<int64_t> first_span(n_yarns + 1, 0);
+    for (int y = 0; y < n_yarns; ++y) first_span[y + 1] = first_span[y] + (off[y + 1] - off[y] - 3);
+    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto yarn_spans = [&](int y) {
         double R = ctrl[4 * off[y] + 3];
         int64_t m = off[y + 1] - off[y];
         H3 n{0, 0, 0};
         double v = 0.0;
+        int64_t g = first_span[y];
         for (int64_t j = 0; j + 3 < m; ++j, ++g) {
             int64_t c0 = off[y] + j;
             H3 p[4];
@@ -392,6 +442,15 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
             for (int q = 0; q < 3; ++q) pr.c[q] = 0.5f * (pr.lo[q] + pr.hi[q]);
             pr.id = (int)g;
         }
+    };
+    {
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nt; ++w)
+            pool.emplace_back([&, w] {
+                for (int y = w; y < n_yarns; y += nt) yarn_spans(y);
+            });
+        for (int y = 0; y < n_yarns; y += nt) yarn_spans(y);
+        for (std::thread& th : pool) th.join();
     }
     Builder B(prims);
     B.nodes.reserve(n_spans);
@@ -405,7 +464,9 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
         B.nodes.push_back(nd);
         B.max_depth = 1;
     } else {
-        B.build(0, (int)n_spans, 0);
+        int levels = 0;
+        while ((1 << levels) < nt) ++levels;
+        B.build_par(0, (int)n_spans, 0, levels);
     }
     if (B.max_depth > kStack)
         return build_fail(err, BYSDF_ERR_INVALID_PARAM, "BVH depth %d exceeds %d", B.max_depth, kStack);
