@@ -415,6 +415,17 @@ __host__ __device__ inline int leaf_code(int first, int count) { return -((first
 // end of a traversal: below every leaf code of a scene of fewer than 2^29 spans
 constexpr int kTraceDone = INT32_MIN;
 
+// Whether the predicate holds on any active lane of the wavefront (on the
+// host, a single lane: the predicate itself).
+__host__ __device__ inline bool wave_any(bool p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __any((int)p) != 0;
+#else
+    return p;
+#endif
+}
+
 // box of child c (0..3) of a wide node
 __host__ __device__ inline float comp4(const float4& v, int c)
 {
@@ -538,13 +549,19 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
     double tb = t_max;  // best sampled entry (bounds the true first entry)
     int sp = 0, code = 0;
     float t0 = (float)t_min - slack;
-    // Two inner loops (the while-while form of Aila and Laine, HPG 2009):
-    // a lane descends through nodes until it holds a leaf, then scans that
-    // leaf one span per step.  In a wavefront the node loop runs until
-    // every lane holds a leaf or is done, so the expensive span scans run
-    // with most lanes active instead of alternating with node steps.  The
-    // visiting order of each ray, and so its result, is unchanged.
-    while (code != kTraceDone) {
+    // Two inner loops (the while-while form of Aila and Laine, HPG 2009,
+    // with their postponed leaves): a lane that reaches a leaf holds it and
+    // goes on through nodes until every lane of the wavefront holds a leaf
+    // or is done; then the held leaves are scanned one span per step, with
+    // the leaves met meanwhile.  The expensive span scans so run with most
+    // lanes active.  A lane may visit nodes before scanning a leaf it holds,
+    // with the larger bound tb of that moment: that costs only pruning.  A
+    // span that survives the final filter of the candidates (sampled entry
+    // within kCandMargin R of the final tb) passes the scan limit whenever
+    // it is scanned, and the candidate list keeps the smallest entries, so
+    // the refined candidates, and the hit, do not depend on the order.
+    int leaf = 0;  // the held leaf's code, 0 for none
+    while (code != kTraceDone || leaf != 0) {
         while (code >= 0) {
             const float t1 = (float)tb + slack;
             const WNode n = S.node[code];
@@ -584,10 +601,15 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
             } else {
                 code = sp > 0 ? stk[--sp * stride] : kTraceDone;
             }
+            if (leaf == 0 && code < 0 && code != kTraceDone) {
+                leaf = code;
+                code = sp > 0 ? stk[--sp * stride] : kTraceDone;
+            }
+            if (!wave_any(leaf == 0 && code != kTraceDone)) break;
         }
-        while (code < 0 && code != kTraceDone) {
+        while (leaf != 0) {
             int first, count;
-            decode_leaf(code, &first, &count);
+            decode_leaf(leaf, &first, &count);
             SpanRec r = S.span[first];
             bool skip = false;
             for (int j = 0; j < nex; ++j) skip |= ex[j] == r.yarn;
@@ -616,11 +638,16 @@ __host__ __device__ inline RayHit closest_hit(const SceneView& S, D3 o, D3 d, do
                     }
                 }
             }
-            // the leaf's next span, or the next entry of the stack
-            if (count > 1)
-                code = leaf_code(first + 1, count - 1);
-            else
+            // the leaf's next span, else a leaf met meanwhile (and the next
+            // entry of the stack behind it)
+            if (count > 1) {
+                leaf = leaf_code(first + 1, count - 1);
+            } else if (code < 0 && code != kTraceDone) {
+                leaf = code;
                 code = sp > 0 ? stk[--sp * stride] : kTraceDone;
+            } else {
+                leaf = 0;
+            }
         }
     }
     RayHit best{t_max, 0.0, -1};
