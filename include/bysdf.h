@@ -44,7 +44,7 @@ extern "C" {
 #define BYSDF_OK 0
 #define BYSDF_ERR_INVALID_ARG (-1)      /* null / misaligned pointer, bad size */
 #define BYSDF_ERR_INVALID_PARAM (-2)    /* a type parameter out of its range  */
-#define BYSDF_ERR_OOM (-3)              /* device allocation failed            */
+#define BYSDF_ERR_OOM (-3)              /* device (or host) allocation failed  */
 #define BYSDF_ERR_LAUNCH (-4)           /* kernel launch or HIP call failed    */
 #define BYSDF_ERR_UNSUPPORTED_DEVICE (-5)
 

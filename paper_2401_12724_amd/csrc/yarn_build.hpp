@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <exception>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -159,9 +161,32 @@ struct Builder {
         nodes.push_back(BNode{});
         Builder up(prims);
         int c1 = 0;
-        std::thread th([&] { c1 = up.build_par(mid, e, depth + 1, levels - 1); });
-        int c0 = build_par(b, mid, depth + 1, levels - 1);
-        th.join();
+        std::exception_ptr up_fail, lo_fail;
+        auto upper = [&] {
+            try {
+                c1 = up.build_par(mid, e, depth + 1, levels - 1);
+            } catch (...) {
+                up_fail = std::current_exception();
+            }
+        };
+        // a thread that cannot be started leaves its half to this one
+        std::thread th;
+        try {
+            th = std::thread(upper);
+        } catch (const std::system_error&) {
+        }
+        int c0 = 0;
+        try {
+            c0 = build_par(b, mid, depth + 1, levels - 1);
+        } catch (...) {
+            lo_fail = std::current_exception();
+        }
+        if (th.joinable())
+            th.join();
+        else if (!lo_fail)
+            upper();
+        if (lo_fail) std::rethrow_exception(lo_fail);
+        if (up_fail) std::rethrow_exception(up_fail);
         const int base = (int)nodes.size();
         for (BNode nd : up.nodes) {
             if (nd.d.x >= 0) nd.d.x += base;
@@ -444,12 +469,21 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
         }
     };
     {
+        // (the per-yarn work allocates nothing and cannot throw; a worker
+        // that cannot be started leaves its yarns to this thread)
         std::vector<std::thread> pool;
-        for (int w = 1; w < nt; ++w)
-            pool.emplace_back([&, w] {
+        int started = 1;
+        try {
+            pool.reserve(nt);
+            for (; started < nt; ++started)
+                pool.emplace_back([&, w = started] {
+                    for (int y = w; y < n_yarns; y += nt) yarn_spans(y);
+                });
+        } catch (const std::exception&) {
+        }
+        for (int w = 0; w < nt; ++w)
+            if (w == 0 || w >= started)
                 for (int y = w; y < n_yarns; y += nt) yarn_spans(y);
-            });
-        for (int y = 0; y < n_yarns; y += nt) yarn_spans(y);
         for (std::thread& th : pool) th.join();
     }
     Builder B(prims);

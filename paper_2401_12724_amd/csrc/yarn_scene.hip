@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -123,7 +124,12 @@ extern "C" int yarn_scene_create(const float* ctrl, const int64_t* off, int32_t 
     *out = nullptr;
     HostScene hs;
     std::string err;
-    int rc = yarn_scene_build_host(ctrl, off, n_yarns, yarn_type, yarn_phase, &hs, &err);
+    int rc;
+    try {
+        rc = yarn_scene_build_host(ctrl, off, n_yarns, yarn_type, yarn_phase, &hs, &err);
+    } catch (const std::bad_alloc&) {
+        return fail(BYSDF_ERR_OOM, "host memory exhausted while building the scene");
+    }
     if (rc) return fail(rc, "%s", err.c_str());
     int dev = 0;
     rc = check_gfx950(&dev);
