@@ -20,6 +20,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <new>
 #include <vector>
 
 #include "../../include/bysdf.h"
@@ -62,6 +63,18 @@ __attribute__((visibility("hidden"))) int bysdf_set_error(int code, const char* 
 }
 
 extern "C" const char* bysdf_version(void) { return "bysdf-gfx950 0.1"; }
+// Entry points that allocate host memory run through this: an exhausted
+// heap becomes an error code instead of an exception through the C boundary.
+template <class F>
+static int host_guard(F&& body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail(BYSDF_ERR_OOM, "host memory exhausted");
+    }
+}
+
 extern "C" const char* bysdf_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------------ handle
@@ -1613,8 +1626,7 @@ __attribute__((visibility("hidden"))) BysdfTypesView bysdf_types_view(const bysd
 
 static bool aligned4(const void* p) { return p && ((uintptr_t)p & 3u) == 0; }
 
-extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, bysdf_types_t** out,
-                                  hipStream_t stream)
+static int types_create(const bysdf_type_params* p, int32_t n_types, bysdf_types_t** out, hipStream_t stream)
 {
     if (!out) return fail(BYSDF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -1704,6 +1716,12 @@ extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, b
     return BYSDF_OK;
 }
 
+extern "C" int bysdf_types_create(const bysdf_type_params* p, int32_t n_types, bysdf_types_t** out,
+                                  hipStream_t stream)
+{
+    return host_guard([&] { return types_create(p, n_types, out, stream); });
+}
+
 extern "C" int bysdf_types_destroy(bysdf_types_t* h)
 {
     if (!h) return BYSDF_OK;
@@ -1719,7 +1737,7 @@ extern "C" int32_t bysdf_types_count(const bysdf_types_t* h)
     return h->n_types;
 }
 
-extern "C" int bysdf_types_table(const bysdf_types_t* h, int32_t ti, float* host_out, int64_t cap)
+static int types_table(const bysdf_types_t* h, int32_t ti, float* host_out, int64_t cap)
 {
     if (!h || !host_out) return fail(BYSDF_ERR_INVALID_ARG, "NULL argument");
     if (ti < 0 || ti >= h->n_types) return fail(BYSDF_ERR_INVALID_ARG, "type index out of range");
@@ -1735,6 +1753,11 @@ extern "C" int bysdf_types_table(const bysdf_types_t* h, int32_t ti, float* host
         host_out[3 * i + 2] = tmp[i].z;
     }
     return BYSDF_OK;
+}
+
+extern "C" int bysdf_types_table(const bysdf_types_t* h, int32_t ti, float* host_out, int64_t cap)
+{
+    return host_guard([&] { return types_table(h, ti, host_out, cap); });
 }
 
 extern "C" int bysdf_types_set_theta(bysdf_types_t* h, const float* theta, hipStream_t stream)
@@ -2007,9 +2030,9 @@ struct HostTab {
     float4 operator()(int i) const { return p[i]; }
 };
 
-extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, int64_t n,
-                               const float* h, const float* u, const float* v, const float* wi,
-                               const float* wo, const float* xi, int32_t mode, double* counts)
+static int count_ops(const bysdf_type_params* p, const float* table, int64_t n, const float* h, const float* u,
+                     const float* v, const float* wi, const float* wo, const float* xi, int32_t mode,
+                     double* counts)
 {
     if (!p || !table || !h || !u || !v || !wi || !counts || n < 1 || mode < 0 || mode > 2)
         return fail(BYSDF_ERR_INVALID_ARG, "bad argument");
@@ -2058,6 +2081,13 @@ extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, i
         counts[5 * k + 4] = tally.trans[k] / n;
     }
     return BYSDF_OK;
+}
+
+extern "C" int bysdf_count_ops(const bysdf_type_params* p, const float* table, int64_t n,
+                               const float* h, const float* u, const float* v, const float* wi,
+                               const float* wo, const float* xi, int32_t mode, double* counts)
+{
+    return host_guard([&] { return count_ops(p, table, n, h, u, v, wi, wo, xi, mode, counts); });
 }
 
 // ------------------------------------------------------------------ adjoint API
