@@ -1,7 +1,7 @@
 // yarn_scene.hip -- yarn scenes (B-spline centrelines, frames, BVH) and the
 // ray / yarn-tube intersection kernel of libbysdf (see include/bysdf.h).
 //
-// Scene build (host, once per scene, yarn_build.hpp): per span the rotation-minimising
+// Scene build (host threads, once per scene, yarn_build.hpp): per span the rotation-minimising
 // frame at its start (double reflection, 16 steps per span) and the arc
 // length from the yarn start (5-point Gauss-Legendre per span); a binned
 // SAH BVH over the span boxes (control-point hull grown by R), with object

@@ -14,7 +14,11 @@
 // node: a node holds its four child boxes as structure of arrays and the
 // child codes in one 128-byte line, so a ray fetches half as many nodes
 // one after another as in the binary tree.  Hit children are visited near
-// first, and the per-thread stack lives in LDS.
+// first, and the per-thread stack lives in LDS.  The closest-hit traversal
+// runs nodes and span scans in separate loops, with postponed leaves, so
+// the span scans of a wavefront run together; the point query for tubes
+// holding the origin stops each span's distance test as soon as a sample
+// decides it.
 #pragma once
 
 #include <hip/hip_runtime.h>
