@@ -392,6 +392,12 @@ int yarn_scene_create(const float* ctrl_xyzr, const int64_t* yarn_offsets, int32
                       const int32_t* yarn_type, const float* yarn_phase, yarn_scene_t** out,
                       hipStream_t stream);
 
+/* Host threads a scene build (yarn_scene_create) may use: n >= 1, or 0 for
+ * the default (the hardware's thread count, at most 16).  The built scene
+ * does not depend on it.  Applies to the builds that start afterwards, in
+ * every thread of the process.  INVALID_ARG for n < 0 or n > 256. */
+int yarn_scene_build_threads(int32_t n);
+
 /* Release a scene (NULL is accepted). */
 int yarn_scene_destroy(yarn_scene_t* scene);
 

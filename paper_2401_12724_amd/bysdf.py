@@ -157,6 +157,7 @@ def lib():
                                           _vp, C.c_size_t, _vp]
         L.yarn_scene_create.argtypes = [_vp, _vp, C.c_int32, _vp, _vp, C.POINTER(_vp), _vp]
         L.yarn_scene_destroy.argtypes = [_vp]
+        L.yarn_scene_build_threads.argtypes = [C.c_int32]
         L.yarn_scene_info.argtypes = [_vp, C.POINTER(C.c_int64)]
         L.yarn_tube_intersect.argtypes = [_vp, C.POINTER(RaySoA), C.c_int64, C.c_float,
                                           C.POINTER(HitSoA), _vp]
@@ -587,6 +588,11 @@ def yarn_scene_create(ctrl, yarn_off, yarn_type=None, yarn_phase=None, stream=No
                                  _stream(stream))
     _check(rc, "yarn_scene_create")
     return Scene(h.value, n_y)
+
+
+def yarn_scene_build_threads(n: int) -> None:
+    """Host threads later scene builds may use (0: the default)."""
+    _check(lib().yarn_scene_build_threads(int(n)), "yarn_scene_build_threads")
 
 
 def yarn_scene_info(scene: Scene) -> dict:

@@ -7,6 +7,7 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -30,6 +31,13 @@ inline int build_fail(std::string* err, int code, const char* fmt, ...)
     va_end(ap);
     if (err) *err = buf;
     return code;
+}
+
+// Host threads a build may use (0: the hardware's count, at most 16).
+inline std::atomic<int>& build_threads_setting()
+{
+    static std::atomic<int> n{0};
+    return n;
 }
 
 // host-side arrays of a scene, as uploaded
@@ -415,7 +423,8 @@ inline int yarn_scene_build_host(const float* ctrl, const int64_t* off, int32_t 
     // yarns are independent: each thread takes every nt-th yarn
     std::vector<int64_t> first_span(n_yarns + 1, 0);
     for (int y = 0; y < n_yarns; ++y) first_span[y + 1] = first_span[y] + (off[y + 1] - off[y] - 3);
-    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int set = build_threads_setting().load();
+    const int nt = set > 0 ? set : (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     auto yarn_spans = [&](int y) {
         double R = ctrl[4 * off[y] + 3];
         int64_t m = off[y + 1] - off[y];

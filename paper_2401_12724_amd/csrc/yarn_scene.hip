@@ -116,6 +116,13 @@ static void free_scene(yarn_scene* s)
     delete s;
 }
 
+extern "C" int yarn_scene_build_threads(int32_t n)
+{
+    if (n < 0 || n > 256) return fail(BYSDF_ERR_INVALID_ARG, "build threads must be in 0..256");
+    build_threads_setting().store(n);
+    return 0;
+}
+
 extern "C" int yarn_scene_create(const float* ctrl, const int64_t* off, int32_t n_yarns,
                                  const int32_t* yarn_type, const float* yarn_phase, yarn_scene_t** out,
                                  hipStream_t stream)

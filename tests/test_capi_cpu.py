@@ -99,6 +99,9 @@ def test_scene_arguments_rejected_on_host(L):
     info = (C.c_int64 * 6)()
     assert L.yarn_scene_info(None, info) == bysdf.ERR_INVALID_ARG
     assert L.yarn_tube_intersect(None, None, 0, C.c_float(0.0), None, None) == bysdf.ERR_INVALID_ARG
+    assert L.yarn_scene_build_threads(-1) == bysdf.ERR_INVALID_ARG
+    assert L.yarn_scene_build_threads(257) == bysdf.ERR_INVALID_ARG
+    assert L.yarn_scene_build_threads(0) == bysdf.OK
 
 
 def test_renderer_philox_known_answers(L):

@@ -100,6 +100,26 @@ def test_full_weave_sampled(torch_cuda):
     assert both.sum() > 3000
 
 
+def test_scene_build_independent_of_threads(torch_cuda):
+    """The full weave built on one host thread and on the default number
+    gives the same scene and the same intersections, byte for byte."""
+    torch = torch_cuda
+    ctrl, off, ty, ph = W.weave()
+    rng = np.random.default_rng(7)
+    o, d = W.pinhole_rays(W.weave_camera(), rng.integers(0, 1920, 20000), rng.integers(0, 1080, 20000))
+    tm = np.full(len(o), 1e3, np.float32)
+    try:
+        bysdf.yarn_scene_build_threads(1)
+        S1 = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    finally:
+        bysdf.yarn_scene_build_threads(0)
+    S0 = bysdf.yarn_scene_create(ctrl, off, ty, ph)
+    assert bysdf.yarn_scene_info(S1) == bysdf.yarn_scene_info(S0)
+    g1, g0 = _run(torch, S1, o, d, tm), _run(torch, S0, o, d, tm)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+
+
 def test_origins_inside_and_near_tubes(torch_cuda):
     """Rays in random directions from points at 0 to 1.2 R off a yarn's
     centreline on the small weave: inside the tube the point query excludes
